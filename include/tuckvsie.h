@@ -1,0 +1,198 @@
+/*
+ * libtuckvsie -- matrix-vector products with a Tucker-compressed VSIE
+ * coil-to-body coupling matrix on AMD Instinct MI355X (gfx950).
+ *
+ * The coupling matrix Z (q*nv rows, m columns) maps coil currents to voxel
+ * fields (Sec. II.A.1 of Giannakopoulos et al., "Compression of volume-
+ * surface integral equation matrices via Tucker decomposition for magnetic
+ * resonance applications").  Column j is q stacked vectors, each reshaped to
+ * an n1 x n2 x n3 voxel tensor Z^{kj} and held in Tucker form
+ *     Z^{kj} = G x1 U1 x2 U2 x3 U3                       (eq. 6, Sec. III.A)
+ * with per-tensor multilinear ranks (r1, r2, r3).  The library computes
+ *     Y = Z X      (Algorithm 1, Sec. III.B)
+ *     X = Z^* Y    (Algorithm 2, Sec. III.B; ^* = conjugate transpose)
+ * without ever forming Z, and builds the Tucker form from dense columns with
+ * the truncated HOSVD (Sec. II.B.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are interleaved (re, im).  Host factor arrays are
+ *   complex128 (double pairs); device vectors are complex64 (float pairs).
+ * - Tensor t = k + q*j is component k (0-based) of column j.
+ * - Row order of Y is [Y^1; ...; Y^q] (Algorithm 1's last step): row
+ *   k*nv + i1 + n1*(i2 + n2*i3) holds voxel (i1, i2, i3) of component k,
+ *   i.e. each block is the column-major vectorisation (:) of its tensor.
+ * - Multi-vector operands are column-major with a leading dimension: entry
+ *   (row, col) of X lives at X[row + ld*col].
+ * - Streams are hipStream_t passed as void* (NULL = default stream).  Every
+ *   hot-path call is asynchronous on its stream, never allocates and never
+ *   synchronises.
+ * - Ownership: the caller owns every buffer it passes (vectors, workspace);
+ *   a plan owns the device copy of its factors until tv_plan_destroy.
+ * - Errors: every call returns a tv_status.  Argument errors are detected on
+ *   the host before any device work is queued; the detail of the last error
+ *   on the calling thread is available from tv_last_error().  Device faults
+ *   surface at the caller's next synchronisation.
+ * - A plan is read-only after creation: concurrent calls on different
+ *   streams are safe if each uses its own workspace.
+ */
+#ifndef TUCKVSIE_H
+#define TUCKVSIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TV_OK = 0,
+  TV_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad enum    */
+  TV_ERR_SHAPE = -2,         /* grid / leading dimension inconsistent    */
+  TV_ERR_RANK = -3,          /* rank < 1, > grid size or > TV_MAX_RANK   */
+  TV_ERR_OOM = -4,           /* device or host allocation failed         */
+  TV_ERR_HIP = -5,           /* a HIP runtime call failed                */
+  TV_ERR_NOT_SUPPORTED = -6, /* valid request outside what is built      */
+  TV_ERR_NUMERIC = -7,       /* non-finite factor values                 */
+  TV_ERR_WORKSPACE = -8      /* workspace missing or too small           */
+} tv_status;
+
+/* Arithmetic of the products.  FP32: factors stored as float, products on
+ * FP32 MFMA with FP32 accumulation.  BF16X3: every FP32 operand x is split
+ * into bf16 hi = rn(x), lo = rn(x - hi) and a*b is formed as
+ * hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation. */
+typedef enum { TV_PREC_FP32 = 0, TV_PREC_BF16X3 = 1 } tv_precision;
+
+/* Largest multilinear rank a plan may hold in any mode. */
+#define TV_MAX_RANK 64
+
+typedef struct {
+  int32_t n1, n2, n3; /* voxel grid (Sec. III.A: nv = n1*n2*n3)            */
+  int32_t q;          /* tensors per column: 3 (PWC) or 12 (PWL), any >= 1 */
+  int64_t m;          /* columns (coil basis functions)                    */
+} tv_grid;
+
+typedef struct tv_plan_s* tv_plan;
+
+typedef struct {
+  tv_grid grid;
+  tv_precision precision;
+  int32_t max_rank[3];     /* largest r1, r2, r3 over all tensors          */
+  double mean_rank[3];     /* mean r1, r2, r3                              */
+  int64_t sum_r1;          /* sum of r1 over all q*m tensors               */
+  size_t factor_bytes;     /* Tucker entries x 8 B (complex64), Table II   */
+  size_t device_bytes;     /* device memory the plan holds (packed forms)  */
+  double flops_matvec;     /* algorithmic real flops of one Z x (p = 1)    */
+  double flops_rmatvec;    /* algorithmic real flops of one Z^* y (p = 1)  */
+} tv_plan_info_t;
+
+/* ------------------------------------------------------------------------
+ * Plan creation from given Tucker factors (eq. 6).
+ *
+ * ranks : host int32[q*m][3], (r1, r2, r3) of tensor t = k + q*j.
+ * cores : host complex128, the q*m cores concatenated in tensor order; core
+ *         t is r1*r2*r3 values, G[a,b,c] at a + r1*(b + r2*c).
+ * u1, u2, u3 : host complex128, the factors concatenated in tensor order;
+ *         U_n of tensor t is n_n x r_n column-major, U[i,a] at i + n_n*a.
+ * The library copies and repacks the factors (FP64 -> FP32 round to
+ * nearest even) into device memory it allocates; the host arrays may be
+ * freed on return.  Synchronous.  Returns TV_ERR_RANK for a rank outside
+ * [1, min(n_n, TV_MAX_RANK)], TV_ERR_NUMERIC for non-finite values.
+ * ---------------------------------------------------------------------- */
+tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks,
+                               const double* cores, const double* u1,
+                               const double* u2, const double* u3,
+                               tv_precision precision, tv_plan* out);
+
+/* Release a plan and its device memory.  NULL is accepted. */
+tv_status tv_plan_destroy(tv_plan plan);
+
+/* Sizes, ranks and operation counts of a plan. */
+tv_status tv_plan_info(tv_plan plan, tv_plan_info_t* info);
+
+/* Copy the ranks (int32[q*m][3]) and, if the pointers are non-NULL, the
+ * complex128 factors of a plan back to host arrays in the layout of
+ * tv_plan_from_factors (sizes from tv_plan_info / the ranks).  Synchronous.
+ * Factors are returned as stored (FP32 values widened to FP64). */
+tv_status tv_plan_export_factors(tv_plan plan, int32_t* ranks, double* cores,
+                                 double* u1, double* u2, double* u3);
+
+/* ------------------------------------------------------------------------
+ * Workspace needed by tv_matvec (op = 0) or tv_rmatvec (op = 1) for nrhs
+ * right-hand sides.  May be 0; a larger workspace is always accepted.
+ * ---------------------------------------------------------------------- */
+tv_status tv_workspace_bytes(tv_plan plan, int32_t op, int32_t nrhs,
+                             size_t* bytes);
+
+/* Y = Z X (Algorithm 1).  x: device complex64, m x nrhs, leading dim ldx
+ * >= m.  y: device complex64, q*nv x nrhs, leading dim ldy >= q*nv,
+ * overwritten.  ws: device workspace of at least tv_workspace_bytes(op=0)
+ * bytes (may be NULL if that is 0).  x and y must not overlap.  The result
+ * is deterministic: fixed reduction order, no atomics. */
+tv_status tv_matvec(tv_plan plan, const void* x, int64_t ldx, int32_t nrhs,
+                    void* y, int64_t ldy, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* X = Z^* Y (Algorithm 2).  y: device complex64, q*nv x nrhs, leading dim
+ * ldy >= q*nv.  x: device complex64, m x nrhs, leading dim ldx >= m,
+ * overwritten.  ws as for tv_matvec with op = 1.  Deterministic. */
+tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
+                     void* x, int64_t ldx, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* ------------------------------------------------------------------------
+ * Synthetic coil columns on the device (stand-in for the MoM assembly of
+ * Sec. II.A.1): column j is the E-field operator of eq. (2), with the
+ * Green's function of eq. (3), applied to a unit point current at pos[j]
+ * with unit orientation ori[j] (host double[ncols][3] arrays), evaluated on
+ * the centred grid of voxel edge h at wavenumber k0.
+ * basis 0 (PWC, q = 3): the field at each voxel centre.
+ * basis 1 (PWL, q = 12): tensor 4c + l is (1/h^3) * integral over the voxel
+ *   of field component c times phi_l, phi_0 = 1, phi_l = (x_l - centre_l)/h,
+ *   by the 2x2x2 Gauss-Legendre rule.
+ * out: device complex128, ncols*q*nv values, column j's tensor k at
+ *   out + 2*((j*q + k)*nv + v), v = i1 + n1*(i2 + n2*i3).  Asynchronous.
+ * ---------------------------------------------------------------------- */
+tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h,
+                            double k0, int32_t basis, int64_t ncols,
+                            const double* pos, const double* ori, void* out,
+                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Compression (truncated HOSVD, Sec. II.B.1) of dense columns on the device.
+ *
+ * tv_compress_begin creates an empty plan for grid->m columns.  Each mode
+ * keeps the smallest rank whose discarded squared singular values sum to at
+ * most tol^2 * ||Z^{kj}||_F^2 / 3, extended over near-equal singular
+ * values and clamped to [rank_min, min(rank_cap, n_n, TV_MAX_RANK)]
+ * (rank_cap <= 0 means no cap).
+ * tv_compress_append compresses the next ncols columns, given as device
+ * complex128 in the layout written by tv_dipole_columns; work happens on
+ * `stream`, and the call synchronises it before returning.
+ * tv_plan_finalize packs the plan for the products once all m columns are
+ * in; only then may it be used with tv_matvec / tv_rmatvec.
+ * ---------------------------------------------------------------------- */
+tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min,
+                            int32_t rank_cap, tv_precision precision,
+                            tv_plan* out);
+tv_status tv_compress_append(tv_plan plan, const void* cols, int64_t ncols,
+                             void* stream);
+tv_status tv_plan_finalize(tv_plan plan, void* stream);
+
+/* Largest singular-value tail discarded per mode for every tensor appended
+ * so far: host double[q*m][3] of sum_{i > r_n} sigma_i^2 / ||Z^{kj}||^2
+ * (the HOSVD bound's terms, relative).  Synchronous. */
+tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
+
+/* Human-readable name of a status code (static storage). */
+const char* tv_status_string(tv_status status);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char* tv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUCKVSIE_H */

@@ -1,0 +1,483 @@
+// Host side of libtuckvsie: validation, plan packing, tiling and dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "tv_internal.h"
+
+namespace tv {
+
+static thread_local std::string g_last_error;
+
+tv_status set_error(tv_status s, const std::string& msg) {
+  g_last_error = std::string(tv_status_string(s)) + ": " + msg;
+  return s;
+}
+void clear_error() { g_last_error.clear(); }
+tv_status hip_error(hipError_t e, const char* what) {
+  return set_error(e == hipErrorOutOfMemory ? TV_ERR_OOM : TV_ERR_HIP,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t fused_lds_bytes(int t2, int t3, int r1max, int r2max, int nwg);
+
+// Column tiling of the fused kernels: each workgroup owns every voxel row i1
+// (2*n1 real rows, split over wm waves of nb 32-row MFMA blocks) and
+// nwg = 32*wn columns (i2, i3) of the mode-1 unfolding.
+static tv_status choose_tiling(const tv_grid& g, Tiling* T) {
+  const int nbt0 = (g.n1 + 15) / 16;
+  int wm = 1;
+  while ((nbt0 + wm - 1) / wm > 8) wm *= 2;
+  if (wm > 4) return set_error(TV_ERR_NOT_SUPPORTED, "n1 > 512 is not built");
+  T->wm = wm;
+  T->nb = (nbt0 + wm - 1) / wm;
+  T->nbt = T->nb * wm;
+  T->n1p = 16 * T->nbt;
+  T->wn = 4 / wm;
+  T->nwg = 32 * T->wn;
+  int64_t best = -1;
+  for (int t2 = T->nwg; t2 >= 1; t2 /= 2) {
+    const int t3 = T->nwg / t2;
+    const int64_t cover = (int64_t)((g.n2 + t2 - 1) / t2) * t2 * ((g.n3 + t3 - 1) / t3) * t3;
+    if (best < 0 || cover < best) {
+      best = cover;
+      T->t2 = t2;
+      T->t3 = t3;
+    }
+  }
+  T->tiles2 = (g.n2 + T->t2 - 1) / T->t2;
+  T->tiles3 = (g.n3 + T->t3 - 1) / T->t3;
+  T->tiles = (int64_t)T->tiles2 * T->tiles3;
+  return TV_OK;
+}
+
+static tv_status validate_grid(const tv_grid* g) {
+  if (!g) return set_error(TV_ERR_INVALID_ARG, "grid is NULL");
+  if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1 || g->q < 1 || g->m < 1)
+    return set_error(TV_ERR_SHAPE, "grid sizes must be >= 1");
+  if ((int64_t)g->n1 * g->n2 * g->n3 * g->q > (int64_t)1 << 40)
+    return set_error(TV_ERR_SHAPE, "grid too large");
+  if (g->m > (int64_t)1 << 30) return set_error(TV_ERR_SHAPE, "too many columns");
+  return TV_OK;
+}
+
+template <typename T>
+static tv_status dev_alloc(T** p, size_t count, size_t* total) {
+  *p = nullptr;
+  if (count == 0) return TV_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_error(e, "hipMalloc");
+  }
+  *total += count * sizeof(T);
+  return TV_OK;
+}
+
+template <typename T>
+static tv_status upload(T* d, const std::vector<T>& h) {
+  if (h.empty()) return TV_OK;
+  hipError_t e = hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e == hipSuccess ? TV_OK : hip_error(e, "hipMemcpy to device");
+}
+
+static void free_device(tv_plan_s* p) {
+  hipFree(p->d_meta);
+  hipFree(p->d_cores);
+  hipFree(p->d_u2t);
+  hipFree(p->d_u3t);
+  hipFree(p->d_apack);
+  hipFree(p->d_apack_koff);
+  hipFree(p->d_split_f);
+  hipFree(p->d_split_a);
+  p->d_meta = nullptr;
+  p->d_cores = p->d_u2t = p->d_u3t = nullptr;
+  p->d_apack = nullptr;
+  p->d_apack_koff = nullptr;
+  p->d_split_f = p->d_split_a = nullptr;
+  p->device_bytes = 0;
+}
+
+// Offsets of every tensor's factors in the concatenated host arrays.
+static tv_status compute_offsets(tv_plan_s* p) {
+  const tv_grid& g = p->grid;
+  const int64_t K = (int64_t)g.q * g.m;
+  p->g_off.assign(K + 1, 0);
+  p->u1_off.assign(K + 1, 0);
+  p->u2_off.assign(K + 1, 0);
+  p->u3_off.assign(K + 1, 0);
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  for (int d = 0; d < 3; ++d) p->max_r[d] = 0;
+  p->sum_r1 = 0;
+  for (int64_t t = 0; t < K; ++t) {
+    const int32_t* r = &p->ranks[3 * t];
+    for (int d = 0; d < 3; ++d) {
+      if (r[d] < 1 || r[d] > dims[d] || r[d] > TV_MAX_RANK) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "tensor %lld mode %d rank %d outside [1, min(%d, %d)]",
+                 (long long)t, d + 1, r[d], dims[d], TV_MAX_RANK);
+        return set_error(TV_ERR_RANK, buf);
+      }
+      p->max_r[d] = std::max(p->max_r[d], (int)r[d]);
+    }
+    p->sum_r1 += r[0];
+    p->g_off[t + 1] = p->g_off[t] + (int64_t)r[0] * r[1] * r[2];
+    p->u1_off[t + 1] = p->u1_off[t] + (int64_t)g.n1 * r[0];
+    p->u2_off[t + 1] = p->u2_off[t] + (int64_t)g.n2 * r[1];
+    p->u3_off[t + 1] = p->u3_off[t] + (int64_t)g.n3 * r[2];
+  }
+  return TV_OK;
+}
+
+// Balanced column ranges per component: S contiguous ranges with about
+// equal sum of r1 (the K extent of the stacked mode-1 GEMM).
+static std::vector<int32_t> make_split(const tv_plan_s* p, int S) {
+  const tv_grid& g = p->grid;
+  std::vector<int32_t> out((size_t)g.q * (S + 1));
+  for (int k = 0; k < g.q; ++k) {
+    const int64_t total = p->sum_r1_k[k];
+    int64_t acc = 0;
+    int s = 1;
+    out[(size_t)k * (S + 1)] = 0;
+    for (int64_t j = 0; j < g.m && s < S; ++j) {
+      acc += p->ranks[3 * (k + (int64_t)g.q * j)];
+      while (s < S && acc * S >= total * s) out[(size_t)k * (S + 1) + s++] = (int32_t)(j + 1);
+    }
+    while (s < S) out[(size_t)k * (S + 1) + s++] = (int32_t)g.m;
+    out[(size_t)k * (S + 1) + S] = (int32_t)g.m;
+  }
+  return out;
+}
+
+// Pack the FP64 host factors into the device layouts of the fused kernels.
+static tv_status pack_and_upload(tv_plan_s* p) {
+  const tv_grid& g = p->grid;
+  const int64_t K = (int64_t)g.q * g.m;
+  tv_status st = choose_tiling(g, &p->tiling);
+  if (st != TV_OK) return st;
+  const Tiling& T = p->tiling;
+  if (fused_lds_bytes(T.t2, T.t3, p->max_r[0], p->max_r[1], T.nwg) > 160 * 1024)
+    return set_error(TV_ERR_NOT_SUPPORTED, "ranks too large for the LDS tile");
+
+  // per-tensor metadata, component-major [k][j]
+  std::vector<TensorMeta> meta((size_t)K);
+  p->sum_r1_k.assign(g.q, 0);
+  for (int64_t j = 0; j < g.m; ++j)
+    for (int k = 0; k < g.q; ++k) {
+      const int64_t t = k + (int64_t)g.q * j;
+      TensorMeta& M = meta[(size_t)k * g.m + j];
+      M.r1 = p->ranks[3 * t];
+      M.r2 = p->ranks[3 * t + 1];
+      M.r3 = p->ranks[3 * t + 2];
+      M.arow = (int32_t)p->sum_r1_k[k];
+      M.g_off = p->g_off[t];
+      M.u2_off = p->u2_off[t];
+      M.u3_off = p->u3_off[t];
+      p->sum_r1_k[k] += M.r1;
+    }
+
+  // FP32 copies; U2, U3 transposed to row-major (i, r)
+  std::vector<float2> cores((size_t)p->g_off[K]);
+  for (size_t i = 0; i < cores.size(); ++i)
+    cores[i] = make_float2((float)p->cores[2 * i], (float)p->cores[2 * i + 1]);
+  std::vector<float2> u2t((size_t)p->u2_off[K]), u3t((size_t)p->u3_off[K]);
+  for (int64_t t = 0; t < K; ++t) {
+    const int r2 = p->ranks[3 * t + 1], r3 = p->ranks[3 * t + 2];
+    for (int b = 0; b < r2; ++b)
+      for (int i = 0; i < g.n2; ++i) {
+        const size_t src = p->u2_off[t] + i + (size_t)g.n2 * b;
+        u2t[p->u2_off[t] + (size_t)i * r2 + b] =
+            make_float2((float)p->u2[2 * src], (float)p->u2[2 * src + 1]);
+      }
+    for (int c = 0; c < r3; ++c)
+      for (int i = 0; i < g.n3; ++i) {
+        const size_t src = p->u3_off[t] + i + (size_t)g.n3 * c;
+        u3t[p->u3_off[t] + (size_t)i * r3 + c] =
+            make_float2((float)p->u3[2 * src], (float)p->u3[2 * src + 1]);
+      }
+  }
+
+  // stacked U1 per component in MFMA A-operand lane order:
+  // apack[koff + (row*nbt + blk)*64 + lane] = A_emb[m = 32*blk + lane%32][lane/32]
+  // with A_emb[2 i1 + s][p] = Ar (s==p), -Ai (s=0,p=1), Ai (s=1,p=0)
+  p->apack_koff.assign(g.q + 1, 0);
+  for (int k = 0; k < g.q; ++k)
+    p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * T.nbt * 64;
+  std::vector<float> apack((size_t)p->apack_koff[g.q], 0.f);
+  for (int64_t j = 0; j < g.m; ++j)
+    for (int k = 0; k < g.q; ++k) {
+      const int64_t t = k + (int64_t)g.q * j;
+      const TensorMeta& M = meta[(size_t)k * g.m + j];
+      for (int a = 0; a < M.r1; ++a) {
+        float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * T.nbt) * 64];
+        for (int blk = 0; blk < T.nbt; ++blk)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int mrow = 32 * blk + (lane & 31);
+            const int i1 = mrow >> 1, s = mrow & 1, pp = lane >> 5;
+            float v = 0.f;
+            if (i1 < g.n1) {
+              const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * a;
+              const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
+              v = (float)(s == pp ? ar : (s == 0 ? -ai : ai));
+            }
+            row[blk * 64 + lane] = v;
+          }
+      }
+    }
+
+  // column splits: spread the work over enough workgroups to fill the chip
+  const int64_t base = (int64_t)g.q * T.tiles;
+  int sf = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + base - 1) / base));
+  int sa = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + base - 1) / base));
+  sf = (int)std::max<int64_t>(1, std::min<int64_t>(sf, g.m));
+  sa = (int)std::max<int64_t>(1, std::min<int64_t>(sa, g.m));
+  p->split_f = sf;
+  p->split_a = sa;
+  std::vector<int32_t> spf = make_split(p, sf), spa = make_split(p, sa);
+
+  free_device(p);
+  size_t tot = 0;
+  if ((st = dev_alloc(&p->d_meta, meta.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_cores, cores.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_u2t, u2t.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_u3t, u3t.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_apack, apack.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_apack_koff, p->apack_koff.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_split_f, spf.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_split_a, spa.size(), &tot)) != TV_OK) {
+    free_device(p);
+    return st;
+  }
+  p->device_bytes = tot;
+  if ((st = upload(p->d_meta, meta)) != TV_OK || (st = upload(p->d_cores, cores)) != TV_OK ||
+      (st = upload(p->d_u2t, u2t)) != TV_OK || (st = upload(p->d_u3t, u3t)) != TV_OK ||
+      (st = upload(p->d_apack, apack)) != TV_OK ||
+      (st = upload(p->d_apack_koff, p->apack_koff)) != TV_OK ||
+      (st = upload(p->d_split_f, spf)) != TV_OK || (st = upload(p->d_split_a, spa)) != TV_OK) {
+    free_device(p);
+    return st;
+  }
+  p->finalized = true;
+  return TV_OK;
+}
+
+static bool all_finite(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+tv_status finalize_plan(tv_plan_s* p) { return pack_and_upload(p); }
+
+tv_status validate_ranks_and_offsets(tv_plan_s* p) { return compute_offsets(p); }
+
+}  // namespace tv
+
+using namespace tv;
+
+extern "C" {
+
+const char* tv_status_string(tv_status s) {
+  switch (s) {
+    case TV_OK: return "TV_OK";
+    case TV_ERR_INVALID_ARG: return "TV_ERR_INVALID_ARG";
+    case TV_ERR_SHAPE: return "TV_ERR_SHAPE";
+    case TV_ERR_RANK: return "TV_ERR_RANK";
+    case TV_ERR_OOM: return "TV_ERR_OOM";
+    case TV_ERR_HIP: return "TV_ERR_HIP";
+    case TV_ERR_NOT_SUPPORTED: return "TV_ERR_NOT_SUPPORTED";
+    case TV_ERR_NUMERIC: return "TV_ERR_NUMERIC";
+    case TV_ERR_WORKSPACE: return "TV_ERR_WORKSPACE";
+  }
+  return "TV_ERR_UNKNOWN";
+}
+
+const char* tv_last_error(void) { return g_last_error.c_str(); }
+
+tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const double* cores,
+                               const double* u1, const double* u2, const double* u3,
+                               tv_precision precision, tv_plan* out) {
+  clear_error();
+  if (!out) return set_error(TV_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  tv_status st = validate_grid(grid);
+  if (st != TV_OK) return st;
+  if (!ranks || !cores || !u1 || !u2 || !u3)
+    return set_error(TV_ERR_INVALID_ARG, "ranks and factor arrays must be non-NULL");
+  if (precision != TV_PREC_FP32 && precision != TV_PREC_BF16X3)
+    return set_error(TV_ERR_INVALID_ARG, "unknown precision");
+  if (precision == TV_PREC_BF16X3)
+    return set_error(TV_ERR_NOT_SUPPORTED, "BF16X3 plans are not built yet");
+  tv_plan_s* p = new (std::nothrow) tv_plan_s;
+  if (!p) return set_error(TV_ERR_OOM, "host allocation");
+  p->grid = *grid;
+  p->precision = precision;
+  p->appended = grid->m;
+  const int64_t K = (int64_t)grid->q * grid->m;
+  p->ranks.assign(ranks, ranks + 3 * K);
+  if ((st = compute_offsets(p)) != TV_OK) {
+    delete p;
+    return st;
+  }
+  try {
+    p->cores.assign(cores, cores + 2 * p->g_off[K]);
+    p->u1.assign(u1, u1 + 2 * p->u1_off[K]);
+    p->u2.assign(u2, u2 + 2 * p->u2_off[K]);
+    p->u3.assign(u3, u3 + 2 * p->u3_off[K]);
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return set_error(TV_ERR_OOM, "host copy of factors");
+  }
+  if (!all_finite(p->cores.data(), p->cores.size()) || !all_finite(p->u1.data(), p->u1.size()) ||
+      !all_finite(p->u2.data(), p->u2.size()) || !all_finite(p->u3.data(), p->u3.size())) {
+    delete p;
+    return set_error(TV_ERR_NUMERIC, "non-finite factor values");
+  }
+  if ((st = pack_and_upload(p)) != TV_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return TV_OK;
+}
+
+tv_status tv_plan_destroy(tv_plan p) {
+  clear_error();
+  if (!p) return TV_OK;
+  free_device(p);
+  delete p;
+  return TV_OK;
+}
+
+tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
+  clear_error();
+  if (!p || !info) return set_error(TV_ERR_INVALID_ARG, "plan and info must be non-NULL");
+  std::memset(info, 0, sizeof *info);
+  info->grid = p->grid;
+  info->precision = p->precision;
+  const int64_t K = (int64_t)p->grid.q * p->appended_or_all();
+  double sum[3] = {0, 0, 0};
+  double fl = 0.0;
+  const double n1 = p->grid.n1, n2 = p->grid.n2, n3 = p->grid.n3;
+  for (int64_t t = 0; t < K; ++t) {
+    const double r1 = p->ranks[3 * t], r2 = p->ranks[3 * t + 1], r3 = p->ranks[3 * t + 2];
+    for (int d = 0; d < 3; ++d) {
+      sum[d] += p->ranks[3 * t + d];
+      info->max_rank[d] = std::max(info->max_rank[d], p->ranks[3 * t + d]);
+    }
+    info->factor_bytes += (size_t)8 * (size_t)(r1 * r2 * r3 + n1 * r1 + n2 * r2 + n3 * r3);
+    info->sum_r1 += (int64_t)r1;
+    // modes 2, 3 then 1 (Table III's decompression term r q nv m dominates)
+    fl += 8.0 * (r1 * r2 * r3 * n2 + r1 * r3 * n2 * n3 + r1 * n1 * n2 * n3);
+  }
+  for (int d = 0; d < 3; ++d) info->mean_rank[d] = K ? sum[d] / (double)K : 0.0;
+  info->device_bytes = p->device_bytes;
+  info->flops_matvec = fl;
+  info->flops_rmatvec = fl + 8.0 * (double)K * n1 * n2 * n3;
+  return TV_OK;
+}
+
+tv_status tv_plan_export_factors(tv_plan p, int32_t* ranks, double* cores, double* u1,
+                                 double* u2, double* u3) {
+  clear_error();
+  if (!p || !ranks) return set_error(TV_ERR_INVALID_ARG, "plan and ranks must be non-NULL");
+  const int64_t K = (int64_t)p->grid.q * p->appended_or_all();
+  std::memcpy(ranks, p->ranks.data(), sizeof(int32_t) * 3 * K);
+  if (cores) std::memcpy(cores, p->cores.data(), sizeof(double) * 2 * p->g_off[K]);
+  if (u1) std::memcpy(u1, p->u1.data(), sizeof(double) * 2 * p->u1_off[K]);
+  if (u2) std::memcpy(u2, p->u2.data(), sizeof(double) * 2 * p->u2_off[K]);
+  if (u3) std::memcpy(u3, p->u3.data(), sizeof(double) * 2 * p->u3_off[K]);
+  return TV_OK;
+}
+
+tv_status tv_workspace_bytes(tv_plan p, int32_t op, int32_t nrhs, size_t* bytes) {
+  clear_error();
+  if (!p || !bytes) return set_error(TV_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
+  if (op != 0 && op != 1) return set_error(TV_ERR_INVALID_ARG, "op must be 0 or 1");
+  if (nrhs < 1) return set_error(TV_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  const tv_grid& g = p->grid;
+  const int64_t nv = (int64_t)g.n1 * g.n2 * g.n3;
+  if (op == 0)
+    *bytes = p->split_f > 1 ? (size_t)8 * p->split_f * g.q * nv : 0;
+  else
+    *bytes = (size_t)8 * g.q * p->tiling.tiles * g.m;
+  return TV_OK;
+}
+
+static tv_status check_call(tv_plan p, const void* in, int64_t ldin, int64_t rows_in,
+                            int32_t nrhs, const void* out, int64_t ldout, int64_t rows_out,
+                            int op, const void* ws, size_t ws_bytes) {
+  if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
+  if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  if (!in || !out) return set_error(TV_ERR_INVALID_ARG, "vector pointers must be non-NULL");
+  if (nrhs < 1) return set_error(TV_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (ldin < rows_in || ldout < rows_out)
+    return set_error(TV_ERR_SHAPE, "leading dimension smaller than the number of rows");
+  if (((uintptr_t)in | (uintptr_t)out) % 8)
+    return set_error(TV_ERR_INVALID_ARG, "complex64 vectors must be 8-byte aligned");
+  const char* ib = (const char*)in;
+  const char* ob = (const char*)out;
+  const size_t in_len = 8 * (size_t)(ldin * (nrhs - 1) + rows_in);
+  const size_t out_len = 8 * (size_t)(ldout * (nrhs - 1) + rows_out);
+  if (ib < ob + out_len && ob < ib + in_len)
+    return set_error(TV_ERR_INVALID_ARG, "input and output overlap");
+  size_t need = 0;
+  tv_status st = tv_workspace_bytes(p, op, nrhs, &need);
+  if (st != TV_OK) return st;
+  if (need && (!ws || ws_bytes < need)) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "workspace of %zu bytes needed, %zu given", need,
+             ws ? ws_bytes : (size_t)0);
+    return set_error(TV_ERR_WORKSPACE, buf);
+  }
+  if (need && (uintptr_t)ws % 16) return set_error(TV_ERR_INVALID_ARG, "workspace alignment");
+  return TV_OK;
+}
+
+tv_status tv_matvec(tv_plan p, const void* x, int64_t ldx, int32_t nrhs, void* y, int64_t ldy,
+                    void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
+  const int64_t rows = (int64_t)p->grid.q * p->grid.n1 * p->grid.n2 * p->grid.n3;
+  tv_status st = check_call(p, x, ldx, p->grid.m, nrhs, y, ldy, rows, 0, ws, ws_bytes);
+  if (st != TV_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int32_t c = 0; c < nrhs; ++c) {
+    const float2* xc = (const float2*)x + (int64_t)c * ldx;
+    float2* yc = (float2*)y + (int64_t)c * ldy;
+    if (p->split_f > 1) {
+      st = launch_forward_f32(p, xc, (float2*)ws, p->split_f, p->d_split_f, rows, s);
+      if (st == TV_OK) st = launch_sum_partials((const float2*)ws, p->split_f, rows, yc, s);
+    } else {
+      st = launch_forward_f32(p, xc, yc, 1, p->d_split_f, rows, s);
+    }
+    if (st != TV_OK) return st;
+  }
+  return TV_OK;
+}
+
+tv_status tv_rmatvec(tv_plan p, const void* y, int64_t ldy, int32_t nrhs, void* x, int64_t ldx,
+                     void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
+  const int64_t rows = (int64_t)p->grid.q * p->grid.n1 * p->grid.n2 * p->grid.n3;
+  tv_status st = check_call(p, y, ldy, rows, nrhs, x, ldx, p->grid.m, 1, ws, ws_bytes);
+  if (st != TV_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int32_t c = 0; c < nrhs; ++c) {
+    const float2* yc = (const float2*)y + (int64_t)c * ldy;
+    float2* xc = (float2*)x + (int64_t)c * ldx;
+    st = launch_adjoint_f32(p, yc, (float2*)ws, p->split_a, p->d_split_a, s);
+    if (st == TV_OK)
+      st = launch_reduce_adjoint((const float2*)ws, p->grid.q, p->tiling.tiles, p->grid.m, xc,
+                                 s);
+    if (st != TV_OK) return st;
+  }
+  return TV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Synthetic coupling-matrix columns on the device, FP64.
+//
+// Stand-in for the MoM assembly (Sec. II.A.1): the coil element of column j
+// is a unit point current p_j at r_j, and the E-field operator of eq. (2)
+// with the Green's function of eq. (3), g = exp(-i k0 R) / (4 pi R), gives
+//   E(r) = (grad grad + k0^2) g p
+//        = k0^2 g [ (1 - i/(k0R) - 1/(k0R)^2) p + (-1 + 3i/(k0R) + 3/(k0R)^2) (Rh.p) Rh ]
+// with R = r - r_j, Rh = R / |R|.  PWC voxels take the value at the centre;
+// PWL voxels project on {1, (x - xc)/h, (y - yc)/h, (z - zc)/h} with the
+// 2x2x2 Gauss-Legendre rule, divided by the voxel volume.
+#include "tv_internal.h"
+
+namespace tv {
+
+struct ColParams {
+  int n1, n2, n3;
+  double h, k0;
+  int basis;      // 0 PWC, 1 PWL
+  int64_t ncols;
+  const double* src;  // device [ncols][6]: position then orientation
+  double2* out;
+};
+
+__device__ inline void point_field(double x, double y, double z, const double* s, double k0,
+                                   double2 E[3]) {
+  const double dx = x - s[0], dy = y - s[1], dz = z - s[2];
+  const double R = sqrt(dx * dx + dy * dy + dz * dz);
+  const double inv = 1.0 / R;
+  const double hx = dx * inv, hy = dy * inv, hz = dz * inv;
+  const double kr = k0 * R, ikr = 1.0 / kr, ikr2 = ikr * ikr;
+  double sn, cs;
+  sincos(kr, &sn, &cs);
+  // k0^2 g = k0^2 (cos kR - i sin kR) / (4 pi R)
+  const double amp = k0 * k0 * inv * 0.07957747154594767;  // 1/(4 pi)
+  const double gr = amp * cs, gi = -amp * sn;
+  // a = (1 - ikr2) - i ikr ; b = (-1 + 3 ikr2) + 3 i ikr
+  const double ar = 1.0 - ikr2, ai = -ikr;
+  const double br = -1.0 + 3.0 * ikr2, bi = 3.0 * ikr;
+  const double rp = hx * s[3] + hy * s[4] + hz * s[5];
+  const double hv[3] = {hx, hy, hz};
+  for (int c = 0; c < 3; ++c) {
+    const double tr = ar * s[3 + c] + br * rp * hv[c];
+    const double ti = ai * s[3 + c] + bi * rp * hv[c];
+    E[c] = make_double2(gr * tr - gi * ti, gr * ti + gi * tr);
+  }
+}
+
+__global__ void columns_kernel(ColParams P) {
+  const int64_t nv = (int64_t)P.n1 * P.n2 * P.n3;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (v >= nv || j >= P.ncols) return;
+  const int i1 = (int)(v % P.n1);
+  const int i2 = (int)((v / P.n1) % P.n2);
+  const int i3 = (int)(v / ((int64_t)P.n1 * P.n2));
+  const double cx = (i1 - 0.5 * (P.n1 - 1)) * P.h;
+  const double cy = (i2 - 0.5 * (P.n2 - 1)) * P.h;
+  const double cz = (i3 - 0.5 * (P.n3 - 1)) * P.h;
+  __shared__ double s[6];
+  if (threadIdx.x < 6) s[threadIdx.x] = P.src[j * 6 + threadIdx.x];
+  __syncthreads();
+  if (P.basis == 0) {
+    double2 E[3];
+    point_field(cx, cy, cz, s, P.k0, E);
+    for (int c = 0; c < 3; ++c) P.out[(j * 3 + c) * nv + v] = E[c];
+    return;
+  }
+  // PWL: tensor 4c + l, nodes at centre +- h/(2 sqrt 3) per axis, weight 1/8
+  const double off = 0.28867513459481287;  // 1 / (2 sqrt 3)
+  double2 acc[12];
+  for (int i = 0; i < 12; ++i) acc[i] = make_double2(0.0, 0.0);
+  for (int q = 0; q < 8; ++q) {
+    const double ux = (q & 1) ? off : -off;
+    const double uy = (q & 2) ? off : -off;
+    const double uz = (q & 4) ? off : -off;
+    double2 E[3];
+    point_field(cx + ux * P.h, cy + uy * P.h, cz + uz * P.h, s, P.k0, E);
+    const double phi[4] = {0.125, 0.125 * ux, 0.125 * uy, 0.125 * uz};
+    for (int c = 0; c < 3; ++c)
+      for (int l = 0; l < 4; ++l) {
+        acc[4 * c + l].x += E[c].x * phi[l];
+        acc[4 * c + l].y += E[c].y * phi[l];
+      }
+  }
+  for (int t = 0; t < 12; ++t) P.out[(j * 12 + t) * nv + v] = acc[t];
+}
+
+}  // namespace tv
+
+using namespace tv;
+
+extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h, double k0,
+                                       int32_t basis, int64_t ncols, const double* pos,
+                                       const double* ori, void* out, void* stream) {
+  clear_error();
+  if (n1 < 1 || n2 < 1 || n3 < 1 || ncols < 0)
+    return set_error(TV_ERR_SHAPE, "grid sizes must be >= 1 and ncols >= 0");
+  if (!(h > 0.0) || !(k0 > 0.0)) return set_error(TV_ERR_INVALID_ARG, "h and k0 must be > 0");
+  if (basis != 0 && basis != 1) return set_error(TV_ERR_INVALID_ARG, "basis must be 0 or 1");
+  if (ncols == 0) return TV_OK;
+  if (!pos || !ori || !out) return set_error(TV_ERR_INVALID_ARG, "NULL pointer");
+  if (ncols > 65535) return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 columns per call");
+  const int64_t nv = (int64_t)n1 * n2 * n3;
+  // every voxel centre must be away from every source
+  const double half[3] = {0.5 * (n1 - 1) * h, 0.5 * (n2 - 1) * h, 0.5 * (n3 - 1) * h};
+  std::vector<double> src((size_t)ncols * 6);
+  for (int64_t j = 0; j < ncols; ++j) {
+    double d2 = 0.0, on = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double p = pos[3 * j + c];
+      const double nearest = p < -half[c] ? -half[c] : (p > half[c] ? half[c] : p);
+      d2 += (p - nearest) * (p - nearest);
+      on += ori[3 * j + c] * ori[3 * j + c];
+      src[6 * j + c] = p;
+      src[6 * j + 3 + c] = ori[3 * j + c];
+    }
+    if (!(d2 > (0.25 * h) * (0.25 * h)))
+      return set_error(TV_ERR_INVALID_ARG, "a source lies inside the voxel domain");
+    if (!(fabs(on - 1.0) < 1e-9)) return set_error(TV_ERR_INVALID_ARG, "orientation not unit");
+  }
+  double* d_src = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMallocAsync((void**)&d_src, src.size() * sizeof(double), st);
+  if (e != hipSuccess) return hip_error(e, "hipMallocAsync");
+  e = hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    hipFreeAsync(d_src, st);
+    return hip_error(e, "hipMemcpyAsync");
+  }
+  ColParams P{n1, n2, n3, h, k0, basis, ncols, d_src, (double2*)out};
+  hipLaunchKernelGGL(columns_kernel, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
+                     dim3(256), 0, st, P);
+  e = hipGetLastError();
+  hipFreeAsync(d_src, st);
+  // the host staging vector must outlive the async copy
+  hipError_t e2 = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_error(e, "columns kernel launch");
+  if (e2 != hipSuccess) return hip_error(e2, "hipStreamSynchronize");
+  return TV_OK;
+}

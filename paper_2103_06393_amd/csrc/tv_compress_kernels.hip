@@ -1,0 +1,370 @@
+// Device kernels of the truncated HOSVD (Sec. II.B.1), all FP64.
+//
+// For a tensor A (n1 x n2 x n3, complex) the mode-d factor U_d holds the
+// leading left singular vectors of the unfolding A_(d), i.e. the leading
+// eigenvectors of the Gram matrix S_d = A_(d) A_(d)^*; the singular values are
+// the square roots of its eigenvalues.  The core is A x1 U1^* x2 U2^* x3 U3^*
+// (eq. 6/7).  Kernels:
+//   gram_kernel     S_d for every tensor and mode, 64 x 64 output tiles
+//   jacobi_kernel   cyclic parallel Jacobi eigensolver of one Hermitian
+//                   matrix (n <= 64) per workgroup, held in LDS
+//   proj1/2/3       the three n-mode products with U_d^* that form the core
+#include "tv_internal.h"
+
+namespace tv {
+
+__device__ __forceinline__ double2 zfma_conj_b(double2 a, double2 b, double2 c) {
+  // c + a * conj(b)
+  c.x = fma(a.x, b.x, c.x);
+  c.x = fma(a.y, b.y, c.x);
+  c.y = fma(a.y, b.x, c.y);
+  c.y = fma(-a.x, b.y, c.y);
+  return c;
+}
+__device__ __forceinline__ double2 zfma_conj_a(double2 a, double2 b, double2 c) {
+  // c + conj(a) * b
+  c.x = fma(a.x, b.x, c.x);
+  c.x = fma(a.y, b.y, c.x);
+  c.y = fma(a.x, b.y, c.y);
+  c.y = fma(-a.y, b.x, c.y);
+  return c;
+}
+
+// Element (i, o) of the mode-d unfolding: o enumerates the other two indices
+// with the lower one fastest.
+__device__ __forceinline__ int64_t unfold_index(int d, int64_t i, int64_t o, int n1, int n2) {
+  if (d == 0) return i + (int64_t)n1 * o;
+  if (d == 1) return (o % n1) + (int64_t)n1 * i + (int64_t)n1 * n2 * (o / n1);
+  return o + (int64_t)n1 * n2 * i;
+}
+
+// S_d = A_(d) A_(d)^*, one 64 x 64 tile of one (tensor, mode) per workgroup.
+// grid.x = tensors * 3 * tiles * tiles with tiles = ceil(nmax / 64).
+__global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A, int ntens,
+                                                   int n1, int n2, int n3, int nmax,
+                                                   double2* __restrict__ S) {
+  constexpr int OC = 16;
+  __shared__ double2 Xr[64][OC + 1];
+  __shared__ double2 Xc[64][OC + 1];
+  const int tiles = (nmax + 63) / 64;
+  int64_t b = blockIdx.x;
+  const int tj = (int)(b % tiles);
+  b /= tiles;
+  const int ti = (int)(b % tiles);
+  b /= tiles;
+  const int d = (int)(b % 3);
+  const int t = (int)(b / 3);
+  if (t >= ntens) return;
+  const int dims[3] = {n1, n2, n3};
+  const int n = dims[d];
+  if (ti * 64 >= n || tj * 64 >= n) return;
+  const int64_t nv = (int64_t)n1 * n2 * n3;
+  const int64_t no = nv / n;
+  const double2* At = A + (int64_t)t * nv;
+  const int tid = threadIdx.x;
+  const int r0 = 4 * (tid / 16), c0 = 4 * (tid % 16);
+  double2 acc[4][4];
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  for (int64_t o0 = 0; o0 < no; o0 += OC) {
+    for (int e = tid; e < 64 * OC; e += 256) {
+      int i, oc;
+      if (d == 0) {
+        i = e % 64;
+        oc = e / 64;
+      } else {
+        oc = e % OC;
+        i = e / OC;
+      }
+      const int64_t o = o0 + oc;
+      const int ir = ti * 64 + i, ic = tj * 64 + i;
+      Xr[i][oc] = (ir < n && o < no) ? At[unfold_index(d, ir, o, n1, n2)] : make_double2(0, 0);
+      Xc[i][oc] = (ic < n && o < no) ? At[unfold_index(d, ic, o, n1, n2)] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int oc = 0; oc < OC; ++oc) {
+      double2 a[4], c[4];
+      for (int u = 0; u < 4; ++u) a[u] = Xr[r0 + u][oc];
+      for (int v = 0; v < 4; ++v) c[v] = Xc[c0 + v][oc];
+      for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) acc[u][v] = zfma_conj_b(a[u], c[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double2* St = S + ((int64_t)d * ntens + t) * nmax * nmax;
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * 64 + r0 + u, j = tj * 64 + c0 + v;
+      if (i < n && j < n) St[(int64_t)i * n + j] = acc[u][v];
+    }
+}
+
+// Cyclic Jacobi for a Hermitian n x n matrix (n <= 64) in LDS.  Rounds use
+// the round-robin pairing, so the n/2 rotations of a round touch disjoint
+// rows/columns and are applied together: first A <- A J, V <- V J on
+// columns, then A <- J^* A on rows.  For a pair (i, j) with A_ij = d e^{i phi}
+// the rotation is J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] where (c, s)
+// diagonalise the real matrix [[A_ii, d], [d, A_jj]] (Golub and Van Loan's
+// symmetric 2x2 Schur step).  Output: eigenvalues W (unsorted) and
+// eigenvectors as the columns of V, both per matrix.
+__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ S, int n,
+                                                     int64_t stride, double* __restrict__ W,
+                                                     int64_t wstride, double2* __restrict__ Vout,
+                                                     int max_sweeps) {
+  extern __shared__ double2 jsm[];
+  const int np = n + (n & 1);
+  double2* A = jsm;              // n x n, row-major
+  double2* V = A + n * n;        // n x n
+  double* rc = reinterpret_cast<double*>(V + n * n);  // [np/2] c
+  double* rs = rc + np / 2;                           // s
+  double* rpr = rs + np / 2;                          // cos phi
+  double* rpi = rpr + np / 2;                         // sin phi
+  int* pi = reinterpret_cast<int*>(rpi + np / 2);
+  int* pj = pi + np / 2;
+  double* red = reinterpret_cast<double*>(pj + np / 2 + 2);  // [2][256]
+  const int tid = threadIdx.x;
+  const int64_t mat = blockIdx.x;
+  const double2* Sm = S + mat * stride;
+  for (int e = tid; e < n * n; e += 256) {
+    A[e] = Sm[e];
+    V[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int half = np / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = tid; e < n * n; e += 256) {
+      const double2 v = A[e];
+      const double a2 = v.x * v.x + v.y * v.y;
+      if (e / n == e % n) dia += a2;
+      else off += a2;
+    }
+    red[tid] = off;
+    red[256 + tid] = dia;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        red[tid] += red[tid + s];
+        red[256 + tid] += red[256 + tid + s];
+      }
+      __syncthreads();
+    }
+    const bool done = !(red[0] > 1e-30 * red[256]);
+    __syncthreads();
+    if (done) break;
+    for (int round = 0; round < np - 1; ++round) {
+      if (tid < half) {
+        int i, j;
+        if (tid == 0) {
+          i = np - 1;
+          j = round;
+        } else {
+          i = (round + tid) % (np - 1);
+          j = (round - tid + (np - 1)) % (np - 1);
+        }
+        if (i > j) {
+          const int tmp = i;
+          i = j;
+          j = tmp;
+        }
+        double c = 1.0, s = 0.0, cp = 1.0, sp = 0.0;
+        if (j < n) {
+          const double2 aij = A[i * n + j];
+          const double dd = sqrt(aij.x * aij.x + aij.y * aij.y);
+          const double aii = A[i * n + i].x, ajj = A[j * n + j].x;
+          if (dd > 1e-300 && dd > 1e-17 * sqrt(fabs(aii * ajj))) {
+            cp = aij.x / dd;
+            sp = aij.y / dd;
+            const double tau = (ajj - aii) / (2.0 * dd);
+            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+        }
+        rc[tid] = c;
+        rs[tid] = s;
+        rpr[tid] = cp;
+        rpi[tid] = sp;
+        pi[tid] = i;
+        pj[tid] = j < n ? j : -1;
+      }
+      __syncthreads();
+      // columns: A <- A J and V <- V J
+      for (int e = tid; e < half * n; e += 256) {
+        const int p = e / n, r = e % n;
+        const int i = pi[p], j = pj[p];
+        if (j < 0) continue;
+        const double c = rc[p], s = rs[p];
+        // -s e^{-i phi} and c e^{-i phi}
+        const double2 m1 = make_double2(-s * rpr[p], s * rpi[p]);
+        const double2 m2 = make_double2(c * rpr[p], -c * rpi[p]);
+        double2 x = A[r * n + i], y = A[r * n + j];
+        A[r * n + i] = make_double2(c * x.x + m1.x * y.x - m1.y * y.y,
+                                    c * x.y + m1.x * y.y + m1.y * y.x);
+        A[r * n + j] = make_double2(s * x.x + m2.x * y.x - m2.y * y.y,
+                                    s * x.y + m2.x * y.y + m2.y * y.x);
+        x = V[r * n + i];
+        y = V[r * n + j];
+        V[r * n + i] = make_double2(c * x.x + m1.x * y.x - m1.y * y.y,
+                                    c * x.y + m1.x * y.y + m1.y * y.x);
+        V[r * n + j] = make_double2(s * x.x + m2.x * y.x - m2.y * y.y,
+                                    s * x.y + m2.x * y.y + m2.y * y.x);
+      }
+      __syncthreads();
+      // rows: A <- J^* A, J^* = [[c, -s e^{i phi}], [s, c e^{i phi}]]
+      for (int e = tid; e < half * n; e += 256) {
+        const int p = e / n, r = e % n;
+        const int i = pi[p], j = pj[p];
+        if (j < 0) continue;
+        const double c = rc[p], s = rs[p];
+        const double2 m1 = make_double2(-s * rpr[p], -s * rpi[p]);
+        const double2 m2 = make_double2(c * rpr[p], c * rpi[p]);
+        const double2 x = A[i * n + r], y = A[j * n + r];
+        A[i * n + r] = make_double2(c * x.x + m1.x * y.x - m1.y * y.y,
+                                    c * x.y + m1.x * y.y + m1.y * y.x);
+        A[j * n + r] = make_double2(s * x.x + m2.x * y.x - m2.y * y.y,
+                                    s * x.y + m2.x * y.y + m2.y * y.x);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < n; i += 256) W[mat * wstride + i] = A[i * n + i].x;
+  double2* Vm = Vout + mat * stride;
+  for (int e = tid; e < n * n; e += 256) Vm[e] = V[e];
+}
+
+size_t jacobi_lds_bytes(int n) {
+  const int np = n + (n & 1);
+  return 16 * (size_t)2 * n * n + 8 * (size_t)4 * (np / 2) + 4 * (size_t)(np + 2) +
+         8 * 512 + 16;
+}
+
+// T1[t][a][o] = sum_i1 conj(U1[i1, a]) A[i1 + n1 o]; workgroup = 64 values of
+// o, all a; U1 given column-major n1 x r1 at u1 + u1off[t].
+__global__ __launch_bounds__(256) void proj1_kernel(const double2* __restrict__ A, int n1,
+                                                    int64_t no, const double2* __restrict__ u1,
+                                                    const int64_t* __restrict__ u1off,
+                                                    const int* __restrict__ rk, int r1max,
+                                                    double2* __restrict__ T1) {
+  __shared__ double2 Us[64][65];
+  __shared__ double2 As[64][65];
+  const int64_t chunks = (no + 63) / 64;
+  const int t = (int)(blockIdx.x / chunks);
+  const int64_t o0 = (blockIdx.x % chunks) * 64;
+  const int r1 = rk[3 * t];
+  const int64_t nv = (int64_t)n1 * no;
+  const double2* At = A + (int64_t)t * nv;
+  const double2* U = u1 + u1off[t];
+  const int tid = threadIdx.x;
+  const int ol = tid % 64;
+  double2 acc[16];
+  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < n1; i0 += 64) {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int i = e % 64, x = e / 64;  // x = a (for U) or o (for A)
+      Us[i][x] = (i0 + i < n1 && x < r1) ? U[(i0 + i) + (int64_t)n1 * x] : make_double2(0, 0);
+      As[i][x] = (i0 + i < n1 && o0 + x < no) ? At[(i0 + i) + (int64_t)n1 * (o0 + x)]
+                                              : make_double2(0, 0);
+    }
+    __syncthreads();
+    // thread (ol, ag) computes a = ag + 4 q for q < 16
+    const int ag = tid / 64;
+    for (int i = 0; i < 64; ++i) {
+      const double2 av = As[i][ol];
+      for (int q = 0; q < 16; ++q) acc[q] = zfma_conj_a(Us[i][ag + 4 * q], av, acc[q]);
+    }
+    __syncthreads();
+  }
+  const int ag = tid / 64;
+  if (o0 + ol < no)
+    for (int q = 0; q < 16; ++q) {
+      const int a = ag + 4 * q;
+      if (a < r1) T1[((int64_t)t * r1max + a) * no + o0 + ol] = acc[q];
+    }
+}
+
+// T2[t][(a, b)][i3] = sum_i2 conj(U2[i2, b]) T1[t][a][i2 + n2 i3]
+__global__ void proj2_kernel(const double2* __restrict__ T1, int n2, int n3, int r1max,
+                             int r2max, const double2* __restrict__ u2,
+                             const int64_t* __restrict__ u2off, const int* __restrict__ rk,
+                             double2* __restrict__ T2) {
+  const int t = blockIdx.y;
+  const int r1 = rk[3 * t], r2 = rk[3 * t + 1];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)r1 * r2 * n3;
+  if (idx >= total) return;
+  const int i3 = (int)(idx % n3);
+  const int ab = (int)(idx / n3);
+  const int a = ab % r1, b = ab / r1;
+  const int64_t no = (int64_t)n2 * n3;
+  const double2* src = T1 + ((int64_t)t * r1max + a) * no + (int64_t)n2 * i3;
+  const double2* U = u2 + u2off[t] + (int64_t)n2 * b;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i2 = 0; i2 < n2; ++i2) acc = zfma_conj_a(U[i2], src[i2], acc);
+  T2[((int64_t)t * r1max * r2max + a + (int64_t)r1 * b) * n3 + i3] = acc;
+}
+
+// G[t][a + r1 (b + r2 c)] = sum_i3 conj(U3[i3, c]) T2[t][(a, b)][i3]
+__global__ void proj3_kernel(const double2* __restrict__ T2, int n3, int r1max, int r2max,
+                             const double2* __restrict__ u3, const int64_t* __restrict__ u3off,
+                             const int* __restrict__ rk, const int64_t* __restrict__ goff,
+                             double2* __restrict__ G) {
+  const int t = blockIdx.y;
+  const int r1 = rk[3 * t], r2 = rk[3 * t + 1], r3 = rk[3 * t + 2];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= r1 * r2 * r3) return;
+  const int ab = idx % (r1 * r2), c = idx / (r1 * r2);
+  const double2* src = T2 + ((int64_t)t * r1max * r2max + ab) * n3;
+  const double2* U = u3 + u3off[t] + (int64_t)n3 * c;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i3 = 0; i3 < n3; ++i3) acc = zfma_conj_a(U[i3], src[i3], acc);
+  G[goff[t] + idx] = acc;
+}
+
+static tv_status last(const char* what) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TV_OK : hip_error(e, what);
+}
+
+tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
+                      hipStream_t st) {
+  const int tiles = (nmax + 63) / 64;
+  const int64_t blocks = (int64_t)ntens * 3 * tiles * tiles;
+  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, ntens, n1, n2,
+                     n3, nmax, S);
+  return last("gram_kernel");
+}
+
+tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
+                        int64_t wstride, double2* V, hipStream_t st) {
+  const size_t lds = jacobi_lds_bytes(n);
+  hipError_t e = hipFuncSetAttribute((const void*)jacobi_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(jacobi)");
+  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)nmat), dim3(256), lds, st, S, n, stride, W,
+                     wstride, V, 40);
+  return last("jacobi_kernel");
+}
+
+tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const double2* u1,
+                      const double2* u2, const double2* u3, const int64_t* offs,
+                      const int* ranks, int r1max, int r2max, double2* T1, double2* T2,
+                      double2* G, hipStream_t st) {
+  const int64_t no = (int64_t)n2 * n3;
+  const int64_t chunks = (no + 63) / 64;
+  hipLaunchKernelGGL(proj1_kernel, dim3((unsigned)(chunks * ntens)), dim3(256), 0, st, A, n1,
+                     no, u1, offs, ranks, r1max, T1);
+  tv_status s = last("proj1_kernel");
+  if (s != TV_OK) return s;
+  const int64_t tot2 = (int64_t)r1max * r2max * n3;
+  hipLaunchKernelGGL(proj2_kernel, dim3((unsigned)((tot2 + 255) / 256), (unsigned)ntens),
+                     dim3(256), 0, st, T1, n2, n3, r1max, r2max, u2, offs + ntens, ranks, T2);
+  if ((s = last("proj2_kernel")) != TV_OK) return s;
+  const int tot3 = r1max * r2max * TV_MAX_RANK;
+  hipLaunchKernelGGL(proj3_kernel, dim3((unsigned)((tot3 + 255) / 256), (unsigned)ntens),
+                     dim3(256), 0, st, T2, n3, r1max, r2max, u3, offs + 2 * ntens, ranks,
+                     offs + 3 * ntens, G);
+  return last("proj3_kernel");
+}
+
+}  // namespace tv

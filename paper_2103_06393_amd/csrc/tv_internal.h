@@ -1,0 +1,87 @@
+// Internal structures shared by the host library and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tuckvsie.h"
+
+namespace tv {
+
+// Per-tensor metadata on the device, indexed [k * m + j].
+struct TensorMeta {
+  int32_t r1, r2, r3;
+  int32_t arow;    // first row of this tensor in component k's stacked A_k
+  int64_t g_off;   // core G[a,b,c] (complex) at g_off + a + r1*(b + r2*c)
+  int64_t u2_off;  // U2 row-major: U2[i2][b] at u2_off + i2*r2 + b
+  int64_t u3_off;  // U3 row-major: U3[i3][c] at u3_off + i3*r3 + c
+};
+
+// Geometry of the fused FP32 / BF16 kernels for one plan.
+struct Tiling {
+  int wm, wn;      // waves along M (voxel rows) and N (columns of Y^k_(1))
+  int nb;          // 32-row MFMA blocks per wave along M
+  int nbt;         // total 32-row blocks (2*n1p/32), = wm*nb
+  int n1p;         // n1 padded to 16*nbt
+  int nwg;         // columns per workgroup, 32*wn
+  int t2, t3;      // workgroup column tile: t2 values of i2 x t3 of i3
+  int tiles2, tiles3;
+  int64_t tiles;   // per component
+};
+
+}  // namespace tv
+
+struct tv_plan_s {
+  tv_grid grid{};
+  tv_precision precision = TV_PREC_FP32;
+  bool finalized = false;
+  std::vector<int32_t> ranks;  // [q*m][3], tensor t = k + q*j
+
+  // host FP64 factors (kept for export and for packing), tensor order t
+  std::vector<int64_t> g_off, u1_off, u2_off, u3_off;  // complex offsets
+  std::vector<double> cores, u1, u2, u3;               // interleaved re,im
+
+  // compression parameters and per-tensor relative discarded energies
+  double tol = 0.0;
+  int32_t rank_min = 1, rank_cap = 0;
+  int64_t appended = 0;               // columns whose factors are present
+  std::vector<double> rel_discarded;  // [q*m][3]
+  int64_t appended_or_all() const { return appended; }
+
+  // device packed form
+  tv::Tiling tiling{};
+  tv::TensorMeta* d_meta = nullptr;
+  float2* d_cores = nullptr;
+  float2* d_u2t = nullptr;
+  float2* d_u3t = nullptr;
+  float* d_apack = nullptr;        // FP32 real-embedded U1, MFMA lane order
+  int64_t* d_apack_koff = nullptr;
+  std::vector<int64_t> apack_koff;
+  std::vector<int64_t> sum_r1_k;   // rows of A_k per component
+  int split_f = 1, split_a = 1;    // column splits of the forward / adjoint
+  int32_t* d_split_f = nullptr;    // [q][split+1] first column per split
+  int32_t* d_split_a = nullptr;
+  size_t device_bytes = 0;
+  int max_r[3] = {0, 0, 0};
+  int64_t sum_r1 = 0;
+};
+
+namespace tv {
+tv_status set_error(tv_status s, const std::string& msg);
+tv_status hip_error(hipError_t e, const char* what);
+void clear_error();
+
+// kernels (tv_matvec_f32.hip)
+tv_status launch_forward_f32(const tv_plan_s* p, const float2* x, float2* out,
+                             int split, const int32_t* d_split, int64_t out_stride,
+                             hipStream_t st);
+tv_status launch_adjoint_f32(const tv_plan_s* p, const float2* y, float2* partial,
+                             int split, const int32_t* d_split, hipStream_t st);
+tv_status launch_sum_partials(const float2* ws, int split, int64_t n, float2* y,
+                              hipStream_t st);
+tv_status launch_reduce_adjoint(const float2* partial, int q, int64_t tiles,
+                                int64_t m, float2* x, hipStream_t st);
+}  // namespace tv

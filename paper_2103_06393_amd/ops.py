@@ -1,0 +1,134 @@
+"""Torch-facing wrappers over the C ABI.
+
+``TuckerPlan`` holds a device plan and runs Y = Z X / X = Z^* Y on torch
+complex64 CUDA tensors through ``tv_matvec`` / ``tv_rmatvec``; outputs and
+workspaces come from torch's caching allocator, the library itself never
+allocates on these calls.  ``TuckerMatvec`` is the autograd Function whose
+backward is the adjoint kernel: for the linear map y = Z x the
+vector-Jacobian product is Z^* g (the conjugate transpose needed by the GMT
+cost gradient, Sec. II.A.2).
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import lib
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class TuckerPlan:
+    def __init__(self, handle: int):
+        self.handle = handle
+        self.info = lib.tv_plan_info(handle)
+        g = self.info.grid
+        self.dims = (g.n1, g.n2, g.n3)
+        self.q = g.q
+        self.m = g.m
+        self.nv = g.n1 * g.n2 * g.n3
+        self.rows = self.q * self.nv
+        self._ws = {}
+
+    # -- construction ---------------------------------------------------
+    @classmethod
+    def from_factors(cls, dims, q, m, ranks, cores, u1, u2, u3,
+                     precision: int = lib.TV_PREC_FP32) -> "TuckerPlan":
+        grid = lib.make_grid(*dims, q, m)
+        return cls(lib.tv_plan_from_factors(grid, ranks, cores, u1, u2, u3,
+                                            precision))
+
+    @classmethod
+    def compress_dipoles(cls, dims, h, k0, basis, pos, ori, tol, rank_min=1,
+                         rank_cap=0, precision: int = lib.TV_PREC_FP32,
+                         chunk: Optional[int] = None) -> "TuckerPlan":
+        """Generate point-current columns on the device and compress them
+        with the library's truncated HOSVD, a chunk of columns at a time."""
+        q = 3 if basis == 0 else 12
+        m = int(pos.shape[0])
+        nv = int(np.prod(dims))
+        grid = lib.make_grid(*dims, q, m)
+        h_plan = lib.tv_compress_begin(grid, tol, rank_min, rank_cap, precision)
+        try:
+            if chunk is None:       # about 2 GiB of complex128 columns
+                chunk = max(1, min(m, (2 << 30) // (16 * q * nv)))
+            buf = torch.empty(chunk * q * nv * 2, dtype=torch.float64,
+                              device="cuda")
+            st = _stream()
+            for j0 in range(0, m, chunk):
+                n = min(chunk, m - j0)
+                lib.tv_dipole_columns(*dims, h, k0, basis, pos[j0:j0 + n],
+                                      ori[j0:j0 + n], buf.data_ptr(), st)
+                lib.tv_compress_append(h_plan, buf.data_ptr(), n, st)
+            del buf
+            lib.tv_plan_finalize(h_plan, st)
+        except Exception:
+            lib.tv_plan_destroy(h_plan)
+            raise
+        return cls(h_plan)
+
+    def close(self):
+        if self.handle:
+            lib.tv_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- products ---------------------------------------------------------
+    def workspace(self, op: int, nrhs: int) -> torch.Tensor:
+        key = (op, nrhs)
+        if key not in self._ws:
+            n = lib.tv_workspace_bytes(self.handle, op, nrhs)
+            self._ws[key] = torch.empty(max(n, 16), dtype=torch.uint8,
+                                        device="cuda")
+        return self._ws[key]
+
+    def matvec(self, x: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """Y = Z X for x of shape (m,) or (m, p), complex64 on the GPU."""
+        vec = x.dim() == 1
+        X = x.reshape(self.m, -1)
+        p = X.shape[1]
+        Xc = X.t().contiguous()                  # column-major m x p
+        Y = out if out is not None else torch.empty(
+            (p, self.rows), dtype=torch.complex64, device=x.device)
+        ws = self.workspace(0, p)
+        lib.tv_matvec(self.handle, Xc.data_ptr(), self.m, p, Y.data_ptr(),
+                      self.rows, ws.data_ptr(), ws.numel(), _stream())
+        return Y.reshape(-1) if vec else Y.t()
+
+    def rmatvec(self, y: torch.Tensor, out: Optional[torch.Tensor] = None):
+        """X = Z^* Y for y of shape (q nv,) or (q nv, p), complex64."""
+        vec = y.dim() == 1
+        Yv = y.reshape(self.rows, -1)
+        p = Yv.shape[1]
+        Yc = Yv.t().contiguous()
+        X = out if out is not None else torch.empty(
+            (p, self.m), dtype=torch.complex64, device=y.device)
+        ws = self.workspace(1, p)
+        lib.tv_rmatvec(self.handle, Yc.data_ptr(), self.rows, p, X.data_ptr(),
+                       self.m, ws.data_ptr(), ws.numel(), _stream())
+        return X.reshape(-1) if vec else X.t()
+
+    def export_factors(self):
+        return lib.tv_plan_export_factors(self.handle)
+
+
+class TuckerMatvec(torch.autograd.Function):
+    """y = Z x with the hand-written Z^* kernel as the backward."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, plan: TuckerPlan):
+        ctx.plan = plan
+        return plan.matvec(x)
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        return ctx.plan.rmatvec(g.contiguous()), None
