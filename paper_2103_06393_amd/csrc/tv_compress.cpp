@@ -1,10 +1,81 @@
 // Truncated-HOSVD compression (Sec. II.B.1): host orchestration.
+//
+// Per batch of columns: FP64 Gram matrices of the three unfoldings of every
+// tensor and their eigendecomposition on the device; the rank rule on the
+// host; the core A x1 U1^* x2 U2^* x3 U3^* on the device.  Factors are kept
+// in FP64 on the host until tv_plan_finalize packs the plan.
+//
+// Rank rule (the paper leaves the tolerance-to-rank map open): per mode keep
+// the smallest r whose discarded eigenvalues (squared singular values) sum to
+// at most tol^2 ||A||^2 / 3, so the HOSVD error bound gives a relative error
+// of at most tol; extend r across singular values equal to within 1e-10;
+// clamp to [rank_min, min(rank_cap, n, TV_MAX_RANK)].
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <numeric>
 
 #include "tv_internal.h"
+
+namespace tv {
+tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
+                      hipStream_t st);
+tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
+                        int64_t wstride, double2* V, hipStream_t st);
+tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const double2* u1,
+                      const double2* u2, const double2* u3, const int64_t* offs,
+                      const int* ranks, int r1max, int r2max, double2* T1, double2* T2,
+                      double2* G, hipStream_t st);
+tv_status finalize_plan(tv_plan_s* p);
+tv_status validate_ranks_and_offsets(tv_plan_s* p);
+
+// Device scratch of one append call, released on every exit path.
+struct DevScratch {
+  std::vector<void*> ptrs;
+  ~DevScratch() {
+    for (void* q : ptrs) hipFree(q);
+  }
+  template <typename T>
+  tv_status alloc(T** p, size_t count) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return hip_error(e, "hipMalloc (compression scratch)");
+    }
+    ptrs.push_back(*p);
+    return TV_OK;
+  }
+};
+
+// Rank of one mode from its eigenvalues sorted in descending order.
+int select_rank(const std::vector<double>& lam, double tol, int rank_min, int rank_cap,
+                double* rel_tail) {
+  const int n = (int)lam.size();
+  double trace = 0.0;
+  for (double v : lam) trace += std::max(v, 0.0);
+  std::vector<double> tail(n + 1, 0.0);  // tail[r] = sum_{i >= r} lam_i
+  for (int i = n - 1; i >= 0; --i) tail[i] = tail[i + 1] + std::max(lam[i], 0.0);
+  const double budget = tol * tol * trace / 3.0;
+  int r = n;
+  for (int c = 0; c <= n; ++c)
+    if (tail[c] <= budget) {
+      r = c;
+      break;
+    }
+  int cap = std::min(n, TV_MAX_RANK);
+  if (rank_cap > 0) cap = std::min(cap, rank_cap);
+  while (r > 0 && r < cap &&
+         std::sqrt(std::max(lam[r], 0.0)) >= (1.0 - 1e-10) * std::sqrt(std::max(lam[r - 1], 0.0)))
+    ++r;
+  r = std::max(r, rank_min);
+  r = std::min(r, cap);
+  *rel_tail = trace > 0.0 ? tail[r] / trace : 0.0;
+  return r;
+}
+
+}  // namespace tv
 
 using namespace tv;
 
@@ -24,6 +95,9 @@ tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min, i
   if (rank_cap > 0 && rank_cap < rank_min) return set_error(TV_ERR_RANK, "rank_cap < rank_min");
   if (precision != TV_PREC_FP32 && precision != TV_PREC_BF16X3)
     return set_error(TV_ERR_INVALID_ARG, "unknown precision");
+  const int nmax = std::max(grid->n1, std::max(grid->n2, grid->n3));
+  if (nmax > 64)
+    return set_error(TV_ERR_NOT_SUPPORTED, "device compression is built for n1, n2, n3 <= 64");
   tv_plan_s* p = new (std::nothrow) tv_plan_s;
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = *grid;
@@ -38,20 +112,145 @@ tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min, i
 
 tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* stream) {
   clear_error();
-  (void)cols;
-  (void)ncols;
-  (void)stream;
   if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
-  return set_error(TV_ERR_NOT_SUPPORTED, "device compression is not built yet");
+  if (p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is already finalized");
+  if (ncols < 0 || p->appended + ncols > p->grid.m)
+    return set_error(TV_ERR_SHAPE, "more columns than the plan holds");
+  if (ncols == 0) return TV_OK;
+  if (!cols) return set_error(TV_ERR_INVALID_ARG, "cols is NULL");
+  if (ncols * p->grid.q > 65535)
+    return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 tensors per append call");
+  const tv_grid& g = p->grid;
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  const int nmax = std::max(g.n1, std::max(g.n2, g.n3));
+  const int64_t nv = (int64_t)g.n1 * g.n2 * g.n3;
+  const int T = (int)(ncols * g.q);
+  hipStream_t st = (hipStream_t)stream;
+  const double2* A = (const double2*)cols;
+  DevScratch ds;
+  tv_status s;
+
+  // 1. Gram matrices S_d (mode-major) and their eigendecomposition
+  const int64_t mat = (int64_t)nmax * nmax;
+  double2 *dS, *dV;
+  double* dW;
+  if ((s = ds.alloc(&dS, (size_t)3 * T * mat)) != TV_OK) return s;
+  if ((s = ds.alloc(&dV, (size_t)3 * T * mat)) != TV_OK) return s;
+  if ((s = ds.alloc(&dW, (size_t)3 * T * nmax)) != TV_OK) return s;
+  if ((s = launch_gram(A, T, g.n1, g.n2, g.n3, nmax, dS, st)) != TV_OK) return s;
+  for (int d = 0; d < 3; ++d)
+    if ((s = launch_jacobi(dS + (int64_t)d * T * mat, T, dims[d], mat, dW + (int64_t)d * T * nmax,
+                           nmax, dV + (int64_t)d * T * mat, st)) != TV_OK)
+      return s;
+  std::vector<double> W((size_t)3 * T * nmax);
+  std::vector<double2> V((size_t)3 * T * mat);
+  hipError_t e = hipMemcpyAsync(W.data(), dW, W.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(V.data(), dV, V.size() * sizeof(double2), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_error(e, "eigendecomposition readback");
+
+  // 2. ranks and factors on the host
+  std::vector<int> rk((size_t)3 * T);
+  std::vector<double> reld((size_t)3 * T);
+  std::vector<std::vector<double2>> U(3);
+  std::vector<int64_t> offs((size_t)4 * T, 0);  // u1, u2, u3, g offsets (complex)
+  int64_t tot[4] = {0, 0, 0, 0};
+  for (int t = 0; t < T; ++t) {
+    for (int d = 0; d < 3; ++d) {
+      const int n = dims[d];
+      const double* w = &W[((size_t)d * T + t) * nmax];
+      std::vector<int> idx(n);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
+      std::vector<double> lam(n);
+      for (int i = 0; i < n; ++i) lam[i] = w[idx[i]];
+      double rt = 0.0;
+      const int r = select_rank(lam, p->tol, p->rank_min, p->rank_cap, &rt);
+      rk[3 * t + d] = r;
+      reld[3 * t + d] = rt;
+      offs[(size_t)d * T + t] = tot[d];
+      const double2* Vm = &V[((size_t)d * T + t) * mat];  // row-major n x n
+      for (int a = 0; a < r; ++a)
+        for (int i = 0; i < n; ++i) U[d].push_back(Vm[(size_t)i * n + idx[a]]);
+      tot[d] += (int64_t)n * r;
+    }
+    offs[(size_t)3 * T + t] = tot[3];
+    tot[3] += (int64_t)rk[3 * t] * rk[3 * t + 1] * rk[3 * t + 2];
+  }
+  int r1max = 1, r2max = 1;
+  for (int t = 0; t < T; ++t) {
+    r1max = std::max(r1max, rk[3 * t]);
+    r2max = std::max(r2max, rk[3 * t + 1]);
+  }
+
+  // 3. core = A x1 U1^* x2 U2^* x3 U3^* on the device
+  double2 *dU1, *dU2, *dU3, *dT1, *dT2, *dG;
+  int64_t* dOffs;
+  int* dRk;
+  if ((s = ds.alloc(&dU1, U[0].size())) != TV_OK || (s = ds.alloc(&dU2, U[1].size())) != TV_OK ||
+      (s = ds.alloc(&dU3, U[2].size())) != TV_OK ||
+      (s = ds.alloc(&dT1, (size_t)T * r1max * g.n2 * g.n3)) != TV_OK ||
+      (s = ds.alloc(&dT2, (size_t)T * r1max * r2max * g.n3)) != TV_OK ||
+      (s = ds.alloc(&dG, (size_t)tot[3])) != TV_OK || (s = ds.alloc(&dOffs, offs.size())) != TV_OK ||
+      (s = ds.alloc(&dRk, rk.size())) != TV_OK)
+    return s;
+  e = hipMemcpyAsync(dU1, U[0].data(), U[0].size() * sizeof(double2), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dU2, U[1].data(), U[1].size() * sizeof(double2), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dU3, U[2].data(), U[2].size() * sizeof(double2), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dOffs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dRk, rk.data(), rk.size() * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_error(e, "factor upload");
+  if ((s = launch_proj(A, T, g.n1, g.n2, g.n3, dU1, dU2, dU3, dOffs, dRk, r1max, r2max, dT1, dT2,
+                       dG, st)) != TV_OK)
+    return s;
+  std::vector<double2> G((size_t)tot[3]);
+  e = hipMemcpyAsync(G.data(), dG, G.size() * sizeof(double2), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_error(e, "core readback");
+
+  // 4. append to the plan's host factors (tensor order t = k + q j)
+  try {
+    for (int t = 0; t < T; ++t)
+      for (int d = 0; d < 3; ++d) p->ranks.push_back(rk[3 * t + d]);
+    p->rel_discarded.insert(p->rel_discarded.end(), reld.begin(), reld.end());
+    auto put = [](std::vector<double>& dst, const double2* src, size_t n) {
+      const size_t o = dst.size();
+      dst.resize(o + 2 * n);
+      std::memcpy(&dst[o], src, n * sizeof(double2));
+    };
+    put(p->cores, G.data(), G.size());
+    put(p->u1, U[0].data(), U[0].size());
+    put(p->u2, U[1].data(), U[1].size());
+    put(p->u3, U[2].data(), U[2].size());
+  } catch (const std::bad_alloc&) {
+    return set_error(TV_ERR_OOM, "host factor storage");
+  }
+  p->appended += ncols;
+  // offsets of what has been appended so far (for export before finalize)
+  tv_grid part = p->grid;
+  part.m = p->appended;
+  const tv_grid full = p->grid;
+  p->grid = part;
+  s = validate_ranks_and_offsets(p);
+  p->grid = full;
+  return s;
 }
 
 tv_status tv_plan_finalize(tv_plan p, void* stream) {
   clear_error();
   (void)stream;
   if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
+  if (p->finalized) return TV_OK;
   if (p->appended != p->grid.m)
     return set_error(TV_ERR_INVALID_ARG, "not all columns have been appended");
-  return set_error(TV_ERR_NOT_SUPPORTED, "device compression is not built yet");
+  tv_status s = validate_ranks_and_offsets(p);
+  if (s != TV_OK) return s;
+  return finalize_plan(p);
 }
 
 tv_status tv_compress_discarded(tv_plan p, double* rel) {

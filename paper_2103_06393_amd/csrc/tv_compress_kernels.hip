@@ -239,46 +239,46 @@ size_t jacobi_lds_bytes(int n) {
          8 * 512 + 16;
 }
 
-// T1[t][a][o] = sum_i1 conj(U1[i1, a]) A[i1 + n1 o]; workgroup = 64 values of
-// o, all a; U1 given column-major n1 x r1 at u1 + u1off[t].
+// T1[t][a][o] = sum_i1 conj(U1[i1, a]) A[i1 + n1 o]; workgroup = 32 values of
+// o and all a; U1 given column-major n1 x r1 at u1 + u1off[t].
 __global__ __launch_bounds__(256) void proj1_kernel(const double2* __restrict__ A, int n1,
                                                     int64_t no, const double2* __restrict__ u1,
                                                     const int64_t* __restrict__ u1off,
                                                     const int* __restrict__ rk, int r1max,
                                                     double2* __restrict__ T1) {
-  __shared__ double2 Us[64][65];
-  __shared__ double2 As[64][65];
-  const int64_t chunks = (no + 63) / 64;
+  __shared__ double2 Us[32][65];
+  __shared__ double2 As[32][33];
+  const int64_t chunks = (no + 31) / 32;
   const int t = (int)(blockIdx.x / chunks);
-  const int64_t o0 = (blockIdx.x % chunks) * 64;
+  const int64_t o0 = (blockIdx.x % chunks) * 32;
   const int r1 = rk[3 * t];
   const int64_t nv = (int64_t)n1 * no;
   const double2* At = A + (int64_t)t * nv;
   const double2* U = u1 + u1off[t];
   const int tid = threadIdx.x;
-  const int ol = tid % 64;
-  double2 acc[16];
-  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int i0 = 0; i0 < n1; i0 += 64) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int i = e % 64, x = e / 64;  // x = a (for U) or o (for A)
-      Us[i][x] = (i0 + i < n1 && x < r1) ? U[(i0 + i) + (int64_t)n1 * x] : make_double2(0, 0);
-      As[i][x] = (i0 + i < n1 && o0 + x < no) ? At[(i0 + i) + (int64_t)n1 * (o0 + x)]
+  const int ol = tid % 32, ag = tid / 32;  // a = ag + 8 q
+  double2 acc[8];
+  for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < n1; i0 += 32) {
+    for (int e = tid; e < 32 * 64; e += 256) {
+      const int i = e % 32, a = e / 32;
+      Us[i][a] = (i0 + i < n1 && a < r1) ? U[(i0 + i) + (int64_t)n1 * a] : make_double2(0, 0);
+    }
+    for (int e = tid; e < 32 * 32; e += 256) {
+      const int i = e % 32, o = e / 32;
+      As[i][o] = (i0 + i < n1 && o0 + o < no) ? At[(i0 + i) + (int64_t)n1 * (o0 + o)]
                                               : make_double2(0, 0);
     }
     __syncthreads();
-    // thread (ol, ag) computes a = ag + 4 q for q < 16
-    const int ag = tid / 64;
-    for (int i = 0; i < 64; ++i) {
+    for (int i = 0; i < 32; ++i) {
       const double2 av = As[i][ol];
-      for (int q = 0; q < 16; ++q) acc[q] = zfma_conj_a(Us[i][ag + 4 * q], av, acc[q]);
+      for (int q = 0; q < 8; ++q) acc[q] = zfma_conj_a(Us[i][ag + 8 * q], av, acc[q]);
     }
     __syncthreads();
   }
-  const int ag = tid / 64;
   if (o0 + ol < no)
-    for (int q = 0; q < 16; ++q) {
-      const int a = ag + 4 * q;
+    for (int q = 0; q < 8; ++q) {
+      const int a = ag + 8 * q;
       if (a < r1) T1[((int64_t)t * r1max + a) * no + o0 + ol] = acc[q];
     }
 }
@@ -351,7 +351,7 @@ tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const
                       const int* ranks, int r1max, int r2max, double2* T1, double2* T2,
                       double2* G, hipStream_t st) {
   const int64_t no = (int64_t)n2 * n3;
-  const int64_t chunks = (no + 63) / 64;
+  const int64_t chunks = (no + 31) / 32;
   hipLaunchKernelGGL(proj1_kernel, dim3((unsigned)(chunks * ntens)), dim3(256), 0, st, A, n1,
                      no, u1, offs, ranks, r1max, T1);
   tv_status s = last("proj1_kernel");

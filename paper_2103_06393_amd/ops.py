@@ -55,7 +55,7 @@ class TuckerPlan:
         h_plan = lib.tv_compress_begin(grid, tol, rank_min, rank_cap, precision)
         try:
             if chunk is None:       # about 2 GiB of complex128 columns
-                chunk = max(1, min(m, (2 << 30) // (16 * q * nv)))
+                chunk = max(1, min(m, (2 << 30) // (16 * q * nv), 65535 // q))
             buf = torch.empty(chunk * q * nv * 2, dtype=torch.float64,
                               device="cuda")
             st = _stream()
