@@ -141,6 +141,18 @@ tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
                      void* x, int64_t ldx, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* Pick the fastest workgroup column tile and column split of the fused
+ * kernels for this plan by timing every candidate on the device (HIP
+ * events, `stream`), for op 0 (tv_matvec), 1 (tv_rmatvec) or 2 (both).
+ * Results are cached in the JSON file cache_path (NULL: no cache), keyed by
+ * device architecture, grid, q, m, precision and a hash of the ranks; a
+ * cached entry is applied without timing.  Allocates and synchronises (a
+ * set-up call); afterwards tv_workspace_bytes reflects the chosen
+ * configuration.  Results do not depend on the configuration beyond
+ * floating-point summation order. */
+tv_status tv_autotune(tv_plan plan, int32_t op, const char* cache_path,
+                      void* stream);
+
 /* ------------------------------------------------------------------------
  * Synthetic coil columns on the device (stand-in for the MoM assembly of
  * Sec. II.A.1): column j is the E-field operator of eq. (2), with the
@@ -184,6 +196,35 @@ tv_status tv_plan_finalize(tv_plan plan, void* stream);
  * so far: host double[q*m][3] of sum_{i > r_n} sigma_i^2 / ||Z^{kj}||^2
  * (the HOSVD bound's terms, relative).  Synchronous. */
 tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
+
+/* ------------------------------------------------------------------------
+ * Batched products with many right-hand sides (Table III's multi-vector
+ * form): nplans plans on one voxel grid (same n1, n2, n3, q), plan c with
+ * nrhs[c] right-hand sides, in one persistent launch.
+ *   op 0:  Y_c = Z_c X_c,    in[c] = X_c (m_c x nrhs[c]), out[c] = Y_c
+ *   op 1:  X_c = Z_c^* Y_c,  in[c] = Y_c (q nv x nrhs[c]), out[c] = X_c
+ * Every tensor is decompressed once per voxel tile and applied to all
+ * right-hand sides on MFMA (FP32, whatever the plans' precision).
+ * tv_batch_create builds the work queue (device memory it owns, ordered
+ * longest job first) and is synchronous; plans must outlive the batch.
+ * tv_batch_run queues one small counter-reset kernel and one persistent
+ * kernel on `stream`: no allocation, no synchronisation and no memset, so
+ * it may be captured into a hipGraph.  Pointer arrays are host arrays of
+ * nplans device pointers (column-major, leading dimensions ld_in/ld_out);
+ * outputs are overwritten.  ws: at least tv_batch_workspace_bytes bytes,
+ * 16-byte aligned; concurrent runs need distinct workspaces.
+ * Deterministic: fixed summation order, no floating-point atomics.
+ * ---------------------------------------------------------------------- */
+#define TV_BATCH_MAX_PLANS 32
+typedef struct tv_batch_s* tv_batch;
+tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op,
+                          const int32_t* nrhs, tv_batch* out);
+tv_status tv_batch_workspace_bytes(tv_batch batch, size_t* bytes);
+tv_status tv_batch_run(tv_batch batch, const void* const* in,
+                       const int64_t* ld_in, void* const* out,
+                       const int64_t* ld_out, void* ws, size_t ws_bytes,
+                       void* stream);
+tv_status tv_batch_destroy(tv_batch batch);
 
 /* Human-readable name of a status code (static storage). */
 const char* tv_status_string(tv_status status);

@@ -24,10 +24,26 @@ tv_status hip_error(hipError_t e, const char* what) {
 
 size_t fused_lds_bytes(int t2, int t3, int r1max, int r2max, int nwg);
 
+// bf16 bits of x, round to nearest even (via FP32; finite inputs)
+static uint32_t bf16_bits(double x) {
+  const float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+static double bf16_value(uint32_t h) {
+  const uint32_t u = h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
 // Column tiling of the fused kernels: each workgroup owns every voxel row i1
 // (2*n1 real rows, split over wm waves of nb 32-row MFMA blocks) and
-// nwg = 32*wn columns (i2, i3) of the mode-1 unfolding.
-static tv_status choose_tiling(const tv_grid& g, Tiling* T) {
+// nwg = 32*wn columns (i2, i3) of the mode-1 unfolding, t2 values of i2 by
+// t3 = nwg / t2 values of i3.  t2 = 0 picks the shape covering the fewest
+// columns beyond the grid.
+tv_status make_tiling(const tv_grid& g, int t2req, Tiling* T) {
   const int nbt0 = (g.n1 + 15) / 16;
   int wm = 1;
   while ((nbt0 + wm - 1) / wm > 8) wm *= 2;
@@ -38,14 +54,22 @@ static tv_status choose_tiling(const tv_grid& g, Tiling* T) {
   T->n1p = 16 * T->nbt;
   T->wn = 4 / wm;
   T->nwg = 32 * T->wn;
-  int64_t best = -1;
-  for (int t2 = T->nwg; t2 >= 1; t2 /= 2) {
-    const int t3 = T->nwg / t2;
-    const int64_t cover = (int64_t)((g.n2 + t2 - 1) / t2) * t2 * ((g.n3 + t3 - 1) / t3) * t3;
-    if (best < 0 || cover < best) {
-      best = cover;
-      T->t2 = t2;
-      T->t3 = t3;
+  if (t2req) {
+    if (t2req < 2 || t2req > T->nwg || (T->nwg % t2req) != 0)
+      return set_error(TV_ERR_INVALID_ARG, "t2 must divide the workgroup's columns and be >= 2");
+    T->t2 = t2req;
+    T->t3 = T->nwg / t2req;
+  } else {
+    int64_t best = -1;
+    for (int t2 = T->nwg; t2 >= 2; t2 /= 2) {  // column pairs share one i3
+      const int t3 = T->nwg / t2;
+      const int64_t cover =
+          (int64_t)((g.n2 + t2 - 1) / t2) * t2 * ((g.n3 + t3 - 1) / t3) * t3;
+      if (best < 0 || cover < best) {
+        best = cover;
+        T->t2 = t2;
+        T->t3 = t3;
+      }
     }
   }
   T->tiles2 = (g.n2 + T->t2 - 1) / T->t2;
@@ -53,6 +77,8 @@ static tv_status choose_tiling(const tv_grid& g, Tiling* T) {
   T->tiles = (int64_t)T->tiles2 * T->tiles3;
   return TV_OK;
 }
+
+static tv_status choose_tiling(const tv_grid& g, Tiling* T) { return make_tiling(g, 0, T); }
 
 static tv_status validate_grid(const tv_grid* g) {
   if (!g) return set_error(TV_ERR_INVALID_ARG, "grid is NULL");
@@ -87,15 +113,18 @@ static tv_status upload(T* d, const std::vector<T>& h) {
 static void free_device(tv_plan_s* p) {
   hipFree(p->d_meta);
   hipFree(p->d_cores);
+  hipFree(p->d_u1t);
   hipFree(p->d_u2t);
   hipFree(p->d_u3t);
   hipFree(p->d_apack);
+  hipFree(p->d_apack_bf);
   hipFree(p->d_apack_koff);
   hipFree(p->d_split_f);
   hipFree(p->d_split_a);
   p->d_meta = nullptr;
-  p->d_cores = p->d_u2t = p->d_u3t = nullptr;
+  p->d_cores = p->d_u1t = p->d_u2t = p->d_u3t = nullptr;
   p->d_apack = nullptr;
+  p->d_apack_bf = nullptr;
   p->d_apack_koff = nullptr;
   p->d_split_f = p->d_split_a = nullptr;
   p->device_bytes = 0;
@@ -152,18 +181,44 @@ static std::vector<int32_t> make_split(const tv_plan_s* p, int S) {
   return out;
 }
 
+tv_status set_split(tv_plan_s* p, int op, int S) {
+  S = (int)std::max<int64_t>(1, std::min<int64_t>(S, p->grid.m));
+  std::vector<int32_t> sp = make_split(p, S);
+  int32_t* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, sp.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(d, sp.data(), sp.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    return hip_error(e, "split table upload");
+  }
+  if (op == 0) {
+    hipFree(p->d_split_f);
+    p->d_split_f = d;
+    p->split_f = S;
+  } else {
+    hipFree(p->d_split_a);
+    p->d_split_a = d;
+    p->split_a = S;
+  }
+  return TV_OK;
+}
+
 // Pack the FP64 host factors into the device layouts of the fused kernels.
 static tv_status pack_and_upload(tv_plan_s* p) {
   const tv_grid& g = p->grid;
   const int64_t K = (int64_t)g.q * g.m;
   tv_status st = choose_tiling(g, &p->tiling);
   if (st != TV_OK) return st;
+  p->tiling_a = p->tiling;
   const Tiling& T = p->tiling;
   if (fused_lds_bytes(T.t2, T.t3, p->max_r[0], p->max_r[1], T.nwg) > 160 * 1024)
     return set_error(TV_ERR_NOT_SUPPORTED, "ranks too large for the LDS tile");
 
   // per-tensor metadata, component-major [k][j]
+  const bool bf = p->precision == TV_PREC_BF16X3;
   std::vector<TensorMeta> meta((size_t)K);
+  std::vector<int64_t> chunks_k(g.q, 0);
   p->sum_r1_k.assign(g.q, 0);
   for (int64_t j = 0; j < g.m; ++j)
     for (int k = 0; k < g.q; ++k) {
@@ -172,20 +227,29 @@ static tv_status pack_and_upload(tv_plan_s* p) {
       M.r1 = p->ranks[3 * t];
       M.r2 = p->ranks[3 * t + 1];
       M.r3 = p->ranks[3 * t + 2];
-      M.arow = (int32_t)p->sum_r1_k[k];
+      M.arow = (int32_t)(bf ? chunks_k[k] : p->sum_r1_k[k]);
       M.g_off = p->g_off[t];
       M.u2_off = p->u2_off[t];
       M.u3_off = p->u3_off[t];
+      M.u1_off = p->u1_off[t];
       p->sum_r1_k[k] += M.r1;
+      chunks_k[k] += (M.r1 + 7) / 8;
     }
 
   // FP32 copies; U2, U3 transposed to row-major (i, r)
   std::vector<float2> cores((size_t)p->g_off[K]);
   for (size_t i = 0; i < cores.size(); ++i)
     cores[i] = make_float2((float)p->cores[2 * i], (float)p->cores[2 * i + 1]);
-  std::vector<float2> u2t((size_t)p->u2_off[K]), u3t((size_t)p->u3_off[K]);
+  std::vector<float2> u1t((size_t)p->u1_off[K]), u2t((size_t)p->u2_off[K]),
+      u3t((size_t)p->u3_off[K]);
   for (int64_t t = 0; t < K; ++t) {
-    const int r2 = p->ranks[3 * t + 1], r3 = p->ranks[3 * t + 2];
+    const int r1 = p->ranks[3 * t], r2 = p->ranks[3 * t + 1], r3 = p->ranks[3 * t + 2];
+    for (int a = 0; a < r1; ++a)
+      for (int i = 0; i < g.n1; ++i) {
+        const size_t src = p->u1_off[t] + i + (size_t)g.n1 * a;
+        u1t[p->u1_off[t] + (size_t)i * r1 + a] =
+            make_float2((float)p->u1[2 * src], (float)p->u1[2 * src + 1]);
+      }
     for (int b = 0; b < r2; ++b)
       for (int i = 0; i < g.n2; ++i) {
         const size_t src = p->u2_off[t] + i + (size_t)g.n2 * b;
@@ -200,33 +264,66 @@ static tv_status pack_and_upload(tv_plan_s* p) {
       }
   }
 
-  // stacked U1 per component in MFMA A-operand lane order:
-  // apack[koff + (row*nbt + blk)*64 + lane] = A_emb[m = 32*blk + lane%32][lane/32]
-  // with A_emb[2 i1 + s][p] = Ar (s==p), -Ai (s=0,p=1), Ai (s=1,p=0)
+  // stacked U1 per component in MFMA A-operand lane order, as the real
+  // embedding A_emb[2 i1 + s][(a, p)] = Ar (s == p), -Ai (s = 0, p = 1),
+  // Ai (s = 1, p = 0).
+  // FP32: apack[koff + (row*nbt + blk)*64 + lane] = A_emb[32 blk + lane%32][(row, lane/32)]
+  // BF16X3: apack_bf[koff + ((chunk*nbt + blk)*2 + hl)*64 + lane] = 8 bf16 (hi or lo)
+  //   for K slots 8 (lane/32) + i, i < 8, slot k = (row 8 chunk + k/2, part k%2)
+  auto emb = [&](int64_t t, int i1, int s, int a, int pp) -> double {
+    if (i1 >= g.n1 || a >= p->ranks[3 * t]) return 0.0;
+    const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * a;
+    const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
+    return s == pp ? ar : (s == 0 ? -ai : ai);
+  };
   p->apack_koff.assign(g.q + 1, 0);
-  for (int k = 0; k < g.q; ++k)
-    p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * T.nbt * 64;
-  std::vector<float> apack((size_t)p->apack_koff[g.q], 0.f);
-  for (int64_t j = 0; j < g.m; ++j)
-    for (int k = 0; k < g.q; ++k) {
-      const int64_t t = k + (int64_t)g.q * j;
-      const TensorMeta& M = meta[(size_t)k * g.m + j];
-      for (int a = 0; a < M.r1; ++a) {
-        float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * T.nbt) * 64];
-        for (int blk = 0; blk < T.nbt; ++blk)
-          for (int lane = 0; lane < 64; ++lane) {
-            const int mrow = 32 * blk + (lane & 31);
-            const int i1 = mrow >> 1, s = mrow & 1, pp = lane >> 5;
-            float v = 0.f;
-            if (i1 < g.n1) {
-              const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * a;
-              const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
-              v = (float)(s == pp ? ar : (s == 0 ? -ai : ai));
+  std::vector<float> apack;
+  std::vector<uint4> apack_bf;
+  if (!bf) {
+    for (int k = 0; k < g.q; ++k)
+      p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * T.nbt * 64;
+    apack.assign((size_t)p->apack_koff[g.q], 0.f);
+    for (int64_t j = 0; j < g.m; ++j)
+      for (int k = 0; k < g.q; ++k) {
+        const int64_t t = k + (int64_t)g.q * j;
+        const TensorMeta& M = meta[(size_t)k * g.m + j];
+        for (int a = 0; a < M.r1; ++a) {
+          float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * T.nbt) * 64];
+          for (int blk = 0; blk < T.nbt; ++blk)
+            for (int lane = 0; lane < 64; ++lane) {
+              const int mrow = 32 * blk + (lane & 31);
+              row[blk * 64 + lane] = (float)emb(t, mrow >> 1, mrow & 1, a, lane >> 5);
             }
-            row[blk * 64 + lane] = v;
-          }
+        }
       }
-    }
+  } else {
+    for (int k = 0; k < g.q; ++k)
+      p->apack_koff[k + 1] = p->apack_koff[k] + chunks_k[k] * T.nbt * 128;
+    apack_bf.assign((size_t)p->apack_koff[g.q], make_uint4(0, 0, 0, 0));
+    for (int64_t j = 0; j < g.m; ++j)
+      for (int k = 0; k < g.q; ++k) {
+        const int64_t t = k + (int64_t)g.q * j;
+        const TensorMeta& M = meta[(size_t)k * g.m + j];
+        for (int c = 0; c < (M.r1 + 7) / 8; ++c)
+          for (int blk = 0; blk < T.nbt; ++blk)
+            for (int lane = 0; lane < 64; ++lane) {
+              const int mrow = 32 * blk + (lane & 31);
+              uint32_t hi[8], lo[8];
+              for (int i = 0; i < 8; ++i) {
+                const int kk = 8 * (lane >> 5) + i;
+                const double v = emb(t, mrow >> 1, mrow & 1, 8 * c + kk / 2, kk % 2);
+                hi[i] = bf16_bits(v);
+                lo[i] = bf16_bits(v - bf16_value(hi[i]));
+              }
+              uint4* dst = &apack_bf[p->apack_koff[k] +
+                                     (((int64_t)(M.arow + c) * T.nbt + blk) * 2) * 64 + lane];
+              dst[0] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16),
+                                  hi[4] | (hi[5] << 16), hi[6] | (hi[7] << 16));
+              dst[64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
+                                   lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
+            }
+      }
+  }
 
   // column splits: spread the work over enough workgroups to fill the chip
   const int64_t base = (int64_t)g.q * T.tiles;
@@ -242,9 +339,11 @@ static tv_status pack_and_upload(tv_plan_s* p) {
   size_t tot = 0;
   if ((st = dev_alloc(&p->d_meta, meta.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_cores, cores.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_u1t, u1t.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_u2t, u2t.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_u3t, u3t.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_apack, apack.size(), &tot)) != TV_OK ||
+      (st = dev_alloc(&p->d_apack_bf, apack_bf.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_apack_koff, p->apack_koff.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_split_f, spf.size(), &tot)) != TV_OK ||
       (st = dev_alloc(&p->d_split_a, spa.size(), &tot)) != TV_OK) {
@@ -253,8 +352,10 @@ static tv_status pack_and_upload(tv_plan_s* p) {
   }
   p->device_bytes = tot;
   if ((st = upload(p->d_meta, meta)) != TV_OK || (st = upload(p->d_cores, cores)) != TV_OK ||
-      (st = upload(p->d_u2t, u2t)) != TV_OK || (st = upload(p->d_u3t, u3t)) != TV_OK ||
+      (st = upload(p->d_u1t, u1t)) != TV_OK || (st = upload(p->d_u2t, u2t)) != TV_OK ||
+      (st = upload(p->d_u3t, u3t)) != TV_OK ||
       (st = upload(p->d_apack, apack)) != TV_OK ||
+      (st = upload(p->d_apack_bf, apack_bf)) != TV_OK ||
       (st = upload(p->d_apack_koff, p->apack_koff)) != TV_OK ||
       (st = upload(p->d_split_f, spf)) != TV_OK || (st = upload(p->d_split_a, spa)) != TV_OK) {
     free_device(p);
@@ -309,8 +410,6 @@ tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const 
     return set_error(TV_ERR_INVALID_ARG, "ranks and factor arrays must be non-NULL");
   if (precision != TV_PREC_FP32 && precision != TV_PREC_BF16X3)
     return set_error(TV_ERR_INVALID_ARG, "unknown precision");
-  if (precision == TV_PREC_BF16X3)
-    return set_error(TV_ERR_NOT_SUPPORTED, "BF16X3 plans are not built yet");
   tv_plan_s* p = new (std::nothrow) tv_plan_s;
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = *grid;
@@ -404,7 +503,7 @@ tv_status tv_workspace_bytes(tv_plan p, int32_t op, int32_t nrhs, size_t* bytes)
   if (op == 0)
     *bytes = p->split_f > 1 ? (size_t)8 * p->split_f * g.q * nv : 0;
   else
-    *bytes = (size_t)8 * g.q * p->tiling.tiles * g.m;
+    *bytes = (size_t)8 * g.q * p->tiling_a.tiles * g.m;
   return TV_OK;
 }
 
@@ -473,7 +572,7 @@ tv_status tv_rmatvec(tv_plan p, const void* y, int64_t ldy, int32_t nrhs, void* 
     float2* xc = (float2*)x + (int64_t)c * ldx;
     st = launch_adjoint_f32(p, yc, (float2*)ws, p->split_a, p->d_split_a, s);
     if (st == TV_OK)
-      st = launch_reduce_adjoint((const float2*)ws, p->grid.q, p->tiling.tiles, p->grid.m, xc,
+      st = launch_reduce_adjoint((const float2*)ws, p->grid.q, p->tiling_a.tiles, p->grid.m, xc,
                                  s);
     if (st != TV_OK) return st;
   }

@@ -27,6 +27,8 @@ tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const
                       const double2* u2, const double2* u3, const int64_t* offs,
                       const int* ranks, int r1max, int r2max, double2* T1, double2* T2,
                       double2* G, hipStream_t st);
+tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, double* W,
+                              double2* U, double* tr, double2* ws, hipStream_t st);
 tv_status finalize_plan(tv_plan_s* p);
 tv_status validate_ranks_and_offsets(tv_plan_s* p);
 
@@ -49,22 +51,28 @@ struct DevScratch {
   }
 };
 
-// Rank of one mode from its eigenvalues sorted in descending order.
-int select_rank(const std::vector<double>& lam, double tol, int rank_min, int rank_cap,
-                double* rel_tail) {
-  const int n = (int)lam.size();
-  double trace = 0.0;
-  for (double v : lam) trace += std::max(v, 0.0);
-  std::vector<double> tail(n + 1, 0.0);  // tail[r] = sum_{i >= r} lam_i
-  for (int i = n - 1; i >= 0; --i) tail[i] = tail[i + 1] + std::max(lam[i], 0.0);
+// Rank of one mode from its leading eigenvalues lam (descending, L of the
+// n_full eigenvalues of the Gram matrix) and the Gram trace: the tail of
+// the spectrum beyond r is trace - sum_{i<r} lam_i.
+int select_rank(const std::vector<double>& lam, double trace, int n_full, double tol,
+                int rank_min, int rank_cap, double* rel_tail) {
+  const int L = (int)lam.size();
+  trace = std::max(trace, 0.0);
+  std::vector<double> tail(L + 1, 0.0);
+  double head = 0.0;
+  for (int r = 0; r <= L; ++r) {
+    tail[r] = std::max(trace - head, 0.0);
+    if (r < L) head += std::max(lam[r], 0.0);
+  }
+  if (L == n_full) tail[L] = 0.0;
   const double budget = tol * tol * trace / 3.0;
-  int r = n;
-  for (int c = 0; c <= n; ++c)
+  int r = L;
+  for (int c = 0; c <= L; ++c)
     if (tail[c] <= budget) {
       r = c;
       break;
     }
-  int cap = std::min(n, TV_MAX_RANK);
+  int cap = std::min(L, TV_MAX_RANK);
   if (rank_cap > 0) cap = std::min(cap, rank_cap);
   while (r > 0 && r < cap &&
          std::sqrt(std::max(lam[r], 0.0)) >= (1.0 - 1e-10) * std::sqrt(std::max(lam[r - 1], 0.0)))
@@ -96,8 +104,8 @@ tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min, i
   if (precision != TV_PREC_FP32 && precision != TV_PREC_BF16X3)
     return set_error(TV_ERR_INVALID_ARG, "unknown precision");
   const int nmax = std::max(grid->n1, std::max(grid->n2, grid->n3));
-  if (nmax > 64)
-    return set_error(TV_ERR_NOT_SUPPORTED, "device compression is built for n1, n2, n3 <= 64");
+  if (nmax > 256)
+    return set_error(TV_ERR_NOT_SUPPORTED, "device compression is built for n1, n2, n3 <= 256");
   tv_plan_s* p = new (std::nothrow) tv_plan_s;
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = *grid;
@@ -130,25 +138,47 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* s
   DevScratch ds;
   tv_status s;
 
-  // 1. Gram matrices S_d (mode-major) and their eigendecomposition
+  // 1. Gram matrices S_d (mode-major) and their (leading) eigenpairs: the
+  //    full Jacobi eigendecomposition for modes of length <= 64, the leading
+  //    64 pairs by subspace iteration otherwise
   const int64_t mat = (int64_t)nmax * nmax;
-  double2 *dS, *dV;
-  double* dW;
+  double2* dS;
   if ((s = ds.alloc(&dS, (size_t)3 * T * mat)) != TV_OK) return s;
-  if ((s = ds.alloc(&dV, (size_t)3 * T * mat)) != TV_OK) return s;
-  if ((s = ds.alloc(&dW, (size_t)3 * T * nmax)) != TV_OK) return s;
   if ((s = launch_gram(A, T, g.n1, g.n2, g.n3, nmax, dS, st)) != TV_OK) return s;
-  for (int d = 0; d < 3; ++d)
-    if ((s = launch_jacobi(dS + (int64_t)d * T * mat, T, dims[d], mat, dW + (int64_t)d * T * nmax,
-                           nmax, dV + (int64_t)d * T * mat, st)) != TV_OK)
-      return s;
-  std::vector<double> W((size_t)3 * T * nmax);
-  std::vector<double2> V((size_t)3 * T * mat);
-  hipError_t e = hipMemcpyAsync(W.data(), dW, W.size() * sizeof(double), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(V.data(), dV, V.size() * sizeof(double2), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_error(e, "eigendecomposition readback");
+  std::vector<std::vector<double>> W(3), TR(3);
+  std::vector<std::vector<double2>> V(3);
+  int L[3];
+  for (int d = 0; d < 3; ++d) {
+    const int n = dims[d];
+    L[d] = n <= 64 ? n : 64;
+    double2* dV;
+    double *dW, *dTr = nullptr;
+    if ((s = ds.alloc(&dV, (size_t)T * n * L[d])) != TV_OK) return s;
+    if ((s = ds.alloc(&dW, (size_t)T * L[d])) != TV_OK) return s;
+    const double2* Sd = dS + (int64_t)d * T * mat;
+    if (n <= 64) {
+      if ((s = launch_jacobi(Sd, T, n, mat, dW, n, dV, st)) != TV_OK) return s;
+    } else {
+      double2* dWs;
+      if ((s = ds.alloc(&dTr, (size_t)T)) != TV_OK) return s;
+      if ((s = ds.alloc(&dWs, (size_t)T * (3 * (size_t)n * 64 + 64 * 64))) != TV_OK) return s;
+      if ((s = launch_subspace_eig(Sd, T, n, mat, dW, dV, dTr, dWs, st)) != TV_OK) return s;
+    }
+    W[d].resize((size_t)T * L[d]);
+    V[d].resize((size_t)T * n * L[d]);
+    hipError_t e = hipMemcpyAsync(W[d].data(), dW, W[d].size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(V[d].data(), dV, V[d].size() * sizeof(double2), hipMemcpyDeviceToHost,
+                         st);
+    if (e == hipSuccess && dTr) {
+      TR[d].resize(T);
+      e = hipMemcpyAsync(TR[d].data(), dTr, T * sizeof(double), hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_error(e, "eigenpair readback");
+  }
+  hipError_t e;
 
   // 2. ranks and factors on the host
   std::vector<int> rk((size_t)3 * T);
@@ -158,21 +188,26 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* s
   int64_t tot[4] = {0, 0, 0, 0};
   for (int t = 0; t < T; ++t) {
     for (int d = 0; d < 3; ++d) {
-      const int n = dims[d];
-      const double* w = &W[((size_t)d * T + t) * nmax];
-      std::vector<int> idx(n);
+      const int n = dims[d], Ld = L[d];
+      const double* w = &W[d][(size_t)t * Ld];
+      std::vector<int> idx(Ld);
       std::iota(idx.begin(), idx.end(), 0);
       std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
-      std::vector<double> lam(n);
-      for (int i = 0; i < n; ++i) lam[i] = w[idx[i]];
+      std::vector<double> lam(Ld);
+      double trace = 0.0;
+      for (int i = 0; i < Ld; ++i) {
+        lam[i] = w[idx[i]];
+        trace += std::max(w[i], 0.0);
+      }
+      if (n > 64) trace = TR[d][t];
       double rt = 0.0;
-      const int r = select_rank(lam, p->tol, p->rank_min, p->rank_cap, &rt);
+      const int r = select_rank(lam, trace, n, p->tol, p->rank_min, p->rank_cap, &rt);
       rk[3 * t + d] = r;
       reld[3 * t + d] = rt;
       offs[(size_t)d * T + t] = tot[d];
-      const double2* Vm = &V[((size_t)d * T + t) * mat];  // row-major n x n
+      const double2* Vm = &V[d][(size_t)t * n * Ld];  // row-major n x Ld
       for (int a = 0; a < r; ++a)
-        for (int i = 0; i < n; ++i) U[d].push_back(Vm[(size_t)i * n + idx[a]]);
+        for (int i = 0; i < n; ++i) U[d].push_back(Vm[(size_t)i * Ld + idx[a]]);
       tot[d] += (int64_t)n * r;
     }
     offs[(size_t)3 * T + t] = tot[3];

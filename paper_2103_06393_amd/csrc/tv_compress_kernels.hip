@@ -368,3 +368,215 @@ tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const
 }
 
 }  // namespace tv
+
+// ---------------------------------------------------------------------------
+// Leading eigenpairs of the Gram matrices of modes longer than 64 (at most 64
+// are ever kept): randomized range finder with one power iteration
+// (Q = orth(S S Omega)), then Rayleigh-Ritz on Q^* S Q (64 x 64, Jacobi).
+// All matrices are row-major, element (i, j) at [i * ld + j].
+namespace tv {
+
+// C[b] = op(A[b]) B[b]; op(A)(i, k) = A[i][k] (trans == 0) or conj(A[k][i]).
+// One 32 x 32 tile of C per workgroup, K staged through LDS in chunks of 16.
+__global__ __launch_bounds__(256) void zgemm_batched_kernel(
+    int trans, int M, int N, int K, const double2* __restrict__ A, int lda, int64_t sA,
+    const double2* __restrict__ B, int ldb, int64_t sB, double2* __restrict__ C, int ldc,
+    int64_t sC, int tilesM, int tilesN) {
+  __shared__ double2 As[32][17];
+  __shared__ double2 Bs[16][33];
+  int64_t blk = blockIdx.x;
+  const int tn = (int)(blk % tilesN);
+  blk /= tilesN;
+  const int tm = (int)(blk % tilesM);
+  const int64_t b = blk / tilesM;
+  const double2* Ab = A + b * sA;
+  const double2* Bb = B + b * sB;
+  const int tid = threadIdx.x;
+  const int ty = tid / 16, tx = tid % 16;  // outputs (2ty..2ty+1, 2tx..2tx+1)
+  double2 acc[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = tid; e < 32 * 16; e += 256) {
+      const int i = e / 16, kk = e % 16;
+      const int gi = tm * 32 + i, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gi < M && gk < K) {
+        if (trans == 0) {
+          v = Ab[(int64_t)gi * lda + gk];
+        } else {
+          v = Ab[(int64_t)gk * lda + gi];
+          v.y = -v.y;
+        }
+      }
+      As[i][kk] = v;
+    }
+    for (int e = tid; e < 16 * 32; e += 256) {
+      const int kk = e / 32, j = e % 32;
+      const int gk = k0 + kk, gj = tn * 32 + j;
+      Bs[kk][j] = (gk < K && gj < N) ? Bb[(int64_t)gk * ldb + gj] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 16; ++kk) {
+      const double2 a0 = As[2 * ty][kk], a1 = As[2 * ty + 1][kk];
+      const double2 b0 = Bs[kk][2 * tx], b1 = Bs[kk][2 * tx + 1];
+      const double2 av[2] = {a0, a1}, bv[2] = {b0, b1};
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          acc[u][v].x = fma(av[u].x, bv[v].x, acc[u][v].x);
+          acc[u][v].x = fma(-av[u].y, bv[v].y, acc[u][v].x);
+          acc[u][v].y = fma(av[u].x, bv[v].y, acc[u][v].y);
+          acc[u][v].y = fma(av[u].y, bv[v].x, acc[u][v].y);
+        }
+    }
+    __syncthreads();
+  }
+  double2* Cb = C + b * sC;
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const int i = tm * 32 + 2 * ty + u, j = tn * 32 + 2 * tx + v;
+      if (i < M && j < N) Cb[(int64_t)i * ldc + j] = acc[u][v];
+    }
+}
+
+// Classical Gram-Schmidt with one reorthogonalisation pass (CGS2), column by
+// column, in place on Z (n x l, row-major).  A column whose norm falls below
+// 1e-13 of its norm before projection lies in the span of the previous
+// ones and is set to zero.  One workgroup per matrix.
+__global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int n, int l,
+                                                   int64_t stride) {
+  __shared__ double2 c[64];
+  __shared__ double red[256];
+  double2* Zb = Z + blockIdx.x * stride;
+  const int tid = threadIdx.x;
+  for (int j = 0; j < l; ++j) {
+    double s = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      const double2 v = Zb[(int64_t)i * l + j];
+      s += v.x * v.x + v.y * v.y;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double nrm0 = sqrt(red[0]);
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      if (tid < j) {
+        double2 a = make_double2(0.0, 0.0);
+        for (int i = 0; i < n; ++i) {
+          const double2 q = Zb[(int64_t)i * l + tid], z = Zb[(int64_t)i * l + j];
+          a.x += q.x * z.x + q.y * z.y;  // conj(q) z
+          a.y += q.x * z.y - q.y * z.x;
+        }
+        c[tid] = a;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += 256) {
+        double2 z = Zb[(int64_t)i * l + j];
+        for (int k = 0; k < j; ++k) {
+          const double2 q = Zb[(int64_t)i * l + k], ck = c[k];
+          z.x -= q.x * ck.x - q.y * ck.y;
+          z.y -= q.x * ck.y + q.y * ck.x;
+        }
+        Zb[(int64_t)i * l + j] = z;
+      }
+      __syncthreads();
+    }
+    s = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      const double2 v = Zb[(int64_t)i * l + j];
+      s += v.x * v.x + v.y * v.y;
+    }
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double nrm = sqrt(red[0]);
+    const double scale = (nrm > 1e-13 * nrm0 && nrm > 1e-300) ? 1.0 / nrm : 0.0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+      double2 v = Zb[(int64_t)i * l + j];
+      Zb[(int64_t)i * l + j] = make_double2(v.x * scale, v.y * scale);
+    }
+    __syncthreads();
+  }
+}
+
+// Deterministic start block Omega (n x l, row-major, complex entries in
+// [-1, 1) + i[-1, 1)) from a 32-bit integer hash of the entry index.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+__global__ void omega_kernel(double2* __restrict__ Om, int n, int l, int64_t stride, int nmat) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * l * nmat) return;
+  const int64_t b = e / ((int64_t)n * l), r = e % ((int64_t)n * l);
+  const uint32_t h1 = mix32((uint32_t)(2 * r + 1)), h2 = mix32((uint32_t)(2 * r + 2) ^ 0x9e3779b9U);
+  Om[b * stride + r] = make_double2(h1 * (2.0 / 4294967296.0) - 1.0, h2 * (2.0 / 4294967296.0) - 1.0);
+}
+
+__global__ void trace_kernel(const double2* __restrict__ S, int n, int64_t stride, int nmat,
+                             double* __restrict__ tr) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nmat) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += S[b * stride + (int64_t)i * n + i].x;
+  tr[b] = s;
+}
+
+tv_status launch_zgemm(int trans, int M, int N, int K, const double2* A, int lda, int64_t sA,
+                       const double2* B, int ldb, int64_t sB, double2* C, int ldc, int64_t sC,
+                       int batch, hipStream_t st) {
+  const int tm = (M + 31) / 32, tn = (N + 31) / 32;
+  hipLaunchKernelGGL(zgemm_batched_kernel, dim3((unsigned)((int64_t)batch * tm * tn)), dim3(256),
+                     0, st, trans, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, tm, tn);
+  return last("zgemm_batched_kernel");
+}
+
+// Leading l = 64 eigenpairs of nmat Hermitian n x n matrices S (n > 64).
+// Outputs: W[b*l + i] eigenvalues (unsorted), U[b*n*l] eigenvectors as the
+// columns of an n x l row-major matrix, tr[b] traces.  ws: 3 * nmat * n * l
+// + nmat * l * l complex.
+tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, double* W,
+                              double2* U, double* tr, double2* ws, hipStream_t st) {
+  const int l = 64;
+  const int64_t nl = (int64_t)n * l, ll = (int64_t)l * l;
+  double2* Q = ws;
+  double2* Z = Q + nmat * nl;
+  double2* V = Z + nmat * nl;
+  double2* T = V + nmat * nl;
+  tv_status s;
+  const int64_t tot = (int64_t)nmat * nl;
+  hipLaunchKernelGGL(omega_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Q, n,
+                     l, nl, nmat);
+  if ((s = last("omega_kernel")) != TV_OK) return s;
+  hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((nmat + 255) / 256)), dim3(256), 0, st, S, n,
+                     sS, nmat, tr);
+  if ((s = last("trace_kernel")) != TV_OK) return s;
+  // Z = S Omega, Q = orth(Z); Z = S Q, Q = orth(Z)
+  for (int it = 0; it < 2; ++it) {
+    if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
+    hipLaunchKernelGGL(cgs2_kernel, dim3((unsigned)nmat), dim3(256), 0, st, Z, n, l, nl);
+    if ((s = last("cgs2_kernel")) != TV_OK) return s;
+    double2* tmp = Q;
+    Q = Z;
+    Z = tmp;
+  }
+  // Rayleigh-Ritz: T = Q^* (S Q), T = W diag(mu) W^*, U = Q W
+  if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
+  if ((s = launch_zgemm(1, l, l, n, Q, l, nl, Z, l, nl, T, l, ll, nmat, st)) != TV_OK) return s;
+  if ((s = launch_jacobi(T, nmat, l, ll, W, l, V, st)) != TV_OK) return s;
+  return launch_zgemm(0, n, l, l, Q, l, nl, V, l, ll, U, l, nl, nmat, st);
+}
+
+}  // namespace tv

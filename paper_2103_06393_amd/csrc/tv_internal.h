@@ -18,6 +18,7 @@ struct TensorMeta {
   int64_t g_off;   // core G[a,b,c] (complex) at g_off + a + r1*(b + r2*c)
   int64_t u2_off;  // U2 row-major: U2[i2][b] at u2_off + i2*r2 + b
   int64_t u3_off;  // U3 row-major: U3[i3][c] at u3_off + i3*r3 + c
+  int64_t u1_off;  // U1 row-major: U1[i1][a] at u1_off + i1*r1 + a
 };
 
 // Geometry of the fused FP32 / BF16 kernels for one plan.
@@ -52,12 +53,15 @@ struct tv_plan_s {
   int64_t appended_or_all() const { return appended; }
 
   // device packed form
-  tv::Tiling tiling{};
+  tv::Tiling tiling{};    // forward kernel tiling
+  tv::Tiling tiling_a{};  // adjoint kernel tiling (sizes its workspace)
   tv::TensorMeta* d_meta = nullptr;
   float2* d_cores = nullptr;
+  float2* d_u1t = nullptr;         // U1 row-major [i1][a] (batched kernels)
   float2* d_u2t = nullptr;
   float2* d_u3t = nullptr;
   float* d_apack = nullptr;        // FP32 real-embedded U1, MFMA lane order
+  uint4* d_apack_bf = nullptr;     // BF16X3: hi/lo bf16 of the same, 8-row chunks
   int64_t* d_apack_koff = nullptr;
   std::vector<int64_t> apack_koff;
   std::vector<int64_t> sum_r1_k;   // rows of A_k per component
@@ -84,4 +88,8 @@ tv_status launch_sum_partials(const float2* ws, int split, int64_t n, float2* y,
                               hipStream_t st);
 tv_status launch_reduce_adjoint(const float2* partial, int q, int64_t tiles,
                                 int64_t m, float2* x, hipStream_t st);
+// tiling with a given i2 extent t2 (0: the one covering the fewest columns)
+tv_status make_tiling(const tv_grid& g, int t2, Tiling* T);
+// (re)build and upload the column split table of one direction
+tv_status set_split(tv_plan_s* p, int op, int S);
 }  // namespace tv

@@ -21,18 +21,36 @@
 // MFMA 32x32x2 f32 lane layout: A operand lane l = A[l%32][l/32], B operand
 // lane l = B[l/32][l%32], accumulator register i of lane l =
 // D[8*(i/4) + 4*(l/32) + i%4][l%32].
+//
+// BF16X3 form: every FP32 operand x is split into bf16 hi = rn(x) and
+// lo = rn(x - hi) (round to nearest even) and the product is accumulated as
+// hi*hi + hi*lo + lo*hi in FP32 on v_mfma_f32_32x32x16_bf16 (A operand lane l
+// holds A[l%32][8(l/32) .. 8(l/32)+7], B operand lane l holds
+// B[8(l/32) .. 8(l/32)+7][l%32]).  One MFMA K step of 16 carries 8 complex
+// rows of B as (Re, Im) pairs; each tensor's rows are padded to a multiple
+// of 8 with zeros.
 #include "tv_internal.h"
 
 namespace tv {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// float -> bf16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_to_float(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ v8bf as_v8bf(uint4 v) { return __builtin_bit_cast(v8bf, v); }
 
 struct KParams {
   const TensorMeta* meta;
   const float2* cores;
   const float2* u2t;
   const float2* u3t;
-  const float* apack;
+  const float* apack;      // FP32 plans
+  const uint4* apack_bf;   // BF16X3 plans: [chunk][blk][hi|lo][lane] 8 x bf16
   const int64_t* apack_koff;
   const int32_t* split;  // [q][S+1] first column of each split
   const float2* vec;     // x (forward) or one column of y (adjoint)
@@ -60,26 +78,58 @@ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
   return c;
 }
 
-// LDS carve-up shared by host sizing and the kernel.
+// LDS carve-up shared by host sizing and the kernel.  r1 is padded to a
+// multiple of 4 in H so that four consecutive rows are one 32-byte load.
+__host__ __device__ inline int pad4(int r) { return (r + 3) & ~3; }
+__host__ __device__ inline int pad8(int r) { return (r + 7) & ~7; }
 __host__ __device__ inline size_t lds_hs_elems(int t3, int r1, int r2) {
-  return (size_t)t3 * r1 * r2;  // float2
+  return (size_t)t3 * pad8(r1) * r2;  // float2
 }
 __host__ __device__ inline size_t lds_u2_elems(int t2, int r2) {
   return (size_t)t2 * r2;  // float2
 }
 __host__ __device__ inline size_t lds_bs_elems(int r1, int nwg) {
-  return (size_t)r1 * 2 * nwg;  // float
+  return (size_t)pad8(r1) * 2 * nwg;  // float (FP32) or 2 x bf16 (hi, lo)
 }
+constexpr int DOT_RING = 8;  // adjoint: tensors whose dots are reduced together
 size_t fused_lds_bytes(int t2, int t3, int r1max, int r2max, int nwg) {
   return 8 * lds_hs_elems(t3, r1max, r2max) + 8 * lds_u2_elems(t2, r2max) +
-         4 * lds_bs_elems(r1max, nwg) + 64;
+         4 * lds_bs_elems(r1max, nwg) + 8 * DOT_RING * 4 * 64;
 }
 
-template <int NB, int WN, bool ADJ>
+// Adjoint: sum the per-lane dot products of tensors [j0, j0 + cnt) (ring
+// slots (j - jb) % DOT_RING) over the 4 waves and 64 lanes in a fixed order
+// and write one partial per tensor.
+__device__ __forceinline__ void flush_dots(const float2* dots, int cnt, int jb, int j0,
+                                           float2* out, int64_t base) {
+  const int tid = threadIdx.x;
+  const int slot_i = tid >> 5, part = tid & 31;
+  float sr = 0.f, si = 0.f;
+  if (slot_i < cnt) {
+    const int slot = (j0 + slot_i - jb) % DOT_RING;
+    const float2* d = dots + slot * 256;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const float2 a = d[w * 64 + part], b = d[w * 64 + 32 + part];
+      sr += a.x;
+      si += a.y;
+      sr += b.x;
+      si += b.y;
+    }
+  }
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) {
+    sr += __shfl_xor(sr, off);
+    si += __shfl_xor(si, off);
+  }
+  if (slot_i < cnt && part == 0) out[base + j0 + slot_i] = make_float2(sr, si);
+}
+
+template <int NB, int WN, bool ADJ, bool BF>
 __global__ __launch_bounds__(256) void fused_f32(KParams P) {
   extern __shared__ float4 smem4[];
   constexpr int NWG = 32 * WN;
-  constexpr int AG = 256 / NWG;
+  constexpr int NP = NWG / 2;  // column pairs per tile
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
@@ -101,7 +151,7 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
   float2* Hs = reinterpret_cast<float2*>(smem4);
   float2* U2s = Hs + lds_hs_elems(P.t3, P.r1max, P.r2max);
   float* Bs = reinterpret_cast<float*>(U2s + lds_u2_elems(T2, P.r2max));
-  float2* red = reinterpret_cast<float2*>(Bs + lds_bs_elems(P.r1max, NWG));
+  float2* dots = reinterpret_cast<float2*>(Bs + lds_bs_elems(P.r1max, NWG));
 
   // this lane's output column (mode-1 fibre) inside the tile
   const int ncol = wn * 32 + (lane & 31);
@@ -135,58 +185,124 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
   }
 
   const TensorMeta* meta = P.meta + (int64_t)k * P.m;
-  const float* Ak = P.apack + P.apack_koff[k];
+  const int64_t pbase = ((int64_t)k * P.tiles + tile) * P.m;
+  int flushed = jb;
+  TensorMeta tn;
+  if (jb < je) tn = meta[jb];
 
   for (int j = jb; j < je; ++j) {
-    const TensorMeta t = meta[j];
+    const TensorMeta t = tn;
+    if (j + 1 < je) tn = meta[j + 1];  // next tensor's metadata in flight
     const int r1 = t.r1, r2 = t.r2, r3 = t.r3;
+    const int r1p = BF ? pad8(r1) : pad4(r1), r1q = r1p >> 2;
     const float2 xj = ADJ ? make_float2(1.f, 0.f) : P.vec[j];
 
-    // stage the tile's U2 rows, b-major so a wave reads consecutive i2
+    // stage the tile's U2 rows, b-major so that threads read consecutive i2
     for (int idx = tid; idx < r2 * T2; idx += 256) {
       const int t2 = idx % T2, b = idx / T2;
       const int ii = i2_0 + t2;
       U2s[idx] = (ii < P.n2) ? P.u2t[t.u2_off + (int64_t)ii * r2 + b]
                              : make_float2(0.f, 0.f);
     }
-    // A) mode-3 contraction of the core for the tile's i3 values
+    // A) mode-3 contraction of the core with the tile's U3 rows, four rows a
+    //    per task: H[t3][b][a] = x_j sum_c G[a,b,c] U3[i3,c]
     const int r12 = r1 * r2;
-    for (int idx = tid; idx < P.t3 * r12; idx += 256) {
-      const int t3 = idx / r12, rem = idx - t3 * r12;  // rem = a + r1*b
-      const int a = rem % r1, b = rem / r1;
+    for (int task = tid; task < P.t3 * r2 * r1q; task += 256) {
+      const int a4 = task % r1q, rest = task / r1q;
+      const int b = rest % r2, t3 = rest / r2;
       const int ii = i3_0 + t3;
-      float2 h = make_float2(0.f, 0.f);
+      float2 h[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h[e] = make_float2(0.f, 0.f);
       if (ii < P.n3) {
-        const float2* g = P.cores + t.g_off + rem;
+        const float2* g = P.cores + t.g_off + 4 * a4 + r1 * b;
         const float2* u3 = P.u3t + t.u3_off + (int64_t)ii * r3;
-        for (int c = 0; c < r3; ++c) h = cfma(g[(int64_t)c * r12], u3[c], h);
-        if (!ADJ) h = cmul(xj, h);
+        const int ne = min(4, r1 - 4 * a4);
+        for (int c = 0; c < r3; ++c) {
+          const float2 u = u3[c];
+          const float2* gc = g + (int64_t)c * r12;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (e < ne) h[e] = cfma(gc[e], u, h[e]);
+        }
+        if (!ADJ) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) h[e] = cmul(xj, h[e]);
+        }
       }
-      Hs[(t3 * r1 + a) * r2 + b] = h;
+      float2* dst = Hs + (t3 * r2 + b) * r1p + 4 * a4;
+      *reinterpret_cast<float4*>(dst) = make_float4(h[0].x, h[0].y, h[1].x, h[1].y);
+      *reinterpret_cast<float4*>(dst + 2) = make_float4(h[2].x, h[2].y, h[3].x, h[3].y);
     }
     __syncthreads();
 
-    // B) mode-2 product per column into the MFMA B tile
-    {
-      const int n = tid % NWG, ag = tid / NWG;
+    // B) mode-2 product per column pair into the MFMA B tile, 4 rows a x 2
+    //    columns per task: B[a][n] = sum_b H[t3(n)][b][a] U2[i2(n), b]
+    for (int task = tid; task < r1q * NP; task += 256) {
+      const int np = task % NP, a4 = task / NP;
+      const int n = 2 * np;
       const int t2n = n % T2, t3n = n / T2;
-      const float2* hrow = Hs + (t3n * r1) * r2;
-      for (int a = ag; a < r1; a += AG) {
-        float2 v = make_float2(0.f, 0.f);
-        for (int b = 0; b < r2; ++b) v = cfma(hrow[a * r2 + b], U2s[b * T2 + t2n], v);
-        Bs[(2 * a) * NWG + n] = v.x;
-        Bs[(2 * a + 1) * NWG + n] = v.y;
+      const float2* hb = Hs + (t3n * r2) * r1p + 4 * a4;
+      const float2* ub = U2s + t2n;
+      float2 v[4][2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e][0] = v[e][1] = make_float2(0.f, 0.f);
+      for (int b = 0; b < r2; ++b) {
+        const float4 h01 = *reinterpret_cast<const float4*>(hb + b * r1p);
+        const float4 h23 = *reinterpret_cast<const float4*>(hb + b * r1p + 2);
+        const float4 uu = *reinterpret_cast<const float4*>(ub + b * T2);
+        const float2 u0 = make_float2(uu.x, uu.y), u1 = make_float2(uu.z, uu.w);
+        const float2 hh[4] = {make_float2(h01.x, h01.y), make_float2(h01.z, h01.w),
+                              make_float2(h23.x, h23.y), make_float2(h23.z, h23.w)};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          v[e][0] = cfma(hh[e], u0, v[e][0]);
+          v[e][1] = cfma(hh[e], u1, v[e][1]);
+        }
+      }
+      if (BF) {
+        // rows 4 a4 .. 4 a4 + 3 are half (a4 & 1) of 8-row chunk a4 / 2: one
+        // 16-byte vector of 8 bf16 (Re, Im of 4 rows) per column, hi and lo
+        uint4* bh = reinterpret_cast<uint4*>(Bs);
+        uint4* bl = bh + (size_t)(r1p / 8) * 2 * NWG;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          uint32_t h[8], l[8];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float re = c ? v[e][1].x : v[e][0].x, im = c ? v[e][1].y : v[e][0].y;
+            h[2 * e] = bf16_rne(re);
+            h[2 * e + 1] = bf16_rne(im);
+            l[2 * e] = bf16_rne(re - bf16_to_float(h[2 * e]));
+            l[2 * e + 1] = bf16_rne(im - bf16_to_float(h[2 * e + 1]));
+          }
+          const size_t at = (size_t)((a4 >> 1) * 2 + (a4 & 1)) * NWG + n + c;
+          bh[at] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                              h[6] | (h[7] << 16));
+          bl[at] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
+                              l[6] | (l[7] << 16));
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int a = 4 * a4 + e;
+          if (a < r1) {
+            *reinterpret_cast<float2*>(Bs + (2 * a) * NWG + n) =
+                make_float2(v[e][0].x, v[e][1].x);
+            *reinterpret_cast<float2*>(Bs + (2 * a + 1) * NWG + n) =
+                make_float2(v[e][0].y, v[e][1].y);
+          }
+        }
       }
     }
     __syncthreads();
 
-    // adjoint: publish the previous column's partial (its wave sums were
-    // written before the barrier above)
-    if (ADJ && tid == 0 && j > jb) {
-      const float2* rr = red + ((j - 1) & 1) * 4;
-      float2 sum = rr[0];
-      for (int w = 1; w < 4; ++w) { sum.x += rr[w].x; sum.y += rr[w].y; }
-      P.out[((int64_t)k * P.tiles + tile) * P.m + (j - 1)] = sum;
+    // adjoint: reduce the dots of the last DOT_RING tensors (their per-lane
+    // values were written before the barrier above)
+    if (ADJ && j - flushed == DOT_RING) {
+      flush_dots(dots, DOT_RING, jb, flushed, P.out, pbase);
+      flushed += DOT_RING;
+      __syncthreads();  // the ring slots are rewritten below
     }
 
     // C) stacked mode-1 product on MFMA
@@ -196,18 +312,41 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[b][i] = 0.f;
     }
-    const float* Arow = Ak + ((int64_t)t.arow * P.nbt + wm * NB) * 64 + lane;
-    const float* Brow = Bs + (lane >> 5) * NWG + wn * 32 + (lane & 31);
-    for (int a = 0; a < r1; ++a) {
-      const float bv = Brow[2 * a * NWG];
-      const float* ap = Arow + (int64_t)a * P.nbt * 64;
+    if (BF) {
+      // t.arow counts 8-row chunks; A chunk layout [chunk][blk][hi|lo][lane]
+      const uint4* Ach = P.apack_bf + P.apack_koff[k] +
+                         ((int64_t)t.arow * P.nbt + wm * NB) * 128 + lane;
+      const uint4* bh = reinterpret_cast<const uint4*>(Bs) + (lane >> 5) * NWG + wn * 32 +
+                        (lane & 31);
+      const uint4* bl = bh + (size_t)(r1p / 8) * 2 * NWG;
+      for (int c = 0; c < r1p / 8; ++c) {
+        const v8bf Bh = as_v8bf(bh[(size_t)c * 2 * NWG]);
+        const v8bf Bl = as_v8bf(bl[(size_t)c * 2 * NWG]);
+        const uint4* ap = Ach + (int64_t)c * P.nbt * 128;
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[b * 64], bv, acc[b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b) {
+          const v8bf Ah = as_v8bf(ap[b * 128]);
+          const v8bf Al = as_v8bf(ap[b * 128 + 64]);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[b], 0, 0, 0);
+        }
+      }
+    } else {
+      const float* Arow = P.apack + P.apack_koff[k] + ((int64_t)t.arow * P.nbt + wm * NB) * 64 +
+                          lane;
+      const float* Brow = Bs + (lane >> 5) * NWG + wn * 32 + (lane & 31);
+      for (int a = 0; a < r1; ++a) {
+        const float bv = Brow[2 * a * NWG];
+        const float* ap = Arow + (int64_t)a * P.nbt * 64;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[b * 64], bv, acc[b], 0, 0, 0);
+      }
     }
 
     if (ADJ) {
-      // conjugated dot product of the Z^{kj} tile with the y tile
+      // conjugated dot product of the Z^{kj} tile with the y tile, per lane
       float dr = 0.f, di = 0.f;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
@@ -220,23 +359,13 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
           di = fmaf(tr, yi, di);
           di = fmaf(-ti, yr, di);
         }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        dr += __shfl_xor(dr, off);
-        di += __shfl_xor(di, off);
-      }
-      if (lane == 0) red[(j & 1) * 4 + wave] = make_float2(dr, di);
+      dots[((j - jb) % DOT_RING) * 256 + wave * 64 + lane] = make_float2(dr, di);
     }
   }
 
   if (ADJ) {
     __syncthreads();
-    if (tid == 0 && je > jb) {
-      const float2* rr = red + ((je - 1) & 1) * 4;
-      float2 sum = rr[0];
-      for (int w = 1; w < 4; ++w) { sum.x += rr[w].x; sum.y += rr[w].y; }
-      P.out[((int64_t)k * P.tiles + tile) * P.m + (je - 1)] = sum;
-    }
+    if (je > flushed) flush_dots(dots, je - flushed, jb, flushed, P.out, pbase);
     return;
   }
 
@@ -275,27 +404,52 @@ __global__ void sum_partials_kernel(const float2* __restrict__ ws, int split, in
   y[i] = s;
 }
 
-__global__ void reduce_adjoint_kernel(const float2* __restrict__ partial, int64_t rows,
-                                      int64_t m, float2* __restrict__ x) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m) return;
+// x[j] = sum over r < rows of partial[r * m + j], in a fixed order: each of
+// the 8 row groups of a block sums its strided rows in sequence (FP64), then
+// the groups are added in index order.
+__global__ __launch_bounds__(256) void reduce_adjoint_kernel(const float2* __restrict__ partial,
+                                                             int64_t rows, int64_t m,
+                                                             float2* __restrict__ x) {
+  __shared__ double2 red[8][32];
+  const int jl = threadIdx.x % 32, g = threadIdx.x / 32;
+  const int64_t j = (int64_t)blockIdx.x * 32 + jl;
   double sr = 0.0, si = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const float2 v = partial[r * m + j];
-    sr += v.x;
-    si += v.y;
+  if (j < m) {
+    int64_t r = g;
+    for (; r + 24 < rows; r += 32) {  // four independent loads in flight
+      const float2 v0 = partial[r * m + j], v1 = partial[(r + 8) * m + j];
+      const float2 v2 = partial[(r + 16) * m + j], v3 = partial[(r + 24) * m + j];
+      sr += v0.x; si += v0.y;
+      sr += v1.x; si += v1.y;
+      sr += v2.x; si += v2.y;
+      sr += v3.x; si += v3.y;
+    }
+    for (; r < rows; r += 8) {
+      const float2 v = partial[r * m + j];
+      sr += v.x;
+      si += v.y;
+    }
   }
-  x[j] = make_float2((float)sr, (float)si);
+  red[g][jl] = make_double2(sr, si);
+  __syncthreads();
+  if (g == 0 && j < m) {
+    double2 t = red[0][jl];
+    for (int q = 1; q < 8; ++q) {
+      t.x += red[q][jl].x;
+      t.y += red[q][jl].y;
+    }
+    x[j] = make_float2((float)t.x, (float)t.y);
+  }
 }
 
 typedef void (*fused_fn)(KParams);
 
-template <bool ADJ>
+template <bool ADJ, bool BF>
 static fused_fn pick(int nb, int wn) {
-#define TV_CASE(NB)                                        \
-  case NB:                                                 \
-    return wn == 4 ? fused_f32<NB, 4, ADJ>                 \
-                   : (wn == 2 ? fused_f32<NB, 2, ADJ> : fused_f32<NB, 1, ADJ>);
+#define TV_CASE(NB)                                                          \
+  case NB:                                                                   \
+    return wn == 4 ? fused_f32<NB, 4, ADJ, BF>                               \
+                   : (wn == 2 ? fused_f32<NB, 2, ADJ, BF> : fused_f32<NB, 1, ADJ, BF>);
   switch (nb) {
     TV_CASE(1) TV_CASE(2) TV_CASE(3) TV_CASE(4)
     TV_CASE(5) TV_CASE(6) TV_CASE(7) TV_CASE(8)
@@ -307,13 +461,14 @@ static fused_fn pick(int nb, int wn) {
 static tv_status launch_fused(const tv_plan_s* p, bool adj, const float2* vec, float2* out,
                               int split, const int32_t* d_split, int64_t out_stride,
                               hipStream_t st) {
-  const Tiling& T = p->tiling;
+  const Tiling& T = adj ? p->tiling_a : p->tiling;
   KParams P;
   P.meta = p->d_meta;
   P.cores = p->d_cores;
   P.u2t = p->d_u2t;
   P.u3t = p->d_u3t;
   P.apack = p->d_apack;
+  P.apack_bf = p->d_apack_bf;
   P.apack_koff = p->d_apack_koff;
   P.split = d_split;
   P.vec = vec;
@@ -335,7 +490,9 @@ static tv_status launch_fused(const tv_plan_s* p, bool adj, const float2* vec, f
   P.r1max = p->max_r[0];
   P.r2max = p->max_r[1];
   P.vec4 = (p->grid.n1 % 2 == 0) && ((uintptr_t)out % 16 == 0) && (out_stride % 2 == 0);
-  fused_fn fn = adj ? pick<true>(T.nb, T.wn) : pick<false>(T.nb, T.wn);
+  const bool bf = p->precision == TV_PREC_BF16X3;
+  fused_fn fn = adj ? (bf ? pick<true, true>(T.nb, T.wn) : pick<true, false>(T.nb, T.wn))
+                    : (bf ? pick<false, true>(T.nb, T.wn) : pick<false, false>(T.nb, T.wn));
   if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no kernel instance for this tiling");
   const size_t lds = fused_lds_bytes(T.t2, T.t3, P.r1max, P.r2max, T.nwg);
   if (lds > 160 * 1024)
@@ -371,7 +528,7 @@ tv_status launch_sum_partials(const float2* ws, int split, int64_t n, float2* y,
 
 tv_status launch_reduce_adjoint(const float2* partial, int q, int64_t tiles, int64_t m,
                                 float2* x, hipStream_t st) {
-  const int64_t blocks = (m + 255) / 256;
+  const int64_t blocks = (m + 31) / 32;
   hipLaunchKernelGGL(reduce_adjoint_kernel, dim3((unsigned)blocks), dim3(256), 0, st, partial,
                      (int64_t)q * tiles, m, x);
   hipError_t e = hipGetLastError();

@@ -83,6 +83,15 @@ _tv_compress_begin = _sig("tv_compress_begin",
 _tv_compress_append = _sig("tv_compress_append", [c_vp, c_vp, c_i64, c_vp])
 _tv_plan_finalize = _sig("tv_plan_finalize", [c_vp, c_vp])
 _tv_compress_discarded = _sig("tv_compress_discarded", [c_vp, _dp])
+_tv_autotune = _sig("tv_autotune", [c_vp, c_i32, ctypes.c_char_p, c_vp])
+_tv_batch_create = _sig("tv_batch_create", [c_i32, ctypes.POINTER(c_vp), c_i32,
+                                            _ip, ctypes.POINTER(c_vp)])
+_tv_batch_workspace_bytes = _sig("tv_batch_workspace_bytes",
+                                 [c_vp, ctypes.POINTER(c_sz)])
+_tv_batch_run = _sig("tv_batch_run", [c_vp, ctypes.POINTER(c_vp),
+                                      ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
+                                      ctypes.POINTER(c_i64), c_vp, c_sz, c_vp])
+_tv_batch_destroy = _sig("tv_batch_destroy", [c_vp])
 _tv_status_string = _sig("tv_status_string", [ctypes.c_int], ctypes.c_char_p)
 _tv_last_error = _sig("tv_last_error", [], ctypes.c_char_p)
 
@@ -90,7 +99,9 @@ EXPORTED = ("tv_plan_from_factors", "tv_plan_destroy", "tv_plan_info",
             "tv_plan_export_factors", "tv_workspace_bytes", "tv_matvec",
             "tv_rmatvec", "tv_dipole_columns", "tv_compress_begin",
             "tv_compress_append", "tv_plan_finalize", "tv_compress_discarded",
-            "tv_status_string", "tv_last_error")
+            "tv_autotune", "tv_batch_create", "tv_batch_workspace_bytes", "tv_batch_run",
+            "tv_batch_destroy", "tv_status_string", "tv_last_error")
+TV_BATCH_MAX_PLANS = 32
 
 
 def _check(status: int, where: str):
@@ -211,3 +222,37 @@ def tv_compress_discarded(plan) -> np.ndarray:
     out = np.zeros((info.grid.q * info.grid.m, 3), np.float64)
     _check(_tv_compress_discarded(plan, _dptr(out)), "tv_compress_discarded")
     return out
+
+
+def tv_batch_create(plans, op: int, nrhs) -> int:
+    n = len(plans)
+    parr = (c_vp * n)(*plans)
+    r = np.ascontiguousarray(nrhs, dtype=np.int32)
+    h = c_vp()
+    _check(_tv_batch_create(n, parr, int(op), r.ctypes.data_as(_ip),
+                            ctypes.byref(h)), "tv_batch_create")
+    return h.value
+
+
+def tv_batch_workspace_bytes(batch: int) -> int:
+    n = c_sz()
+    _check(_tv_batch_workspace_bytes(batch, ctypes.byref(n)),
+           "tv_batch_workspace_bytes")
+    return n.value
+
+
+def tv_batch_run(batch, in_ptrs, ld_in, out_ptrs, ld_out, ws_ptr, ws_bytes,
+                 stream):
+    n = len(in_ptrs)
+    _check(_tv_batch_run(batch, (c_vp * n)(*in_ptrs), (c_i64 * n)(*ld_in),
+                         (c_vp * n)(*out_ptrs), (c_i64 * n)(*ld_out), ws_ptr,
+                         int(ws_bytes), stream), "tv_batch_run")
+
+
+def tv_batch_destroy(batch: int) -> None:
+    _check(_tv_batch_destroy(batch), "tv_batch_destroy")
+
+
+def tv_autotune(plan: int, op: int = 2, cache_path=None, stream=None) -> None:
+    cp = None if cache_path is None else str(cache_path).encode()
+    _check(_tv_autotune(plan, int(op), cp, stream), "tv_autotune")

@@ -117,6 +117,11 @@ class TuckerPlan:
                        self.m, ws.data_ptr(), ws.numel(), _stream())
         return X.reshape(-1) if vec else X.t()
 
+    def autotune(self, op: int = 2, cache_path: Optional[str] = None):
+        """Time the kernel configurations and keep the fastest (set-up call)."""
+        lib.tv_autotune(self.handle, op, cache_path, _stream())
+        self._ws.clear()
+
     def export_factors(self):
         return lib.tv_plan_export_factors(self.handle)
 

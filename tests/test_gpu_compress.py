@@ -130,3 +130,22 @@ def test_c2_sampled_against_uncompressed(gpu_lib, c2_lib):
         E = fields.point_field(pts, wl.pos[j], wl.ori[j], wl.k0)
         ref += x[j] * E[np.arange(len(rows)), k]
     assert np.linalg.norm(got[rows] - ref) <= 10 * wl.tol * np.linalg.norm(ref)
+
+
+def test_long_modes_use_leading_eigenpairs(gpu_lib):
+    """Modes longer than 64 take the leading eigenpairs from subspace
+    iteration; ranks and reconstructions must match the oracle's SVD."""
+    import dataclasses
+    wl = workloads.make("c1")
+    wl = dataclasses.replace(wl, grid=workloads.Grid(80, 72, 40, 0.004),
+                             pos=wl.pos[::8] * 2.2, ori=wl.ori[::8])
+    assert wl.min_distance() > 2 * wl.grid.h
+    P = _compress(wl, chunk=3)
+    S = abi_to_struct(wl.grid.dims, wl.q, *P.export_factors())
+    So = om.compress_columns(wl)
+    assert np.max(np.abs(S.ranks() - So.ranks())) <= 1
+    for j in range(wl.m):
+        T = fields.column_tensors(wl, j)
+        for k in range(3):
+            err = np.linalg.norm(S.t[j][k].full() - T[k]) / np.linalg.norm(T[k])
+            assert err <= wl.tol * 1.05
