@@ -74,10 +74,19 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2",
+                    help="c1, c2 (default), c3, c5, or c4 for the batched path")
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16x3"))
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes --steps "
+                         "times (calibration of the HBM traffic counters)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=os.path.join(
+        os.environ.get("TMPDIR", "/tmp"), "tuckvsie_tune.json"),
+        help="autotuner cache (JSON); a cached entry skips the timing runs")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -91,14 +100,35 @@ def main(argv=None):
     from paper_2103_06393_amd import lib
     from paper_2103_06393_amd.ops import TuckerPlan
 
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": args.steps}), flush=True)
+        return 0
+    if args.workload == "c4":
+        return bench_batch(args)
+    prec = lib.TV_PREC_BF16X3 if args.precision == "bf16x3" else lib.TV_PREC_FP32
     wl = workloads.make(args.workload)
     log(f"[bench] workload {wl.name}: grid {wl.grid.dims}, q={wl.q}, m={wl.m}")
     t0 = time.perf_counter()
     plan = TuckerPlan.compress_dipoles(
         wl.grid.dims, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1,
-        wl.pos, wl.ori, wl.tol, wl.rank_min, wl.rank_cap or 0)
+        wl.pos, wl.ori, wl.tol, wl.rank_min, wl.rank_cap or 0, precision=prec)
     torch.cuda.synchronize()
     log(f"[bench] compressed on GPU in {time.perf_counter() - t0:.2f} s")
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        plan.autotune(2, args.tune_cache)
+        torch.cuda.synchronize()
+        log(f"[bench] autotuned in {time.perf_counter() - t0:.2f} s "
+            f"(workspace fwd {lib.tv_workspace_bytes(plan.handle, 0, 1)} B, "
+            f"adj {lib.tv_workspace_bytes(plan.handle, 1, 1)} B)")
     info = plan.info
     x_np = wl.x()[:, 0]
     y_np = wl.y()[:, 0]
@@ -150,16 +180,20 @@ def main(argv=None):
         f"({tf_a:.1f} TFLOP/s), wall {wall:.3f} s for {K} steps")
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
     ach = tf_a if dom == "adjoint" else tf_f
+    # the BF16 split executes 3 MFMA products per algorithmic one
+    peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
     out = {
         "metric": "compressed VSIE matvecs/s (Zx and Z^H y)",
         "value": value, "unit": "matvecs/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32" if prec == lib.TV_PREC_FP32 else "bf16x3 (f32 accumulate)",
+        "data": "synthetic",
         "config": {
             "workload": f"{wl.name}: {wl.grid.n1}x{wl.grid.n2}x{wl.grid.n3} grid, "
                         f"q={wl.q}, {wl.m} point currents, HOSVD tol {wl.tol:g}, "
-                        f"rank cap {wl.rank_cap}, complex64 vectors, FP32 MFMA",
+                        f"rank cap {wl.rank_cap}, complex64 vectors, "
+                        f"{'FP32' if prec == lib.TV_PREC_FP32 else 'BF16 hi/lo split'} MFMA",
             "grid": list(wl.grid.dims), "q": wl.q, "m": wl.m,
             "mean_rank": [round(v, 3) for v in info.mean_rank],
             "max_rank": list(info.max_rank), "sum_r1": int(info.sum_r1),
@@ -169,8 +203,8 @@ def main(argv=None):
         "tflops_fwd": tf_f, "tflops_adj": tf_a,
         "flops_fwd": info.flops_matvec, "flops_adj": info.flops_rmatvec,
         "roofline": {"kernel": f"fused_f32 ({dom})", "bound": "mfma",
-                     "achieved": ach, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-                     "frac": ach / PEAK_FP32_MFMA, "traffic": None},
+                     "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None},
     }
     if not args.no_cpu:
         cb, cols, y_ref, x_ref = cpu_baseline(wl, plan, x_np, y_np, args.cpu_budget)
@@ -185,6 +219,74 @@ def main(argv=None):
         log(f"[bench] oracle {cb['value']:.4f} matvecs/s on {cb['cores']} threads; "
             f"rel err fwd {out['rel_err_fwd']:.2e} adj {out['rel_err_adj']:.2e}")
     plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(args):
+    """Batched path: 16 coils on a 96x128x112 grid, 32 right-hand sides
+    each, one persistent launch per direction, captured into a graph."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    wls = workloads.make_batch("c4")
+    t0 = time.perf_counter()
+    plans = [TuckerPlan.compress_dipoles(w.grid.dims, w.grid.h, w.k0, 0, w.pos, w.ori,
+                                         w.tol, w.rank_min, w.rank_cap) for w in wls]
+    torch.cuda.synchronize()
+    log(f"[bench] compressed {sum(w.m for w in wls)} columns in {time.perf_counter() - t0:.1f} s")
+    p = 32
+    X = [torch.from_numpy(w.x(p).astype(np.complex64)).cuda().t().contiguous().t() for w in wls]
+    Y = [torch.from_numpy(w.y(p).astype(np.complex64)).cuda().t().contiguous().t() for w in wls]
+    Yo = [torch.empty((p, P.rows), dtype=torch.complex64, device="cuda").t() for P in plans]
+    Xo = [torch.empty((p, P.m), dtype=torch.complex64, device="cuda").t() for P in plans]
+    hs = [P.handle for P in plans]
+    bf = lib.tv_batch_create(hs, 0, [p] * len(plans))
+    ba = lib.tv_batch_create(hs, 1, [p] * len(plans))
+    ws = torch.empty(512, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    fa = ([x.data_ptr() for x in X], [x.stride(1) for x in X], [y.data_ptr() for y in Yo],
+          [y.stride(1) for y in Yo], ws.data_ptr(), 256)
+    aa = ([y.data_ptr() for y in Y], [y.stride(1) for y in Y], [x.data_ptr() for x in Xo],
+          [x.stride(1) for x in Xo], ws.data_ptr() + 256, 256)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        lib.tv_batch_run(bf, *fa, s.cuda_stream)
+        lib.tv_batch_run(ba, *aa, s.cuda_stream)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        lib.tv_batch_run(bf, *fa, s.cuda_stream)
+        lib.tv_batch_run(ba, *aa, s.cuda_stream)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    K = max(1, min(args.steps, 10))
+    e0.record()
+    for _ in range(K):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    nmv = 2 * p * len(plans)
+    fl = 0.0
+    for P in plans:
+        r = np.array(P.export_factors()[0], dtype=np.float64)
+        n1, n2, n3 = P.dims
+        nv = n1 * n2 * n3
+        dec = r[:, 0] * r[:, 1] * r[:, 2] * n2 + r[:, 0] * r[:, 2] * n2 * n3 + r[:, 0] * nv
+        fl += 2 * float(np.sum(8.0 * (dec + nv * p)))   # both directions
+    out = {"metric": "compressed VSIE matvecs/s (Zx and Z^H y), batched",
+           "value": nmv / (ms * 1e-3), "unit": "matvecs/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "c4: 16 coils (64..1024 point currents) on 96x128x112, "
+                                  "32 right-hand sides each, graph replay of both directions"},
+           "tflops": fl / (ms * 1e-3) / 1e12}
+    lib.tv_batch_destroy(bf)
+    lib.tv_batch_destroy(ba)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -22,7 +22,7 @@ namespace tv {
 tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
                       hipStream_t st);
 tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
-                        int64_t wstride, double2* V, hipStream_t st);
+                        int64_t wstride, double2* V, int64_t vstride, hipStream_t st);
 tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const double2* u1,
                       const double2* u2, const double2* u3, const int64_t* offs,
                       const int* ranks, int r1max, int r2max, double2* T1, double2* T2,
@@ -157,7 +157,8 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* s
     if ((s = ds.alloc(&dW, (size_t)T * L[d])) != TV_OK) return s;
     const double2* Sd = dS + (int64_t)d * T * mat;
     if (n <= 64) {
-      if ((s = launch_jacobi(Sd, T, n, mat, dW, n, dV, st)) != TV_OK) return s;
+      // eigenvectors are written compactly, n x n per matrix
+      if ((s = launch_jacobi(Sd, T, n, mat, dW, n, dV, (int64_t)n * n, st)) != TV_OK) return s;
     } else {
       double2* dWs;
       if ((s = ds.alloc(&dTr, (size_t)T)) != TV_OK) return s;

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
 __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ S, int n,
                                                      int64_t stride, double* __restrict__ W,
                                                      int64_t wstride, double2* __restrict__ Vout,
-                                                     int max_sweeps) {
+                                                     int64_t vstride, int max_sweeps) {
   extern __shared__ double2 jsm[];
   const int np = n + (n & 1);
   double2* A = jsm;              // n x n, row-major
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
     }
   }
   for (int i = tid; i < n; i += 256) W[mat * wstride + i] = A[i * n + i].x;
-  double2* Vm = Vout + mat * stride;
+  double2* Vm = Vout + mat * vstride;
   for (int e = tid; e < n * n; e += 256) Vm[e] = V[e];
 }
 
@@ -335,14 +335,19 @@ tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int n
   return last("gram_kernel");
 }
 
+// S: nmat input matrices n x n at stride `stride`; W: n eigenvalues per
+// matrix at stride wstride; V: n x n eigenvectors per matrix at stride
+// vstride (both output strides must leave room for a whole matrix).
 tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
-                        int64_t wstride, double2* V, hipStream_t st) {
+                        int64_t wstride, double2* V, int64_t vstride, hipStream_t st) {
+  if (n < 1 || n > 64 || stride < (int64_t)n * n || vstride < (int64_t)n * n || wstride < n)
+    return set_error(TV_ERR_INVALID_ARG, "jacobi: matrix larger than 64 or strides too small");
   const size_t lds = jacobi_lds_bytes(n);
   hipError_t e = hipFuncSetAttribute((const void*)jacobi_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(jacobi)");
   hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)nmat), dim3(256), lds, st, S, n, stride, W,
-                     wstride, V, 40);
+                     wstride, V, vstride, 40);
   return last("jacobi_kernel");
 }
 
@@ -575,7 +580,7 @@ tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, dou
   // Rayleigh-Ritz: T = Q^* (S Q), T = W diag(mu) W^*, U = Q W
   if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
   if ((s = launch_zgemm(1, l, l, n, Q, l, nl, Z, l, nl, T, l, ll, nmat, st)) != TV_OK) return s;
-  if ((s = launch_jacobi(T, nmat, l, ll, W, l, V, st)) != TV_OK) return s;
+  if ((s = launch_jacobi(T, nmat, l, ll, W, l, V, ll, st)) != TV_OK) return s;
   return launch_zgemm(0, n, l, l, Q, l, nl, V, l, ll, U, l, nl, nmat, st);
 }
 

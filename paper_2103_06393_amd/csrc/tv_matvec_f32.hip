@@ -333,15 +333,36 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
         }
       }
     } else {
+      // rows in groups of 4, the next group's A operand loaded while the
+      // current group's MFMAs run; rows past r1 use zero operands
       const float* Arow = P.apack + P.apack_koff[k] + ((int64_t)t.arow * P.nbt + wm * NB) * 64 +
                           lane;
       const float* Brow = Bs + (lane >> 5) * NWG + wn * 32 + (lane & 31);
-      for (int a = 0; a < r1; ++a) {
-        const float bv = Brow[2 * a * NWG];
-        const float* ap = Arow + (int64_t)a * P.nbt * 64;
+      const int64_t rstride = (int64_t)P.nbt * 64;
+      float an[4][NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ap[b * 64], bv, acc[b], 0, 0, 0);
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) an[e][b] = e < r1 ? Arow[e * rstride + b * 64] : 0.f;
+      for (int a0 = 0; a0 < r1; a0 += 4) {
+        float ac[4][NB], bc[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          bc[e] = a0 + e < r1 ? Brow[2 * (a0 + e) * NWG] : 0.f;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) ac[e][b] = an[e][b];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int a = a0 + 4 + e;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) an[e][b] = a < r1 ? Arow[a * rstride + b * 64] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[e][b], bc[e], acc[b], 0, 0, 0);
       }
     }
 
