@@ -38,9 +38,12 @@ struct BatchStatic {  // per plan, uploaded once
 
 struct BatchArgs {
   const BatchStatic* plans;
-  const int4* items;  // {plan, component, tile or chunk, rhs group}
+  const int4* items;  // forward {plan, component, tile, rhs group};
+                      // adjoint {plan, component * tsplit + slice, chunk, rhs group}
   int nitems;
   int* counter;
+  float2* partial;    // adjoint: one 32 x 32 block per item
+  int tsplit;         // adjoint: voxel-tile slices per (plan, component, chunk)
   int n1, n2, n3, n1p32, tiles2;
   int64_t nv;
   int r1max, r2max;
@@ -193,9 +196,10 @@ __global__ __launch_bounds__(256) void batch_fwd(BatchArgs A) {
   }
 }
 
-// Adjoint: item = (plan, component, chunk of 32 columns, right-hand-side
-// group of 32); the item sweeps every voxel tile of the grid, so its 32 x 32
-// outputs are complete when it ends (no cross-workgroup reduction).
+// Adjoint: item = (plan, component and slice of the voxel tiles, chunk of 32
+// columns, right-hand-side group of 32).  The item sweeps its slice of tiles
+// and stores its 32 x 32 share of W; batch_adj_reduce then sums the shares of
+// every component and slice in a fixed order (Algorithm 2 sums over k).
 template <int NCOL>
 __global__ __launch_bounds__(256) void batch_adj(BatchArgs A) {
   extern __shared__ float4 bsm4[];
@@ -211,7 +215,9 @@ __global__ __launch_bounds__(256) void batch_adj(BatchArgs A) {
     if (it >= A.nitems) break;
     const int4 I = A.items[it];
     const BatchStatic S = A.plans[I.x];
-    const int k = I.y;
+    const int k = I.y / A.tsplit, slice = I.y % A.tsplit;
+    const int tb0 = (int)((int64_t)tiles * slice / A.tsplit);
+    const int tb1 = (int)((int64_t)tiles * (slice + 1) / A.tsplit);
     const int64_t j0 = (int64_t)I.z * 32;
     const int jc = (int)min((int64_t)32, S.m - j0);
     const int rhs = I.w * 32 + (lane & 31);
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(256) void batch_adj(BatchArgs A) {
     v16f acc[2];
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.f;
-    for (int tile = 0; tile < tiles; ++tile) {
+    for (int tile = tb0; tile < tb1; ++tile) {
       const int i2_0 = (tile % A.tiles2) * NCOL, i3 = tile / A.tiles2;
       for (int e = 0; e < 8; ++e) {
         const int jj = wave * 8 + e;
@@ -257,9 +263,8 @@ __global__ __launch_bounds__(256) void batch_adj(BatchArgs A) {
       for (int i = 0; i < 16; ++i) red[((wave * 2 + mb) * 16 + i) * 64 + lane] = acc[mb][i];
     __syncthreads();
     if (wave == 0) {
-      float2* Xo = A.out[I.x];
-      const int64_t ldx = A.ld_out[I.x];
-      const int jj = lane & 31;
+      // this item's share of W (32 right-hand sides x 32 columns), [rl][jj]
+      float2* blk = A.partial + (int64_t)it * 1024;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         float wr = 0.f, wi = 0.f;
@@ -268,10 +273,34 @@ __global__ __launch_bounds__(256) void batch_adj(BatchArgs A) {
           wi += red[((w * 2 + 1) * 16 + i) * 64 + lane];
         }
         const int rl = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int r = I.w * 32 + rl;
-        if (jj < jc && r < A.nrhs[I.x]) Xo[(j0 + jj) + ldx * r] = make_float2(wr, wi);
+        blk[rl * 32 + (lane & 31)] = make_float2(wr, wi);
       }
     }
+  }
+}
+
+// Adjoint epilogue: X_c[j0 + jj][32 g + rl] = sum of the partial blocks of
+// all components and tile slices of (plan, chunk, group), in list order.
+// One workgroup per output block; red_list[b*nper .. (b+1)*nper) are item
+// indices, red_out[b] = {plan, chunk, group}.
+__global__ __launch_bounds__(256) void batch_adj_reduce(BatchArgs A, const int* red_list,
+                                                        const int4* red_out, int nper) {
+  const int4 O = red_out[blockIdx.x];
+  const int* lst = red_list + (int64_t)blockIdx.x * nper;
+  const int64_t m = A.plans[O.x].m;
+  const int64_t j0 = (int64_t)O.y * 32;
+  float2* Xo = A.out[O.x];
+  const int64_t ldx = A.ld_out[O.x];
+  for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int rl = e / 32, jj = e % 32;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int i = 0; i < nper; ++i) {
+      const float2 v = A.partial[(int64_t)lst[i] * 1024 + e];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    const int r = O.z * 32 + rl;
+    if (j0 + jj < m && r < A.nrhs[O.x]) Xo[(j0 + jj) + ldx * r] = acc;
   }
 }
 
@@ -330,6 +359,11 @@ struct tv_batch_s {
   BatchStatic* d_plans = nullptr;
   int4* d_items = nullptr;
   batch_fn fn = nullptr;
+  // adjoint: voxel-tile slices per item and the fixed-order reduction lists
+  int tsplit = 1;
+  int nred = 0, nper = 0;
+  int* d_red_list = nullptr;
+  int4* d_red_out = nullptr;
 };
 
 extern "C" {
@@ -384,18 +418,42 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     delete b;
     return set_error(TV_ERR_NOT_SUPPORTED, "no batched kernel for these sizes and ranks");
   }
-  // work items, longest first (most tensors per item)
+  // work items, longest first (most tensors per item); the adjoint splits
+  // the voxel tiles of each (plan, component, chunk) into tsplit slices so
+  // that there are enough items to fill the device
   std::vector<int> order(nplans);
   for (int c = 0; c < nplans; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->m[x] > b->m[y]; });
+  const int tiles = b->tiles2 * g.n3;
+  if (op == 1) {
+    int64_t base = 0;
+    for (int c = 0; c < nplans; ++c) base += (int64_t)g.q * ((b->m[c] + 31) / 32) * ((nrhs[c] + 31) / 32);
+    b->tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (2048 + base - 1) / base));
+  }
   std::vector<int4> items;
+  std::vector<int> red_list;
+  std::vector<int4> red_out;
   for (int c : order) {
     const int groups = (nrhs[c] + 31) / 32;
-    const int64_t units = op == 0 ? (int64_t)b->tiles2 * g.n3 : (b->m[c] + 31) / 32;
-    for (int k = 0; k < g.q; ++k)
-      for (int64_t u = 0; u < units; ++u)
-        for (int gr = 0; gr < groups; ++gr) items.push_back(make_int4(c, k, (int)u, gr));
+    if (op == 0) {
+      for (int k = 0; k < g.q; ++k)
+        for (int64_t u = 0; u < (int64_t)tiles; ++u)
+          for (int gr = 0; gr < groups; ++gr) items.push_back(make_int4(c, k, (int)u, gr));
+    } else {
+      const int64_t chunks = (b->m[c] + 31) / 32;
+      for (int64_t u = 0; u < chunks; ++u)
+        for (int gr = 0; gr < groups; ++gr) {
+          red_out.push_back(make_int4(c, (int)u, gr, 0));
+          for (int k = 0; k < g.q; ++k)
+            for (int sl = 0; sl < b->tsplit; ++sl) {
+              red_list.push_back((int)items.size());
+              items.push_back(make_int4(c, k * b->tsplit + sl, (int)u, gr));
+            }
+        }
+    }
   }
+  b->nred = (int)red_out.size();
+  b->nper = g.q * b->tsplit;
   if (items.size() > (size_t)INT32_MAX) {
     delete b;
     return set_error(TV_ERR_NOT_SUPPORTED, "too many work items");
@@ -411,6 +469,16 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     e = hipMemcpy(b->d_plans, st.data(), st.size() * sizeof(BatchStatic), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+  if (e == hipSuccess && op == 1) {
+    e = hipMalloc((void**)&b->d_red_list, red_list.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_red_out, red_out.size() * sizeof(int4));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_red_list, red_list.data(), red_list.size() * sizeof(int),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_red_out, red_out.data(), red_out.size() * sizeof(int4),
+                    hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)b->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)b->lds);
@@ -422,6 +490,8 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   if (e != hipSuccess) {
     hipFree(b->d_plans);
     hipFree(b->d_items);
+    hipFree(b->d_red_list);
+    hipFree(b->d_red_out);
     delete b;
     return hip_error(e, "tv_batch_create");
   }
@@ -433,7 +503,8 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
 tv_status tv_batch_workspace_bytes(tv_batch b, size_t* bytes) {
   clear_error();
   if (!b || !bytes) return set_error(TV_ERR_INVALID_ARG, "batch and bytes must be non-NULL");
-  *bytes = 256;  // the work-queue counter
+  // the work-queue counter, then (adjoint) one 32 x 32 complex64 block per item
+  *bytes = 256 + (b->op == 1 ? (size_t)b->nitems * 1024 * 8 : 0);
   return TV_OK;
 }
 
@@ -442,13 +513,17 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   clear_error();
   if (!b || !in || !ld_in || !out || !ld_out)
     return set_error(TV_ERR_INVALID_ARG, "NULL argument");
-  if (!ws || ws_bytes < 256 || (uintptr_t)ws % 16)
-    return set_error(TV_ERR_WORKSPACE, "a 256-byte, 16-byte aligned workspace is needed");
+  size_t need = 0;
+  tv_batch_workspace_bytes(b, &need);
+  if (!ws || ws_bytes < need || (uintptr_t)ws % 16)
+    return set_error(TV_ERR_WORKSPACE, "workspace missing, too small or not 16-byte aligned");
   BatchArgs A;
   A.plans = b->d_plans;
   A.items = b->d_items;
   A.nitems = b->nitems;
   A.counter = (int*)ws;
+  A.partial = (float2*)((char*)ws + 256);
+  A.tsplit = b->tsplit;
   A.n1 = b->grid.n1;
   A.n2 = b->grid.n2;
   A.n3 = b->grid.n3;
@@ -477,7 +552,14 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   if (e != hipSuccess) return hip_error(e, "reset_counter launch");
   hipLaunchKernelGGL(b->fn, dim3((unsigned)b->grid_blocks), dim3(256), b->lds, st, A);
   e = hipGetLastError();
-  return e == hipSuccess ? TV_OK : hip_error(e, "batched kernel launch");
+  if (e != hipSuccess) return hip_error(e, "batched kernel launch");
+  if (b->op == 1) {
+    hipLaunchKernelGGL(batch_adj_reduce, dim3((unsigned)b->nred), dim3(256), 0, st, A,
+                       b->d_red_list, b->d_red_out, b->nper);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "batched reduction launch");
+  }
+  return TV_OK;
 }
 
 tv_status tv_batch_destroy(tv_batch b) {
@@ -485,6 +567,8 @@ tv_status tv_batch_destroy(tv_batch b) {
   if (!b) return TV_OK;
   hipFree(b->d_plans);
   hipFree(b->d_items);
+  hipFree(b->d_red_list);
+  hipFree(b->d_red_out);
   delete b;
   return TV_OK;
 }

@@ -24,6 +24,12 @@ def c4s():
     return wls, structs, plans
 
 
+def _ld(t):
+    """Leading dimension of a column-major (rows x cols) tensor; a single
+    column reports stride 1, its leading dimension is the row count."""
+    return t.shape[0] if t.shape[1] == 1 else t.stride(1)
+
+
 def _run(plans, op, inputs, nrhs):
     import torch
     from paper_2103_06393_amd import lib
@@ -35,8 +41,8 @@ def _run(plans, op, inputs, nrhs):
                 for p, r, n in zip(plans, rows, nrhs)]
         ws = torch.empty(lib.tv_batch_workspace_bytes(b), dtype=torch.uint8, device="cuda")
         ins = [x.t().contiguous().t() for x in inputs]
-        lib.tv_batch_run(b, [x.data_ptr() for x in ins], [x.stride(1) for x in ins],
-                         [y.data_ptr() for y in outs], [y.stride(1) for y in outs],
+        lib.tv_batch_run(b, [x.data_ptr() for x in ins], [_ld(x) for x in ins],
+                         [y.data_ptr() for y in outs], [_ld(y) for y in outs],
                          ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         return [y.cpu().numpy() for y in outs]
@@ -68,8 +74,8 @@ def test_batch_graph_replay(gpu_lib, c4s):
     outs = [torch.zeros((8, p.rows), dtype=torch.complex64, device="cuda").t() for p in plans]
     b = lib.tv_batch_create([p.handle for p in plans], 0, nrhs)
     ws = torch.empty(lib.tv_batch_workspace_bytes(b), dtype=torch.uint8, device="cuda")
-    args = ([x.data_ptr() for x in X], [x.stride(1) for x in X],
-            [y.data_ptr() for y in outs], [y.stride(1) for y in outs], ws.data_ptr(), ws.numel())
+    args = ([x.data_ptr() for x in X], [_ld(x) for x in X],
+            [y.data_ptr() for y in outs], [_ld(y) for y in outs], ws.data_ptr(), ws.numel())
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         lib.tv_batch_run(b, *args, s.cuda_stream)
