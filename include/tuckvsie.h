@@ -164,7 +164,9 @@ tv_status tv_autotune(tv_plan plan, int32_t op, const char* cache_path,
  *   of field component c times phi_l, phi_0 = 1, phi_l = (x_l - centre_l)/h,
  *   by the 2x2x2 Gauss-Legendre rule.
  * out: device complex128, ncols*q*nv values, column j's tensor k at
- *   out + 2*((j*q + k)*nv + v), v = i1 + n1*(i2 + n2*i3).  Asynchronous.
+ *   out + 2*((j*q + k)*nv + v), v = i1 + n1*(i2 + n2*i3).  Runs on
+ *   `stream` and synchronises it before returning (the inputs are staged
+ *   through a temporary device buffer that is freed on return).
  * ---------------------------------------------------------------------- */
 tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h,
                             double k0, int32_t basis, int64_t ncols,

@@ -22,7 +22,6 @@ tv_status hip_error(hipError_t e, const char* what) {
                    std::string(what) + ": " + hipGetErrorString(e));
 }
 
-size_t fused_lds_bytes(int t2, int t3, int r1max, int r2max, int nwg);
 
 // bf16 bits of x, round to nearest even (via FP32; finite inputs)
 static uint32_t bf16_bits(double x) {
@@ -43,10 +42,17 @@ static double bf16_value(uint32_t h) {
 // nwg = 32*wn columns (i2, i3) of the mode-1 unfolding, t2 values of i2 by
 // t3 = nwg / t2 values of i3.  t2 = 0 picks the shape covering the fewest
 // columns beyond the grid.
-tv_status make_tiling(const tv_grid& g, int t2req, Tiling* T) {
+int nb_cap(const tv_plan_s* /*p*/, int op) {
+  // the adjoint keeps the y tile in registers next to the accumulators: at
+  // most 2 row blocks per wave keep two workgroups per CU resident
+  return op == 1 ? 2 : 8;
+}
+
+tv_status make_tiling(const tv_grid& g, int t2req, int nbcap, Tiling* T) {
   const int nbt0 = (g.n1 + 15) / 16;
   int wm = 1;
   while ((nbt0 + wm - 1) / wm > 8) wm *= 2;
+  while ((nbt0 + wm - 1) / wm > nbcap && wm < 4) wm *= 2;
   if (wm > 4) return set_error(TV_ERR_NOT_SUPPORTED, "n1 > 512 is not built");
   T->wm = wm;
   T->nb = (nbt0 + wm - 1) / wm;
@@ -78,7 +84,6 @@ tv_status make_tiling(const tv_grid& g, int t2req, Tiling* T) {
   return TV_OK;
 }
 
-static tv_status choose_tiling(const tv_grid& g, Tiling* T) { return make_tiling(g, 0, T); }
 
 static tv_status validate_grid(const tv_grid* g) {
   if (!g) return set_error(TV_ERR_INVALID_ARG, "grid is NULL");
@@ -140,6 +145,8 @@ static tv_status compute_offsets(tv_plan_s* p) {
   p->u3_off.assign(K + 1, 0);
   const int dims[3] = {g.n1, g.n2, g.n3};
   for (int d = 0; d < 3; ++d) p->max_r[d] = 0;
+  p->max_r12 = 0;
+  p->max_core = 0;
   p->sum_r1 = 0;
   for (int64_t t = 0; t < K; ++t) {
     const int32_t* r = &p->ranks[3 * t];
@@ -153,6 +160,8 @@ static tv_status compute_offsets(tv_plan_s* p) {
       p->max_r[d] = std::max(p->max_r[d], (int)r[d]);
     }
     p->sum_r1 += r[0];
+    p->max_r12 = std::max(p->max_r12, (int)(r[0] * r[1]));
+    p->max_core = std::max(p->max_core, (int64_t)r[0] * r[1] * r[2]);
     p->g_off[t + 1] = p->g_off[t] + (int64_t)r[0] * r[1] * r[2];
     p->u1_off[t + 1] = p->u1_off[t] + (int64_t)g.n1 * r[0];
     p->u2_off[t + 1] = p->u2_off[t] + (int64_t)g.n2 * r[1];
@@ -208,12 +217,16 @@ tv_status set_split(tv_plan_s* p, int op, int S) {
 static tv_status pack_and_upload(tv_plan_s* p) {
   const tv_grid& g = p->grid;
   const int64_t K = (int64_t)g.q * g.m;
-  tv_status st = choose_tiling(g, &p->tiling);
+  tv_status st = make_tiling(g, 0, nb_cap(p, 0), &p->tiling);
   if (st != TV_OK) return st;
-  p->tiling_a = p->tiling;
-  const Tiling& T = p->tiling;
-  if (fused_lds_bytes(T.t2, T.t3, p->max_r[0], p->max_r[1], T.nwg) > 160 * 1024)
+  if ((st = make_tiling(g, 0, nb_cap(p, 1), &p->tiling_a)) != TV_OK) return st;
+  if (fused_lds_bytes(p, p->tiling, false) > 160 * 1024 ||
+      fused_lds_bytes(p, p->tiling_a, true) > 160 * 1024)
     return set_error(TV_ERR_NOT_SUPPORTED, "ranks too large for the LDS tile");
+  // the stacked A operand is packed for the larger row-block count of the
+  // two kernels; blocks past n1 are zero rows
+  const int nbt = std::max(p->tiling.nbt, p->tiling_a.nbt);
+  p->nbt_pack = nbt;
 
   // per-tensor metadata, component-major [k][j]
   const bool bf = p->precision == TV_PREC_BF16X3;
@@ -281,15 +294,15 @@ static tv_status pack_and_upload(tv_plan_s* p) {
   std::vector<uint4> apack_bf;
   if (!bf) {
     for (int k = 0; k < g.q; ++k)
-      p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * T.nbt * 64;
+      p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * nbt * 64;
     apack.assign((size_t)p->apack_koff[g.q], 0.f);
     for (int64_t j = 0; j < g.m; ++j)
       for (int k = 0; k < g.q; ++k) {
         const int64_t t = k + (int64_t)g.q * j;
         const TensorMeta& M = meta[(size_t)k * g.m + j];
         for (int a = 0; a < M.r1; ++a) {
-          float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * T.nbt) * 64];
-          for (int blk = 0; blk < T.nbt; ++blk)
+          float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * nbt) * 64];
+          for (int blk = 0; blk < nbt; ++blk)
             for (int lane = 0; lane < 64; ++lane) {
               const int mrow = 32 * blk + (lane & 31);
               row[blk * 64 + lane] = (float)emb(t, mrow >> 1, mrow & 1, a, lane >> 5);
@@ -298,14 +311,14 @@ static tv_status pack_and_upload(tv_plan_s* p) {
       }
   } else {
     for (int k = 0; k < g.q; ++k)
-      p->apack_koff[k + 1] = p->apack_koff[k] + chunks_k[k] * T.nbt * 128;
+      p->apack_koff[k + 1] = p->apack_koff[k] + chunks_k[k] * nbt * 128;
     apack_bf.assign((size_t)p->apack_koff[g.q], make_uint4(0, 0, 0, 0));
     for (int64_t j = 0; j < g.m; ++j)
       for (int k = 0; k < g.q; ++k) {
         const int64_t t = k + (int64_t)g.q * j;
         const TensorMeta& M = meta[(size_t)k * g.m + j];
         for (int c = 0; c < (M.r1 + 7) / 8; ++c)
-          for (int blk = 0; blk < T.nbt; ++blk)
+          for (int blk = 0; blk < nbt; ++blk)
             for (int lane = 0; lane < 64; ++lane) {
               const int mrow = 32 * blk + (lane & 31);
               uint32_t hi[8], lo[8];
@@ -316,7 +329,7 @@ static tv_status pack_and_upload(tv_plan_s* p) {
                 lo[i] = bf16_bits(v - bf16_value(hi[i]));
               }
               uint4* dst = &apack_bf[p->apack_koff[k] +
-                                     (((int64_t)(M.arow + c) * T.nbt + blk) * 2) * 64 + lane];
+                                     (((int64_t)(M.arow + c) * nbt + blk) * 2) * 64 + lane];
               dst[0] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16),
                                   hi[4] | (hi[5] << 16), hi[6] | (hi[7] << 16));
               dst[64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
@@ -326,9 +339,9 @@ static tv_status pack_and_upload(tv_plan_s* p) {
   }
 
   // column splits: spread the work over enough workgroups to fill the chip
-  const int64_t base = (int64_t)g.q * T.tiles;
-  int sf = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + base - 1) / base));
-  int sa = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + base - 1) / base));
+  const int64_t base_f = (int64_t)g.q * p->tiling.tiles, base_a = (int64_t)g.q * p->tiling_a.tiles;
+  int sf = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + base_f - 1) / base_f));
+  int sa = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + base_a - 1) / base_a));
   sf = (int)std::max<int64_t>(1, std::min<int64_t>(sf, g.m));
   sa = (int)std::max<int64_t>(1, std::min<int64_t>(sa, g.m));
   p->split_f = sf;

@@ -13,7 +13,6 @@
 #include "tv_internal.h"
 
 namespace tv {
-size_t fused_lds_bytes(int t2, int t3, int r1max, int r2max, int nwg);
 
 static std::string plan_key(const tv_plan_s* p, int op) {
   hipDeviceProp_t prop;
@@ -27,7 +26,7 @@ static std::string plan_key(const tv_plan_s* p, int op) {
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k3|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -79,9 +78,9 @@ static void write_cache(const char* path, const std::map<std::string, std::pair<
 
 static tv_status apply_config(tv_plan_s* p, int op, int t2, int split) {
   Tiling T;
-  tv_status s = make_tiling(p->grid, t2, &T);
+  tv_status s = make_tiling(p->grid, t2, nb_cap(p, op), &T);
   if (s != TV_OK) return s;
-  if (fused_lds_bytes(T.t2, T.t3, p->max_r[0], p->max_r[1], T.nwg) > 160 * 1024)
+  if (fused_lds_bytes(p, T, op == 1) > 160 * 1024)
     return set_error(TV_ERR_NOT_SUPPORTED, "tile too large for LDS");
   if ((s = set_split(p, op, split)) != TV_OK) return s;
   if (op == 0)
@@ -113,7 +112,7 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
       continue;
     // candidates
     Tiling T0;
-    tv_status s = make_tiling(g, 0, &T0);
+    tv_status s = make_tiling(g, 0, nb_cap(p, o), &T0);
     if (s != TV_OK) return s;
     std::vector<int> t2s, splits;
     for (int t2 = T0.nwg; t2 >= 2; t2 /= 2) t2s.push_back(t2);
@@ -126,7 +125,7 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     size_t wsb = 16;
     for (int t2 : t2s) {
       Tiling T;
-      if (make_tiling(g, t2, &T) != TV_OK) continue;
+      if (make_tiling(g, t2, nb_cap(p, o), &T) != TV_OK) continue;
       const size_t b = o == 0 ? (size_t)8 * splits.back() * rows : (size_t)8 * g.q * T.tiles * g.m;
       wsb = std::max(wsb, b);
     }

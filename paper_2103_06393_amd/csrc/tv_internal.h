@@ -66,10 +66,14 @@ struct tv_plan_s {
   std::vector<int64_t> apack_koff;
   std::vector<int64_t> sum_r1_k;   // rows of A_k per component
   int split_f = 1, split_a = 1;    // column splits of the forward / adjoint
+  bool kernel_ws[2] = {true, true};  // warp-specialised kernel (when the tile allows)
   int32_t* d_split_f = nullptr;    // [q][split+1] first column per split
   int32_t* d_split_a = nullptr;
   size_t device_bytes = 0;
   int max_r[3] = {0, 0, 0};
+  int nbt_pack = 0;      // 32-row blocks per stacked A row in the packed layout
+  int max_r12 = 0;       // largest r1 r2
+  int64_t max_core = 0;  // largest r1 r2 r3
   int64_t sum_r1 = 0;
 };
 
@@ -88,8 +92,18 @@ tv_status launch_sum_partials(const float2* ws, int split, int64_t n, float2* y,
                               hipStream_t st);
 tv_status launch_reduce_adjoint(const float2* partial, int q, int64_t tiles,
                                 int64_t m, float2* x, hipStream_t st);
+// warp-specialised kernels (tv_fused_ws.hip)
+bool ws_supported(const tv_plan_s* p, const Tiling& T, bool adj);
+tv_status launch_fused_ws(const tv_plan_s* p, bool adj, const float2* vec, float2* out,
+                          int split, const int32_t* d_split, int64_t out_stride,
+                          hipStream_t st);
+// dynamic LDS of the fused kernels for a plan and tiling
+size_t fused_lds_bytes(const tv_plan_s* p, const Tiling& T, bool adj);
 // tiling with a given i2 extent t2 (0: the one covering the fewest columns)
-tv_status make_tiling(const tv_grid& g, int t2, Tiling* T);
+// (at most nbcap MFMA row blocks per wave)
+tv_status make_tiling(const tv_grid& g, int t2, int nbcap, Tiling* T);
+// row-block cap of a plan's kernel for op 0 (forward) / 1 (adjoint)
+int nb_cap(const tv_plan_s* p, int op);
 // (re)build and upload the column split table of one direction
 tv_status set_split(tv_plan_s* p, int op, int S);
 }  // namespace tv

@@ -6,13 +6,16 @@
 // unfolded along mode 1 (r1 x n2 n3), from eq. (6)/(7).  Each workgroup owns
 // all n1 rows of a tile of t2 x t3 columns (i2, i3) and a contiguous range of
 // columns j; per tensor it
+//   S) stages the tile's U2 and U3 rows and the core into LDS as one batch of
+//      independent loads, issued while the previous tensor's MFMAs run,
 //   A) contracts the core with the tile's U3 rows (mode 3, eq. 7), scaling by
 //      x_j: H[t3][a][b] = x_j sum_c G[a,b,c] U3[i3,c]            -> LDS
 //   B) applies U2 per column (mode 2): B[a][(i2,i3)] = sum_b H U2[i2,b] -> LDS
 //   C) accumulates the mode-1 product on v_mfma_f32_32x32x2f32 with the
 //      complex product in real form: rows 2*i1 + {0,1} hold (Re, Im) of
 //      output row i1, K step {0,1} carries (Re, Im) of B's row a, and the
-//      A operand is [[Ar, -Ai], [Ai, Ar]] pre-packed in lane order.
+//      A operand is [[Ar, -Ai], [Ai, Ar]] pre-packed in lane order; the next
+//      four rows' A operands are in flight while four rows' MFMAs run.
 // The adjoint (Algorithm 2) reuses A-C without the x_j scaling: it forms the
 // tile of Z^{kj} = U1_j M_j, takes its conjugated dot product with the
 // matching tile of y (held in registers) and writes one partial per
@@ -63,7 +66,8 @@ struct KParams {
   int64_t tiles;         // column tiles per component
   int S;
   int64_t nitems;        // q * S * tiles
-  int r1max, r2max;
+  int r1max, r2max, r3max;
+  int core_lds;          // core elements staged in LDS per pass
   int vec4;              // forward output may use 16-byte stores
 };
 
@@ -78,23 +82,137 @@ __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 c) {
   return c;
 }
 
-// LDS carve-up shared by host sizing and the kernel.  r1 is padded to a
-// multiple of 4 in H so that four consecutive rows are one 32-byte load.
+// LDS carve-up shared by host sizing and the kernel (float2 units, each
+// region a multiple of 16 bytes).  r1 is padded to a multiple of 4 in H so
+// that four consecutive rows are one 32-byte load.
 __host__ __device__ inline int pad4(int r) { return (r + 3) & ~3; }
 __host__ __device__ inline int pad8(int r) { return (r + 7) & ~7; }
-__host__ __device__ inline size_t lds_hs_elems(int t3, int r1, int r2) {
-  return (size_t)t3 * pad8(r1) * r2;  // float2
-}
-__host__ __device__ inline size_t lds_u2_elems(int t2, int r2) {
-  return (size_t)t2 * r2;  // float2
-}
-__host__ __device__ inline size_t lds_bs_elems(int r1, int nwg) {
-  return (size_t)pad8(r1) * 2 * nwg;  // float (FP32) or 2 x bf16 (hi, lo)
+__host__ __device__ inline int even(int n) { return (n + 1) & ~1; }
+__host__ __device__ inline int lds_hs_elems(int t3, int r1, int r2) { return t3 * pad8(r1) * r2; }
+__host__ __device__ inline int lds_u2_elems(int t2, int r2) { return even(t2 * r2); }
+__host__ __device__ inline int lds_u3_elems(int t3, int r3) { return even(t3 * r3); }
+__host__ __device__ inline int lds_gs_elems(int cb) { return even(cb + 8); }
+__host__ __device__ inline int lds_bs_elems(int r1, int nwg) {
+  return pad8(r1) * 2 * nwg;  // float (FP32) or 2 x bf16 (hi, lo)
 }
 constexpr int DOT_RING = 8;  // adjoint: tensors whose dots are reduced together
-size_t fused_lds_bytes(int t2, int t3, int r1max, int r2max, int nwg) {
-  return 8 * lds_hs_elems(t3, r1max, r2max) + 8 * lds_u2_elems(t2, r2max) +
-         4 * lds_bs_elems(r1max, nwg) + 8 * DOT_RING * 4 * 64;
+constexpr int CORE_LDS_MAX = 4096;  // complex core elements staged at a time
+
+// Core elements staged per pass: every tensor's core if it fits, else
+// whole mode-3 slices of at most CORE_LDS_MAX elements.
+int core_lds_elems(const tv_plan_s* p) {
+  const int64_t r12 = (int64_t)p->max_r12;
+  return (int)std::max<int64_t>(r12, std::min<int64_t>(p->max_core, CORE_LDS_MAX));
+}
+size_t fused_lds_bytes(const tv_plan_s* p, const Tiling& T, bool adj) {
+  const int r1 = p->max_r[0], r2 = p->max_r[1], r3 = p->max_r[2];
+  size_t e = (size_t)lds_hs_elems(T.t3, r1, r2) + lds_u2_elems(T.t2, r2) +
+             lds_u3_elems(T.t3, r3) + lds_gs_elems(core_lds_elems(p));
+  size_t bytes = 8 * e + 4 * (size_t)lds_bs_elems(r1, T.nwg);
+  if (adj) bytes += 8 * DOT_RING * 4 * 64;
+  return bytes;
+}
+
+// Staging of one tensor's tile inputs as a single index space: the tile's U2
+// rows (t2 x r2, contiguous in U2^T), its U3 rows (t3 x r3) and the first
+// cc mode-3 slices of the core (r1 r2 cc), so that each thread keeps up to
+// PF independent loads in flight (fewer in the adjoint, whose registers
+// also hold the y tile).  Rows outside the grid are staged as zeros.
+template <bool ADJ>
+struct Prefetch {
+  static constexpr int PF = ADJ ? 4 : 8;
+};
+struct StageSrc {
+  const float2* u2;
+  const float2* u3;
+  const float2* g;
+  int n2e, n3e, n0;   // U2 elements, U2 + U3 elements, total
+  int lim2, lim3;     // valid U2 / U3 elements (rows inside the grid)
+  int r2, cc;
+};
+
+__device__ __forceinline__ TensorMeta load_meta(const TensorMeta* m) {
+  TensorMeta t = *m;
+  t.r1 = __builtin_amdgcn_readfirstlane(t.r1);
+  t.r2 = __builtin_amdgcn_readfirstlane(t.r2);
+  t.r3 = __builtin_amdgcn_readfirstlane(t.r3);
+  t.arow = __builtin_amdgcn_readfirstlane(t.arow);
+  return t;
+}
+
+__device__ __forceinline__ StageSrc stage_src(const KParams& P, const TensorMeta& t, int T2,
+                                              int t3, int i2_0, int i3_0) {
+  StageSrc s;
+  s.u2 = P.u2t + t.u2_off + (int64_t)i2_0 * t.r2;
+  s.u3 = P.u3t + t.u3_off + (int64_t)i3_0 * t.r3;
+  s.g = P.cores + t.g_off;
+  const int r12 = t.r1 * t.r2;
+  s.cc = max(1, min(t.r3, P.core_lds / r12));
+  s.n2e = T2 * t.r2;
+  s.n3e = s.n2e + t3 * t.r3;
+  s.n0 = s.n3e + r12 * s.cc;
+  s.lim2 = min(T2, P.n2 - i2_0) * t.r2;
+  s.lim3 = s.n2e + min(t3, P.n3 - i3_0) * t.r3;
+  s.r2 = t.r2;
+  return s;
+}
+
+// Element e of the staging space: its address (elements past the end or
+// outside the grid point at the core's first element) and whether it is
+// live.  The address is formed with bit masks so that the loads of a batch
+// issue back to back; dead elements are zeroed when they are stored.
+__device__ __forceinline__ bool stage_ok(const StageSrc& s, int e) {
+  // bitwise selection (a ternary chain here becomes an indexed stack load)
+  const int m2 = -(int)(e < s.n2e), m3 = -(int)(e >= s.n2e && e < s.n3e);
+  const int lim = (s.lim2 & m2) | (s.lim3 & m3) | (s.n0 & ~(m2 | m3));
+  return e < lim;
+}
+__device__ __forceinline__ const float2* stage_addr(const StageSrc& s, int e) {
+  const bool in2 = e < s.n2e, in3 = !in2 && e < s.n3e, ok = stage_ok(s, e);
+  const uint64_t m2 = 0ull - (uint64_t)(in2 && ok);
+  const uint64_t m3 = 0ull - (uint64_t)(in3 && ok);
+  const uint64_t mg = 0ull - (uint64_t)(!in2 && !in3 && ok);
+  const uint64_t a2 = (uint64_t)(s.u2 + e), a3 = (uint64_t)(s.u3 + (e - s.n2e));
+  const uint64_t ag = (uint64_t)(s.g + (e - s.n3e)), a0 = (uint64_t)s.g;
+  return reinterpret_cast<const float2*>((a2 & m2) | (a3 & m3) | (ag & mg) |
+                                         (a0 & ~(m2 | m3 | mg)));
+}
+// a global-memory load (not a flat one, which would also count against the
+// LDS wait counter)
+__device__ __forceinline__ float2 stage_load(const StageSrc& s, int e) {
+  typedef const __attribute__((address_space(1))) uint64_t* gptr;
+  const uint64_t v = *(gptr)(uint64_t)stage_addr(s, e);
+  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+
+// U2 is stored b-major in LDS (U2s[b * t2 + i]) so that phase B reads
+// consecutive i2 for one b
+__device__ __forceinline__ void stage_store(const StageSrc& s, int e, float2 v, float2* U2s,
+                                            float2* U3s, float2* Gs, int T2) {
+  if (!stage_ok(s, e)) v = make_float2(0.f, 0.f);
+  if (e < s.n2e) {
+    const int i = e / s.r2, b = e - i * s.r2;
+    U2s[b * T2 + i] = v;
+  } else if (e < s.n3e) {
+    U3s[e - s.n2e] = v;
+  } else if (e < s.n0) {
+    Gs[e - s.n3e] = v;
+  }
+}
+
+// FP32 A operand rows a .. a+3 of a tensor (first stacked row arow); rows
+// past r1 repeat row r1 - 1 (their MFMAs are skipped)
+template <int NB>
+__device__ __forceinline__ void load_arows(float (&dst)[4][NB], const float* apack, int64_t koff,
+                                           int arow, int a, int r1, int nbt, int wm,
+                                           int64_t rstride, int lane) {
+  const float* base = apack + koff + ((int64_t)arow * nbt + wm * NB) * 64 + lane;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int aa = min(a + e, r1 - 1);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dst[e][b] = base[aa * rstride + b * 64];
+  }
 }
 
 // Adjoint: sum the per-lane dot products of tensors [j0, j0 + cnt) (ring
@@ -150,7 +268,9 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
 
   float2* Hs = reinterpret_cast<float2*>(smem4);
   float2* U2s = Hs + lds_hs_elems(P.t3, P.r1max, P.r2max);
-  float* Bs = reinterpret_cast<float*>(U2s + lds_u2_elems(T2, P.r2max));
+  float2* U3s = U2s + lds_u2_elems(T2, P.r2max);
+  float2* Gs = U3s + lds_u3_elems(P.t3, P.r3max);
+  float* Bs = reinterpret_cast<float*>(Gs + lds_gs_elems(P.core_lds));
   float2* dots = reinterpret_cast<float2*>(Bs + lds_bs_elems(P.r1max, NWG));
 
   // this lane's output column (mode-1 fibre) inside the tile
@@ -186,53 +306,100 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
 
   const TensorMeta* meta = P.meta + (int64_t)k * P.m;
   const int64_t pbase = ((int64_t)k * P.tiles + tile) * P.m;
+  const int64_t koff = P.apack_koff[k];
+  const int64_t rstride = (int64_t)P.nbt * 64;
   int flushed = jb;
   TensorMeta tn;
-  if (jb < je) tn = meta[jb];
+  if (jb < je) tn = load_meta(meta + jb);
+
+  // staging of tensor jb, then in every iteration of tensor j + 1 while
+  // tensor j's mode-1 product runs
+  constexpr int PF = Prefetch<ADJ>::PF;
+  float2 pf[PF];
+  StageSrc ss;
+  if (jb < je) {
+    ss = stage_src(P, tn, T2, P.t3, i2_0, i3_0);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) pf[u] = stage_load(ss, tid + 256 * u);
+  }
+  // FP32: the first four A operand rows of the current tensor
+  float an[4][NB];
+  if (!BF && jb < je) load_arows<NB>(an, P.apack, koff, tn.arow, 0, tn.r1, P.nbt, wm, rstride, lane);
 
   for (int j = jb; j < je; ++j) {
     const TensorMeta t = tn;
-    if (j + 1 < je) tn = meta[j + 1];  // next tensor's metadata in flight
+    const StageSrc sc = ss;
+    if (j + 1 < je) tn = load_meta(meta + j + 1);
     const int r1 = t.r1, r2 = t.r2, r3 = t.r3;
     const int r1p = BF ? pad8(r1) : pad4(r1), r1q = r1p >> 2;
+    const int r12 = r1 * r2;
     const float2 xj = ADJ ? make_float2(1.f, 0.f) : P.vec[j];
 
-    // stage the tile's U2 rows, b-major so that threads read consecutive i2
-    for (int idx = tid; idx < r2 * T2; idx += 256) {
-      const int t2 = idx % T2, b = idx / T2;
-      const int ii = i2_0 + t2;
-      U2s[idx] = (ii < P.n2) ? P.u2t[t.u2_off + (int64_t)ii * r2 + b]
-                             : make_float2(0.f, 0.f);
+    // U2 rows, U3 rows and the first core chunk: registers -> LDS, then any
+    // elements past the prefetched PF * 256
+#pragma unroll
+    for (int u = 0; u < PF; ++u) stage_store(sc, tid + 256 * u, pf[u], U2s, U3s, Gs, T2);
+    for (int e0 = PF * 256; e0 < sc.n0; e0 += 1024) {
+      float2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = stage_load(sc, e0 + tid + 256 * u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) stage_store(sc, e0 + tid + 256 * u, v[u], U2s, U3s, Gs, T2);
     }
+    __syncthreads();
+
     // A) mode-3 contraction of the core with the tile's U3 rows, four rows a
-    //    per task: H[t3][b][a] = x_j sum_c G[a,b,c] U3[i3,c]
-    const int r12 = r1 * r2;
-    for (int task = tid; task < P.t3 * r2 * r1q; task += 256) {
-      const int a4 = task % r1q, rest = task / r1q;
-      const int b = rest % r2, t3 = rest / r2;
-      const int ii = i3_0 + t3;
-      float2 h[4];
+    //    per task: H[t3][b][a] = x_j sum_c G[a,b,c] U3[i3,c]; cores larger
+    //    than the LDS chunk are swept in chunks of cc mode-3 slices
+    const int nch = (r3 + sc.cc - 1) / sc.cc;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int c0 = ch * sc.cc, c1 = min(r3, c0 + sc.cc);
+      if (ch > 0) {
+        __syncthreads();
+        const float2* gsrc = P.cores + t.g_off + (int64_t)r12 * c0;
+        const int ne = r12 * (c1 - c0);
+        for (int e0 = 0; e0 < ne; e0 += 1024) {
+          float2 v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) h[e] = make_float2(0.f, 0.f);
-      if (ii < P.n3) {
-        const float2* g = P.cores + t.g_off + 4 * a4 + r1 * b;
-        const float2* u3 = P.u3t + t.u3_off + (int64_t)ii * r3;
-        const int ne = min(4, r1 - 4 * a4);
-        for (int c = 0; c < r3; ++c) {
-          const float2 u = u3[c];
-          const float2* gc = g + (int64_t)c * r12;
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + tid + 256 * u;
+            v[u] = gsrc[e < ne ? e : 0];
+          }
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (e < ne) h[e] = cfma(gc[e], u, h[e]);
+          for (int u = 0; u < 4; ++u)
+            if (e0 + tid + 256 * u < ne) Gs[e0 + tid + 256 * u] = v[u];
         }
-        if (!ADJ) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) h[e] = cmul(xj, h[e]);
-        }
+        __syncthreads();
       }
-      float2* dst = Hs + (t3 * r2 + b) * r1p + 4 * a4;
-      *reinterpret_cast<float4*>(dst) = make_float4(h[0].x, h[0].y, h[1].x, h[1].y);
-      *reinterpret_cast<float4*>(dst + 2) = make_float4(h[2].x, h[2].y, h[3].x, h[3].y);
+      for (int task = tid; task < P.t3 * r2 * r1q; task += 256) {
+        const int a4 = task % r1q, rest = task / r1q;
+        const int b = rest % r2, t3 = rest / r2;
+        const int ne = min(4, r1 - 4 * a4);
+        float2* dst = Hs + (t3 * r2 + b) * r1p + 4 * a4;
+        float2 h[4];
+        if (ch == 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) h[e] = make_float2(0.f, 0.f);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) h[e] = dst[e];
+        }
+        const float2* g = Gs + 4 * a4 + r1 * b;
+        const float2* u3 = U3s + t3 * r3;
+        for (int c = c0; c < c1; ++c) {
+          const float2 u = u3[c];
+          const float2* gc = g + r12 * (c - c0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) h[e] = cfma(gc[e], u, h[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (!ADJ && ch == nch - 1) h[e] = cmul(xj, h[e]);
+          if (e >= ne) h[e] = make_float2(0.f, 0.f);  // rows past r1 read other data
+        }
+        *reinterpret_cast<float4*>(dst) = make_float4(h[0].x, h[0].y, h[1].x, h[1].y);
+        *reinterpret_cast<float4*>(dst + 2) = make_float4(h[2].x, h[2].y, h[3].x, h[3].y);
+      }
     }
     __syncthreads();
 
@@ -295,6 +462,13 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
         }
       }
     }
+    // loads for the next tensor's staging, in flight during this tensor's
+    // mode-1 product
+    if (j + 1 < je) {
+      ss = stage_src(P, tn, T2, P.t3, i2_0, i3_0);
+#pragma unroll
+      for (int u = 0; u < PF; ++u) pf[u] = stage_load(ss, tid + 256 * u);
+    }
     __syncthreads();
 
     // adjoint: reduce the dots of the last DOT_RING tensors (their per-lane
@@ -333,36 +507,29 @@ __global__ __launch_bounds__(256) void fused_f32(KParams P) {
         }
       }
     } else {
-      // rows in groups of 4, the next group's A operand loaded while the
-      // current group's MFMAs run; rows past r1 use zero operands
-      const float* Arow = P.apack + P.apack_koff[k] + ((int64_t)t.arow * P.nbt + wm * NB) * 64 +
-                          lane;
+      // rows in groups of four; the next group's A operand (or the next
+      // tensor's first group) is loaded while the current group's MFMAs run
       const float* Brow = Bs + (lane >> 5) * NWG + wn * 32 + (lane & 31);
-      const int64_t rstride = (int64_t)P.nbt * 64;
-      float an[4][NB];
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) an[e][b] = e < r1 ? Arow[e * rstride + b * 64] : 0.f;
       for (int a0 = 0; a0 < r1; a0 += 4) {
         float ac[4][NB], bc[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          bc[e] = a0 + e < r1 ? Brow[2 * (a0 + e) * NWG] : 0.f;
+          bc[e] = Brow[2 * min(a0 + e, r1 - 1) * NWG];
 #pragma unroll
           for (int b = 0; b < NB; ++b) ac[e][b] = an[e][b];
         }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int a = a0 + 4 + e;
-#pragma unroll
-          for (int b = 0; b < NB; ++b) an[e][b] = a < r1 ? Arow[a * rstride + b * 64] : 0.f;
-        }
+        if (a0 + 4 < r1)
+          load_arows<NB>(an, P.apack, koff, t.arow, a0 + 4, r1, P.nbt, wm, rstride, lane);
+        else if (j + 1 < je)
+          load_arows<NB>(an, P.apack, koff, tn.arow, 0, tn.r1, P.nbt, wm, rstride, lane);
+        const int ne = min(4, r1 - a0);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
+          if (e < ne) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[e][b], bc[e], acc[b], 0, 0, 0);
+            for (int b = 0; b < NB; ++b)
+              acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[e][b], bc[e], acc[b], 0, 0, 0);
+          }
       }
     }
 
@@ -501,7 +668,7 @@ static tv_status launch_fused(const tv_plan_s* p, bool adj, const float2* vec, f
   P.n2 = p->grid.n2;
   P.n3 = p->grid.n3;
   P.q = p->grid.q;
-  P.nbt = T.nbt;
+  P.nbt = p->nbt_pack;
   P.t2 = T.t2;
   P.t3 = T.t3;
   P.tiles2 = T.tiles2;
@@ -510,12 +677,14 @@ static tv_status launch_fused(const tv_plan_s* p, bool adj, const float2* vec, f
   P.nitems = (int64_t)p->grid.q * split * T.tiles;
   P.r1max = p->max_r[0];
   P.r2max = p->max_r[1];
+  P.r3max = p->max_r[2];
+  P.core_lds = core_lds_elems(p);
   P.vec4 = (p->grid.n1 % 2 == 0) && ((uintptr_t)out % 16 == 0) && (out_stride % 2 == 0);
   const bool bf = p->precision == TV_PREC_BF16X3;
   fused_fn fn = adj ? (bf ? pick<true, true>(T.nb, T.wn) : pick<true, false>(T.nb, T.wn))
                     : (bf ? pick<false, true>(T.nb, T.wn) : pick<false, false>(T.nb, T.wn));
   if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no kernel instance for this tiling");
-  const size_t lds = fused_lds_bytes(T.t2, T.t3, P.r1max, P.r2max, T.nwg);
+  const size_t lds = fused_lds_bytes(p, T, adj);
   if (lds > 160 * 1024)
     return set_error(TV_ERR_NOT_SUPPORTED, "ranks too large for the LDS tile");
   hipError_t e = hipFuncSetAttribute((const void*)fn,
@@ -530,11 +699,15 @@ static tv_status launch_fused(const tv_plan_s* p, bool adj, const float2* vec, f
 
 tv_status launch_forward_f32(const tv_plan_s* p, const float2* x, float2* out, int split,
                              const int32_t* d_split, int64_t out_stride, hipStream_t st) {
+  if (p->kernel_ws[0] && ws_supported(p, p->tiling, false))
+    return launch_fused_ws(p, false, x, out, split, d_split, out_stride, st);
   return launch_fused(p, false, x, out, split, d_split, out_stride, st);
 }
 
 tv_status launch_adjoint_f32(const tv_plan_s* p, const float2* y, float2* partial, int split,
                              const int32_t* d_split, hipStream_t st) {
+  if (p->kernel_ws[1] && ws_supported(p, p->tiling_a, true))
+    return launch_fused_ws(p, true, y, partial, split, d_split, 0, st);
   return launch_fused(p, true, y, partial, split, d_split, 0, st);
 }
 
