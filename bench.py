@@ -13,6 +13,7 @@ Prints one JSON line on stdout (progress goes to stderr).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,6 +27,30 @@ if ROOT not in sys.path:
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_BF16_MFMA = 2516.6     # TFLOP/s, dense BF16 matrix
 PEAK_HBM = 8000.0           # GB/s
+
+# HBM bytes per launch of the dominant kernel: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for
+# a plain copy of known size.  A figure holds only for the kernel source it was
+# taken on (checked by hash); after a change it is reported as null until the
+# counters are taken again.
+MEASURED_TRAFFIC = {
+    ("c2", "fp32", "adjoint"): {
+        "bytes": 39128890,
+        "source": "paper_2103_06393_amd/csrc/tv_fused_ws.hip",
+        "sha256": "5a5ee74a0bd70e9fc90df8fc343d1afde9ca5f7fe9525954ec39472b44d6da8b",
+        "profile": "profiles/ws_fused_c2_fp32_pmc.md",
+    },
+}
+
+
+def measured_traffic(workload: str, precision: str, direction: str):
+    e = MEASURED_TRAFFIC.get((workload, precision, direction))
+    if not e:
+        return None
+    with open(os.path.join(ROOT, e["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
+            return None
+    return e["bytes"]
 
 
 def log(*a):
@@ -179,11 +204,15 @@ def main(argv=None):
     log(f"[bench] fwd {fwd_ms:.4f} ms ({tf_f:.1f} TFLOP/s), adj {adj_ms:.4f} ms "
         f"({tf_a:.1f} TFLOP/s), wall {wall:.3f} s for {K} steps")
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
+    d = 1 if dom == "adjoint" else 0
+    info = plan.info  # after autotuning: the launch configuration in use
+    kname = "tv::ws_fused" if info.kernel[d] else "tv::fused_f32"
+    pname = "fp32" if prec == lib.TV_PREC_FP32 else "bf16x3"
     ach = tf_a if dom == "adjoint" else tf_f
     # the BF16 split executes 3 MFMA products per algorithmic one
     peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
     out = {
-        "metric": "compressed VSIE matvecs/s (Zx and Z^H y)",
+        "metric": "compressed VSIE matvecs/s (Zx and Z^H y), TFLOP/s and % MFMA peak",
         "value": value, "unit": "matvecs/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -202,9 +231,13 @@ def main(argv=None):
         "fwd_ms": fwd_ms, "adj_ms": adj_ms,
         "tflops_fwd": tf_f, "tflops_adj": tf_a,
         "flops_fwd": info.flops_matvec, "flops_adj": info.flops_rmatvec,
-        "roofline": {"kernel": f"fused_f32 ({dom})", "bound": "mfma",
+        "roofline": {"kernel": f"{kname} ({dom})", "bound": "mfma",
                      "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak, "traffic": None},
+                     "frac": ach / peak,
+                     "traffic": measured_traffic(wl.name, pname, dom)},
+        "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
+                   "splits": list(info.splits),
+                   "kernel": ["warp-specialised" if v else "phased" for v in info.kernel]},
     }
     if not args.no_cpu:
         cb, cols, y_ref, x_ref = cpu_baseline(wl, plan, x_np, y_np, args.cpu_budget)

@@ -85,6 +85,10 @@ typedef struct {
   size_t device_bytes;     /* device memory the plan holds (packed forms)  */
   double flops_matvec;     /* algorithmic real flops of one Z x (p = 1)    */
   double flops_rmatvec;    /* algorithmic real flops of one Z^* y (p = 1)  */
+  /* launch configuration of the fused kernels, [0] forward, [1] adjoint:
+   * tile extent along i2 and i3, column splits, and the kernel family
+   * (0: phased, 1: warp-specialised producer/consumer)                     */
+  int32_t tile_t2[2], tile_t3[2], splits[2], kernel[2];
 } tv_plan_info_t;
 
 /* ------------------------------------------------------------------------

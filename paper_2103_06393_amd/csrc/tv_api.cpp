@@ -489,6 +489,13 @@ tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
   info->device_bytes = p->device_bytes;
   info->flops_matvec = fl;
   info->flops_rmatvec = fl + 8.0 * (double)K * n1 * n2 * n3;
+  for (int o = 0; o < 2; ++o) {
+    const Tiling& T = o == 0 ? p->tiling : p->tiling_a;
+    info->tile_t2[o] = T.t2;
+    info->tile_t3[o] = T.t3;
+    info->splits[o] = o == 0 ? p->split_f : p->split_a;
+    info->kernel[o] = (p->finalized && p->kernel_ws[o] && ws_supported(p, T, o == 1)) ? 1 : 0;
+  }
   return TV_OK;
 }
 

@@ -149,47 +149,33 @@ __device__ __forceinline__ void load_arows(float (&dst)[4][NB], const float* bas
 }
 
 // Mode-3 contraction on the producer threads: H[t3][b][a] = x_j sum_c
-// G[a,b,c] U3[i3,c], four rows a per task (rows r1 <= a < r1p are zeros);
-// the loads of two mode-3 slices are issued together.  G is the staged
-// core in LDS or the core in global memory (two instances).
+// G[a,b,c] U3[i3,c], one row a per task so that all producer waves share
+// the work (rows r1 <= a < r1p are zeros); the loads of four mode-3 slices
+// are issued together.  G is the staged core in LDS or the core in global
+// memory (two instances).
 template <bool ADJ>
 __device__ __forceinline__ void mode3(const float2* G, const float2* U3s, float2* H, int r1,
                                       int r1p, int r2, int r3, int t3n, float2 xj, int ptid) {
-  const int r12 = r1 * r2, r1q = r1p >> 2;
-  for (int task = ptid; task < t3n * r2 * r1q; task += 256) {
-    const int a4 = task % r1q, rest = task / r1q;
-    const int b = rest % r2, t3 = rest / r2;
-    const int ne = r1 - 4 * a4;
-    const float2* g = G + r1 * b;
+  const int r12 = r1 * r2;
+  for (int task = ptid; task < t3n * r2 * r1p; task += 256) {
+    const int row = task / r1p, a = task - row * r1p;  // row = t3 * r2 + b
+    const int t3 = row / r2, b = row - t3 * r2;
+    const float2* g = G + min(a, r1 - 1) + r1 * b;
     const float2* u3 = U3s + t3 * r3;
-    int ai[4];
+    float2 h = make_float2(0.f, 0.f);
+    for (int c0 = 0; c0 < r3; c0 += 4) {
+      float2 gv[4], uv[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) ai[e] = min(4 * a4 + e, r1 - 1);
-    float2 h[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) h[e] = make_float2(0.f, 0.f);
-    for (int c0 = 0; c0 < r3; c0 += 2) {
-      float2 gv[2][4], uv[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < 4; ++q) {
         const int c = min(c0 + q, r3 - 1);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) gv[q][e] = g[(int64_t)c * r12 + ai[e]];
+        gv[q] = g[(int64_t)c * r12];
         uv[q] = c0 + q < r3 ? u3[c] : make_float2(0.f, 0.f);
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) h[e] = cfma(gv[q][e], uv[q], h[e]);
+      for (int q = 0; q < 4; ++q) h = cfma(gv[q], uv[q], h);
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (!ADJ) h[e] = cmul(xj, h[e]);
-      if (e >= ne) h[e] = make_float2(0.f, 0.f);
-    }
-    float2* dst = H + (t3 * r2 + b) * r1p + 4 * a4;
-    *reinterpret_cast<float4*>(dst) = make_float4(h[0].x, h[0].y, h[1].x, h[1].y);
-    *reinterpret_cast<float4*>(dst + 2) = make_float4(h[2].x, h[2].y, h[3].x, h[3].y);
+    if (!ADJ) h = cmul(xj, h);
+    H[task] = a < r1 ? h : make_float2(0.f, 0.f);
   }
 }
 
@@ -358,63 +344,63 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
       if (t >= 0 && t < cnt) {
         const int r1 = tc.r1, r2 = tc.r2;
         const int r1p = BF ? ws_pad8(r1) : ws_pad4(r1);
-        // B) mode 2 for the wave's 32 columns: B[a][n] = sum_b H[t3][b][a]
-        //    U2[i2(n), b]; lane (half, column) takes 4-row groups a4 = half,
-        //    half + 2, ...; BQ values of b at a time, loads first (BQ is 2
-        //    when the accumulators of 4 row blocks already fill registers)
+        // B) mode 2 on MFMA for the wave's 32 columns, 16 rows a per block:
+        //    B[2a+s][n] = sum_b Hemb[2a+s][t] U2emb[t][n], one K step per b,
+        //    with Hemb = [[Re H, -Im H], [Im H, Re H]] and U2emb[t][n] the
+        //    real (t = 0) or imaginary (t = 1) part of U2[i2(n), b]
         {
-          constexpr int BQ = NB >= 4 ? 2 : 4;
-          const float2* H = Hbuf + (t & 1) * he + t3n * r2 * r1p;
+          const float2* Ht = Hbuf + (t & 1) * he + t3n * r2 * r1p;
           const float2* u2 = U2buf + (t % 3) * u2e + t2n;
-          for (int a4 = half; a4 < r1p / 4; a4 += 2) {
-            float2 v[4];
+          const int sa = lane & 1;
+          for (int mb = 0; mb * 16 < r1; ++mb) {
+            const int a = mb * 16 + (cl >> 1);
+            const bool aok = a < r1;
+            const float2* hr = Ht + min(a, r1 - 1);
+            v16f d;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = make_float2(0.f, 0.f);
-            const float2* hb = H + 4 * a4;
-            for (int b0 = 0; b0 < r2; b0 += BQ) {
-              float4 h01[BQ], h23[BQ];
-              float2 u[BQ];
+            for (int i = 0; i < 16; ++i) d[i] = 0.f;
+            for (int b0 = 0; b0 < r2; b0 += 4) {
+              float av[4], bv[4];
 #pragma unroll
-              for (int q = 0; q < BQ; ++q) {
-                const int b = min(b0 + q, r2 - 1);
-                h01[q] = *reinterpret_cast<const float4*>(hb + b * r1p);
-                h23[q] = *reinterpret_cast<const float4*>(hb + b * r1p + 2);
-                u[q] = b0 + q < r2 ? u2[b * T2] : make_float2(0.f, 0.f);
+              for (int q = 0; q < 4; ++q) {
+                const int bb = min(b0 + q, r2 - 1);
+                const float2 h = hr[bb * r1p];
+                const float2 u = u2[bb * T2];
+                const float x = sa == half ? h.x : (sa ? h.y : -h.y);
+                av[q] = (aok && b0 + q < r2) ? x : 0.f;
+                bv[q] = half ? u.y : u.x;
               }
 #pragma unroll
-              for (int q = 0; q < BQ; ++q) {
-                v[0] = cfma(make_float2(h01[q].x, h01[q].y), u[q], v[0]);
-                v[1] = cfma(make_float2(h01[q].z, h01[q].w), u[q], v[1]);
-                v[2] = cfma(make_float2(h23[q].x, h23[q].y), u[q], v[2]);
-                v[3] = cfma(make_float2(h23[q].z, h23[q].w), u[q], v[3]);
-              }
+              for (int q = 0; q < 4; ++q)
+                d = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv[q], d, 0, 0, 0);
             }
+            // lane (cl, half) holds rows m = 32 mb + 8 (i/4) + 4 half + i%4
             if constexpr (BF) {
-              // rows 4 a4 .. 4 a4 + 3 are half (a4 & 1) of 8-row chunk a4 / 2
-              uint4* bh = reinterpret_cast<uint4*>(Bw);
-              uint4* bl = bh + (size_t)(r1p / 8) * 2 * 32;
-              uint32_t h[8], l[8];
+              // 4 consecutive real rows per i/4: one half of a uint4 (8 bf16)
+              uint2* bh = reinterpret_cast<uint2*>(Bw);
+              uint2* bl = bh + (size_t)(r1p / 8) * 2 * 32 * 2;
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                h[2 * e] = bf16_rne(v[e].x);
-                h[2 * e + 1] = bf16_rne(v[e].y);
-                l[2 * e] = bf16_rne(v[e].x - bf16_to_float(h[2 * e]));
-                l[2 * e + 1] = bf16_rne(v[e].y - bf16_to_float(h[2 * e + 1]));
+              for (int g = 0; g < 4; ++g) {
+                const int q8 = 4 * mb + g;  // 8-row group of real rows 8 q8 ..
+                if (q8 * 4 < r1p) {
+                  uint32_t hh[4], ll[4];
+#pragma unroll
+                  for (int e = 0; e < 4; ++e) {
+                    hh[e] = bf16_rne(d[4 * g + e]);
+                    ll[e] = bf16_rne(d[4 * g + e] - bf16_to_float(hh[e]));
+                  }
+                  // uint4 index ((q8 / 2) * 2 + q8 % 2) * 32 + cl = q8 * 32 + cl
+                  const int at = (q8 * 32 + cl) * 2 + half;
+                  bh[at] = make_uint2(hh[0] | (hh[1] << 16), hh[2] | (hh[3] << 16));
+                  bl[at] = make_uint2(ll[0] | (ll[1] << 16), ll[2] | (ll[3] << 16));
+                }
               }
-              const int at = ((a4 >> 1) * 2 + (a4 & 1)) * 32 + cl;
-              bh[at] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                                  h[6] | (h[7] << 16));
-              bl[at] = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16),
-                                  l[6] | (l[7] << 16));
             } else {
               float* Bf = reinterpret_cast<float*>(Bw);
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const int a = 4 * a4 + e;
-                if (a < r1) {
-                  Bf[(2 * a) * 32 + cl] = v[e].x;
-                  Bf[(2 * a + 1) * 32 + cl] = v[e].y;
-                }
+              for (int i = 0; i < 16; ++i) {
+                const int m = 32 * mb + 8 * (i >> 2) + 4 * half + (i & 3);
+                if (m < 2 * r1) Bf[m * 32 + cl] = d[i];
               }
             }
           }

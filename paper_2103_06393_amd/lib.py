@@ -43,7 +43,8 @@ class tv_plan_info_t(ctypes.Structure):
                 ("max_rank", c_i32 * 3), ("mean_rank", c_dbl * 3),
                 ("sum_r1", c_i64), ("factor_bytes", c_sz),
                 ("device_bytes", c_sz), ("flops_matvec", c_dbl),
-                ("flops_rmatvec", c_dbl)]
+                ("flops_rmatvec", c_dbl), ("tile_t2", c_i32 * 2),
+                ("tile_t3", c_i32 * 2), ("splits", c_i32 * 2), ("kernel", c_i32 * 2)]
 
 
 class TuckVsieError(RuntimeError):
