@@ -318,14 +318,14 @@ size_t batch_lds_bytes(int op, int ncol, int n1p32, int r1max, int r2max) {
 typedef void (*batch_fn)(BatchArgs);
 
 static batch_fn pick_fwd(int ncol, int bpw) {
-  if (ncol == 32 && bpw == 8) return batch_fwd<32, 8>;
-  if (ncol == 16 && bpw == 8) return batch_fwd<16, 8>;
-  if (ncol == 8 && bpw == 6) return batch_fwd<8, 6>;
-  if (ncol == 8 && bpw == 8) return batch_fwd<8, 8>;
-  if (ncol == 4 && bpw == 5) return batch_fwd<4, 5>;
-  if (ncol == 4 && bpw == 6) return batch_fwd<4, 6>;
-  if (ncol == 4 && bpw == 7) return batch_fwd<4, 7>;
-  if (ncol == 4 && bpw == 8) return batch_fwd<4, 8>;
+#define TV_BF(NC)                                   \
+  if (ncol == NC) {                                 \
+    if (bpw == 1) return batch_fwd<NC, 1>;          \
+    if (bpw == 2) return batch_fwd<NC, 2>;          \
+    if (bpw == 3) return batch_fwd<NC, 3>;          \
+  }
+  TV_BF(1) TV_BF(2) TV_BF(4) TV_BF(8) TV_BF(16)
+#undef TV_BF
   return nullptr;
 }
 
@@ -396,8 +396,16 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   b->n1p32 = (g.n1 + 31) / 32 * 32;
   const int nb1 = b->n1p32 / 32;
   if (op == 0) {
-    int ncol = 1;
-    while (ncol * 2 * nb1 <= 32) ncol *= 2;
+    // columns per tile: the widest power of two whose nb1 * ncol 32-voxel
+    // blocks split evenly over the 4 waves with at most 3 blocks per wave
+    // (each block holds 32 accumulator registers per real/imaginary half)
+    int ncol = 0;
+    for (int c = 16; c >= 1 && !ncol; c /= 2)
+      if ((nb1 * c) % 4 == 0 && nb1 * c / 4 <= 3) ncol = c;
+    if (!ncol) {
+      delete b;
+      return set_error(TV_ERR_NOT_SUPPORTED, "no batched tile for this n1");
+    }
     b->ncol = ncol;
     b->bpw = nb1 * ncol / 4;
   } else {
