@@ -9,16 +9,17 @@
 //     tensor s into LDS (loads in flight while they compute), and contract
 //     the core of tensor s - 1 with the tile's U3 rows (mode 3, eq. 7, scaled
 //     by x_j) into H;
-//   consumer waves (4), step s: apply U2 to H for tensor s - 2 (mode 2) for
-//     the wave's own 32 columns into a private B tile, then run that
-//     tensor's mode-1 product on MFMA, the A operand (stacked U1) streaming
-//     from L2 one group of rows ahead.
+//   consumer waves (4), step s: apply U2 to H for tensor s - 2 (mode 2, on
+//     16x16x4 MFMAs, 16 columns per task) into the shared B tile of that
+//     tensor, and run tensor s - 3's mode-1 product on MFMA from the B tile
+//     built one step earlier, the A operand (stacked U1) streaming from L2
+//     one group of rows ahead.
 //
 // A single wave issues VALU work at a fraction of a SIMD's rate, so the
 // mode-2 work (the largest VALU term) sits with the consumers, whose MFMAs
 // leave the VALU idle, and the producers keep the loads and the mode-3
 // contraction.  Staging is triple-buffered for U2 and double-buffered for
-// the core and U3; H is double-buffered.  In the adjoint the consumers also
+// the core and U3; H and the B tile are double-buffered.  In the adjoint the consumers also
 // form the conjugated dot of the decompressed tile with the y tile held in
 // registers, and a producer wave reduces those per-lane dots one step later.
 //
@@ -35,6 +36,7 @@ namespace tv {
 namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 struct WsParams {
@@ -111,9 +113,9 @@ constexpr int WS_META_RING = 128;
 __host__ __device__ inline int ws_pad4(int r) { return (r + 3) & ~3; }
 __host__ __device__ inline int ws_pad8(int r) { return (r + 7) & ~7; }
 __host__ __device__ inline int ws_even(int n) { return (n + 1) & ~1; }
-// one consumer wave's B tile: pad8(r1) rows x 2 (Re, Im) x 32 columns floats
-// (BF16: hi and lo bf16)
-__host__ __device__ inline int ws_bw_elems(int r1max) { return ws_pad8(r1max) * 32; }
+// one B tile: pad8(r1) rows x 2 (Re, Im) x nwg columns floats (BF16: hi and
+// lo bf16)
+__host__ __device__ inline int ws_b_elems(int r1max, int nwg) { return ws_pad8(r1max) * nwg; }
 // staging: U2 tile rows (b-major), t2 x r2; U3 tile rows t3 x r3 then core
 __host__ __device__ inline int ws_u2_elems(int t2, int r2max) { return ws_even(t2 * r2max); }
 __host__ __device__ inline int ws_cu_elems(int t3, int r3max, int cb) {
@@ -126,7 +128,7 @@ __host__ __device__ inline int ws_h_elems(int t3, int r1max, int r2max) {
 
 size_t ws_lds_bytes(const tv_plan_s* p, const Tiling& T, bool adj, int cb) {
   const int r1 = p->max_r[0], r2 = p->max_r[1], r3 = p->max_r[2];
-  size_t e = 4 * (size_t)ws_bw_elems(r1) + 3 * (size_t)ws_u2_elems(T.t2, r2) +
+  size_t e = 2 * (size_t)ws_b_elems(r1, T.nwg) + 3 * (size_t)ws_u2_elems(T.t2, r2) +
              2 * (size_t)ws_cu_elems(T.t3, r3, cb) + 2 * (size_t)ws_h_elems(T.t3, r1, r2) +
              (adj ? 2 * 256 : 0);
   return 8 * e + WS_META_RING * (sizeof(TensorMeta) + sizeof(float2));
@@ -277,13 +279,14 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
   const int cnt = je - jb;
   const TensorMeta* meta = P.meta + (int64_t)k * P.m + jb;
 
-  const int bwe = ws_bw_elems(P.r1max);
+  constexpr int NWG = 32 * WN;
+  const int be = ws_b_elems(P.r1max, NWG);
   const int u2e = ws_u2_elems(T2, P.r2max);
   const int u3e = ws_even(P.t3 * P.r3max);
   const int cue = ws_cu_elems(P.t3, P.r3max, P.cb);
   const int he = ws_h_elems(P.t3, P.r1max, P.r2max);
-  float2* Bw0 = reinterpret_cast<float2*>(smem4);
-  float2* U2buf = Bw0 + 4 * bwe;
+  float2* Bbuf = reinterpret_cast<float2*>(smem4);
+  float2* U2buf = Bbuf + 2 * be;
   float2* CUbuf = U2buf + 3 * u2e;
   float2* Hbuf = CUbuf + 2 * cue;
   float2* dots = Hbuf + 2 * he;
@@ -309,7 +312,6 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
     const int64_t fibre = (int64_t)k * P.nv + (int64_t)P.n1 * (i2 + (int64_t)P.n2 * i3);
     const int64_t rstride = (int64_t)P.nbt * 64;
     const float* abase = P.apack + P.apack_koff[k] + wm * NB * 64 + lane;
-    float2* Bw = Bw0 + wave * bwe;  // this wave's B tile (32 columns)
 
     v16f acc[NB];
 #pragma unroll
@@ -339,88 +341,119 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
       if constexpr (!BF) load_arows<NB>(an, abase, tc.arow, 0, tc.r1, P.nbt, rstride);
     }
     const int half = lane >> 5, cl = lane & 31;
-    for (int st = 0; st < cnt + 3; ++st) {
-      const int t = st - 2;  // tensor of this step
-      if (t >= 0 && t < cnt) {
-        const int r1 = tc.r1, r2 = tc.r2;
+    for (int st = 0; st < cnt + 4; ++st) {
+      // B) mode 2 of tensor tb = st - 2 into its B tile, 16 columns per
+      //    task on v_mfma_f32_16x16x4f32 (A lane l = A[l%16][l/16], B lane
+      //    l = B[l/16][l%16], D register r of lane l = D[4(l/16)+r][l%16]):
+      //    B[2a+s][n] = sum_b Hemb[2a+s][2b+t] U2emb[2b+t][n], two b per
+      //    instruction, Hemb = [[Re H, -Im H], [Im H, Re H]] per (a, b) and
+      //    U2emb the real / imaginary parts of U2[i2(n), b]
+      const int tb = st - 2;
+      if (tb >= 0 && tb < cnt) {
+        const TensorMeta mbt = uniform_meta(ML[tb % WS_META_RING]);
+        const int r1 = mbt.r1, r2 = mbt.r2;
         const int r1p = BF ? ws_pad8(r1) : ws_pad4(r1);
-        // B) mode 2 on MFMA for the wave's 32 columns, 16 rows a per block:
-        //    B[2a+s][n] = sum_b Hemb[2a+s][t] U2emb[t][n], one K step per b,
-        //    with Hemb = [[Re H, -Im H], [Im H, Re H]] and U2emb[t][n] the
-        //    real (t = 0) or imaginary (t = 1) part of U2[i2(n), b]
-        {
-          const float2* Ht = Hbuf + (t & 1) * he + t3n * r2 * r1p;
-          const float2* u2 = U2buf + (t % 3) * u2e + t2n;
-          const int sa = lane & 1;
-          for (int mb = 0; mb * 16 < r1; ++mb) {
-            const int a = mb * 16 + (cl >> 1);
-            const bool aok = a < r1;
-            const float2* hr = Ht + min(a, r1 - 1);
-            v16f d;
+        const float2* Hb = Hbuf + (tb & 1) * he;
+        const float2* U2b = U2buf + (tb % 3) * u2e;
+        float2* Bt = Bbuf + (tb & 1) * be;
+        const int m16 = lane & 15, k4 = lane >> 4;  // A row / B column, K index
+        const int sa = m16 & 1, ta = k4 & 1, bq = k4 >> 1;
+        // the wave's chunks ch = wave + 4 c (c < CH) are processed together:
+        // operand loads of 2 QB values of b for all of them, then their MFMAs
+        constexpr int CH = NWG >= 64 ? NWG / 64 : 1;
+        constexpr int QB = CH > 1 ? 2 : 4;  // MFMAs (2 b each) per batch of loads
+        const float2* U2c[CH];
+        const float2* Hcc[CH];
+        int nn[CH];
+        bool live[CH];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) d[i] = 0.f;
-            for (int b0 = 0; b0 < r2; b0 += 4) {
-              float av[4], bv[4];
+        for (int c = 0; c < CH; ++c) {
+          const int ch = wave + 4 * c;
+          live[c] = ch < NWG / 16;
+          nn[c] = ch * 16 + m16;                              // this lane's B column
+          U2c[c] = U2b + (live[c] ? nn[c] % T2 : 0);
+          Hcc[c] = Hb + (live[c] ? (ch * 16) / T2 : 0) * r2 * r1p;  // the chunk's i3 row
+        }
+        for (int mb = 0; mb * 8 < r1; ++mb) {
+          const int a = mb * 8 + (m16 >> 1);
+          const int ac = min(a, r1 - 1);
+          v4f d[CH];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int bb = min(b0 + q, r2 - 1);
-                const float2 h = hr[bb * r1p];
-                const float2 u = u2[bb * T2];
-                const float x = sa == half ? h.x : (sa ? h.y : -h.y);
-                av[q] = (aok && b0 + q < r2) ? x : 0.f;
-                bv[q] = half ? u.y : u.x;
+          for (int c = 0; c < CH; ++c) d[c] = v4f{0.f, 0.f, 0.f, 0.f};
+          for (int b0 = 0; b0 < r2; b0 += 2 * QB) {
+            float av[CH][QB], bv[CH][QB];
+#pragma unroll
+            for (int q = 0; q < QB; ++q) {
+              const int bb = b0 + 2 * q + bq;
+              const bool ok = bb < r2 && a < r1;
+              const int bc = min(bb, r2 - 1);
+#pragma unroll
+              for (int c = 0; c < CH; ++c) {
+                const float2 h = Hcc[c][bc * r1p + ac];
+                const float2 u = U2c[c][bc * T2];
+                const float x = sa == ta ? h.x : (sa ? h.y : -h.y);
+                av[c][q] = ok ? x : 0.f;
+                bv[c][q] = bb < r2 ? (ta ? u.y : u.x) : 0.f;
               }
-#pragma unroll
-              for (int q = 0; q < 4; ++q)
-                d = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bv[q], d, 0, 0, 0);
             }
-            // lane (cl, half) holds rows m = 32 mb + 8 (i/4) + 4 half + i%4
+#pragma unroll
+            for (int q = 0; q < QB; ++q)
+              if (b0 + 2 * q < r2) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c)
+                  d[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c][q], bv[c][q], d[c], 0, 0, 0);
+              }
+          }
+          // lane holds real rows R0 .. R0 + 3 of its column, R0 = 16 mb + 4 k4
+          const int R0 = 16 * mb + 4 * k4;
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            if (!live[c]) continue;
+            const int n = nn[c];
             if constexpr (BF) {
-              // 4 consecutive real rows per i/4: one half of a uint4 (8 bf16)
-              uint2* bh = reinterpret_cast<uint2*>(Bw);
-              uint2* bl = bh + (size_t)(r1p / 8) * 2 * 32 * 2;
+              if (R0 < 2 * r1p) {
+                uint32_t hh[4], ll[4];
 #pragma unroll
-              for (int g = 0; g < 4; ++g) {
-                const int q8 = 4 * mb + g;  // 8-row group of real rows 8 q8 ..
-                if (q8 * 4 < r1p) {
-                  uint32_t hh[4], ll[4];
-#pragma unroll
-                  for (int e = 0; e < 4; ++e) {
-                    hh[e] = bf16_rne(d[4 * g + e]);
-                    ll[e] = bf16_rne(d[4 * g + e] - bf16_to_float(hh[e]));
-                  }
-                  // uint4 index ((q8 / 2) * 2 + q8 % 2) * 32 + cl = q8 * 32 + cl
-                  const int at = (q8 * 32 + cl) * 2 + half;
-                  bh[at] = make_uint2(hh[0] | (hh[1] << 16), hh[2] | (hh[3] << 16));
-                  bl[at] = make_uint2(ll[0] | (ll[1] << 16), ll[2] | (ll[3] << 16));
+                for (int e = 0; e < 4; ++e) {
+                  hh[e] = bf16_rne(d[c][e]);
+                  ll[e] = bf16_rne(d[c][e] - bf16_to_float(hh[e]));
                 }
+                // uint4 (R0 / 8) * nwg + n holds real rows R0 & ~7 .. + 7
+                uint2* bh = reinterpret_cast<uint2*>(Bt);
+                uint2* bl = bh + (size_t)(r1p / 8) * 2 * NWG * 2;
+                const int at = ((R0 >> 3) * NWG + n) * 2 + ((R0 >> 2) & 1);
+                bh[at] = make_uint2(hh[0] | (hh[1] << 16), hh[2] | (hh[3] << 16));
+                bl[at] = make_uint2(ll[0] | (ll[1] << 16), ll[2] | (ll[3] << 16));
               }
             } else {
-              float* Bf = reinterpret_cast<float*>(Bw);
+              float* Bf = reinterpret_cast<float*>(Bt);
 #pragma unroll
-              for (int i = 0; i < 16; ++i) {
-                const int m = 32 * mb + 8 * (i >> 2) + 4 * half + (i & 3);
-                if (m < 2 * r1) Bf[m * 32 + cl] = d[i];
-              }
+              for (int e = 0; e < 4; ++e)
+                if (R0 + e < 2 * r1) Bf[(R0 + e) * NWG + n] = d[c][e];
             }
           }
-          wave_sync();
         }
+      }
+      // C) mode 1 of tensor t = st - 3 on MFMA from its B tile
+      const int t = st - 3;
+      if (t >= 0 && t < cnt) {
+        const int r1 = tc.r1;
+        const int r1p = BF ? ws_pad8(r1) : ws_pad4(r1);
+        const float2* Bt = Bbuf + (t & 1) * be;
         if (ADJ) {
 #pragma unroll
           for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[b][i] = 0.f;
         }
-        // C) mode 1 on MFMA
         if constexpr (BF) {
           const uint4* Ach = P.apack_bf + P.apack_koff[k] +
                              ((int64_t)tc.arow * P.nbt + wm * NB) * 128 + lane;
-          const uint4* bh = reinterpret_cast<const uint4*>(Bw) + half * 32 + cl;
-          const uint4* bl = bh + (size_t)(r1p / 8) * 2 * 32;
+          const uint4* bh = reinterpret_cast<const uint4*>(Bt) + half * NWG + wn * 32 + cl;
+          const uint4* bl = bh + (size_t)(r1p / 8) * 2 * NWG;
           for (int c = 0; c < r1p / 8; ++c) {
-            const v8bf Bh = as_v8bf(bh[c * 2 * 32]);
-            const v8bf Bl = as_v8bf(bl[c * 2 * 32]);
+            const v8bf Bh = as_v8bf(bh[(size_t)c * 2 * NWG]);
+            const v8bf Bl = as_v8bf(bl[(size_t)c * 2 * NWG]);
             const uint4* ap = Ach + (int64_t)c * P.nbt * 128;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -434,12 +467,12 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
         } else {
           // rows in groups of four; the next group's A operand (or the next
           // tensor's first group) is in flight while this group's MFMAs run
-          const float* Brow = reinterpret_cast<const float*>(Bw) + half * 32 + cl;
+          const float* Brow = reinterpret_cast<const float*>(Bt) + half * NWG + wn * 32 + cl;
           for (int a0 = 0; a0 < r1; a0 += 4) {
             float ac[4][NB], bc[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              bc[e] = Brow[2 * min(a0 + e, r1 - 1) * 32];
+              bc[e] = Brow[2 * min(a0 + e, r1 - 1) * NWG];
 #pragma unroll
               for (int b = 0; b < NB; ++b) ac[e][b] = an[e][b];
             }
@@ -506,7 +539,7 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
   const int pw = wave - 4, ptid = tid - 256;
   const int64_t pbase = ((int64_t)k * P.tiles + tile) * P.m;
   Stage SR;
-  for (int st = 0; st < cnt + 3; ++st) {
+  for (int st = 0; st < cnt + 4; ++st) {
     // stage(st): loads issued first, in flight during mode3(st - 1)
     const bool do_stage = st < cnt;
     TensorMeta ts;
@@ -527,10 +560,10 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
       else
         mode3<ADJ>(P.cores + tb.g_off, CU, H, tb.r1, r1p, tb.r2, tb.r3, P.t3, xj, ptid);
     }
-    // adjoint: reduce the per-lane dots of tensor st - 3 (written one step
+    // adjoint: reduce the per-lane dots of tensor st - 4 (written one step
     // earlier) in a fixed order: 4 waves x 64 lanes
-    if (ADJ && pw == 0 && st >= 3 && st - 3 < cnt) {
-      const float2* d = dots + ((st - 3) & 1) * 256;
+    if (ADJ && pw == 0 && st >= 4 && st - 4 < cnt) {
+      const float2* d = dots + ((st - 4) & 1) * 256;
       float sr = 0.f, si = 0.f;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
@@ -543,7 +576,7 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
         sr += __shfl_xor(sr, off);
         si += __shfl_xor(si, off);
       }
-      if (lane == 0) P.out[pbase + jb + st - 3] = make_float2(sr, si);
+      if (lane == 0) P.out[pbase + jb + st - 4] = make_float2(sr, si);
     }
     if (do_stage) {
       float2* CU = CUbuf + (st & 1) * cue;
