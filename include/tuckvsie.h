@@ -210,15 +210,20 @@ tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
  *   op 0:  Y_c = Z_c X_c,    in[c] = X_c (m_c x nrhs[c]), out[c] = Y_c
  *   op 1:  X_c = Z_c^* Y_c,  in[c] = Y_c (q nv x nrhs[c]), out[c] = X_c
  * Every tensor is decompressed once per voxel tile and applied to all
- * right-hand sides on MFMA (FP32, whatever the plans' precision).
- * tv_batch_create builds the work queue (device memory it owns, ordered
- * longest job first) and is synchronous; plans must outlive the batch.
- * tv_batch_run queues one small counter-reset kernel and one persistent
- * kernel on `stream`: no allocation, no synchronisation and no memset, so
- * it may be captured into a hipGraph.  Pointer arrays are host arrays of
- * nplans device pointers (column-major, leading dimensions ld_in/ld_out);
- * outputs are overwritten.  ws: at least tv_batch_workspace_bytes bytes,
- * 16-byte aligned; concurrent runs need distinct workspaces.
+ * right-hand sides on MFMA (FP32, whatever the plans' precision).  With all
+ * ranks <= 32 (and, forward, n1 <= 96) the decompression runs on MFMA too,
+ * from G x3 U3 precomputed per (tensor, i3) into the workspace.
+ * tv_batch_create builds the work queue and the packed operands (device
+ * memory it owns, queue ordered longest job first) and is synchronous;
+ * plans must outlive the batch.
+ * tv_batch_run queues a counter-reset kernel, (MFMA path) the mode-3
+ * kernel, the persistent kernel and (op 1) a reduction kernel on `stream`:
+ * no allocation, no synchronisation and no memset, so it may be captured
+ * into a hipGraph.  Pointer arrays are host arrays of nplans device
+ * pointers (column-major, leading dimensions ld_in/ld_out); outputs are
+ * overwritten.  ws: at least tv_batch_workspace_bytes bytes (on the MFMA
+ * path this includes sum over tensors of r1 r2 n3 complex64), 16-byte
+ * aligned; concurrent runs need distinct workspaces.
  * Deterministic: fixed summation order, no floating-point atomics.
  * ---------------------------------------------------------------------- */
 #define TV_BATCH_MAX_PLANS 32

@@ -8,11 +8,14 @@
 //   forward  Y_tile(V x p) += T(V x 4) X(4 x p), four tensors per step,
 //   adjoint  W(p x 32)     += Y_tile^T(p x V) conj(T)(V x 32), 32 tensors,
 // where T holds decompressed tensor values Z^{kj} on the tile's V voxels.
-// Decompression is wave-local (each wave takes whole tensors: mode-3 on the
-// core, mode-2 per column, mode-1 per voxel row, eq. 6/7) so that a work
-// item needs only two workgroup barriers per step.  Work items are pulled
-// from a queue ordered longest first (most tensors), and the workgroups stay
-// resident until the queue is empty.
+// Two generations of kernels:
+//  * ranks <= 32: decompression on MFMA as well (batch_mode3, then
+//    batch_fwd_mfma / batch_adj_mfma below), eight waves per workgroup;
+//  * otherwise wave-local VALU decompression (each wave takes whole
+//    tensors: mode-3 on the core, mode-2 per column, mode-1 per voxel row,
+//    eq. 6/7), two workgroup barriers per step.
+// Work items are pulled from a queue ordered longest first (most tensors),
+// and the workgroups stay resident until the queue is empty.
 //
 // Complex products on real MFMA (v_mfma_f32_32x32x2f32) use the real forms
 //   [Yr | Yi] = [Tr Ti] [[Xr, Xi], [-Xi, Xr]]
@@ -26,6 +29,15 @@
 namespace tv {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Per tensor, for the MFMA decompression kernels ([k][j] like TensorMeta).
+struct BTensor {
+  int32_t r1, r2;
+  int64_t h_off;    // complex offset of H(i3 = 0) in the mode-3 cache
+  int64_t u1p_off;  // float offset of the packed U1 operand blocks
+  int64_t u2_off;   // complex offset of U2, row-major [i2][b]
+};
 
 struct BatchStatic {  // per plan, uploaded once
   const TensorMeta* meta;
@@ -34,6 +46,7 @@ struct BatchStatic {  // per plan, uploaded once
   const float2* u2t;
   const float2* u3t;
   int64_t m;
+  const BTensor* bt;  // MFMA kernels only
 };
 
 struct BatchArgs {
@@ -47,6 +60,11 @@ struct BatchArgs {
   int n1, n2, n3, n1p32, tiles2;
   int64_t nv;
   int r1max, r2max;
+  // MFMA kernels: mode-3 cache (workspace), packed U1, 16-row chunks per
+  // tensor in the packed U1, 16-row chunks per adjoint tile
+  float2* hcache;
+  const float* u1p;
+  int nch, nic;
   const float2* in[TV_BATCH_MAX_PLANS];
   float2* out[TV_BATCH_MAX_PLANS];
   int64_t ld_in[TV_BATCH_MAX_PLANS];
@@ -306,6 +324,451 @@ __global__ __launch_bounds__(256) void batch_adj_reduce(BatchArgs A, const int* 
 
 __global__ void reset_counter(int* c) { *c = 0; }
 
+// ---------------------------------------------------------------------------
+// MFMA decompression (batched kernels for ranks up to 32)
+//
+// On a voxel tile at one i3 and 8 consecutive i2 columns c0.., tensor j is
+//   T[i1][f] = sum_a U1[i1][a] B[a][f],  B[a][f] = sum_b H[a][b] U2[c0+f][b],
+//   H = G x3 U3[i3]                                   (eq. 6/7, modes 3, 2, 1).
+// H for every (tensor, i3) is computed once per run into the workspace
+// (batch_mode3), so a tile reads r1 r2 values instead of the whole core.
+// Modes 2 and 1 run on v_mfma_f32_16x16x4f32 (A lane l = A[l%16][l/16],
+// B lane l = B[l/16][l%16], D register r = D[4(l/16) + r][l%16]) with the
+// complex products in real form.  Columns are (f, part) = f + 8 part; the K
+// index k = l/16 is (pair member k/2, real/imaginary selector s = k%2), so
+// a K step t covers b (or a) = 2t and 2t + 1:
+//   mode 2: rows a,  A[a][(b,s)]  = s ? Hi : Hr,
+//           B[(b,s)][(f,p)] = p ? (s ? U2r : U2i) : (s ? -U2i : U2r)
+//   mode 1: rows i1, A[i1][(a,s)] = s ? U1i : U1r   (packed: batch_pack_u1),
+//           B[(a,s)][(f,p)] = p ? (s ? Br : Bi) : (s ? -Bi : Br)
+// so D[a][(f,p)] = Re/Im of (H U2^T)[a][f] and D[i1][(f,p)] = Re/Im T[i1][f].
+
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Mode 3 for every tensor of the batch and every i3:
+// hcache[h_off + i3 r1 r2 + a + r1 b] = sum_c G[a, b, c] U3[i3][c].
+// One workgroup per tensor; tlist[x] = {plan, k m + j}.
+__global__ __launch_bounds__(256) void batch_mode3(BatchArgs A, const int2* tlist) {
+  const int2 T = tlist[blockIdx.x];
+  const BatchStatic S = A.plans[T.x];
+  const TensorMeta M = S.meta[T.y];
+  const int64_t ho = S.bt[T.y].h_off;
+  const int r12 = M.r1 * M.r2, r3 = M.r3;
+  const float2* u3 = S.u3t + M.u3_off;
+  for (int task = threadIdx.x; task < r12; task += 256) {
+    float2 g[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      g[c] = c < r3 ? S.cores[M.g_off + task + (int64_t)r12 * c] : make_float2(0.f, 0.f);
+    for (int i3 = 0; i3 < A.n3; ++i3) {
+      float2 h = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        if (c < r3) h = bcfma(g[c], u3[(int64_t)i3 * r3 + c], h);
+      A.hcache[ho + (int64_t)i3 * r12 + task] = h;
+    }
+  }
+}
+
+// Operands of one tensor on one tile, loaded a step before they are used:
+// mode-2 A (H) and B (U2 rows c0..c0+7) lane values, x_j for this lane's
+// right-hand side, and what mode 1 needs of the metadata.
+struct DecOps {
+  float ha[2][16];
+  float ub[16];
+  float2 xv;
+  int r1, r2;
+  int64_t u1p;
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int4 uni_item(int4 v) {
+  return make_int4(uni(v.x), uni(v.y), uni(v.z), uni(v.w));
+}
+
+// Raw buffer loads with the hardware range check: an offset at or beyond
+// num_records bytes reads zero, so masked operands need neither a branch
+// nor a select after the load.  Word 3 is the gfx9 raw-dword format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+#define TV_OOB 0x40000000
+
+// Loads are unconditional and land in their final registers, so the
+// compiler neither branches around them nor waits for each one.  The x_j
+// load clamps the right-hand side (lanes beyond nrhs are never stored).
+__device__ __forceinline__ void dec_load(DecOps& o, const BTensor* bt, int64_t j, bool valid,
+                                         const float2* hc, int i3, int c0, int n2,
+                                         const float2* u2t, const float2* X, int64_t ldx,
+                                         int xr, int lane) {
+  o.r1 = o.r2 = 0;
+  o.u1p = 0;
+  if (!valid) return;
+  // read-only for the kernel's lifetime: constant address space, uniform
+  // index, so these are scalar loads (lgkmcnt, no drain of vector loads)
+  typedef const __attribute__((address_space(4))) BTensor CBT;
+  CBT* T = reinterpret_cast<CBT*>(reinterpret_cast<uintptr_t>(bt)) + j;
+  const int r1 = uni(T->r1), r2 = uni(T->r2);
+  const int64_t h_off = uni64(T->h_off), u2_off = uni64(T->u2_off);
+  o.r1 = r1;
+  o.r2 = r2;
+  o.u1p = uni64(T->u1p_off);
+  const int hi = lane >> 5, s = (lane >> 4) & 1;
+  // H(i3) of this tensor: r1 x r2 complex, element (a, b) at byte 8 (a + r1 b)
+  const __amdgpu_buffer_rsrc_t rh = brsrc(hc + h_off + (int64_t)i3 * r1 * r2, 8u * r1 * r2);
+#pragma unroll
+  for (int ab = 0; ab < 2; ++ab) {
+    if (16 * ab < r1) {
+      const int a = 16 * ab + (lane & 15);
+      const int base = (a < r1 ? 8 * a + 4 * s : TV_OOB) + 8 * r1 * hi;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) o.ha[ab][t] = bload(rh, base + 16 * r1 * t);
+    }
+  }
+  // U2 rows c0 .. c0 + 7 (those below n2): element (f, b) at byte 8 (f r2 + b)
+  const int f = lane & 7, part = (lane >> 3) & 1;
+  const int ncols = min(8, n2 - c0);
+  const __amdgpu_buffer_rsrc_t ru = brsrc(u2t + u2_off + (int64_t)c0 * r2, 8u * ncols * r2);
+  const int ubase = 8 * f * r2 + 4 * (part ^ s);
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int b = 2 * t + hi;
+    o.ub[t] = bload(ru, b < r2 ? ubase + 8 * b : TV_OOB);
+  }
+  if (X) o.xv = X[j + ldx * xr];
+}
+
+// sum_t a[t] b[t] over NP K steps on two accumulators; NP is a template
+// argument so that the chain is straight-line code (the wait counters then
+// stay exact instead of dropping to zero at branch joins).
+template <int NP>
+__device__ __forceinline__ v4f chain16(const float* a, const float* b) {
+  v4f d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NP; t += 2) {
+    d0 = mfma16(a[t], b[t], d0);
+    if (t + 1 < NP) d1 = mfma16(a[t + 1], b[t + 1], d1);
+  }
+  return d0 + d1;
+}
+
+__device__ __forceinline__ v4f chain16_n(int np, const float* a, const float* b) {
+  switch (np) {
+#define TV_CH(N) \
+  case N: return chain16<N>(a, b);
+    TV_CH(1) TV_CH(2) TV_CH(3) TV_CH(4) TV_CH(5) TV_CH(6) TV_CH(7) TV_CH(8)
+    TV_CH(9) TV_CH(10) TV_CH(11) TV_CH(12) TV_CH(13) TV_CH(14) TV_CH(15) TV_CH(16)
+#undef TV_CH
+  }
+  return v4f{0.f, 0.f, 0.f, 0.f};
+}
+
+// Mode 2 on MFMA into the wave's Bc[a][32]: columns f (Re), 8 + f (Im),
+// 16 + f (-Re, unused) and 24 + f (-Im), so that the mode-1 B operand is a
+// plain read.  The U2 operand's sign (-U2i at part 0, s = 1) is applied here.
+__device__ __forceinline__ void dec_mode2(const DecOps& o, float* Bc, int lane) {
+  const int np2 = (o.r2 + 1) >> 1;
+  const bool neg = ((lane >> 3) & 1) == 0 && ((lane >> 4) & 1) == 1;
+  float ub[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) ub[t] = neg ? -o.ub[t] : o.ub[t];
+#pragma unroll
+  for (int ab = 0; ab < 2; ++ab) {
+    if (16 * ab < o.r1) {
+      const v4f d = chain16_n(np2, o.ha[ab], ub);
+      float* dst = Bc + (16 * ab + 4 * (lane >> 4)) * 32 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        dst[32 * r] = d[r];
+        dst[32 * r + 16] = -d[r];
+      }
+    }
+  }
+}
+
+// Mode-1 B operand (the embedded B = H U2^T) for every K step, from Bc;
+// steps t >= (r1 + 1) / 2 are never issued.
+__device__ __forceinline__ void dec_bops(const float* Bc, float* bb, int lane) {
+  const int f = lane & 7, part = (lane >> 3) & 1, s = (lane >> 4) & 1;
+  const int col = f + (part == 0 ? (s ? 24 : 0) : (s ? 0 : 8));
+#pragma unroll
+  for (int t = 0; t < 16; ++t) bb[t] = Bc[(2 * t + (lane >> 5)) * 32 + col];
+}
+
+// U1 operand of 16-row chunk ic (packed lane order) for every K step; steps
+// t >= np1 read the following data (the packed buffer ends with 16 blocks of
+// padding) and are never issued.
+__device__ __forceinline__ void dec_u1ops(const float* u1p, int64_t off, int r1, int ic,
+                                          float* ua, int lane) {
+  const int np1 = (r1 + 1) >> 1;
+  const float* src = u1p + off + (int64_t)ic * np1 * 64 + lane;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) ua[t] = src[t * 64];
+}
+
+// Forward, MFMA decompression.  Item = (plan, component, tile of 8 columns
+// at one i3, right-hand-side group of 32); NB1 = n1p32 / 32 <= 3.  Waves
+// 4..7 produce: in step s wave 4 + w decompresses tensor 4s + w into
+// Ts[s&1][w], its operands loaded one step ahead (U1 chunk by chunk as the
+// previous tensor's chunks retire).  Waves 0..3 consume: in step s wave w
+// applies tensors 4(s-1).. to columns 2w, 2w+1 of the tile (2 NB1 blocks of
+// 32 voxels x 32 right-hand sides on v_mfma_f32_32x32x2f32).  One barrier
+// per step.
+template <int NB1>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+void batch_fwd_mfma(BatchArgs A) {
+  constexpr int NPW = 4, N1P = 32 * NB1, V = 8 * N1P, NCH = 2 * NB1, BPC = 2 * NB1;
+  extern __shared__ float4 bsm4[];
+  __shared__ int s_item;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
+  const bool producer = wave >= 4;
+  const int w = wave & 3;
+  float* Ts = reinterpret_cast<float*>(bsm4);                    // [2][NPW][2][V]
+  float2* Xs = reinterpret_cast<float2*>(Ts + 2 * NPW * 2 * V);  // [2][NPW][32]
+  float* Bc = reinterpret_cast<float*>(Xs + 2 * NPW * 32) + w * 1024;
+  // The two roles run separate item loops (same items, same barrier count
+  // per item), so that neither keeps the other's per-lane constants live.
+  if (!producer) {
+    for (;;) {
+      const int it = next_item(A.counter, &s_item);
+      if (it >= A.nitems) break;
+      const int4 I = uni_item(A.items[it]);
+      const int64_t m = A.plans[I.x].m;
+      const int nbat = (int)((m + 3) / 4);
+      v16f acc[BPC][2];
+#pragma unroll
+      for (int b = 0; b < BPC; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[b][0][i] = acc[b][1][i] = 0.f;
+      for (int s = 0; s <= nbat; ++s) {
+        if (s > 0) {
+          const int pb = (s - 1) & 1;
+          const int nj = (int)min((int64_t)4, m - 4 * (int64_t)(s - 1));
+          for (int jj = 0; jj < nj; ++jj) {
+            const float2 xv = Xs[(pb * NPW + jj) * 32 + (lane & 31)];
+            const float b0 = lane < 32 ? xv.x : -xv.y;
+            const float b1 = lane < 32 ? xv.y : xv.x;
+            const float* tj = Ts + ((pb * NPW + jj) * 2 + (lane >> 5)) * V + 2 * w * N1P + (lane & 31);
+#pragma unroll
+            for (int b = 0; b < BPC; ++b) {
+              const float a = tj[32 * b];
+              acc[b][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[b][0], 0, 0, 0);
+              acc[b][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[b][1], 0, 0, 0);
+            }
+          }
+        }
+        __syncthreads();
+      }
+      const int rhs = I.w * 32 + (lane & 31);
+      if (rhs < A.nrhs[I.x]) {
+        const int k = I.y;
+        const int c0 = (I.z % A.tiles2) * 8, i3 = I.z / A.tiles2;
+        float2* Y = A.out[I.x] + A.ld_out[I.x] * rhs + (int64_t)k * A.nv +
+                    (int64_t)A.n1 * ((int64_t)A.n2 * i3) + 4 * (lane >> 5);
+#pragma unroll
+        for (int b = 0; b < BPC; ++b) {
+          const int col = c0 + 2 * w + b / NB1;
+          if (col < A.n2) {
+            float2* yb = Y + (int64_t)A.n1 * col + 32 * (b % NB1);
+            const int lim = A.n1 - 32 * (b % NB1) - 4 * (lane >> 5);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+              if (8 * (i >> 2) + (i & 3) < lim)
+                yb[8 * (i >> 2) + (i & 3)] = make_float2(acc[b][0][i], acc[b][1][i]);
+          }
+        }
+      }
+    }
+  } else {
+    float* tdst = Ts + (w * 2 + ((lane >> 3) & 1)) * V + (lane & 7) * N1P + 4 * (lane >> 4);
+    for (;;) {
+      const int it = next_item(A.counter, &s_item);
+      if (it >= A.nitems) break;
+      const int4 I = uni_item(A.items[it]);
+      const BatchStatic S = A.plans[I.x];
+      const int k = I.y;
+      const int c0 = (I.z % A.tiles2) * 8, i3 = I.z / A.tiles2;
+      const int64_t m = S.m;
+      const int nbat = (int)((m + 3) / 4);
+      const float2* X = A.in[I.x];
+      const int64_t ldx = A.ld_in[I.x];
+      const int xr = min(I.w * 32 + (lane & 31), A.nrhs[I.x] - 1);
+      const BTensor* bt = S.bt + (int64_t)k * S.m;
+      DecOps op;
+      float ua[NCH][16];
+      dec_load(op, bt, w, w < m, A.hcache, i3, c0, A.n2, S.u2t, X, ldx, xr, lane);
+      if (w < m)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
+      for (int s = 0; s <= nbat; ++s) {
+        const int buf = s & 1;
+        const int64_t j = 4 * (int64_t)s + w;
+        if (s < nbat && j < m) {
+          const int np1 = (op.r1 + 1) >> 1;
+          dec_mode2(op, Bc, lane);
+          if (lane < 32) Xs[(buf * NPW + w) * 32 + lane] = op.xv;
+          const bool nv = s + 1 < nbat && j + 4 < m;
+          dec_load(op, bt, j + 4, nv, A.hcache, i3, c0, A.n2, S.u2t, X, ldx, xr, lane);
+          wave_sync();
+          float bb[16];
+          dec_bops(Bc, bb, lane);
+          float* dst = tdst + buf * NPW * 2 * V;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const v4f d = chain16_n(np1, ua[c], bb);
+            *reinterpret_cast<float4*>(dst + 16 * c) = make_float4(d[0], d[1], d[2], d[3]);
+            if (nv) dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Adjoint, MFMA decompression.  Item = (plan, component and slice of the
+// tiles, chunk of 32 columns, right-hand-side group); a tile is 16 NI rows
+// of i1 x 8 columns at one i3.  Per tile each wave decompresses four of the
+// 32 tensors into Tb[f][i1][jj] (row stride 33 complex, column stride
+// 16 NI + 1 rows, against LDS bank conflicts); then wave w contracts column
+// f = w: W(32 rhs x 32 columns) += Y^T conj(T) on v_mfma_f32_32x32x2f32, one
+// voxel per pair of MFMAs.  The eight waves' W are summed in a fixed order.
+template <int NI>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+void batch_adj_mfma(BatchArgs A) {
+  constexpr int NW = 8, IB = 16 * NI, RS = IB + 1, TS = 33;
+  extern __shared__ float4 bsm4[];
+  __shared__ int s_item;
+  const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
+  float2* Tb = reinterpret_cast<float2*>(bsm4);  // [8][RS][TS]
+  float* Bc = reinterpret_cast<float*>(Tb + 8 * RS * TS) + wave * 1024;
+  const int tiles = A.nic * A.tiles2 * A.n3;
+  for (;;) {
+    const int it = next_item(A.counter, &s_item);
+    if (it >= A.nitems) break;
+    const int4 I = uni_item(A.items[it]);
+    const BatchStatic S = A.plans[I.x];
+    const int k = I.y / A.tsplit, slice = I.y % A.tsplit;
+    const int tb0 = (int)((int64_t)tiles * slice / A.tsplit);
+    const int tb1 = (int)((int64_t)tiles * (slice + 1) / A.tsplit);
+    const int64_t j0 = (int64_t)I.z * 32;
+    const int jc = (int)min((int64_t)32, S.m - j0);
+    const int rhs = min(I.w * 32 + (lane & 31), A.nrhs[I.x] - 1);
+    const float2* Y = A.in[I.x] + A.ld_in[I.x] * rhs + (int64_t)k * A.nv;
+    const BTensor* bt = S.bt + (int64_t)k * S.m + j0;
+    v16f acc[2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[0][i] = acc[1][i] = 0.f;
+    // tile t: i1 chunk (t % nic), column group ((t / nic) % tiles2), i3
+    auto tile_pos = [&](int t, int& ic0, int& c0, int& i3) {
+      ic0 = (t % A.nic) * NI;
+      const int rest = t / A.nic;
+      c0 = (rest % A.tiles2) * 8;
+      i3 = rest / A.tiles2;
+    };
+    // this wave's tensors of the chunk: 4 wave + e, e < nvalid; the operands
+    // of the next one (or of the first one on the next tile) are loaded
+    // while the current one is decompressed, U1 chunk by chunk as each
+    // chunk's registers retire
+    const int nvalid = max(0, min(4, jc - 4 * wave));
+    DecOps op;
+    float ua[NI][16];
+    if (nvalid > 0 && tb0 < tb1) {
+      int ic0, c0, i3;
+      tile_pos(tb0, ic0, c0, i3);
+      dec_load(op, bt, 4 * wave, true, A.hcache, i3, c0, A.n2, S.u2t, nullptr, 0, 0, lane);
+#pragma unroll
+      for (int ic = 0; ic < NI; ++ic) dec_u1ops(A.u1p, op.u1p, op.r1, ic0 + ic, ua[ic], lane);
+    }
+    for (int tile = tb0; tile < tb1; ++tile) {
+      int ic0, c0, i3;
+      tile_pos(tile, ic0, c0, i3);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (e < nvalid) {
+          const int jj = 4 * wave + e;
+          const int np1 = (op.r1 + 1) >> 1;
+          dec_mode2(op, Bc, lane);
+          const bool last = e + 1 == nvalid;
+          const int nt = last ? tile + 1 : tile, ne = last ? 0 : e + 1;
+          int nic0, nc0, ni3;
+          tile_pos(nt, nic0, nc0, ni3);
+          const bool v = nt < tb1;
+          dec_load(op, bt, 4 * wave + ne, v, A.hcache, ni3, nc0, A.n2, S.u2t, nullptr, 0, 0, lane);
+          wave_sync();
+          float bb[16];
+          dec_bops(Bc, bb, lane);
+          float* dst = reinterpret_cast<float*>(Tb) +
+                       (((lane & 7) * RS + 4 * (lane >> 4)) * TS + jj) * 2 + ((lane >> 3) & 1);
+#pragma unroll
+          for (int ic = 0; ic < NI; ++ic) {
+            const v4f d = chain16_n(np1, ua[ic], bb);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[(16 * ic + r) * TS * 2] = d[r];
+            if (v) dec_u1ops(A.u1p, op.u1p, op.r1, nic0 + ic, ua[ic], lane);
+          }
+        }
+      }
+      __syncthreads();
+      // column f = wave of the tile
+      // (T is zero on rows i1 >= n1 and columns >= n2, so clamped reads of
+      // y there contribute nothing; lanes beyond nrhs are never stored)
+      const int col = min(c0 + wave, A.n2 - 1);
+      const float2* yc = Y + (int64_t)A.n1 * (col + (int64_t)A.n2 * i3);
+      const float2* tc = Tb + wave * RS * TS + (lane & 31);
+#pragma unroll 8
+      for (int i = 0; i < IB; ++i) {
+        const int i1 = min(16 * ic0 + i, A.n1 - 1);
+        const float2 yv = yc[i1];
+        const float2 tb = tc[i * TS];
+        const float bv = lane < 32 ? tb.x : -tb.y;
+        const float a0 = lane < 32 ? yv.x : -yv.y;
+        const float a1 = lane < 32 ? yv.y : yv.x;
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[1], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    // sum the eight waves' W in a fixed order
+    float* red = reinterpret_cast<float*>(Tb);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) red[((wave * 2 + mb) * 16 + i) * 64 + lane] = acc[mb][i];
+    __syncthreads();
+    if (wave == 0) {
+      float2* blk = A.partial + (int64_t)it * 1024;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        float wr = 0.f, wi = 0.f;
+        for (int w = 0; w < NW; ++w) {
+          wr += red[((w * 2 + 0) * 16 + i) * 64 + lane];
+          wi += red[((w * 2 + 1) * 16 + i) * 64 + lane];
+        }
+        const int rl = 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        blk[rl * 32 + (lane & 31)] = make_float2(wr, wi);
+      }
+    }
+  }
+}
+
+size_t batch_mfma_lds_bytes(int op, int nb) {
+  if (op == 0) return sizeof(float) * (2 * 4 * 2 * (8 * 32 * nb) + 2 * 4 * 64 + 4 * 1024);
+  const size_t tb = sizeof(float2) * 8 * (16 * nb + 1) * 33;
+  return std::max(tb, sizeof(float) * 8 * 2 * 16 * 64) + sizeof(float) * 8 * 1024;
+}
+
 size_t batch_lds_bytes(int op, int ncol, int n1p32, int r1max, int r2max) {
   const size_t per = (size_t)4 * (r1max * r2max + r1max * ncol);
   const size_t V = (size_t)n1p32 * ncol;
@@ -364,7 +827,32 @@ struct tv_batch_s {
   int nred = 0, nper = 0;
   int* d_red_list = nullptr;
   int4* d_red_out = nullptr;
+  // MFMA decompression kernels (ranks <= 32): per-tensor records, packed U1,
+  // tensor list of the mode-3 kernel, mode-3 cache size in complex values
+  bool mfma = false;
+  int nch = 0, nic = 0;
+  int ntensors = 0;
+  int64_t hcache = 0;
+  BTensor* d_bt = nullptr;
+  float* d_u1p = nullptr;
+  int2* d_tlist = nullptr;
 };
+
+static void batch_free(tv_batch_s* b) {
+  hipFree(b->d_plans);
+  hipFree(b->d_items);
+  hipFree(b->d_red_list);
+  hipFree(b->d_red_out);
+  hipFree(b->d_bt);
+  hipFree(b->d_u1p);
+  hipFree(b->d_tlist);
+  delete b;
+}
+
+static size_t batch_hcache_offset(const tv_batch_s* b) {
+  const size_t head = 256 + (b->op == 1 ? (size_t)b->nitems * 1024 * 8 : 0);
+  return (head + 255) / 256 * 256;
+}
 
 extern "C" {
 
@@ -395,48 +883,66 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   b->grid = g;
   b->n1p32 = (g.n1 + 31) / 32 * 32;
   const int nb1 = b->n1p32 / 32;
-  if (op == 0) {
+  int r3max = 1;
+  for (int c = 0; c < nplans; ++c) {
+    b->r1max = std::max(b->r1max, plans[c]->max_r[0]);
+    b->r2max = std::max(b->r2max, plans[c]->max_r[1]);
+    r3max = std::max(r3max, plans[c]->max_r[2]);
+    b->m.push_back(plans[c]->grid.m);
+    b->nrhs.push_back(nrhs[c]);
+  }
+  // MFMA decompression for ranks up to 32 (forward: n1 <= 96); otherwise the
+  // wave-local VALU decompression kernels
+  b->mfma = b->r1max <= 32 && b->r2max <= 32 && r3max <= 32 && (op == 1 || nb1 <= 3);
+  if (b->mfma) {
+    b->ncol = 8;
+    if (op == 0) {
+      b->bpw = nb1;
+      b->fn = nb1 == 1 ? batch_fwd_mfma<1> : nb1 == 2 ? batch_fwd_mfma<2> : batch_fwd_mfma<3>;
+    } else {
+      const int ni = std::min(3, (g.n1 + 15) / 16);
+      b->bpw = ni;
+      b->nic = (g.n1 + 16 * ni - 1) / (16 * ni);
+      b->fn = ni == 1 ? batch_adj_mfma<1> : ni == 2 ? batch_adj_mfma<2> : batch_adj_mfma<3>;
+    }
+    b->nch = std::max(b->n1p32 / 16, op == 1 ? b->nic * b->bpw : 0);
+    b->lds = batch_mfma_lds_bytes(op, b->bpw);
+  } else if (op == 0) {
     // columns per tile: the widest power of two whose nb1 * ncol 32-voxel
     // blocks split evenly over the 4 waves with at most 3 blocks per wave
     // (each block holds 32 accumulator registers per real/imaginary half)
     int ncol = 0;
     for (int c = 16; c >= 1 && !ncol; c /= 2)
       if ((nb1 * c) % 4 == 0 && nb1 * c / 4 <= 3) ncol = c;
-    if (!ncol) {
-      delete b;
-      return set_error(TV_ERR_NOT_SUPPORTED, "no batched tile for this n1");
-    }
     b->ncol = ncol;
-    b->bpw = nb1 * ncol / 4;
+    b->bpw = ncol ? nb1 * ncol / 4 : 0;
+    b->fn = ncol ? pick_fwd(b->ncol, b->bpw) : nullptr;
+    b->lds = batch_lds_bytes(op, b->ncol, b->n1p32, b->r1max, b->r2max);
   } else {
     int ncol = 1;
     while (ncol * 2 * b->n1p32 <= 384) ncol *= 2;
     b->ncol = ncol;
+    b->fn = pick_adj(b->ncol);
+    b->lds = batch_lds_bytes(op, b->ncol, b->n1p32, b->r1max, b->r2max);
   }
-  b->tiles2 = (g.n2 + b->ncol - 1) / b->ncol;
-  for (int c = 0; c < nplans; ++c) {
-    b->r1max = std::max(b->r1max, plans[c]->max_r[0]);
-    b->r2max = std::max(b->r2max, plans[c]->max_r[1]);
-    b->m.push_back(plans[c]->grid.m);
-    b->nrhs.push_back(nrhs[c]);
-  }
-  b->lds = batch_lds_bytes(op, b->ncol, b->n1p32, b->r1max, b->r2max);
-  b->fn = op == 0 ? pick_fwd(b->ncol, b->bpw) : pick_adj(b->ncol);
   if (!b->fn || b->lds > 160 * 1024) {
     delete b;
     return set_error(TV_ERR_NOT_SUPPORTED, "no batched kernel for these sizes and ranks");
   }
+  const int threads = b->mfma ? 512 : 256;
+  b->tiles2 = (g.n2 + b->ncol - 1) / b->ncol;
   // work items, longest first (most tensors per item); the adjoint splits
   // the voxel tiles of each (plan, component, chunk) into tsplit slices so
   // that there are enough items to fill the device
   std::vector<int> order(nplans);
   for (int c = 0; c < nplans; ++c) order[c] = c;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->m[x] > b->m[y]; });
-  const int tiles = b->tiles2 * g.n3;
+  const int tiles = b->tiles2 * g.n3 * (b->mfma && op == 1 ? b->nic : 1);
   if (op == 1) {
+    const int64_t target = b->mfma ? 4096 : 2048;
     int64_t base = 0;
     for (int c = 0; c < nplans; ++c) base += (int64_t)g.q * ((b->m[c] + 31) / 32) * ((nrhs[c] + 31) / 32);
-    b->tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (2048 + base - 1) / base));
+    b->tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (target + base - 1) / base));
   }
   std::vector<int4> items;
   std::vector<int> red_list;
@@ -467,11 +973,74 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     return set_error(TV_ERR_NOT_SUPPORTED, "too many work items");
   }
   b->nitems = (int)items.size();
+  // MFMA kernels: per-tensor records, the mode-3 cache layout and U1 packed
+  // in the 16x16x4 A-operand lane order, u1p[off + (ic np1 + t) 64 + l] =
+  // Re/Im (s = (l/16)%2) of U1[16 ic + l%16][2t + l/32], zero outside
+  std::vector<std::vector<BTensor>> bts(nplans);
+  std::vector<float> u1p;
+  std::vector<int2> tlist;
+  if (b->mfma) {
+    size_t u1n = 0;
+    for (int c = 0; c < nplans; ++c) {
+      const tv_plan_s* P = plans[c];
+      for (int64_t t = 0; t < (int64_t)g.q * P->grid.m; ++t)
+        u1n += (size_t)b->nch * ((P->ranks[3 * t] + 1) / 2) * 64;
+    }
+    u1p.assign(u1n + 16 * 64, 0.f);  // padding read by steps beyond np1
+    size_t u1o = 0;
+    for (int c = 0; c < nplans; ++c) {
+      const tv_plan_s* P = plans[c];
+      const int64_t m = P->grid.m;
+      bts[c].resize((size_t)g.q * m);
+      for (int k = 0; k < g.q; ++k)
+        for (int64_t j = 0; j < m; ++j) {
+          const int64_t t = k + (int64_t)g.q * j;
+          const int r1 = P->ranks[3 * t], r2 = P->ranks[3 * t + 1], np1 = (r1 + 1) / 2;
+          BTensor& T = bts[c][(size_t)k * m + j];
+          T.r1 = r1;
+          T.r2 = r2;
+          T.h_off = b->hcache;
+          T.u1p_off = (int64_t)u1o;
+          T.u2_off = P->u2_off[t];
+          b->hcache += (int64_t)r1 * r2 * g.n3;
+          for (int ic = 0; ic < b->nch; ++ic)
+            for (int tt = 0; tt < np1; ++tt)
+              for (int l = 0; l < 64; ++l) {
+                const int i1 = 16 * ic + (l & 15), a = 2 * tt + (l >> 5), sp = (l >> 4) & 1;
+                if (i1 < g.n1 && a < r1)
+                  u1p[u1o + ((size_t)ic * np1 + tt) * 64 + l] =
+                      (float)P->u1[2 * (P->u1_off[t] + i1 + (size_t)g.n1 * a) + sp];
+              }
+          u1o += (size_t)b->nch * np1 * 64;
+          tlist.push_back(make_int2(c, (int)(k * m + j)));
+        }
+    }
+    b->ntensors = (int)tlist.size();
+  }
   std::vector<BatchStatic> st(nplans);
   for (int c = 0; c < nplans; ++c)
     st[c] = BatchStatic{plans[c]->d_meta, plans[c]->d_cores, plans[c]->d_u1t, plans[c]->d_u2t,
-                        plans[c]->d_u3t, plans[c]->grid.m};
-  hipError_t e = hipMalloc((void**)&b->d_plans, st.size() * sizeof(BatchStatic));
+                        plans[c]->d_u3t, plans[c]->grid.m, nullptr};
+  hipError_t e = hipSuccess;
+  if (b->mfma) {
+    size_t nbt = 0;
+    for (int c = 0; c < nplans; ++c) nbt += bts[c].size();
+    e = hipMalloc((void**)&b->d_bt, nbt * sizeof(BTensor));
+    size_t o = 0;
+    for (int c = 0; c < nplans && e == hipSuccess; ++c) {
+      st[c].bt = b->d_bt + o;
+      e = hipMemcpy(b->d_bt + o, bts[c].data(), bts[c].size() * sizeof(BTensor),
+                    hipMemcpyHostToDevice);
+      o += bts[c].size();
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_u1p, std::max<size_t>(1, u1p.size()) * sizeof(float));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_u1p, u1p.data(), u1p.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_tlist, tlist.size() * sizeof(int2));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_tlist, tlist.data(), tlist.size() * sizeof(int2), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_plans, st.size() * sizeof(BatchStatic));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_items, items.size() * sizeof(int4));
   if (e == hipSuccess)
     e = hipMemcpy(b->d_plans, st.data(), st.size() * sizeof(BatchStatic), hipMemcpyHostToDevice);
@@ -494,13 +1063,9 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)b->fn, 256, b->lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)b->fn, threads, b->lds);
   if (e != hipSuccess) {
-    hipFree(b->d_plans);
-    hipFree(b->d_items);
-    hipFree(b->d_red_list);
-    hipFree(b->d_red_out);
-    delete b;
+    batch_free(b);
     return hip_error(e, "tv_batch_create");
   }
   b->grid_blocks = std::max(1, std::min(b->nitems, cus * std::max(per_cu, 1)));
@@ -511,8 +1076,10 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
 tv_status tv_batch_workspace_bytes(tv_batch b, size_t* bytes) {
   clear_error();
   if (!b || !bytes) return set_error(TV_ERR_INVALID_ARG, "batch and bytes must be non-NULL");
-  // the work-queue counter, then (adjoint) one 32 x 32 complex64 block per item
-  *bytes = 256 + (b->op == 1 ? (size_t)b->nitems * 1024 * 8 : 0);
+  // the work-queue counter, (adjoint) one 32 x 32 complex64 block per item,
+  // then (MFMA kernels) the mode-3 cache, sum over tensors of r1 r2 n3 complex64
+  *bytes = b->mfma ? batch_hcache_offset(b) + (size_t)b->hcache * 8
+                   : 256 + (b->op == 1 ? (size_t)b->nitems * 1024 * 8 : 0);
   return TV_OK;
 }
 
@@ -540,6 +1107,10 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   A.nv = (int64_t)b->grid.n1 * b->grid.n2 * b->grid.n3;
   A.r1max = b->r1max;
   A.r2max = b->r2max;
+  A.hcache = b->mfma ? (float2*)((char*)ws + batch_hcache_offset(b)) : nullptr;
+  A.u1p = b->d_u1p;
+  A.nch = b->nch;
+  A.nic = b->nic;
   const int64_t rows = (int64_t)b->grid.q * A.nv;
   for (int c = 0; c < b->nplans; ++c) {
     const int64_t rin = b->op == 0 ? b->m[c] : rows, rout = b->op == 0 ? rows : b->m[c];
@@ -558,7 +1129,14 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, A.counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "reset_counter launch");
-  hipLaunchKernelGGL(b->fn, dim3((unsigned)b->grid_blocks), dim3(256), b->lds, st, A);
+  if (b->mfma) {
+    hipLaunchKernelGGL(batch_mode3, dim3((unsigned)b->ntensors), dim3(256), 0, st, A,
+                       (const int2*)b->d_tlist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "mode-3 kernel launch");
+  }
+  hipLaunchKernelGGL(b->fn, dim3((unsigned)b->grid_blocks), dim3(b->mfma ? 512 : 256), b->lds,
+                     st, A);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "batched kernel launch");
   if (b->op == 1) {
@@ -573,11 +1151,7 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
 tv_status tv_batch_destroy(tv_batch b) {
   clear_error();
   if (!b) return TV_OK;
-  hipFree(b->d_plans);
-  hipFree(b->d_items);
-  hipFree(b->d_red_list);
-  hipFree(b->d_red_out);
-  delete b;
+  batch_free(b);
   return TV_OK;
 }
 

@@ -95,3 +95,58 @@ def test_batch_graph_replay(gpu_lib, c4s):
     lib.tv_batch_destroy(b)
     for c, S in enumerate(structs):
         assert rel_err(eager[c], om.alg1(S, X[c].cpu().numpy())) <= 1e-5
+
+
+# Shapes chosen to reach every batched kernel: forward with n1p32 / 32 = 3,
+# 2, 1 (MFMA decompression) and n1 = 128 (wave-local decompression), adjoint
+# with 48-, 48-, 16- and 48-row i1 chunks; ragged column groups (n2 not a
+# multiple of 8), counts of tensors off the 4- and 32-multiples, ranks above
+# 16 (two 16-row a-blocks) and odd ranks; the last case has ranks above 32
+# and runs the VALU decompression in both directions.
+MFMA_CASES = [
+    ((96, 20, 7), 3, (37, 9), 32, 41),
+    ((40, 9, 5), 1, (6, 3), 20, 42),
+    ((13, 17, 3), 2, (70, 5), 13, 43),
+    ((128, 6, 4), 1, (5, 4), 8, 44),
+    ((24, 20, 36), 1, (4, 2), 36, 45),
+]
+
+
+@pytest.mark.parametrize("dims,q,ms,rmax,seed", MFMA_CASES)
+def test_batch_kernels_against_oracle(gpu_lib, dims, q, ms, rmax, seed):
+    import torch
+    from paper_2103_06393_amd.ops import TuckerPlan
+    from tests.plans import random_struct
+    structs = [random_struct(dims, q, m, rmax, seed + 10 * c) for c, m in enumerate(ms)]
+    plans = [TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S)) for S in structs]
+    nrhs = [33, 1][:len(plans)]
+    X = [workloads.complex_normal((S.m, n), 500 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    Y = [workloads.complex_normal((S.q * S.nv, n), 600 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    cx = lambda a: torch.from_numpy(a.astype(np.complex64)).cuda()  # noqa: E731
+    print(f"batched kernels dims={dims} q={q} m={ms} rmax={rmax}", flush=True)
+    got_f = _run(plans, 0, [cx(x) for x in X], nrhs)
+    got_a = _run(plans, 1, [cx(y) for y in Y], nrhs)
+    for c, S in enumerate(structs):
+        assert rel_err(got_f[c], om.alg1(S, X[c])) <= 1e-5, ("forward", c)
+        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
+
+
+def test_batch_adjoint_items_span_tiles(gpu_lib):
+    """Enough work that each adjoint item sweeps several voxel tiles, with
+    partial 32-column chunks (waves owning 0, 1 or 4 columns), so that the
+    operand prefetch across tiles is exercised; forward checked too."""
+    import torch
+    from paper_2103_06393_amd.ops import TuckerPlan
+    from tests.plans import random_struct
+    dims, q = (40, 16, 120), 3
+    ms, nrhs = (40, 33, 9, 64), [40, 33, 7, 64]
+    structs = [random_struct(dims, q, m, 24, 70 + c) for c, m in enumerate(ms)]
+    plans = [TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S)) for S in structs]
+    X = [workloads.complex_normal((S.m, n), 700 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    Y = [workloads.complex_normal((S.q * S.nv, n), 800 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    cx = lambda a: torch.from_numpy(a.astype(np.complex64)).cuda()  # noqa: E731
+    got_f = _run(plans, 0, [cx(x) for x in X], nrhs)
+    got_a = _run(plans, 1, [cx(y) for y in Y], nrhs)
+    for c, S in enumerate(structs):
+        assert rel_err(got_f[c], om.alg1(S, X[c])) <= 1e-5, ("forward", c)
+        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
