@@ -32,11 +32,13 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Per tensor, for the MFMA decompression kernels ([k][j] like TensorMeta).
+// Operands are stored in the MFMA lane order of the kernels, four K steps
+// per lane in 16 bytes ("quads"): a block of 64 lanes x 4 floats = 1 KB.
 struct BTensor {
   int32_t r1, r2;
-  int64_t h_off;    // complex offset of H(i3 = 0) in the mode-3 cache
-  int64_t u1p_off;  // float offset of the packed U1 operand blocks
-  int64_t u2_off;   // complex offset of U2, row-major [i2][b]
+  int64_t h_off;    // float offset of H(i3 = 0) in the mode-3 cache
+  int64_t u1p_off;  // float offset of the packed U1 blocks
+  int64_t u2p_off;  // float offset of the packed U2 blocks
 };
 
 struct BatchStatic {  // per plan, uploaded once
@@ -62,8 +64,9 @@ struct BatchArgs {
   int r1max, r2max;
   // MFMA kernels: mode-3 cache (workspace), packed U1, 16-row chunks per
   // tensor in the packed U1, 16-row chunks per adjoint tile
-  float2* hcache;
+  float* hcache;
   const float* u1p;
+  const float* u2p;
   int nch, nic;
   const float2* in[TV_BATCH_MAX_PLANS];
   float2* out[TV_BATCH_MAX_PLANS];
@@ -347,27 +350,57 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Mode 3 for every tensor of the batch and every i3:
-// hcache[h_off + i3 r1 r2 + a + r1 b] = sum_c G[a, b, c] U3[i3][c].
-// One workgroup per tensor; tlist[x] = {plan, k m + j}.
+// Packed operand layouts (np = (r + 1) / 2 K steps, nq = (np + 3) / 4 quads,
+// nab = (r1 + 15) / 16 row blocks of 16; value 0 outside the ranks/grid):
+//   H   [i3][ab < nab][q < nq2][lane][4]: step t = 4q + i of lane l holds
+//       Re/Im (s = (l/16)%2) of H[16 ab + l%16][2t + l/32]          (mode 2 A)
+//   U2  [cg][q < nq2][lane][4]: Re/Im (part ^ s) of U2[8 cg + l%8][2t + l/32],
+//       part = (l/8)%2; the sign of -U2i is applied at the MFMA      (mode 2 B)
+//   U1  [ic][q < nq1][lane][4]: Re/Im (s) of U1[16 ic + l%16][2t + l/32]   (mode 1 A)
+
+// Mode 3 for every tensor of the batch and every i3, written in the packed
+// H layout: H[a, b] = sum_c G[a, b, c] U3[i3][c].  One workgroup per tensor,
+// tlist[x] = {plan, k m + j}.  A thread computes one complex entry (both of
+// its packed floats) for 16 consecutive i3 from the core fibre G[a, b, :]
+// held in registers; U3 (n3 x r3) is staged in LDS when it fits (LDSU3).
+template <bool LDSU3>
 __global__ __launch_bounds__(256) void batch_mode3(BatchArgs A, const int2* tlist) {
+  extern __shared__ float2 u3s[];
   const int2 T = tlist[blockIdx.x];
   const BatchStatic S = A.plans[T.x];
   const TensorMeta M = S.meta[T.y];
   const int64_t ho = S.bt[T.y].h_off;
-  const int r12 = M.r1 * M.r2, r3 = M.r3;
+  const int r1 = M.r1, r2 = M.r2, r12 = r1 * r2, r3 = M.r3, n3 = A.n3;
+  const int nq2 = (((r2 + 1) >> 1) + 3) >> 2, hq = ((r1 + 15) >> 4) * nq2;
   const float2* u3 = S.u3t + M.u3_off;
-  for (int task = threadIdx.x; task < r12; task += 256) {
+  if (LDSU3) {
+    for (int i = threadIdx.x; i < n3 * r3; i += 256) u3s[i] = u3[i];
+    __syncthreads();
+  }
+  const int nblk = (n3 + 15) / 16;
+  // entry e: block e / 128 (= ab nq2 + q), lane l with bit 4 (s) clear, step
+  // in quad i; the real part goes to lane l, the imaginary part to l + 16
+  for (int item = threadIdx.x; item < hq * 128 * nblk; item += 256) {
+    const int e = item % (hq * 128), i30 = 16 * (item / (hq * 128));
+    const int blk = e >> 7, rem = e & 127, i = rem & 3, lo = rem >> 2;
+    const int l = (lo & 15) | ((lo >> 4) << 5);
+    const int ab = blk / nq2, q = blk % nq2;
+    const int a = 16 * ab + (l & 15), bb = 2 * (4 * q + i) + (l >> 5);
+    const bool ok = a < r1 && bb < r2;
     float2 g[32];
 #pragma unroll
     for (int c = 0; c < 32; ++c)
-      g[c] = c < r3 ? S.cores[M.g_off + task + (int64_t)r12 * c] : make_float2(0.f, 0.f);
-    for (int i3 = 0; i3 < A.n3; ++i3) {
+      g[c] = ok && c < r3 ? S.cores[M.g_off + a + r1 * bb + (int64_t)r12 * c] : make_float2(0.f, 0.f);
+    const int64_t p0 = ho + (int64_t)blk * 256 + l * 4 + i;
+    const int i3e = min(i30 + 16, n3);
+    for (int i3 = i30; i3 < i3e; ++i3) {
       float2 h = make_float2(0.f, 0.f);
 #pragma unroll
       for (int c = 0; c < 32; ++c)
-        if (c < r3) h = bcfma(g[c], u3[(int64_t)i3 * r3 + c], h);
-      A.hcache[ho + (int64_t)i3 * r12 + task] = h;
+        if (c < r3) h = bcfma(g[c], LDSU3 ? u3s[i3 * r3 + c] : u3[i3 * r3 + c], h);
+      float* dst = A.hcache + p0 + (int64_t)i3 * hq * 256;
+      dst[0] = h.x;
+      dst[64] = h.y;
     }
   }
 }
@@ -403,50 +436,50 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* p, uint32_t 
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off) {
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
+// four K steps t = 4q .. 4q + 3 of one packed quad block into dst[4q ..]
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, int off, float* dst) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  dst[0] = __uint_as_float(v[0]);
+  dst[1] = __uint_as_float(v[1]);
+  dst[2] = __uint_as_float(v[2]);
+  dst[3] = __uint_as_float(v[3]);
+}
 #define TV_OOB 0x40000000
 
 // Loads are unconditional and land in their final registers, so the
-// compiler neither branches around them nor waits for each one.  The x_j
-// load clamps the right-hand side (lanes beyond nrhs are never stored).
-__device__ __forceinline__ void dec_load(DecOps& o, const BTensor* bt, int64_t j, bool valid,
-                                         const float2* hc, int i3, int c0, int n2,
-                                         const float2* u2t, const float2* X, int64_t ldx,
-                                         int xr, int lane) {
-  o.r1 = o.r2 = 0;
-  o.u1p = 0;
-  if (!valid) return;
+// compiler neither branches around them nor waits for each one.  Callers
+// pass an index that is always valid (clamped) and discard what they do not
+// use: every path through a loop then issues the same loads in the same
+// order, which keeps the wait counts exact at the joins.  The x_j load (WX)
+// clamps the right-hand side (lanes beyond nrhs are never stored).
+template <bool WX>
+__device__ __forceinline__ void dec_load(DecOps& o, const BTensor* bt, int64_t j,
+                                         const float* hc, const float* u2p, int i3, int c0,
+                                         const float2* X, int64_t ldx, int xr, int lane) {
   // read-only for the kernel's lifetime: constant address space, uniform
   // index, so these are scalar loads (lgkmcnt, no drain of vector loads)
   typedef const __attribute__((address_space(4))) BTensor CBT;
   CBT* T = reinterpret_cast<CBT*>(reinterpret_cast<uintptr_t>(bt)) + j;
   const int r1 = uni(T->r1), r2 = uni(T->r2);
-  const int64_t h_off = uni64(T->h_off), u2_off = uni64(T->u2_off);
+  const int64_t h_off = uni64(T->h_off), u2p_off = uni64(T->u2p_off);
   o.r1 = r1;
   o.r2 = r2;
   o.u1p = uni64(T->u1p_off);
-  const int hi = lane >> 5, s = (lane >> 4) & 1;
-  // H(i3) of this tensor: r1 x r2 complex, element (a, b) at byte 8 (a + r1 b)
-  const __amdgpu_buffer_rsrc_t rh = brsrc(hc + h_off + (int64_t)i3 * r1 * r2, 8u * r1 * r2);
+  const int nab = (r1 + 15) >> 4, nq2 = (((r2 + 1) >> 1) + 3) >> 2;
+  // packed H(i3): nab x nq2 blocks; quads beyond are out of range (zero)
+  const __amdgpu_buffer_rsrc_t rh =
+      brsrc(hc + h_off + (int64_t)i3 * nab * nq2 * 256, 1024u * nab * nq2);
 #pragma unroll
-  for (int ab = 0; ab < 2; ++ab) {
-    if (16 * ab < r1) {
-      const int a = 16 * ab + (lane & 15);
-      const int base = (a < r1 ? 8 * a + 4 * s : TV_OOB) + 8 * r1 * hi;
+  for (int ab = 0; ab < 2; ++ab)
 #pragma unroll
-      for (int t = 0; t < 16; ++t) o.ha[ab][t] = bload(rh, base + 16 * r1 * t);
-    }
-  }
-  // U2 rows c0 .. c0 + 7 (those below n2): element (f, b) at byte 8 (f r2 + b)
-  const int f = lane & 7, part = (lane >> 3) & 1;
-  const int ncols = min(8, n2 - c0);
-  const __amdgpu_buffer_rsrc_t ru = brsrc(u2t + u2_off + (int64_t)c0 * r2, 8u * ncols * r2);
-  const int ubase = 8 * f * r2 + 4 * (part ^ s);
+    for (int q = 0; q < 4; ++q)
+      bload4(rh, ab < nab && q < nq2 ? ((ab * nq2 + q) * 64 + lane) * 16 : TV_OOB, &o.ha[ab][4 * q]);
+  // packed U2 of column group c0 / 8
+  const __amdgpu_buffer_rsrc_t ru = brsrc(u2p + u2p_off + (int64_t)(c0 >> 3) * nq2 * 256, 1024u * nq2);
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int b = 2 * t + hi;
-    o.ub[t] = bload(ru, b < r2 ? ubase + 8 * b : TV_OOB);
-  }
-  if (X) o.xv = X[j + ldx * xr];
+  for (int q = 0; q < 4; ++q) bload4(ru, q < nq2 ? (q * 64 + lane) * 16 : TV_OOB, &o.ub[4 * q]);
+  if (WX) o.xv = X[j + ldx * xr];
 }
 
 // sum_t a[t] b[t] over NP K steps on two accumulators; NP is a template
@@ -506,15 +539,16 @@ __device__ __forceinline__ void dec_bops(const float* Bc, float* bb, int lane) {
   for (int t = 0; t < 16; ++t) bb[t] = Bc[(2 * t + (lane >> 5)) * 32 + col];
 }
 
-// U1 operand of 16-row chunk ic (packed lane order) for every K step; steps
-// t >= np1 read the following data (the packed buffer ends with 16 blocks of
-// padding) and are never issued.
+// U1 operand of 16-row chunk ic for every K step (packed quads; quads
+// beyond nq1 are out of range and read zero; steps t >= np1 are never
+// issued as MFMAs).  All loads are issued on every path so that the wait
+// counts stay exact.
 __device__ __forceinline__ void dec_u1ops(const float* u1p, int64_t off, int r1, int ic,
                                           float* ua, int lane) {
-  const int np1 = (r1 + 1) >> 1;
-  const float* src = u1p + off + (int64_t)ic * np1 * 64 + lane;
+  const int nq1 = (((r1 + 1) >> 1) + 3) >> 2;
+  const __amdgpu_buffer_rsrc_t r = brsrc(u1p + off + (int64_t)ic * nq1 * 256, 1024u * nq1);
 #pragma unroll
-  for (int t = 0; t < 16; ++t) ua[t] = src[t * 64];
+  for (int q = 0; q < 4; ++q) bload4(r, q < nq1 ? (q * 64 + lane) * 16 : TV_OOB, &ua[4 * q]);
 }
 
 // Forward, MFMA decompression.  Item = (plan, component, tile of 8 columns
@@ -607,29 +641,34 @@ void batch_fwd_mfma(BatchArgs A) {
       const BTensor* bt = S.bt + (int64_t)k * S.m;
       DecOps op;
       float ua[NCH][16];
-      dec_load(op, bt, w, w < m, A.hcache, i3, c0, A.n2, S.u2t, X, ldx, xr, lane);
-      if (w < m)
+      // tensor indices are clamped to m - 1: loads are always issued, and
+      // only the MFMA and LDS work is skipped for tensors beyond m
+      dec_load<true>(op, bt, min((int64_t)w, m - 1), A.hcache, A.u2p, i3, c0, X, ldx, xr, lane);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
+      for (int c = 0; c < NCH; ++c) dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
       for (int s = 0; s <= nbat; ++s) {
         const int buf = s & 1;
         const int64_t j = 4 * (int64_t)s + w;
-        if (s < nbat && j < m) {
-          const int np1 = (op.r1 + 1) >> 1;
+        const bool have = s < nbat && j < m;
+        const int np1 = (op.r1 + 1) >> 1;
+        if (have) {
           dec_mode2(op, Bc, lane);
           if (lane < 32) Xs[(buf * NPW + w) * 32 + lane] = op.xv;
-          const bool nv = s + 1 < nbat && j + 4 < m;
-          dec_load(op, bt, j + 4, nv, A.hcache, i3, c0, A.n2, S.u2t, X, ldx, xr, lane);
+        }
+        dec_load<true>(op, bt, min(j + 4, m - 1), A.hcache, A.u2p, i3, c0, X, ldx, xr, lane);
+        float bb[16];
+        if (have) {
           wave_sync();
-          float bb[16];
           dec_bops(Bc, bb, lane);
-          float* dst = tdst + buf * NPW * 2 * V;
+        }
+        float* dst = tdst + buf * NPW * 2 * V;
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) {
+        for (int c = 0; c < NCH; ++c) {
+          if (have) {
             const v4f d = chain16_n(np1, ua[c], bb);
             *reinterpret_cast<float4*>(dst + 16 * c) = make_float4(d[0], d[1], d[2], d[3]);
-            if (nv) dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
           }
+          dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
         }
         __syncthreads();
       }
@@ -677,47 +716,50 @@ void batch_adj_mfma(BatchArgs A) {
       c0 = (rest % A.tiles2) * 8;
       i3 = rest / A.tiles2;
     };
-    // this wave's tensors of the chunk: 4 wave + e, e < nvalid; the operands
-    // of the next one (or of the first one on the next tile) are loaded
-    // while the current one is decompressed, U1 chunk by chunk as each
-    // chunk's registers retire
-    const int nvalid = max(0, min(4, jc - 4 * wave));
+    // this wave's columns of the chunk are 4 wave + e, e < 4, valid below
+    // jc; the operands of the next slot (or of slot 0 on the next tile) are
+    // loaded while the current one is decompressed, U1 chunk by chunk as
+    // each chunk's registers retire.  Slot indices are clamped to jc - 1 so
+    // that every slot issues the same loads; invalid slots skip the work.
     DecOps op;
     float ua[NI][16];
-    if (nvalid > 0 && tb0 < tb1) {
+    {
       int ic0, c0, i3;
       tile_pos(tb0, ic0, c0, i3);
-      dec_load(op, bt, 4 * wave, true, A.hcache, i3, c0, A.n2, S.u2t, nullptr, 0, 0, lane);
+      dec_load<false>(op, bt, min(4 * wave, jc - 1), A.hcache, A.u2p, i3, c0, nullptr, 0, 0,
+                      lane);
 #pragma unroll
       for (int ic = 0; ic < NI; ++ic) dec_u1ops(A.u1p, op.u1p, op.r1, ic0 + ic, ua[ic], lane);
     }
     for (int tile = tb0; tile < tb1; ++tile) {
       int ic0, c0, i3;
       tile_pos(tile, ic0, c0, i3);
+      int nic0, nc0, ni3;
+      tile_pos(min(tile + 1, tb1 - 1), nic0, nc0, ni3);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (e < nvalid) {
-          const int jj = 4 * wave + e;
-          const int np1 = (op.r1 + 1) >> 1;
-          dec_mode2(op, Bc, lane);
-          const bool last = e + 1 == nvalid;
-          const int nt = last ? tile + 1 : tile, ne = last ? 0 : e + 1;
-          int nic0, nc0, ni3;
-          tile_pos(nt, nic0, nc0, ni3);
-          const bool v = nt < tb1;
-          dec_load(op, bt, 4 * wave + ne, v, A.hcache, ni3, nc0, A.n2, S.u2t, nullptr, 0, 0, lane);
+        const int jj = 4 * wave + e;
+        const bool have = jj < jc;
+        const int np1 = (op.r1 + 1) >> 1;
+        if (have) dec_mode2(op, Bc, lane);
+        const int pj = e < 3 ? min(jj + 1, jc - 1) : min(4 * wave, jc - 1);
+        const int pi3 = e < 3 ? i3 : ni3, pc0 = e < 3 ? c0 : nc0, pic0 = e < 3 ? ic0 : nic0;
+        dec_load<false>(op, bt, pj, A.hcache, A.u2p, pi3, pc0, nullptr, 0, 0, lane);
+        float bb[16];
+        if (have) {
           wave_sync();
-          float bb[16];
           dec_bops(Bc, bb, lane);
-          float* dst = reinterpret_cast<float*>(Tb) +
-                       (((lane & 7) * RS + 4 * (lane >> 4)) * TS + jj) * 2 + ((lane >> 3) & 1);
+        }
+        float* dst = reinterpret_cast<float*>(Tb) +
+                     (((lane & 7) * RS + 4 * (lane >> 4)) * TS + jj) * 2 + ((lane >> 3) & 1);
 #pragma unroll
-          for (int ic = 0; ic < NI; ++ic) {
+        for (int ic = 0; ic < NI; ++ic) {
+          if (have) {
             const v4f d = chain16_n(np1, ua[ic], bb);
 #pragma unroll
             for (int r = 0; r < 4; ++r) dst[(16 * ic + r) * TS * 2] = d[r];
-            if (v) dec_u1ops(A.u1p, op.u1p, op.r1, nic0 + ic, ua[ic], lane);
           }
+          dec_u1ops(A.u1p, op.u1p, op.r1, pic0 + ic, ua[ic], lane);
         }
       }
       __syncthreads();
@@ -813,7 +855,7 @@ struct tv_batch_s {
   int nplans = 0;
   tv_grid grid{};
   int n1p32 = 0, ncol = 0, bpw = 0, tiles2 = 0;
-  int r1max = 1, r2max = 1;
+  int r1max = 1, r2max = 1, r3max = 1;
   int nitems = 0;
   int grid_blocks = 0;
   size_t lds = 0;
@@ -827,14 +869,15 @@ struct tv_batch_s {
   int nred = 0, nper = 0;
   int* d_red_list = nullptr;
   int4* d_red_out = nullptr;
-  // MFMA decompression kernels (ranks <= 32): per-tensor records, packed U1,
-  // tensor list of the mode-3 kernel, mode-3 cache size in complex values
+  // MFMA decompression kernels (ranks <= 32): per-tensor records, packed U1
+  // and U2, tensor list of the mode-3 kernel, mode-3 cache size in floats
   bool mfma = false;
   int nch = 0, nic = 0;
   int ntensors = 0;
   int64_t hcache = 0;
   BTensor* d_bt = nullptr;
   float* d_u1p = nullptr;
+  float* d_u2p = nullptr;
   int2* d_tlist = nullptr;
 };
 
@@ -845,6 +888,7 @@ static void batch_free(tv_batch_s* b) {
   hipFree(b->d_red_out);
   hipFree(b->d_bt);
   hipFree(b->d_u1p);
+  hipFree(b->d_u2p);
   hipFree(b->d_tlist);
   delete b;
 }
@@ -883,7 +927,7 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   b->grid = g;
   b->n1p32 = (g.n1 + 31) / 32 * 32;
   const int nb1 = b->n1p32 / 32;
-  int r3max = 1;
+  int& r3max = b->r3max;
   for (int c = 0; c < nplans; ++c) {
     b->r1max = std::max(b->r1max, plans[c]->max_r[0]);
     b->r2max = std::max(b->r2max, plans[c]->max_r[1]);
@@ -973,21 +1017,24 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     return set_error(TV_ERR_NOT_SUPPORTED, "too many work items");
   }
   b->nitems = (int)items.size();
-  // MFMA kernels: per-tensor records, the mode-3 cache layout and U1 packed
-  // in the 16x16x4 A-operand lane order, u1p[off + (ic np1 + t) 64 + l] =
-  // Re/Im (s = (l/16)%2) of U1[16 ic + l%16][2t + l/32], zero outside
+  // MFMA kernels: per-tensor records, the mode-3 cache layout, and U1 and U2
+  // packed in the kernels' operand order (quads of four K steps per lane)
   std::vector<std::vector<BTensor>> bts(nplans);
-  std::vector<float> u1p;
+  std::vector<float> u1p, u2p;
   std::vector<int2> tlist;
   if (b->mfma) {
-    size_t u1n = 0;
+    const int ncg = (g.n2 + 7) / 8;
+    size_t u1n = 0, u2n = 0;
     for (int c = 0; c < nplans; ++c) {
       const tv_plan_s* P = plans[c];
-      for (int64_t t = 0; t < (int64_t)g.q * P->grid.m; ++t)
-        u1n += (size_t)b->nch * ((P->ranks[3 * t] + 1) / 2) * 64;
+      for (int64_t t = 0; t < (int64_t)g.q * P->grid.m; ++t) {
+        u1n += (size_t)b->nch * (((P->ranks[3 * t] + 1) / 2 + 3) / 4) * 256;
+        u2n += (size_t)ncg * (((P->ranks[3 * t + 1] + 1) / 2 + 3) / 4) * 256;
+      }
     }
-    u1p.assign(u1n + 16 * 64, 0.f);  // padding read by steps beyond np1
-    size_t u1o = 0;
+    u1p.assign(u1n, 0.f);
+    u2p.assign(u2n, 0.f);
+    size_t u1o = 0, u2o = 0;
     for (int c = 0; c < nplans; ++c) {
       const tv_plan_s* P = plans[c];
       const int64_t m = P->grid.m;
@@ -995,23 +1042,38 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
       for (int k = 0; k < g.q; ++k)
         for (int64_t j = 0; j < m; ++j) {
           const int64_t t = k + (int64_t)g.q * j;
-          const int r1 = P->ranks[3 * t], r2 = P->ranks[3 * t + 1], np1 = (r1 + 1) / 2;
+          const int r1 = P->ranks[3 * t], r2 = P->ranks[3 * t + 1];
+          const int nq1 = ((r1 + 1) / 2 + 3) / 4, nq2 = ((r2 + 1) / 2 + 3) / 4;
           BTensor& T = bts[c][(size_t)k * m + j];
           T.r1 = r1;
           T.r2 = r2;
           T.h_off = b->hcache;
           T.u1p_off = (int64_t)u1o;
-          T.u2_off = P->u2_off[t];
-          b->hcache += (int64_t)r1 * r2 * g.n3;
+          T.u2p_off = (int64_t)u2o;
+          b->hcache += (int64_t)g.n3 * ((r1 + 15) / 16) * nq2 * 256;
+          // block (ic, q), lane l, step t = 4q + i: Re/Im (l/16 % 2) of U1[16 ic + l%16][2t + l/32]
           for (int ic = 0; ic < b->nch; ++ic)
-            for (int tt = 0; tt < np1; ++tt)
-              for (int l = 0; l < 64; ++l) {
-                const int i1 = 16 * ic + (l & 15), a = 2 * tt + (l >> 5), sp = (l >> 4) & 1;
-                if (i1 < g.n1 && a < r1)
-                  u1p[u1o + ((size_t)ic * np1 + tt) * 64 + l] =
-                      (float)P->u1[2 * (P->u1_off[t] + i1 + (size_t)g.n1 * a) + sp];
-              }
-          u1o += (size_t)b->nch * np1 * 64;
+            for (int q = 0; q < nq1; ++q)
+              for (int l = 0; l < 64; ++l)
+                for (int i = 0; i < 4; ++i) {
+                  const int i1 = 16 * ic + (l & 15), a = 2 * (4 * q + i) + (l >> 5);
+                  if (i1 < g.n1 && a < r1)
+                    u1p[u1o + (((size_t)ic * nq1 + q) * 64 + l) * 4 + i] = (float)
+                        P->u1[2 * (P->u1_off[t] + i1 + (size_t)g.n1 * a) + ((l >> 4) & 1)];
+                }
+          // block (cg, q), lane l, step t: Re/Im (part ^ s) of U2[8 cg + l%8][2t + l/32]
+          for (int cg = 0; cg < ncg; ++cg)
+            for (int q = 0; q < nq2; ++q)
+              for (int l = 0; l < 64; ++l)
+                for (int i = 0; i < 4; ++i) {
+                  const int i2 = 8 * cg + (l & 7), bb = 2 * (4 * q + i) + (l >> 5);
+                  const int comp = ((l >> 3) ^ (l >> 4)) & 1;
+                  if (i2 < g.n2 && bb < r2)
+                    u2p[u2o + (((size_t)cg * nq2 + q) * 64 + l) * 4 + i] =
+                        (float)P->u2[2 * (P->u2_off[t] + i2 + (size_t)g.n2 * bb) + comp];
+                }
+          u1o += (size_t)b->nch * nq1 * 256;
+          u2o += (size_t)ncg * nq2 * 256;
           tlist.push_back(make_int2(c, (int)(k * m + j)));
         }
     }
@@ -1033,9 +1095,12 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
                     hipMemcpyHostToDevice);
       o += bts[c].size();
     }
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_u1p, std::max<size_t>(1, u1p.size()) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_u1p, u1p.size() * sizeof(float));
     if (e == hipSuccess)
       e = hipMemcpy(b->d_u1p, u1p.data(), u1p.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_u2p, u2p.size() * sizeof(float));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_u2p, u2p.data(), u2p.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_tlist, tlist.size() * sizeof(int2));
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tlist, tlist.data(), tlist.size() * sizeof(int2), hipMemcpyHostToDevice);
@@ -1077,8 +1142,9 @@ tv_status tv_batch_workspace_bytes(tv_batch b, size_t* bytes) {
   clear_error();
   if (!b || !bytes) return set_error(TV_ERR_INVALID_ARG, "batch and bytes must be non-NULL");
   // the work-queue counter, (adjoint) one 32 x 32 complex64 block per item,
-  // then (MFMA kernels) the mode-3 cache, sum over tensors of r1 r2 n3 complex64
-  *bytes = b->mfma ? batch_hcache_offset(b) + (size_t)b->hcache * 8
+  // then (MFMA kernels) the packed mode-3 cache, about r1 r2 n3 complex64 per
+  // tensor (row blocks of 16 and quads of four K steps rounded up)
+  *bytes = b->mfma ? batch_hcache_offset(b) + (size_t)b->hcache * 4
                    : 256 + (b->op == 1 ? (size_t)b->nitems * 1024 * 8 : 0);
   return TV_OK;
 }
@@ -1107,8 +1173,9 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   A.nv = (int64_t)b->grid.n1 * b->grid.n2 * b->grid.n3;
   A.r1max = b->r1max;
   A.r2max = b->r2max;
-  A.hcache = b->mfma ? (float2*)((char*)ws + batch_hcache_offset(b)) : nullptr;
+  A.hcache = b->mfma ? (float*)((char*)ws + batch_hcache_offset(b)) : nullptr;
   A.u1p = b->d_u1p;
+  A.u2p = b->d_u2p;
   A.nch = b->nch;
   A.nic = b->nic;
   const int64_t rows = (int64_t)b->grid.q * A.nv;
@@ -1130,8 +1197,13 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "reset_counter launch");
   if (b->mfma) {
-    hipLaunchKernelGGL(batch_mode3, dim3((unsigned)b->ntensors), dim3(256), 0, st, A,
-                       (const int2*)b->d_tlist);
+    const size_t u3b = sizeof(float2) * b->grid.n3 * b->r3max;
+    if (u3b <= 64 * 1024)
+      hipLaunchKernelGGL(batch_mode3<true>, dim3((unsigned)b->ntensors), dim3(256), u3b, st, A,
+                         (const int2*)b->d_tlist);
+    else
+      hipLaunchKernelGGL(batch_mode3<false>, dim3((unsigned)b->ntensors), dim3(256), 0, st, A,
+                         (const int2*)b->d_tlist);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "mode-3 kernel launch");
   }
