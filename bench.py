@@ -344,7 +344,8 @@ def bench_batch(args):
                                   "32 right-hand sides each, graph replay of both directions"},
            "tflops": fl / (ms * 1e-3) / 1e12,
            "unbatched_ms_per_step": ms_plain, "batched_speedup": ms_plain / ms,
-           "max_rel_diff_vs_unbatched": dev}
+           "max_rel_diff_vs_unbatched": dev,
+           "workspace_bytes": {"forward": int(wsf.numel()), "adjoint": int(wsa.numel())}}
     lib.tv_batch_destroy(bf)
     lib.tv_batch_destroy(ba)
     print(json.dumps(out), flush=True)
