@@ -692,6 +692,9 @@ void batch_adj_mfma(BatchArgs A) {
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   float2* Tb = reinterpret_cast<float2*>(bsm4);  // [8][RS][TS]
   float* Bc = reinterpret_cast<float*>(Tb + 8 * RS * TS) + wave * 1024;
+  // y window of this wave: 8 voxels x 32 right-hand sides, row stride 33
+  float2* Ysw = reinterpret_cast<float2*>(reinterpret_cast<float*>(Tb + 8 * RS * TS) + 8 * 1024) +
+                wave * 8 * 33;
   const int tiles = A.nic * A.tiles2 * A.n3;
   for (;;) {
     const int it = next_item(A.counter, &s_item);
@@ -703,8 +706,17 @@ void batch_adj_mfma(BatchArgs A) {
     const int tb1 = (int)((int64_t)tiles * (slice + 1) / A.tsplit);
     const int64_t j0 = (int64_t)I.z * 32;
     const int jc = (int)min((int64_t)32, S.m - j0);
-    const int rhs = min(I.w * 32 + (lane & 31), A.nrhs[I.x] - 1);
-    const float2* Y = A.in[I.x] + A.ld_in[I.x] * rhs + (int64_t)k * A.nv;
+    // y is read in windows of 8 voxels of the wave's column: lane l loads
+    // voxel l % 8 of right-hand sides l / 8 + 8 q (q < 4), so that a load
+    // instruction touches 8 half cache lines instead of 32 lines; the window
+    // is transposed through LDS.  Rows >= n1, columns >= n2 and right-hand
+    // sides >= nrhs are read clamped: T is zero there, and lanes beyond nrhs
+    // are never stored.
+    const float2* yq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      yq[q] = A.in[I.x] + (int64_t)k * A.nv +
+              A.ld_in[I.x] * min(I.w * 32 + (lane >> 3) + 8 * q, A.nrhs[I.x] - 1);
     const BTensor* bt = S.bt + (int64_t)k * S.m + j0;
     v16f acc[2];
 #pragma unroll
@@ -721,11 +733,20 @@ void batch_adj_mfma(BatchArgs A) {
     // loaded while the current one is decompressed, U1 chunk by chunk as
     // each chunk's registers retire.  Slot indices are clamped to jc - 1 so
     // that every slot issues the same loads; invalid slots skip the work.
+    auto wload = [&](int wic0, int wc0, int wi3, int w, float2* yr) {
+      const int col = min(wc0 + wave, A.n2 - 1);
+      const int i1 = min(16 * wic0 + 8 * w + (lane & 7), A.n1 - 1);
+      const int64_t off = (int64_t)A.n1 * (col + (int64_t)A.n2 * wi3) + i1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yr[q] = yq[q][off];
+    };
+    float2 yr[4];
     DecOps op;
     float ua[NI][16];
     {
       int ic0, c0, i3;
       tile_pos(tb0, ic0, c0, i3);
+      wload(ic0, c0, i3, 0, yr);
       dec_load<false>(op, bt, min(4 * wave, jc - 1), A.hcache, A.u2p, i3, c0, nullptr, 0, 0,
                       lane);
 #pragma unroll
@@ -763,22 +784,28 @@ void batch_adj_mfma(BatchArgs A) {
         }
       }
       __syncthreads();
-      // column f = wave of the tile
-      // (T is zero on rows i1 >= n1 and columns >= n2, so clamped reads of
-      // y there contribute nothing; lanes beyond nrhs are never stored)
-      const int col = min(c0 + wave, A.n2 - 1);
-      const float2* yc = Y + (int64_t)A.n1 * (col + (int64_t)A.n2 * i3);
+      // column f = wave of the tile, window by window
       const float2* tc = Tb + wave * RS * TS + (lane & 31);
-#pragma unroll 8
-      for (int i = 0; i < IB; ++i) {
-        const int i1 = min(16 * ic0 + i, A.n1 - 1);
-        const float2 yv = yc[i1];
-        const float2 tb = tc[i * TS];
-        const float bv = lane < 32 ? tb.x : -tb.y;
-        const float a0 = lane < 32 ? yv.x : -yv.y;
-        const float a1 = lane < 32 ? yv.y : yv.x;
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[1], 0, 0, 0);
+#pragma unroll
+      for (int w = 0; w < IB / 8; ++w) {
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ysw[(lane & 7) * 33 + (lane >> 3) + 8 * q] = yr[q];
+        wave_sync();
+        if (w + 1 < IB / 8)
+          wload(ic0, c0, i3, w + 1, yr);
+        else
+          wload(nic0, nc0, ni3, 0, yr);  // first window of the next tile
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const float2 yv = Ysw[i * 33 + (lane & 31)];
+          const float2 tb = tc[(8 * w + i) * TS];
+          const float bv = lane < 32 ? tb.x : -tb.y;
+          const float a0 = lane < 32 ? yv.x : -yv.y;
+          const float a1 = lane < 32 ? yv.y : yv.x;
+          acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[1], 0, 0, 0);
+        }
       }
       __syncthreads();
     }
@@ -807,8 +834,10 @@ void batch_adj_mfma(BatchArgs A) {
 
 size_t batch_mfma_lds_bytes(int op, int nb) {
   if (op == 0) return sizeof(float) * (2 * 4 * 2 * (8 * 32 * nb) + 2 * 4 * 64 + 4 * 1024);
+  // Tb, then Bc, then the y windows; the final reduction reuses the start
   const size_t tb = sizeof(float2) * 8 * (16 * nb + 1) * 33;
-  return std::max(tb, sizeof(float) * 8 * 2 * 16 * 64) + sizeof(float) * 8 * 1024;
+  const size_t all = tb + sizeof(float) * 8 * 1024 + sizeof(float2) * 8 * 8 * 33;
+  return std::max(all, sizeof(float) * 8 * 2 * 16 * 64);
 }
 
 size_t batch_lds_bytes(int op, int ncol, int n1p32, int r1max, int r2max) {
