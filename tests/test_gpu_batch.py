@@ -101,14 +101,16 @@ def test_batch_graph_replay(gpu_lib, c4s):
 # 2, 1 (MFMA decompression) and n1 = 128 (wave-local decompression), adjoint
 # with 48-, 48-, 16- and 48-row i1 chunks; ragged column groups (n2 not a
 # multiple of 8), counts of tensors off the 4- and 32-multiples, ranks above
-# 16 (two 16-row a-blocks) and odd ranks; the last case has ranks above 32
-# and runs the VALU decompression in both directions.
+# 16 (two 16-row a-blocks) and odd ranks; the fifth case has ranks above 32
+# and runs the VALU decompression in both directions; the last has q = 12
+# (the piecewise-linear basis: 3 field components x 4 basis functions).
 MFMA_CASES = [
     ((96, 20, 7), 3, (37, 9), 32, 41),
     ((40, 9, 5), 1, (6, 3), 20, 42),
     ((13, 17, 3), 2, (70, 5), 13, 43),
     ((128, 6, 4), 1, (5, 4), 8, 44),
     ((24, 20, 36), 1, (4, 2), 36, 45),
+    ((20, 12, 6), 12, (10, 3), 12, 46),
 ]
 
 
