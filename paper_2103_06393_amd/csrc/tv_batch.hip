@@ -570,7 +570,7 @@ void batch_fwd_mfma(BatchArgs A) {
   const int w = wave & 3;
   float* Ts = reinterpret_cast<float*>(bsm4);                    // [2][NPW][2][V]
   float2* Xs = reinterpret_cast<float2*>(Ts + 2 * NPW * 2 * V);  // [2][NPW][32]
-  float* Bc = reinterpret_cast<float*>(Xs + 2 * NPW * 32) + w * 1024;
+  float* Bc = reinterpret_cast<float*>(Xs + 2 * NPW * 32) + w * 1024;  // [2][NPW][1024]
   // The two roles run separate item loops (same items, same barrier count
   // per item), so that neither keeps the other's per-lane constants live.
   if (!producer) {
@@ -641,26 +641,33 @@ void batch_fwd_mfma(BatchArgs A) {
       const BTensor* bt = S.bt + (int64_t)k * S.m;
       DecOps op;
       float ua[NCH][16];
-      // tensor indices are clamped to m - 1: loads are always issued, and
-      // only the MFMA and LDS work is skipped for tensors beyond m
+      // Tensor j = 4s + w is decompressed in step s: its mode 2 ran in step
+      // s - 1 (into Bc[s & 1]), so that step s starts mode 1 at once and runs
+      // the next tensor's mode 2 alongside.  Tensor indices are clamped to
+      // m - 1: loads are always issued, and only the MFMA and LDS work is
+      // skipped for tensors beyond m.
       dec_load<true>(op, bt, min((int64_t)w, m - 1), A.hcache, A.u2p, i3, c0, X, ldx, xr, lane);
 #pragma unroll
       for (int c = 0; c < NCH; ++c) dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
+      float2 xcur = op.xv;
+      int r1cur = op.r1;
+      if (w < m) dec_mode2(op, Bc, lane);
+      dec_load<true>(op, bt, min((int64_t)w + 4, m - 1), A.hcache, A.u2p, i3, c0, X, ldx, xr, lane);
       for (int s = 0; s <= nbat; ++s) {
         const int buf = s & 1;
         const int64_t j = 4 * (int64_t)s + w;
         const bool have = s < nbat && j < m;
-        const int np1 = (op.r1 + 1) >> 1;
-        if (have) {
-          dec_mode2(op, Bc, lane);
-          if (lane < 32) Xs[(buf * NPW + w) * 32 + lane] = op.xv;
-        }
-        dec_load<true>(op, bt, min(j + 4, m - 1), A.hcache, A.u2p, i3, c0, X, ldx, xr, lane);
+        const int np1 = (r1cur + 1) >> 1;
+        if (have && lane < 32) Xs[(buf * NPW + w) * 32 + lane] = xcur;
+        wave_sync();
         float bb[16];
-        if (have) {
-          wave_sync();
-          dec_bops(Bc, bb, lane);
-        }
+        if (have) dec_bops(Bc + buf * NPW * 1024, bb, lane);
+        // mode 2 of tensor j + 4 (operands in op) into the other Bc buffer
+        if (s + 1 < nbat && j + 4 < m) dec_mode2(op, Bc + (buf ^ 1) * NPW * 1024, lane);
+        const float2 x4 = op.xv;
+        const int r1n = op.r1;
+        const int64_t u1n = op.u1p;
+        dec_load<true>(op, bt, min(j + 8, m - 1), A.hcache, A.u2p, i3, c0, X, ldx, xr, lane);
         float* dst = tdst + buf * NPW * 2 * V;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -668,8 +675,10 @@ void batch_fwd_mfma(BatchArgs A) {
             const v4f d = chain16_n(np1, ua[c], bb);
             *reinterpret_cast<float4*>(dst + 16 * c) = make_float4(d[0], d[1], d[2], d[3]);
           }
-          dec_u1ops(A.u1p, op.u1p, op.r1, c, ua[c], lane);
+          dec_u1ops(A.u1p, u1n, r1n, c, ua[c], lane);  // U1 of tensor j + 4
         }
+        xcur = x4;
+        r1cur = r1n;
         __syncthreads();
       }
     }
@@ -833,7 +842,7 @@ void batch_adj_mfma(BatchArgs A) {
 }
 
 size_t batch_mfma_lds_bytes(int op, int nb) {
-  if (op == 0) return sizeof(float) * (2 * 4 * 2 * (8 * 32 * nb) + 2 * 4 * 64 + 4 * 1024);
+  if (op == 0) return sizeof(float) * (2 * 4 * 2 * (8 * 32 * nb) + 2 * 4 * 64 + 2 * 4 * 1024);
   // Tb, then Bc, then the y windows; the final reduction reuses the start
   const size_t tb = sizeof(float2) * 8 * (16 * nb + 1) * 33;
   const size_t all = tb + sizeof(float) * 8 * 1024 + sizeof(float2) * 8 * 8 * 33;
