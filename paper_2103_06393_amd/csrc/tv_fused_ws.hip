@@ -358,6 +358,12 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
         float2* Bt = Bbuf + (tb & 1) * be;
         const int m16 = lane & 15, k4 = lane >> 4;  // A row / B column, K index
         const int sa = m16 & 1, ta = k4 & 1, bq = k4 >> 1;
+        // Hemb entry as Re H * cx + Im H * cy with per-lane constants: a
+        // select between the loaded parts is compiled into a branch with a
+        // one-float LDS read and a full wait per operand
+        const float cx = sa == ta ? 1.f : 0.f;
+        const float cy = sa == ta ? 0.f : (sa ? 1.f : -1.f);
+        const float ux = ta ? 0.f : 1.f, uy = ta ? 1.f : 0.f;
         // the wave's chunks ch = wave + 4 c (c < CH) are processed together:
         // operand loads of 2 QB values of b for all of them, then their MFMAs
         constexpr int CH = NWG >= 64 ? NWG / 64 : 1;
@@ -389,11 +395,14 @@ __attribute__((amdgpu_waves_per_eu(WsOccupancy<NB, ADJ>::waves))) void ws_fused(
               const int bc = min(bb, r2 - 1);
 #pragma unroll
               for (int c = 0; c < CH; ++c) {
+                // masks folded into the weights (the clamped reads are
+                // finite), so that the loads are not sunk into branches
+                const float wx = ok ? cx : 0.f, wy = ok ? cy : 0.f;
+                const float vx = bb < r2 ? ux : 0.f, vy = bb < r2 ? uy : 0.f;
                 const float2 h = Hcc[c][bc * r1p + ac];
                 const float2 u = U2c[c][bc * T2];
-                const float x = sa == ta ? h.x : (sa ? h.y : -h.y);
-                av[c][q] = ok ? x : 0.f;
-                bv[c][q] = bb < r2 ? (ta ? u.y : u.x) : 0.f;
+                av[c][q] = fmaf(h.x, wx, h.y * wy);
+                bv[c][q] = fmaf(u.x, vx, u.y * vy);
               }
             }
 #pragma unroll
