@@ -25,7 +25,6 @@ def _stream() -> int:
 class TuckerPlan:
     def __init__(self, handle: int):
         self.handle = handle
-        self.info = lib.tv_plan_info(handle)
         g = self.info.grid
         self.dims = (g.n1, g.n2, g.n3)
         self.q = g.q
@@ -33,6 +32,12 @@ class TuckerPlan:
         self.nv = g.n1 * g.n2 * g.n3
         self.rows = self.q * self.nv
         self._ws = {}
+
+    @property
+    def info(self) -> lib.tv_plan_info_t:
+        """Plan summary queried now (the launch configuration changes with
+        autotuning)."""
+        return lib.tv_plan_info(self.handle)
 
     # -- construction ---------------------------------------------------
     @classmethod
