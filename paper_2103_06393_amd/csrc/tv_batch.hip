@@ -350,6 +350,21 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16X3 apply: bf16 round to nearest even (finite values), hi/lo split
+typedef __bf16 bv8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ uint32_t bt_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bt_f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ uint32_t bt_pack(uint32_t lo16, uint32_t hi16) {
+  return (lo16 & 0xFFFFu) | (hi16 << 16);
+}
+__device__ __forceinline__ v16f mfma_bf(uint4 a, uint4 b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bv8, a),
+                                                 __builtin_bit_cast(bv8, b), c, 0, 0, 0);
+}
+
 // Packed operand layouts (np = (r + 1) / 2 K steps, nq = (np + 3) / 4 quads,
 // nab = (r1 + 15) / 16 row blocks of 16; value 0 outside the ranks/grid):
 //   H   [i3][ab < nab][q < nq2][lane][4]: step t = 4q + i of lane l holds
@@ -559,7 +574,7 @@ __device__ __forceinline__ void dec_u1ops(const float* u1p, int64_t off, int r1,
 // applies tensors 4(s-1).. to columns 2w, 2w+1 of the tile (2 NB1 blocks of
 // 32 voxels x 32 right-hand sides on v_mfma_f32_32x32x2f32).  One barrier
 // per step.
-template <int NB1>
+template <int NB1, bool BF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 void batch_fwd_mfma(BatchArgs A) {
   constexpr int NPW = 4, N1P = 32 * NB1, V = 8 * N1P, NCH = 2 * NB1, BPC = 2 * NB1;
@@ -586,7 +601,49 @@ void batch_fwd_mfma(BatchArgs A) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[b][0][i] = acc[b][1][i] = 0.f;
       for (int s = 0; s <= nbat; ++s) {
-        if (s > 0) {
+        if (BF && s > 0) {
+          // BF16X3: one v_mfma_f32_32x32x16_bf16 pair per output covers the
+          // four tensors of the step.  K slot 8h + 4p + t holds the hi (h = 0,
+          // lanes < 32) or lo (h = 1) half of part p of tensor t's value; the
+          // B operands hold x in the real form of the output (Re: xr, -xi;
+          // Im: xi, xr), hi in both halves for the first MFMA and lo against
+          // the hi halves of T for the second: Th Xh + Tl Xh + Th Xl.
+          const int pb = (s - 1) & 1;
+          const int nj = (int)min((int64_t)4, m - 4 * (int64_t)(s - 1));
+          uint32_t xr_h[4], xr_l[4], xi_h[4], xi_l[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float2 xv = t < nj ? Xs[(pb * NPW + t) * 32 + (lane & 31)] : make_float2(0.f, 0.f);
+            xr_h[t] = bt_rne(xv.x);
+            xr_l[t] = bt_rne(xv.x - bt_f(xr_h[t]));
+            xi_h[t] = bt_rne(xv.y);
+            xi_l[t] = bt_rne(xv.y - bt_f(xi_h[t]));
+          }
+          const bool lo = lane < 32;
+          const uint32_t sg = 0x8000u;  // bf16 sign bit
+          const uint4 b1r = make_uint4(bt_pack(xr_h[0], xr_h[1]), bt_pack(xr_h[2], xr_h[3]),
+                                       bt_pack(xi_h[0] ^ sg, xi_h[1] ^ sg),
+                                       bt_pack(xi_h[2] ^ sg, xi_h[3] ^ sg));
+          const uint4 b1i = make_uint4(bt_pack(xi_h[0], xi_h[1]), bt_pack(xi_h[2], xi_h[3]),
+                                       bt_pack(xr_h[0], xr_h[1]), bt_pack(xr_h[2], xr_h[3]));
+          const uint4 b2r = lo ? make_uint4(bt_pack(xr_l[0], xr_l[1]), bt_pack(xr_l[2], xr_l[3]),
+                                            bt_pack(xi_l[0] ^ sg, xi_l[1] ^ sg),
+                                            bt_pack(xi_l[2] ^ sg, xi_l[3] ^ sg))
+                               : make_uint4(0u, 0u, 0u, 0u);
+          const uint4 b2i = lo ? make_uint4(bt_pack(xi_l[0], xi_l[1]), bt_pack(xi_l[2], xi_l[3]),
+                                            bt_pack(xr_l[0], xr_l[1]), bt_pack(xr_l[2], xr_l[3]))
+                               : make_uint4(0u, 0u, 0u, 0u);
+          const uint4* ta = reinterpret_cast<const uint4*>(Ts) + (pb * 2 + (lane >> 5)) * V +
+                            2 * w * N1P + (lane & 31);
+#pragma unroll
+          for (int b = 0; b < BPC; ++b) {
+            const uint4 a = ta[32 * b];
+            acc[b][0] = mfma_bf(a, b1r, acc[b][0]);
+            acc[b][0] = mfma_bf(a, b2r, acc[b][0]);
+            acc[b][1] = mfma_bf(a, b1i, acc[b][1]);
+            acc[b][1] = mfma_bf(a, b2i, acc[b][1]);
+          }
+        } else if (s > 0) {
           const int pb = (s - 1) & 1;
           const int nj = (int)min((int64_t)4, m - 4 * (int64_t)(s - 1));
           for (int jj = 0; jj < nj; ++jj) {
@@ -671,7 +728,22 @@ void batch_fwd_mfma(BatchArgs A) {
         float* dst = tdst + buf * NPW * 2 * V;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-          if (have) {
+          if constexpr (BF) {
+            // hi and lo halves into K slot 4 part + w of the 16-byte records
+            // [buf][h][voxel]; a tensor beyond m writes zeros (its slot is
+            // part of every MFMA's K)
+            v4f d = {0.f, 0.f, 0.f, 0.f};
+            if (have) d = chain16_n(np1, ua[c], bb);
+            unsigned short* rec = reinterpret_cast<unsigned short*>(Ts) +
+                                  ((size_t)(buf * 2) * V + (lane & 7) * N1P + 16 * c +
+                                   4 * (lane >> 4)) * 8 + 4 * ((lane >> 3) & 1) + w;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint32_t h = bt_rne(d[r]);
+              rec[r * 8] = (unsigned short)h;
+              rec[(size_t)V * 8 + r * 8] = (unsigned short)bt_rne(d[r] - bt_f(h));
+            }
+          } else if (have) {
             const v4f d = chain16_n(np1, ua[c], bb);
             *reinterpret_cast<float4*>(dst + 16 * c) = make_float4(d[0], d[1], d[2], d[3]);
           }
@@ -910,6 +982,7 @@ struct tv_batch_s {
   // MFMA decompression kernels (ranks <= 32): per-tensor records, packed U1
   // and U2, tensor list of the mode-3 kernel, mode-3 cache size in floats
   bool mfma = false;
+  bool bf = false;          // forward apply in BF16X3 (all plans BF16X3)
   int nch = 0, nic = 0;
   int ntensors = 0;
   int64_t hcache = 0;
@@ -980,7 +1053,15 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     b->ncol = 8;
     if (op == 0) {
       b->bpw = nb1;
-      b->fn = nb1 == 1 ? batch_fwd_mfma<1> : nb1 == 2 ? batch_fwd_mfma<2> : batch_fwd_mfma<3>;
+      bool bf = true;
+      for (int c = 0; c < nplans; ++c) bf = bf && plans[c]->precision == TV_PREC_BF16X3;
+      b->bf = bf;
+      if (bf)
+        b->fn = nb1 == 1 ? batch_fwd_mfma<1, true> : nb1 == 2 ? batch_fwd_mfma<2, true>
+                                                              : batch_fwd_mfma<3, true>;
+      else
+        b->fn = nb1 == 1 ? batch_fwd_mfma<1, false> : nb1 == 2 ? batch_fwd_mfma<2, false>
+                                                               : batch_fwd_mfma<3, false>;
     } else {
       const int ni = std::min(3, (g.n1 + 15) / 16);
       b->bpw = ni;

@@ -152,3 +152,29 @@ def test_batch_adjoint_items_span_tiles(gpu_lib):
     for c, S in enumerate(structs):
         assert rel_err(got_f[c], om.alg1(S, X[c])) <= 1e-5, ("forward", c)
         assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
+
+
+def test_batch_bf16x3_forward(gpu_lib):
+    """Plans in BF16X3 form: the batched forward applies the decompressed
+    tensors with the hi/lo split on v_mfma_f32_32x32x16_bf16 (Th Xh + Tl Xh
+    + Th Xl, FP32 accumulation); checked against the FP64 oracle below the
+    1e-3 bar of the split form (and far inside it)."""
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    from tests.plans import random_struct
+    dims, q = (96, 20, 7), 3
+    ms, nrhs = (37, 9), [33, 5]
+    structs = [random_struct(dims, q, m, 32, 90 + c) for c, m in enumerate(ms)]
+    plans = [TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
+                                     precision=lib.TV_PREC_BF16X3) for S in structs]
+    X = [workloads.complex_normal((S.m, n), 910 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    Y = [workloads.complex_normal((S.q * S.nv, n), 920 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    cx = lambda a: torch.from_numpy(a.astype(np.complex64)).cuda()  # noqa: E731
+    got_f = _run(plans, 0, [cx(x) for x in X], nrhs)
+    got_a = _run(plans, 1, [cx(y) for y in Y], nrhs)
+    for c, S in enumerate(structs):
+        ef = rel_err(got_f[c], om.alg1(S, X[c]))
+        print(f"bf16x3 batched forward, plan {c}: rel err {ef:.2e}", flush=True)
+        assert ef <= 1e-4, ("forward", c, ef)
+        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
