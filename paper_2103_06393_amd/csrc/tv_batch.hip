@@ -764,7 +764,7 @@ void batch_fwd_mfma(BatchArgs A) {
 // 16 NI + 1 rows, against LDS bank conflicts); then wave w contracts column
 // f = w: W(32 rhs x 32 columns) += Y^T conj(T) on v_mfma_f32_32x32x2f32, one
 // voxel per pair of MFMAs.  The eight waves' W are summed in a fixed order.
-template <int NI>
+template <int NI, bool BF>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
 void batch_adj_mfma(BatchArgs A) {
   constexpr int NW = 8, IB = 16 * NI, RS = IB + 1, TS = 33;
@@ -854,18 +854,76 @@ void batch_adj_mfma(BatchArgs A) {
         }
         float* dst = reinterpret_cast<float*>(Tb) +
                      (((lane & 7) * RS + 4 * (lane >> 4)) * TS + jj) * 2 + ((lane >> 3) & 1);
+        // BF16X3: 16-byte records [h][quad][jj] of four voxels x (Re, Im);
+        // quad = f (IB / 4) + i1 / 4 within the tile
+        unsigned short* dsb = reinterpret_cast<unsigned short*>(Tb) +
+                              (((lane & 7) * (IB / 4) + (lane >> 4)) * 32 + jj) * 8 +
+                              ((lane >> 3) & 1);
 #pragma unroll
         for (int ic = 0; ic < NI; ++ic) {
           if (have) {
             const v4f d = chain16_n(np1, ua[ic], bb);
+            if constexpr (BF) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[(16 * ic + r) * TS * 2] = d[r];
+              for (int r = 0; r < 4; ++r) {
+                const uint32_t h = bt_rne(d[r]);
+                dsb[ic * 4 * 32 * 8 + 2 * r] = (unsigned short)h;
+                dsb[2 * IB * 32 * 8 + ic * 4 * 32 * 8 + 2 * r] =
+                    (unsigned short)bt_rne(d[r] - bt_f(h));
+              }
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dst[(16 * ic + r) * TS * 2] = d[r];
+            }
           }
           dec_u1ops(A.u1p, op.u1p, op.r1, pic0 + ic, ua[ic], lane);
         }
       }
       __syncthreads();
       // column f = wave of the tile, window by window
+      if constexpr (BF) {
+        // BF16X3: K slot 8h + 2v + p of a quad of four voxels; A = y of the
+        // quad (hi for lanes < 32, lo for the others), A' = (Im, -Re) of the
+        // same, B = T's hi halves in both slot halves (Yh Th + Yl Th) or its
+        // lo halves against y's hi (Yh Tl): Wr from A, Wi from A'.
+        const uint4* tq = reinterpret_cast<const uint4*>(Tb) + wave * (IB / 4) * 32 + (lane & 31);
+        uint32_t* yw = reinterpret_cast<uint32_t*>(Ysw);  // [h][2 quads][32 rhs][4 words]
+#pragma unroll
+        for (int w = 0; w < IB / 8; ++w) {
+          wave_sync();
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float2 y = yr[q];
+            const uint32_t hr = bt_rne(y.x), hi = bt_rne(y.y);
+            const uint32_t lr = bt_rne(y.x - bt_f(hr)), li = bt_rne(y.y - bt_f(hi));
+            const int i = lane & 7, rhs = (lane >> 3) + 8 * q;
+            const int o = ((i >> 2) * 32 + rhs) * 4 + (i & 3);
+            yw[o] = bt_pack(hr, hi);
+            yw[2 * 32 * 4 + o] = bt_pack(lr, li);
+          }
+          wave_sync();
+          if (w + 1 < IB / 8)
+            wload(ic0, c0, i3, w + 1, yr);
+          else
+            wload(nic0, nc0, ni3, 0, yr);  // first window of the next tile
+#pragma unroll
+          for (int qd = 0; qd < 2; ++qd) {
+            const uint4 a = reinterpret_cast<const uint4*>(yw)[((lane >> 5) * 2 + qd) * 32 + (lane & 31)];
+            uint4 a2;  // (Im, -Re) per voxel
+            a2.x = (a.x >> 16) | ((a.x ^ 0x8000u) << 16);
+            a2.y = (a.y >> 16) | ((a.y ^ 0x8000u) << 16);
+            a2.z = (a.z >> 16) | ((a.z ^ 0x8000u) << 16);
+            a2.w = (a.w >> 16) | ((a.w ^ 0x8000u) << 16);
+            const int quad = 2 * w + qd;
+            const uint4 b1 = tq[quad * 32];
+            const uint4 b2 = lane < 32 ? tq[2 * IB * 32 + quad * 32] : make_uint4(0u, 0u, 0u, 0u);
+            acc[0] = mfma_bf(a, b1, acc[0]);
+            acc[0] = mfma_bf(a, b2, acc[0]);
+            acc[1] = mfma_bf(a2, b1, acc[1]);
+            acc[1] = mfma_bf(a2, b2, acc[1]);
+          }
+        }
+      } else {
       const float2* tc = Tb + wave * RS * TS + (lane & 31);
 #pragma unroll
       for (int w = 0; w < IB / 8; ++w) {
@@ -887,6 +945,7 @@ void batch_adj_mfma(BatchArgs A) {
           acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[0], 0, 0, 0);
           acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[1], 0, 0, 0);
         }
+      }
       }
       __syncthreads();
     }
@@ -1066,7 +1125,15 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
       const int ni = std::min(3, (g.n1 + 15) / 16);
       b->bpw = ni;
       b->nic = (g.n1 + 16 * ni - 1) / (16 * ni);
-      b->fn = ni == 1 ? batch_adj_mfma<1> : ni == 2 ? batch_adj_mfma<2> : batch_adj_mfma<3>;
+      bool bf = true;
+      for (int c = 0; c < nplans; ++c) bf = bf && plans[c]->precision == TV_PREC_BF16X3;
+      b->bf = bf;
+      if (bf)
+        b->fn = ni == 1 ? batch_adj_mfma<1, true> : ni == 2 ? batch_adj_mfma<2, true>
+                                                            : batch_adj_mfma<3, true>;
+      else
+        b->fn = ni == 1 ? batch_adj_mfma<1, false> : ni == 2 ? batch_adj_mfma<2, false>
+                                                             : batch_adj_mfma<3, false>;
     }
     b->nch = std::max(b->n1p32 / 16, op == 1 ? b->nic * b->bpw : 0);
     b->lds = batch_mfma_lds_bytes(op, b->bpw);

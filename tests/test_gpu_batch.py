@@ -154,11 +154,11 @@ def test_batch_adjoint_items_span_tiles(gpu_lib):
         assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
 
 
-def test_batch_bf16x3_forward(gpu_lib):
-    """Plans in BF16X3 form: the batched forward applies the decompressed
-    tensors with the hi/lo split on v_mfma_f32_32x32x16_bf16 (Th Xh + Tl Xh
-    + Th Xl, FP32 accumulation); checked against the FP64 oracle below the
-    1e-3 bar of the split form (and far inside it)."""
+def test_batch_bf16x3(gpu_lib):
+    """Plans in BF16X3 form: both batched directions apply the decompressed
+    tensors with the hi/lo split on v_mfma_f32_32x32x16_bf16 (three of the
+    four hi/lo products, FP32 accumulation); checked against the FP64 oracle
+    below the 1e-3 bar of the split form (and far inside it)."""
     import torch
     from paper_2103_06393_amd import lib
     from paper_2103_06393_amd.ops import TuckerPlan
@@ -177,4 +177,6 @@ def test_batch_bf16x3_forward(gpu_lib):
         ef = rel_err(got_f[c], om.alg1(S, X[c]))
         print(f"bf16x3 batched forward, plan {c}: rel err {ef:.2e}", flush=True)
         assert ef <= 1e-4, ("forward", c, ef)
-        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
+        ea = rel_err(got_a[c], om.alg2(S, Y[c]))
+        print(f"bf16x3 batched adjoint, plan {c}: rel err {ea:.2e}", flush=True)
+        assert ea <= 1e-4, ("adjoint", c, ea)
