@@ -346,7 +346,7 @@ def bench_batch(args):
            "value": nmv / (ms * 1e-3), "unit": "matvecs/s", "n_gpus": 1, "steps": K,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16x3 forward apply (f32 decompression, adjoint and accumulation)" if bf
+           "dtype": "bf16x3 apply (f32 decompression and accumulation)" if bf
            else "f32", "data": "synthetic",
            "config": {"workload": "c4: 16 coils (64..1024 point currents) on 96x128x112, "
                                   "32 right-hand sides each, graph replay of both directions"},

@@ -210,8 +210,8 @@ tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
  *   op 0:  Y_c = Z_c X_c,    in[c] = X_c (m_c x nrhs[c]), out[c] = Y_c
  *   op 1:  X_c = Z_c^* Y_c,  in[c] = Y_c (q nv x nrhs[c]), out[c] = X_c
  * Every tensor is decompressed once per voxel tile and applied to all
- * right-hand sides on MFMA, in FP32; when every plan is TV_PREC_BF16X3 the
- * forward applies with the BF16 hi/lo split (FP32 accumulation).  With all
+ * right-hand sides on MFMA, in FP32; when every plan is TV_PREC_BF16X3 both
+ * directions apply with the BF16 hi/lo split (FP32 accumulation).  With all
  * ranks <= 32 (and, forward, n1 <= 96) the decompression runs on MFMA too,
  * from G x3 U3 precomputed per (tensor, i3) into the workspace.
  * tv_batch_create builds the work queue and the packed operands (device
