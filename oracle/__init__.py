@@ -16,10 +16,13 @@ Contents (each function cites the passage of the paper it follows):
                  Sec. III.B, single-entry decompression (Sec. III.C), dense
                  truth, the least-squares loss and its gradient.
 * ``accounting`` memory and operation counts of Tables II and III.
+* ``aca``        adaptive cross approximation with partial pivoting, dense
+                 or with U compressed column by column (Algorithm 3), and
+                 the ACA + Tucker products (Sec. II.B.2, III.B, III.C).
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests against
 closed forms, theorems, brute force or numbers printed in the paper, except
 the field values of specific geometries, which the paper never prints
 (parity unpinned beyond the closed-form and invariant checks).
 """
-from . import accounting, fields, hosvd, matvec  # noqa: F401
+from . import aca, accounting, fields, hosvd, matvec  # noqa: F401

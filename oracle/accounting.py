@@ -54,3 +54,25 @@ def matvec_flops(rank_array, dims, p: int = 1) -> float:
         dec = r1 * r2 * r3 * n2 + r1 * r3 * n2 * n3 + r1 * nv
         tot += 8.0 * (dec + (nv * p if p > 1 else 0))
     return tot
+
+
+def aca_tucker_bytes(rank_array, dims, m: int, rc: int) -> int:
+    """ACA+Tucker assembly, Table II: the q r_c Tucker tensors of U's
+    columns plus V (m r_c entries)."""
+    return tucker_bytes(rank_array, dims) + BYTES_C128 * m * rc
+
+
+def aca_matvec_flops(rank_array, dims, m: int, p: int = 1) -> float:
+    """Real flops of one ACA+Tucker product, Table III: the Tucker product
+    over U's r_c columns plus the coil-side product with V, O(r_c m p)
+    (8 real flops per complex multiply-add)."""
+    ra = np.asarray(rank_array).reshape(-1, 3)
+    return matvec_flops(ra, dims, p) + 8.0 * m * p * _columns(ra, rank_array)
+
+
+def _columns(ra, rank_array) -> int:
+    """r_c from a rank array shaped (r_c, q, 3)."""
+    shape = np.asarray(rank_array).shape
+    if len(shape) != 3:
+        raise ValueError("rank_array must be shaped (r_c, q, 3)")
+    return int(shape[0])

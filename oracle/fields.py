@@ -95,3 +95,31 @@ def column_vector(wl, j: int) -> np.ndarray:
     """
     T = column_tensors(wl, j)
     return np.concatenate([T[k].reshape(-1, order="F") for k in range(wl.q)])
+
+
+def row_vector(wl, i: int) -> np.ndarray:
+    """Row i of the coupling matrix (length m): the field of every coil
+    element at one voxel and component.
+
+    Row i is component k of voxel v = i1 + n1 (i2 + n2 i3), k nv + v = i
+    (Algorithm 1's row order).  Evaluated dipole by dipole, independently of
+    the voxel-vectorised ``column_tensors``.
+    """
+    nv = wl.grid.nv
+    k, v = divmod(int(i), nv)
+    n1, n2 = wl.grid.n1, wl.grid.n2
+    idx = (v % n1, (v // n1) % n2, v // (n1 * n2))
+    centre = np.array([wl.grid.axis(d)[idx[d]] for d in range(3)])
+    if wl.basis == "pwc":
+        return point_field(centre, wl.pos, wl.ori, wl.k0)[:, k]
+    c, l = divmod(k, 4)
+    h = wl.grid.h
+    out = np.zeros(wl.m, dtype=np.complex128)
+    for sx in (-1.0, 1.0):
+        for sy in (-1.0, 1.0):
+            for sz in (-1.0, 1.0):
+                s = np.array([sx, sy, sz]) * _GL2
+                E = point_field(centre + s * h, wl.pos, wl.ori, wl.k0)
+                phi = (1.0, s[0], s[1], s[2])[l]
+                out += E[:, c] * (phi / 8.0)
+    return out

@@ -190,6 +190,66 @@ def _face_workload(name, grid: Grid, m: int, seed_geo: int, seed_x: int,
                     nrhs, seed_x, seed_y)
 
 
+FREQ_3T = 123.0e6           # Sec. IV.B.2 operating frequency, Hz
+
+
+def _bodycoil(name, dims, h, m, basis, tol, seed_geo, seed_x, seed_y,
+              rank_min=1, cap=None) -> Workload:
+    """Body-coil stand-in for Sec. IV.B.2 with point currents in place of
+    the RWG functions: 32 legs (radius 35.5 cm, length 45 cm, z-directed),
+    two end rings (phi-directed) and a conductive shield (radius 37.2 cm,
+    length 1.5 m, tangential currents at seeded random positions and
+    angles), all centred at the origin around the voxel box.  A quarter of
+    the m elements lie on the coil (legs 3/4, rings 1/4), the rest on the
+    shield.
+    """
+    rng = np.random.default_rng(seed_geo)
+    rc, lc, rs, ls = 0.355, 0.45, 0.372, 1.5
+    n_coil = m // 4
+    per_leg = max(1, (3 * n_coil) // (4 * 32))
+    n_ring = max(1, (n_coil - 32 * per_leg) // 2)
+    pos, ori = [], []
+    for leg in range(32):
+        phi = 2.0 * math.pi * leg / 32
+        for t in range(per_leg):
+            z = -lc / 2 + lc * (t + 0.5) / per_leg
+            pos.append((rc * math.cos(phi), rc * math.sin(phi), z))
+            ori.append((0.0, 0.0, 1.0))
+    for z in (-lc / 2, lc / 2):
+        for t in range(n_ring):
+            phi = 2.0 * math.pi * (t + 0.5) / n_ring
+            pos.append((rc * math.cos(phi), rc * math.sin(phi), z))
+            ori.append((-math.sin(phi), math.cos(phi), 0.0))
+    for _ in range(m - len(pos)):
+        phi = rng.uniform(0.0, 2.0 * math.pi)
+        z = rng.uniform(-ls / 2, ls / 2)
+        a = rng.uniform(0.0, 2.0 * math.pi)
+        pos.append((rs * math.cos(phi), rs * math.sin(phi), z))
+        ori.append((-math.cos(a) * math.sin(phi), math.cos(a) * math.cos(phi),
+                    math.sin(a)))
+    grid = Grid(dims[0], dims[1], dims[2], h)
+    return Workload(name, grid, basis, FREQ_3T, np.asarray(pos, np.float64),
+                    np.asarray(ori, np.float64), tol, rank_min, cap, 1,
+                    seed_x, seed_y)
+
+
+# Body-coil workloads: the box of Sec. IV.B.2 (81 x 44 x 108 voxels at 5 mm,
+# 205 x 109 x 270 at 2 mm, 409 x 219 x 541 at 1 mm) and 9450 coil elements;
+# ``aca_s`` keeps the geometry at 2.5 cm voxels and 400 elements for the
+# oracle.  The tolerance is the ACA tolerance of Sec. IV.B.2 (1e-3).
+BODYCOIL = {
+    "aca_s": ((16, 9, 22), 0.025, 400),
+    "aca5": ((81, 44, 108), 0.005, 9450),
+    "aca2": ((205, 109, 270), 0.002, 9450),
+    "aca1": ((409, 219, 541), 0.001, 9450),
+}
+
+
+def make_bodycoil(name: str, basis: str = "pwc") -> Workload:
+    dims, h, m = BODYCOIL[name]
+    return _bodycoil(name, dims, h, m, basis, 1e-3, 6, 61, 62)
+
+
 def make(name: str) -> Workload:
     """Build a named single-plan workload."""
     if name == "tiny":          # oracle-only unit tests: 8^3, 6 dipoles
