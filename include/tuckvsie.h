@@ -238,6 +238,36 @@ tv_status tv_batch_run(tv_batch batch, const void* const* in,
                        void* stream);
 tv_status tv_batch_destroy(tv_batch batch);
 
+/* ------------------------------------------------------------------------
+ * ACA + Tucker products (Sec. III.B, the substitution stated after
+ * Algorithms 1 and 2; Table III, row ACA+Tucker).  The coupling matrix is
+ * held as Z ~= U V^* (cross approximation, Sec. II.B.2; Algorithm 3 builds
+ * it with U compressed column by column):
+ *   plan : the r_c columns of U as Tucker tensors (grid->m = r_c);
+ *   v    : V, m x r_c, device complex64, column-major, V[j, l] at
+ *          v[j + ldv*l], ldv >= m (m = coil basis functions).
+ *   tv_aca_matvec:   Y = U (V^* X)   x: m x nrhs (ldx >= m),
+ *                                    y: q nv x nrhs (ldy >= q nv)
+ *   tv_aca_rmatvec:  X = V (U^* Y)   y: q nv x nrhs, x: m x nrhs
+ * Outputs are overwritten.  V^* X and V W accumulate in FP64 in a fixed
+ * order; the Tucker products are those of tv_matvec / tv_rmatvec, so the
+ * result is deterministic.  nrhs <= 65535.
+ * ws: device workspace of at least tv_aca_workspace_bytes(op) bytes
+ * (op 0 forward, 1 adjoint), 16-byte aligned, not overlapping any operand:
+ * the r_c x nrhs intermediate followed by the Tucker product's workspace.
+ * Asynchronous on `stream`; no allocation, no synchronisation.  Argument
+ * errors (NULL pointers, ldv < m, overlaps, small workspace) are reported
+ * before any work is queued.
+ * ---------------------------------------------------------------------- */
+tv_status tv_aca_workspace_bytes(tv_plan plan, int32_t op, int32_t nrhs,
+                                 size_t* bytes);
+tv_status tv_aca_matvec(tv_plan plan, const void* v, int64_t m, int64_t ldv,
+                        const void* x, int64_t ldx, int32_t nrhs, void* y,
+                        int64_t ldy, void* ws, size_t ws_bytes, void* stream);
+tv_status tv_aca_rmatvec(tv_plan plan, const void* v, int64_t m, int64_t ldv,
+                         const void* y, int64_t ldy, int32_t nrhs, void* x,
+                         int64_t ldx, void* ws, size_t ws_bytes, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* tv_status_string(tv_status status);
 

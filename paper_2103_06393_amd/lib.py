@@ -93,6 +93,13 @@ _tv_batch_run = _sig("tv_batch_run", [c_vp, ctypes.POINTER(c_vp),
                                       ctypes.POINTER(c_i64), ctypes.POINTER(c_vp),
                                       ctypes.POINTER(c_i64), c_vp, c_sz, c_vp])
 _tv_batch_destroy = _sig("tv_batch_destroy", [c_vp])
+_tv_aca_workspace_bytes = _sig("tv_aca_workspace_bytes",
+                               [c_vp, c_i32, c_i32, ctypes.POINTER(c_sz)])
+_tv_aca_matvec = _sig("tv_aca_matvec", [c_vp, c_vp, c_i64, c_i64, c_vp, c_i64,
+                                        c_i32, c_vp, c_i64, c_vp, c_sz, c_vp])
+_tv_aca_rmatvec = _sig("tv_aca_rmatvec", [c_vp, c_vp, c_i64, c_i64, c_vp,
+                                          c_i64, c_i32, c_vp, c_i64, c_vp,
+                                          c_sz, c_vp])
 _tv_status_string = _sig("tv_status_string", [ctypes.c_int], ctypes.c_char_p)
 _tv_last_error = _sig("tv_last_error", [], ctypes.c_char_p)
 
@@ -101,7 +108,8 @@ EXPORTED = ("tv_plan_from_factors", "tv_plan_destroy", "tv_plan_info",
             "tv_rmatvec", "tv_dipole_columns", "tv_compress_begin",
             "tv_compress_append", "tv_plan_finalize", "tv_compress_discarded",
             "tv_autotune", "tv_batch_create", "tv_batch_workspace_bytes", "tv_batch_run",
-            "tv_batch_destroy", "tv_status_string", "tv_last_error")
+            "tv_batch_destroy", "tv_aca_workspace_bytes", "tv_aca_matvec",
+            "tv_aca_rmatvec", "tv_status_string", "tv_last_error")
 TV_BATCH_MAX_PLANS = 32
 
 
@@ -257,3 +265,24 @@ def tv_batch_destroy(batch: int) -> None:
 def tv_autotune(plan: int, op: int = 2, cache_path=None, stream=None) -> None:
     cp = None if cache_path is None else str(cache_path).encode()
     _check(_tv_autotune(plan, int(op), cp, stream), "tv_autotune")
+
+
+def tv_aca_workspace_bytes(plan: int, op: int, nrhs: int) -> int:
+    n = c_sz()
+    _check(_tv_aca_workspace_bytes(plan, int(op), int(nrhs), ctypes.byref(n)),
+           "tv_aca_workspace_bytes")
+    return n.value
+
+
+def tv_aca_matvec(plan, v_ptr, m, ldv, x_ptr, ldx, nrhs, y_ptr, ldy, ws_ptr,
+                  ws_bytes, stream):
+    _check(_tv_aca_matvec(plan, v_ptr, int(m), int(ldv), x_ptr, int(ldx),
+                          int(nrhs), y_ptr, int(ldy), ws_ptr, int(ws_bytes),
+                          stream), "tv_aca_matvec")
+
+
+def tv_aca_rmatvec(plan, v_ptr, m, ldv, y_ptr, ldy, nrhs, x_ptr, ldx, ws_ptr,
+                   ws_bytes, stream):
+    _check(_tv_aca_rmatvec(plan, v_ptr, int(m), int(ldv), y_ptr, int(ldy),
+                           int(nrhs), x_ptr, int(ldx), ws_ptr, int(ws_bytes),
+                           stream), "tv_aca_rmatvec")

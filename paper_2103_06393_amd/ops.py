@@ -131,6 +131,56 @@ class TuckerPlan:
         return lib.tv_plan_export_factors(self.handle)
 
 
+class AcaTuckerOperator:
+    """Z ~= U V^* with U's r_c columns in a Tucker plan (Algorithm 3's
+    output) and V (m x r_c, complex64 on the GPU): Z X = U (V^* X) and
+    Z^* Y = V (U^* Y) through tv_aca_matvec / tv_aca_rmatvec (Sec. III.B)."""
+
+    def __init__(self, plan: TuckerPlan, V: torch.Tensor):
+        if V.dim() != 2 or V.shape[1] != plan.m:
+            raise ValueError("V must be m x r_c with r_c = the plan's columns")
+        self.plan = plan
+        self.m = int(V.shape[0])
+        self.rows = plan.rows
+        # column-major m x r_c: the transpose of a contiguous (r_c, m) tensor
+        self.Vc = V.to(torch.complex64).t().contiguous()
+        self._ws = {}
+
+    def workspace(self, op: int, nrhs: int) -> torch.Tensor:
+        key = (op, nrhs)
+        if key not in self._ws:
+            n = lib.tv_aca_workspace_bytes(self.plan.handle, op, nrhs)
+            self._ws[key] = torch.empty(max(n, 16), dtype=torch.uint8,
+                                        device="cuda")
+        return self._ws[key]
+
+    def matvec(self, x: torch.Tensor) -> torch.Tensor:
+        """Y = U (V^* X) for x of shape (m,) or (m, p)."""
+        vec = x.dim() == 1
+        X = x.reshape(self.m, -1)
+        p = X.shape[1]
+        Xc = X.t().contiguous()
+        Y = torch.empty((p, self.rows), dtype=torch.complex64, device=x.device)
+        ws = self.workspace(0, p)
+        lib.tv_aca_matvec(self.plan.handle, self.Vc.data_ptr(), self.m, self.m,
+                          Xc.data_ptr(), self.m, p, Y.data_ptr(), self.rows,
+                          ws.data_ptr(), ws.numel(), _stream())
+        return Y.reshape(-1) if vec else Y.t()
+
+    def rmatvec(self, y: torch.Tensor) -> torch.Tensor:
+        """X = V (U^* Y) for y of shape (q nv,) or (q nv, p)."""
+        vec = y.dim() == 1
+        Yv = y.reshape(self.rows, -1)
+        p = Yv.shape[1]
+        Yc = Yv.t().contiguous()
+        X = torch.empty((p, self.m), dtype=torch.complex64, device=y.device)
+        ws = self.workspace(1, p)
+        lib.tv_aca_rmatvec(self.plan.handle, self.Vc.data_ptr(), self.m,
+                           self.m, Yc.data_ptr(), self.rows, p, X.data_ptr(),
+                           self.m, ws.data_ptr(), ws.numel(), _stream())
+        return X.reshape(-1) if vec else X.t()
+
+
 class TuckerMatvec(torch.autograd.Function):
     """y = Z x with the hand-written Z^* kernel as the backward."""
 

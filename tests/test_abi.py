@@ -93,3 +93,16 @@ def test_call_argument_errors_without_device_work():
         lib.tv_dipole_columns(4, 4, 4, 0.01, 1.0, 0, np.zeros((1, 3)),
                               np.array([[1.0, 0, 0]]), 1, None)
     assert e.value.status == -1
+
+
+def test_aca_entry_points_reject_null_plan():
+    """The ACA + Tucker entry points validate on the host before queueing
+    any device work (no GPU needed for these paths)."""
+    from paper_2103_06393_amd import lib
+    with pytest.raises(lib.TuckVsieError) as e:
+        lib.tv_aca_workspace_bytes(None, 0, 1)
+    assert e.value.status == -1
+    for f in (lib.tv_aca_matvec, lib.tv_aca_rmatvec):
+        with pytest.raises(lib.TuckVsieError) as e:
+            f(None, None, 1, 1, None, 1, 1, None, 1, None, 0, None)
+        assert e.value.status == -1 and "plan is NULL" in str(e.value)
