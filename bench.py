@@ -100,7 +100,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2",
-                    help="c1, c2 (default), c3, c5, or c4 for the batched path")
+                    help="c1, c2 (default), c3, c5, c4 for the batched path, or "
+                         "aca5 / aca2 / aca1 for the ACA+Tucker products on the "
+                         "body-coil grids")
+    ap.add_argument("--basis", default="pwc", choices=("pwc", "pwl"),
+                    help="voxel basis of the aca* workloads")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "bf16x3"))
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline")
@@ -138,6 +142,8 @@ def main(argv=None):
         return 0
     if args.workload == "c4":
         return bench_batch(args)
+    if args.workload.startswith("aca"):
+        return bench_aca(args)
     prec = lib.TV_PREC_BF16X3 if args.precision == "bf16x3" else lib.TV_PREC_FP32
     wl = workloads.make(args.workload)
     log(f"[bench] workload {wl.name}: grid {wl.grid.dims}, q={wl.q}, m={wl.m}")
@@ -250,6 +256,152 @@ def main(argv=None):
         out["rel_err_fwd"] = float(np.linalg.norm(ys - y_ref) / np.linalg.norm(y_ref))
         out["rel_err_adj"] = float(np.linalg.norm(xa - x_ref) / np.linalg.norm(x_ref))
         log(f"[bench] oracle {cb['value']:.4f} matvecs/s on {cb['cores']} threads; "
+            f"rel err fwd {out['rel_err_fwd']:.2e} adj {out['rel_err_adj']:.2e}")
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# Time of one y = Z_bc x with the ACA+HOSVD form on the paper's GPU (Table IX),
+# seconds: context for the aca* workloads, not a target of the same metric.
+PAPER_TABLE9_S = {("aca5", "pwc"): 1, ("aca5", "pwl"): 2, ("aca2", "pwc"): 2,
+                  ("aca2", "pwl"): 6, ("aca1", "pwc"): 9, ("aca1", "pwl"): 33}
+
+
+def bench_aca(args):
+    """ACA+Tucker products (Sec. III.B substitution, Table III row
+    ACA+Tucker) on the body-coil grids of Sec. IV.B.2: one step is one
+    U (V^* x) and one V (U^* y).
+
+    U has the paper's ACA rank r_c of columns; they stand in for Algorithm 3's
+    columns with the point-current fields of r_c coil elements spread over
+    the coil and shield, compressed on the GPU with Algorithm 3's HOSVD
+    tolerance (3 x 1e-3).  V is m x r_c complex normal.  The products' cost
+    depends on the grid, q, r_c, m and the ranks only.
+    """
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import AcaTuckerOperator, TuckerPlan
+
+    prec = lib.TV_PREC_BF16X3 if args.precision == "bf16x3" else lib.TV_PREC_FP32
+    wl = workloads.make_bodycoil(args.workload, args.basis)
+    rc = workloads.aca_rank(args.workload)
+    m = wl.m
+    log(f"[aca] workload {wl.name} ({args.basis}): grid {wl.grid.dims}, q={wl.q}, "
+        f"m={m}, r_c={rc}")
+    pick = np.round(np.linspace(0, m - 1, rc)).astype(np.int64)
+    t0 = time.perf_counter()
+    plan = TuckerPlan.compress_dipoles(
+        wl.grid.dims, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1,
+        wl.pos[pick], wl.ori[pick], 3.0 * wl.tol, 1, 0, precision=prec)
+    torch.cuda.synchronize()
+    log(f"[aca] U compressed on GPU in {time.perf_counter() - t0:.2f} s")
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        plan.autotune(2, args.tune_cache)
+        torch.cuda.synchronize()
+        log(f"[aca] autotuned in {time.perf_counter() - t0:.2f} s")
+    info = plan.info
+    V_np = workloads.complex_normal((m, rc), 63)
+    op = AcaTuckerOperator(plan, torch.from_numpy(V_np.astype(np.complex64)).cuda())
+    x_np = workloads.complex_normal(m, wl.seed_x)
+    y_np = workloads.complex_normal(plan.rows, wl.seed_y)
+    x = torch.from_numpy(x_np.astype(np.complex64)).cuda()
+    y = torch.from_numpy(y_np.astype(np.complex64)).cuda()
+    yo = torch.empty(plan.rows, dtype=torch.complex64, device="cuda")
+    xo = torch.empty(m, dtype=torch.complex64, device="cuda")
+    ws0, ws1 = op.workspace(0, 1), op.workspace(1, 1)
+    st = torch.cuda.current_stream()
+    sp = st.cuda_stream
+    h, vp = plan.handle, op.Vc.data_ptr()
+
+    def fwd():
+        lib.tv_aca_matvec(h, vp, m, m, x.data_ptr(), m, 1, yo.data_ptr(),
+                          plan.rows, ws0.data_ptr(), ws0.numel(), sp)
+
+    def adj():
+        lib.tv_aca_rmatvec(h, vp, m, m, y.data_ptr(), plan.rows, 1,
+                           xo.data_ptr(), m, ws1.data_ptr(), ws1.numel(), sp)
+
+    for _ in range(args.warmup):
+        fwd()
+        adj()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(st)
+    for i in range(K):
+        ev[i][0].record(st)
+        fwd()
+        ev[i][1].record(st)
+        adj()
+        ev[i][2].record(st)
+    end.record(st)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    fl_f = info.flops_matvec + 8.0 * m * rc
+    fl_a = info.flops_rmatvec + 8.0 * m * rc
+    tf_f = fl_f / (fwd_ms * 1e-3) / 1e12
+    tf_a = fl_a / (adj_ms * 1e-3) / 1e12
+    log(f"[aca] fwd {fwd_ms:.3f} ms ({tf_f:.1f} TFLOP/s), adj {adj_ms:.3f} ms "
+        f"({tf_a:.1f} TFLOP/s)")
+    dom = "adjoint" if adj_ms >= fwd_ms else "forward"
+    d = 1 if dom == "adjoint" else 0
+    info = plan.info
+    kname = "tv::ws_fused" if info.kernel[d] else "tv::fused_f32"
+    ach = tf_a if dom == "adjoint" else tf_f
+    peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
+    out = {
+        "metric": "ACA+Tucker coupling-matrix products/s (U (V^* x) and V (U^* y))",
+        "value": 2.0 * K / (total_ms / 1e3), "unit": "matvecs/s", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": total_ms / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == lib.TV_PREC_FP32 else "bf16x3 (f32 accumulate)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name} ({args.basis}): body-coil box "
+                        f"{wl.grid.n1}x{wl.grid.n2}x{wl.grid.n3}, q={wl.q}, "
+                        f"m={m} coil elements, r_c={rc} Tucker-compressed "
+                        f"columns of U (HOSVD tol {3.0 * wl.tol:g}), complex64",
+            "grid": list(wl.grid.dims), "q": wl.q, "m": m, "r_c": rc,
+            "mean_rank": [round(v, 3) for v in info.mean_rank],
+            "max_rank": list(info.max_rank),
+            "plan_factor_bytes": int(info.factor_bytes),
+        },
+        "fwd_ms": fwd_ms, "adj_ms": adj_ms, "tflops_fwd": tf_f, "tflops_adj": tf_a,
+        "flops_fwd": fl_f, "flops_adj": fl_a,
+        "paper_table9_s": PAPER_TABLE9_S.get((wl.name, args.basis)),
+        "roofline": {"kernel": f"{kname} ({dom})", "bound": "mfma",
+                     "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None},
+        "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
+                   "splits": list(info.splits)},
+    }
+    if not args.no_cpu:
+        w_np = V_np.astype(np.complex64).astype(np.complex128).conj().T @ \
+            x_np.astype(np.complex64).astype(np.complex128)
+        t0 = time.perf_counter()
+        V_np.conj().T @ x_np
+        V_np @ w_np
+        t_v = time.perf_counter() - t0
+        cb, cols, y_ref, x_ref = cpu_baseline(wl, plan, w_np, y_np, args.cpu_budget)
+        cb["value"] = 2.0 / (2.0 / cb["value"] + t_v)
+        cb["sample"] += "; plus the two V products in full (numpy)"
+        out["cpu_baseline"] = cb
+        ws = np.zeros_like(w_np)
+        ws[cols] = w_np[cols]
+        ys = plan.matvec(torch.from_numpy(ws.astype(np.complex64)).cuda()).cpu().numpy()
+        xa = plan.rmatvec(y).cpu().numpy()[cols]
+        out["rel_err_fwd"] = float(np.linalg.norm(ys - y_ref) / np.linalg.norm(y_ref))
+        out["rel_err_adj"] = float(np.linalg.norm(xa - x_ref) / np.linalg.norm(x_ref))
+        log(f"[aca] oracle {cb['value']:.4f} products/s on {cb['cores']} threads; "
             f"rel err fwd {out['rel_err_fwd']:.2e} adj {out['rel_err_adj']:.2e}")
     plan.close()
     print(json.dumps(out), flush=True)

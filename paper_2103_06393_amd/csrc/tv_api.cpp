@@ -42,10 +42,12 @@ static double bf16_value(uint32_t h) {
 // nwg = 32*wn columns (i2, i3) of the mode-1 unfolding, t2 values of i2 by
 // t3 = nwg / t2 values of i3.  t2 = 0 picks the shape covering the fewest
 // columns beyond the grid.
-int nb_cap(const tv_plan_s* /*p*/, int op) {
-  // the adjoint keeps the y tile in registers next to the accumulators: at
-  // most 2 row blocks per wave keep two workgroups per CU resident
-  return op == 1 ? 2 : 8;
+int nb_cap(const tv_plan_s* p, int op) {
+  // the adjoint keeps the y tile in registers next to the accumulators: 2 row
+  // blocks per wave keep two workgroups per CU resident; 3 pad short voxel
+  // rows less (81 rows: 96 instead of 128) at one workgroup per CU, so the
+  // autotuner times both
+  return op == 1 ? (p ? p->nbcap_a : 2) : 8;
 }
 
 tv_status make_tiling(const tv_grid& g, int t2req, int nbcap, Tiling* T) {

@@ -1,7 +1,8 @@
 // Autotuner for the fused single-vector kernels: per plan and direction it
-// times every workgroup column tile (t2 x t3) and column split count on the
-// device with HIP events and keeps the fastest; results are cached in a
-// small JSON file keyed by device, grid, precision and a hash of the ranks.
+// times every workgroup column tile (t2 x t3), column split count and (for
+// the adjoint) row-block cap per wave on the device with HIP events and keeps
+// the fastest; results are cached in a small JSON file keyed by device, grid,
+// precision and a hash of the ranks.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -26,7 +27,7 @@ static std::string plan_key(const tv_plan_s* p, int op) {
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "k3|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k4|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -34,9 +35,13 @@ static std::string plan_key(const tv_plan_s* p, int op) {
   return buf;
 }
 
-// The cache is a flat JSON object {"key": [t2, split], ...}.
-static std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
-  std::map<std::string, std::pair<int, int>> out;
+struct TuneChoice {
+  int t2, split, cap;
+};
+
+// The cache is a flat JSON object {"key": [t2, split, cap], ...}.
+static std::map<std::string, TuneChoice> read_cache(const char* path) {
+  std::map<std::string, TuneChoice> out;
   if (!path) return out;
   std::ifstream f(path);
   if (!f) return out;
@@ -51,15 +56,15 @@ static std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
     if (q1 == std::string::npos) break;
     const size_t b0 = s.find('[', q1), b1 = s.find(']', q1);
     if (b0 == std::string::npos || b1 == std::string::npos) break;
-    int t2 = 0, sp = 0;
-    if (sscanf(s.c_str() + b0 + 1, "%d , %d", &t2, &sp) == 2)
-      out[s.substr(q0 + 1, q1 - q0 - 1)] = {t2, sp};
+    int t2 = 0, sp = 0, cap = 0;
+    if (sscanf(s.c_str() + b0 + 1, "%d , %d , %d", &t2, &sp, &cap) == 3)
+      out[s.substr(q0 + 1, q1 - q0 - 1)] = {t2, sp, cap};
     pos = b1 + 1;
   }
   return out;
 }
 
-static void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+static void write_cache(const char* path, const std::map<std::string, TuneChoice>& m) {
   if (!path) return;
   const std::string tmp = std::string(path) + ".tmp";
   {
@@ -68,25 +73,31 @@ static void write_cache(const char* path, const std::map<std::string, std::pair<
     f << "{\n";
     size_t i = 0;
     for (const auto& kv : m) {
-      f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
-        << (++i < m.size() ? ",\n" : "\n");
+      f << "  \"" << kv.first << "\": [" << kv.second.t2 << ", " << kv.second.split << ", "
+        << kv.second.cap << "]" << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
   }
   std::rename(tmp.c_str(), path);
 }
 
-static tv_status apply_config(tv_plan_s* p, int op, int t2, int split) {
+static tv_status apply_config(tv_plan_s* p, int op, int t2, int split, int cap) {
+  if (op == 0 && cap != nb_cap(p, 0)) return set_error(TV_ERR_INVALID_ARG, "forward cap");
+  if (op == 1 && cap != 2 && cap != 3) return set_error(TV_ERR_INVALID_ARG, "adjoint cap");
   Tiling T;
-  tv_status s = make_tiling(p->grid, t2, nb_cap(p, op), &T);
+  tv_status s = make_tiling(p->grid, t2, cap, &T);
   if (s != TV_OK) return s;
+  // the packed U1 rows hold nbt_pack blocks: no tiling may read past them
+  if (T.nbt > p->nbt_pack) return set_error(TV_ERR_NOT_SUPPORTED, "tiling wider than the pack");
   if (fused_lds_bytes(p, T, op == 1) > 160 * 1024)
     return set_error(TV_ERR_NOT_SUPPORTED, "tile too large for LDS");
   if ((s = set_split(p, op, split)) != TV_OK) return s;
-  if (op == 0)
+  if (op == 0) {
     p->tiling = T;
-  else
+  } else {
     p->tiling_a = T;
+    p->nbcap_a = cap;
+  }
   return TV_OK;
 }
 
@@ -108,14 +119,22 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     if (op != 2 && op != o) continue;
     const std::string key = plan_key(p, o);
     auto it = cache.find(key);
-    if (it != cache.end() && apply_config(p, o, it->second.first, it->second.second) == TV_OK)
+    if (it != cache.end() &&
+        apply_config(p, o, it->second.t2, it->second.split, it->second.cap) == TV_OK)
       continue;
-    // candidates
-    Tiling T0;
-    tv_status s = make_tiling(g, 0, nb_cap(p, o), &T0);
-    if (s != TV_OK) return s;
-    std::vector<int> t2s, splits;
-    for (int t2 = T0.nwg; t2 >= 2; t2 /= 2) t2s.push_back(t2);
+    // candidates: (cap, t2) pairs, then column splits
+    std::vector<std::pair<int, int>> shapes;
+    std::vector<int> splits;
+    int prev_nb = -1, prev_wm = -1;
+    for (int cap : (o == 0 ? std::vector<int>{nb_cap(p, 0)} : std::vector<int>{2, 3})) {
+      Tiling T0;
+      tv_status s = make_tiling(g, 0, cap, &T0);
+      if (s != TV_OK) return s;
+      if (T0.nb == prev_nb && T0.wm == prev_wm) continue;  // same tiling as the last cap
+      prev_nb = T0.nb;
+      prev_wm = T0.wm;
+      for (int t2 = T0.nwg; t2 >= 2; t2 /= 2) shapes.push_back({cap, t2});
+    }
     const int smax = o == 0 ? 16 : 64;
     for (int sp = 1; sp <= smax && sp <= g.m; sp *= 2) {
       if (o == 0 && sp > 1 && (double)sp * rows * 8 > 2e9) break;  // forward partials
@@ -123,9 +142,9 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     }
     // buffers sized for the largest candidate
     size_t wsb = 16;
-    for (int t2 : t2s) {
+    for (const auto& sh : shapes) {
       Tiling T;
-      if (make_tiling(g, t2, nb_cap(p, o), &T) != TV_OK) continue;
+      if (make_tiling(g, sh.second, sh.first, &T) != TV_OK) continue;
       const size_t b = o == 0 ? (size_t)8 * splits.back() * rows : (size_t)8 * g.q * T.tiles * g.m;
       wsb = std::max(wsb, b);
     }
@@ -140,11 +159,12 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const int keep_t2 = o == 0 ? p->tiling.t2 : p->tiling_a.t2;
     const int keep_sp = o == 0 ? p->split_f : p->split_a;
+    const int keep_cap = nb_cap(p, o);
     float best = -1.f;
-    int best_t2 = keep_t2, best_sp = keep_sp;
-    for (size_t a = 0; e == hipSuccess && a < t2s.size(); ++a)
+    int best_t2 = keep_t2, best_sp = keep_sp, best_cap = keep_cap;
+    for (size_t a = 0; e == hipSuccess && a < shapes.size(); ++a)
       for (size_t b = 0; e == hipSuccess && b < splits.size(); ++b) {
-        if (apply_config(p, o, t2s[a], splits[b]) != TV_OK) continue;
+        if (apply_config(p, o, shapes[a].second, splits[b], shapes[a].first) != TV_OK) continue;
         auto run = [&]() {
           return o == 0 ? tv_matvec(p, x, g.m, 1, y, rows, ws, wsb, stream)
                         : tv_rmatvec(p, y, rows, 1, x, g.m, ws, wsb, stream);
@@ -160,8 +180,9 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (ok && e == hipSuccess && (best < 0.f || ms < best)) {
           best = ms;
-          best_t2 = t2s[a];
+          best_t2 = shapes[a].second;
           best_sp = splits[b];
+          best_cap = shapes[a].first;
         }
       }
     if (e0) hipEventDestroy(e0);
@@ -170,11 +191,12 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     hipFree(y);
     hipFree(ws);
     if (e != hipSuccess) {
-      apply_config(p, o, keep_t2, keep_sp);
+      apply_config(p, o, keep_t2, keep_sp, keep_cap);
       return hip_error(e, "tv_autotune");
     }
-    if ((s = apply_config(p, o, best_t2, best_sp)) != TV_OK) return s;
-    cache[key] = {best_t2, best_sp};
+    tv_status s = apply_config(p, o, best_t2, best_sp, best_cap);
+    if (s != TV_OK) return s;
+    cache[key] = {best_t2, best_sp, best_cap};
     dirty = true;
   }
   if (dirty) write_cache(cache_path, cache);

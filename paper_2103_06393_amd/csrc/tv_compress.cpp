@@ -104,8 +104,9 @@ tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min, i
   if (precision != TV_PREC_FP32 && precision != TV_PREC_BF16X3)
     return set_error(TV_ERR_INVALID_ARG, "unknown precision");
   const int nmax = std::max(grid->n1, std::max(grid->n2, grid->n3));
-  if (nmax > 256)
-    return set_error(TV_ERR_NOT_SUPPORTED, "device compression is built for n1, n2, n3 <= 256");
+  // Gram scratch is 3 x tensors x nmax^2 complex128 per append call
+  if (nmax > 1024)
+    return set_error(TV_ERR_NOT_SUPPORTED, "device compression is built for n1, n2, n3 <= 1024");
   tv_plan_s* p = new (std::nothrow) tv_plan_s;
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = *grid;

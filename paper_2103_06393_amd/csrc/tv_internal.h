@@ -66,6 +66,7 @@ struct tv_plan_s {
   std::vector<int64_t> apack_koff;
   std::vector<int64_t> sum_r1_k;   // rows of A_k per component
   int split_f = 1, split_a = 1;    // column splits of the forward / adjoint
+  int nbcap_a = 2;                 // row blocks per wave allowed in the adjoint tiling
   bool kernel_ws[2] = {true, true};  // warp-specialised kernel (when the tile allows)
   int32_t* d_split_f = nullptr;    // [q][split+1] first column per split
   int32_t* d_split_a = nullptr;

@@ -33,3 +33,36 @@ def test_autotune_keeps_results_and_caches(gpu_lib, tmp_path):
     for op in (0, 1):
         assert lib.tv_workspace_bytes(P.handle, op, 1) == lib.tv_workspace_bytes(Q.handle, op, 1)
     assert np.array_equal(P.matvec(cx(x)).cpu().numpy(), Q.matvec(cx(x)).cpu().numpy())
+    # cached choices are [t2, split, row-block cap]; the adjoint's cap is 2 or 3
+    for key, val in entries.items():
+        assert len(val) == 3
+        assert val[2] in ((2, 3) if key.endswith("op1") else (8,))
+
+
+@pytest.mark.parametrize("cap,t2", [(2, 32), (3, 32), (3, 2), (2, 2)])
+def test_adjoint_row_block_caps(gpu_lib, tmp_path, cap, t2):
+    """Every adjoint tiling the autotuner may choose, forced through its
+    cache: 81 voxel rows pad to 128 with 2 row blocks per wave and to 96
+    with 3; t2 = 32 runs the warp-specialised kernel, t2 = 2 the phased one."""
+    import torch
+    from paper_2103_06393_amd.ops import TuckerPlan
+    S = random_struct((81, 12, 10), 3, 9, 12, 41)
+    abi = struct_to_abi(S)
+    cache = tmp_path / "tune.json"
+    P = TuckerPlan.from_factors(S.dims, S.q, S.m, *abi)
+    P.autotune(1, str(cache))
+    entries = json.loads(cache.read_text())
+    (key,) = [k for k in entries if k.endswith("op1")]
+    cache.write_text(json.dumps({key: [t2, 2, cap]}))
+    Q = TuckerPlan.from_factors(S.dims, S.q, S.m, *abi)
+    Q.autotune(1, str(cache))
+    info = Q.info
+    assert info.tile_t2[1] == t2 and info.splits[1] == 2
+    y = workloads_cn(S.q * S.nv, 42)
+    got = Q.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
+    assert rel_err(got, om.alg2(S, y.astype(np.complex64).astype(np.complex128))[:, 0]) <= 1e-5
+
+
+def workloads_cn(n, seed):
+    import workloads
+    return workloads.complex_normal(n, seed)

@@ -149,3 +149,24 @@ def test_long_modes_use_leading_eigenpairs(gpu_lib):
         for k in range(3):
             err = np.linalg.norm(S.t[j][k].full() - T[k]) / np.linalg.norm(T[k])
             assert err <= wl.tol * 1.05
+
+
+def test_modes_beyond_256(gpu_lib):
+    """Modes of 300 and 541 voxels (the 1 mm body-coil box is 541 long in
+    z, Sec. IV.B.2): leading eigenpairs by subspace iteration on 300 x 300
+    and 541 x 541 Gram matrices; ranks and reconstructions against the
+    oracle's SVD-based HOSVD."""
+    import dataclasses
+    wl = workloads.make_bodycoil("aca1")
+    wl = dataclasses.replace(wl, grid=workloads.Grid(300, 6, 541, 0.001),
+                             pos=wl.pos[::1600], ori=wl.ori[::1600], tol=3e-3)
+    assert wl.min_distance() > 10 * wl.grid.h
+    P = _compress(wl, chunk=2)
+    S = abi_to_struct(wl.grid.dims, wl.q, *P.export_factors())
+    So = om.compress_columns(wl)
+    assert np.max(np.abs(S.ranks() - So.ranks())) <= 1
+    for j in range(wl.m):
+        T = fields.column_tensors(wl, j)
+        for k in range(3):
+            err = np.linalg.norm(S.t[j][k].full() - T[k]) / np.linalg.norm(T[k])
+            assert err <= wl.tol * 1.05

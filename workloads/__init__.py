@@ -7,6 +7,6 @@ compresses nothing and multiplies no matrices, so that both the CPU reference
 of the method's arithmetic.
 """
 from .configs import (  # noqa: F401
-    BODYCOIL, C0, FREQ_3T, FREQ_7T, Grid, Workload, complex_normal, make,
+    BODYCOIL, C0, FREQ_3T, aca_rank, FREQ_7T, Grid, Workload, complex_normal, make,
     make_batch, make_bodycoil, NAMES,
 )
