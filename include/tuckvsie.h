@@ -268,6 +268,47 @@ tv_status tv_aca_rmatvec(tv_plan plan, const void* v, int64_t m, int64_t ldv,
                          const void* y, int64_t ldy, int32_t nrhs, void* x,
                          int64_t ldx, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Rows of the synthetic coupling matrix (the same point-current fields as
+ * tv_dipole_columns): out[r*nsrc + j] = Z[rows[r], j], device complex128,
+ * row = k nv + i1 + n1 (i2 + n2 i3) (Algorithm 1's row order), nrows <=
+ * 65535, rows in [0, q nv).  Synchronous; allocates a small staging buffer.
+ * ---------------------------------------------------------------------- */
+tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h,
+                         double k0, int32_t basis, int64_t nsrc,
+                         const double* pos, const double* ori, int64_t nrows,
+                         const int64_t* rows, void* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Tucker-based ACA assembly (Algorithm 3, Sec. III.C) of the point-current
+ * coupling matrix Z (q nv x m, grid->m coil elements at pos/ori, host
+ * double[m][3]) on the device: adaptive cross approximation with partial
+ * pivoting in which each new column of U is compressed at once by the
+ * truncated HOSVD (tolerance hosvd_tol, <= 0 for Algorithm 3's 3 tol; rank
+ * rule and clamps as tv_compress_begin), rows of U come from single-element
+ * decompression and products with U from the fused kernels (precision).
+ * The loop stops when |x||y| <= tol sqrt(s) (s the running estimate of
+ * ||U V^*||_F^2, with the cross term 2 Re sum conj(V^* y) (U^* x)), when a
+ * residual row is exactly zero, or after max_terms steps.
+ * Outputs: *u_out a finalized plan of the r_c columns of U (grid m = r_c;
+ * release with tv_plan_destroy); v_out host complex128 m x max_terms,
+ * column-major, first r_c columns written; *rc_out = r_c; *converged_out =
+ * 1 if the stopping test was met; pivots (optional, host int64
+ * [max_terms][2]) the pivot row i and column j of each step; s_out
+ * (optional, host double[max_terms]) the estimate after each step.
+ * basis 0 (PWC) needs q = 3, basis 1 (PWL) q = 12.  Synchronous; allocates
+ * device memory for the duration of the call.  TV_ERR_NUMERIC if the first
+ * pivot row of Z is zero.
+ * ---------------------------------------------------------------------- */
+tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0,
+                          int32_t basis, const double* pos, const double* ori,
+                          double tol, double hosvd_tol, int32_t rank_min,
+                          int32_t rank_cap, int32_t max_terms,
+                          tv_precision precision, tv_plan* u_out,
+                          double* v_out, int32_t* rc_out,
+                          int32_t* converged_out, int64_t* pivots,
+                          double* s_out, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* tv_status_string(tv_status status);
 

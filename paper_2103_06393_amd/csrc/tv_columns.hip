@@ -85,9 +85,128 @@ __global__ void columns_kernel(ColParams P) {
   for (int t = 0; t < 12; ++t) P.out[(j * 12 + t) * nv + v] = acc[t];
 }
 
+// Row `row` of the coupling matrix, one source j per lane: the field of
+// every coil element at one voxel v and tensor index k (row = k nv + v, the
+// row order of Algorithm 1).  Same closed form and quadrature as the columns.
+__global__ void rows_kernel(ColParams P, const int64_t* rows) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P.ncols) return;
+  const int64_t nv = (int64_t)P.n1 * P.n2 * P.n3;
+  const int64_t row = rows[blockIdx.y];
+  const int k = (int)(row / nv);
+  const int64_t v = row - (int64_t)k * nv;
+  const int i1 = (int)(v % P.n1);
+  const int i2 = (int)((v / P.n1) % P.n2);
+  const int i3 = (int)(v / ((int64_t)P.n1 * P.n2));
+  const double cx = (i1 - 0.5 * (P.n1 - 1)) * P.h;
+  const double cy = (i2 - 0.5 * (P.n2 - 1)) * P.h;
+  const double cz = (i3 - 0.5 * (P.n3 - 1)) * P.h;
+  double s[6];
+  for (int c = 0; c < 6; ++c) s[c] = P.src[j * 6 + c];
+  double2* out = P.out + (int64_t)blockIdx.y * P.ncols + j;
+  if (P.basis == 0) {
+    double2 E[3];
+    point_field(cx, cy, cz, s, P.k0, E);
+    *out = E[k];
+    return;
+  }
+  const int c = k / 4, l = k % 4;
+  const double off = 0.28867513459481287;  // 1 / (2 sqrt 3)
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = 0; q < 8; ++q) {
+    const double u[3] = {(q & 1) ? off : -off, (q & 2) ? off : -off, (q & 4) ? off : -off};
+    double2 E[3];
+    point_field(cx + u[0] * P.h, cy + u[1] * P.h, cz + u[2] * P.h, s, P.k0, E);
+    const double phi = l == 0 ? 0.125 : 0.125 * u[l - 1];
+    acc.x += E[c].x * phi;
+    acc.y += E[c].y * phi;
+  }
+  *out = acc;
+}
+
+// Sources as [n][6] (position, orientation), checked to lie outside the
+// voxel domain and to have unit orientations.
+tv_status stage_sources(int n1, int n2, int n3, double h, int64_t n, const double* pos,
+                        const double* ori, std::vector<double>& src) {
+  const double half[3] = {0.5 * (n1 - 1) * h, 0.5 * (n2 - 1) * h, 0.5 * (n3 - 1) * h};
+  src.assign((size_t)n * 6, 0.0);
+  for (int64_t j = 0; j < n; ++j) {
+    double d2 = 0.0, on = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double p = pos[3 * j + c];
+      const double nearest = p < -half[c] ? -half[c] : (p > half[c] ? half[c] : p);
+      d2 += (p - nearest) * (p - nearest);
+      on += ori[3 * j + c] * ori[3 * j + c];
+      src[6 * j + c] = p;
+      src[6 * j + 3 + c] = ori[3 * j + c];
+    }
+    if (!(d2 > (0.25 * h) * (0.25 * h)))
+      return set_error(TV_ERR_INVALID_ARG, "a source lies inside the voxel domain");
+    if (!(fabs(on - 1.0) < 1e-9)) return set_error(TV_ERR_INVALID_ARG, "orientation not unit");
+  }
+  return TV_OK;
+}
+
+tv_status launch_dipole_columns(int n1, int n2, int n3, double h, double k0, int basis,
+                                int64_t ncols, const double* d_src, double2* out,
+                                hipStream_t st) {
+  const int64_t nv = (int64_t)n1 * n2 * n3;
+  ColParams P{n1, n2, n3, h, k0, basis, ncols, d_src, out};
+  hipLaunchKernelGGL(columns_kernel, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
+                     dim3(256), 0, st, P);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TV_OK : hip_error(e, "columns kernel launch");
+}
+
+tv_status launch_dipole_rows(int n1, int n2, int n3, double h, double k0, int basis,
+                             int64_t nsrc, const double* d_src, int64_t nrows,
+                             const int64_t* d_rows, double2* out, hipStream_t st) {
+  ColParams P{n1, n2, n3, h, k0, basis, nsrc, d_src, out};
+  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)((nsrc + 255) / 256), (unsigned)nrows),
+                     dim3(256), 0, st, P, d_rows);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TV_OK : hip_error(e, "rows kernel launch");
+}
+
 }  // namespace tv
 
 using namespace tv;
+
+extern "C" tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h, double k0,
+                                    int32_t basis, int64_t nsrc, const double* pos,
+                                    const double* ori, int64_t nrows, const int64_t* rows,
+                                    void* out, void* stream) {
+  clear_error();
+  if (n1 < 1 || n2 < 1 || n3 < 1 || nsrc < 1 || nrows < 0)
+    return set_error(TV_ERR_SHAPE, "grid sizes and nsrc must be >= 1, nrows >= 0");
+  if (!(h > 0.0) || !(k0 > 0.0)) return set_error(TV_ERR_INVALID_ARG, "h and k0 must be > 0");
+  if (basis != 0 && basis != 1) return set_error(TV_ERR_INVALID_ARG, "basis must be 0 or 1");
+  if (nrows == 0) return TV_OK;
+  if (!pos || !ori || !rows || !out) return set_error(TV_ERR_INVALID_ARG, "NULL pointer");
+  if (nrows > 65535) return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 rows per call");
+  const int64_t total = (int64_t)(basis == 0 ? 3 : 12) * n1 * n2 * n3;
+  for (int64_t r = 0; r < nrows; ++r)
+    if (rows[r] < 0 || rows[r] >= total) return set_error(TV_ERR_SHAPE, "row index out of range");
+  std::vector<double> src;
+  tv_status s = stage_sources(n1, n2, n3, h, nsrc, pos, ori, src);
+  if (s != TV_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  double* d_src = nullptr;
+  int64_t* d_rows = nullptr;
+  hipError_t e = hipMalloc((void**)&d_src, src.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&d_rows, (size_t)nrows * sizeof(int64_t));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_rows, rows, (size_t)nrows * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    s = launch_dipole_rows(n1, n2, n3, h, k0, basis, nsrc, d_src, nrows, d_rows, (double2*)out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(d_src);
+  hipFree(d_rows);
+  if (e != hipSuccess) return hip_error(e, "tv_dipole_rows");
+  return s;
+}
 
 extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h, double k0,
                                        int32_t basis, int64_t ncols, const double* pos,
@@ -102,22 +221,9 @@ extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, doubl
   if (ncols > 65535) return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 columns per call");
   const int64_t nv = (int64_t)n1 * n2 * n3;
   // every voxel centre must be away from every source
-  const double half[3] = {0.5 * (n1 - 1) * h, 0.5 * (n2 - 1) * h, 0.5 * (n3 - 1) * h};
-  std::vector<double> src((size_t)ncols * 6);
-  for (int64_t j = 0; j < ncols; ++j) {
-    double d2 = 0.0, on = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      const double p = pos[3 * j + c];
-      const double nearest = p < -half[c] ? -half[c] : (p > half[c] ? half[c] : p);
-      d2 += (p - nearest) * (p - nearest);
-      on += ori[3 * j + c] * ori[3 * j + c];
-      src[6 * j + c] = p;
-      src[6 * j + 3 + c] = ori[3 * j + c];
-    }
-    if (!(d2 > (0.25 * h) * (0.25 * h)))
-      return set_error(TV_ERR_INVALID_ARG, "a source lies inside the voxel domain");
-    if (!(fabs(on - 1.0) < 1e-9)) return set_error(TV_ERR_INVALID_ARG, "orientation not unit");
-  }
+  std::vector<double> src;
+  tv_status s0 = stage_sources(n1, n2, n3, h, ncols, pos, ori, src);
+  if (s0 != TV_OK) return s0;
   double* d_src = nullptr;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMallocAsync((void**)&d_src, src.size() * sizeof(double), st);

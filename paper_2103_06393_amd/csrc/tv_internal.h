@@ -107,4 +107,12 @@ tv_status make_tiling(const tv_grid& g, int t2, int nbcap, Tiling* T);
 int nb_cap(const tv_plan_s* p, int op);
 // (re)build and upload the column split table of one direction
 tv_status set_split(tv_plan_s* p, int op, int S);
+// point-current fields (tv_columns.hip): sources as device [n][6]
+tv_status stage_sources(int n1, int n2, int n3, double h, int64_t n, const double* pos,
+                        const double* ori, std::vector<double>& src);
+tv_status launch_dipole_columns(int n1, int n2, int n3, double h, double k0, int basis,
+                                int64_t ncols, const double* d_src, double2* out, hipStream_t st);
+tv_status launch_dipole_rows(int n1, int n2, int n3, double h, double k0, int basis,
+                             int64_t nsrc, const double* d_src, int64_t nrows,
+                             const int64_t* d_rows, double2* out, hipStream_t st);
 }  // namespace tv

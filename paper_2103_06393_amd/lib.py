@@ -100,6 +100,14 @@ _tv_aca_matvec = _sig("tv_aca_matvec", [c_vp, c_vp, c_i64, c_i64, c_vp, c_i64,
 _tv_aca_rmatvec = _sig("tv_aca_rmatvec", [c_vp, c_vp, c_i64, c_i64, c_vp,
                                           c_i64, c_i32, c_vp, c_i64, c_vp,
                                           c_sz, c_vp])
+_tv_dipole_rows = _sig("tv_dipole_rows", [c_i32, c_i32, c_i32, c_dbl, c_dbl, c_i32,
+                                          c_i64, _dp, _dp, c_i64,
+                                          ctypes.POINTER(c_i64), c_vp, c_vp])
+_tv_aca_assemble = _sig("tv_aca_assemble",
+                        [ctypes.POINTER(tv_grid), c_dbl, c_dbl, c_i32, _dp, _dp,
+                         c_dbl, c_dbl, c_i32, c_i32, c_i32, ctypes.c_int,
+                         ctypes.POINTER(c_vp), _dp, _ip, _ip,
+                         ctypes.POINTER(c_i64), _dp, c_vp])
 _tv_status_string = _sig("tv_status_string", [ctypes.c_int], ctypes.c_char_p)
 _tv_last_error = _sig("tv_last_error", [], ctypes.c_char_p)
 
@@ -109,7 +117,8 @@ EXPORTED = ("tv_plan_from_factors", "tv_plan_destroy", "tv_plan_info",
             "tv_compress_append", "tv_plan_finalize", "tv_compress_discarded",
             "tv_autotune", "tv_batch_create", "tv_batch_workspace_bytes", "tv_batch_run",
             "tv_batch_destroy", "tv_aca_workspace_bytes", "tv_aca_matvec",
-            "tv_aca_rmatvec", "tv_status_string", "tv_last_error")
+            "tv_aca_rmatvec", "tv_dipole_rows", "tv_aca_assemble",
+            "tv_status_string", "tv_last_error")
 TV_BATCH_MAX_PLANS = 32
 
 
@@ -286,3 +295,40 @@ def tv_aca_rmatvec(plan, v_ptr, m, ldv, y_ptr, ldy, nrhs, x_ptr, ldx, ws_ptr,
     _check(_tv_aca_rmatvec(plan, v_ptr, int(m), int(ldv), y_ptr, int(ldy),
                            int(nrhs), x_ptr, int(ldx), ws_ptr, int(ws_bytes),
                            stream), "tv_aca_rmatvec")
+
+
+def tv_dipole_rows(n1, n2, n3, h, k0, basis, pos, ori, rows, out_ptr, stream):
+    pos = np.ascontiguousarray(pos, np.float64)
+    ori = np.ascontiguousarray(ori, np.float64)
+    r = np.ascontiguousarray(rows, np.int64)
+    _check(_tv_dipole_rows(int(n1), int(n2), int(n3), float(h), float(k0),
+                           int(basis), int(pos.shape[0]), _dptr(pos), _dptr(ori),
+                           int(r.shape[0]), r.ctypes.data_as(ctypes.POINTER(c_i64)),
+                           out_ptr, stream), "tv_dipole_rows")
+
+
+def tv_aca_assemble(grid: tv_grid, h, k0, basis, pos, ori, tol, hosvd_tol=0.0,
+                    rank_min=1, rank_cap=0, max_terms=64,
+                    precision=TV_PREC_FP32, stream=None):
+    """Algorithm 3 on the device.  Returns (plan handle, V complex128
+    (m x r_c), r_c, converged, pivots int64 (r_c x 2), s float64 (r_c,))."""
+    pos = np.ascontiguousarray(pos, np.float64)
+    ori = np.ascontiguousarray(ori, np.float64)
+    m, K = int(grid.m), int(max_terms)
+    V = np.zeros(2 * m * K, np.float64)
+    piv = np.zeros(2 * K, np.int64)
+    sv = np.zeros(K, np.float64)
+    h_plan = c_vp()
+    rc = c_i32()
+    conv = c_i32()
+    _check(_tv_aca_assemble(ctypes.byref(grid), float(h), float(k0), int(basis),
+                            _dptr(pos), _dptr(ori), float(tol), float(hosvd_tol),
+                            int(rank_min), int(rank_cap), K, int(precision),
+                            ctypes.byref(h_plan), _dptr(V), ctypes.byref(rc),
+                            ctypes.byref(conv),
+                            piv.ctypes.data_as(ctypes.POINTER(c_i64)), _dptr(sv),
+                            stream), "tv_aca_assemble")
+    n = rc.value
+    Vc = V.view(np.complex128).reshape(K, m).T[:, :n].copy()
+    return (h_plan.value, Vc, n, bool(conv.value), piv.reshape(K, 2)[:n].copy(),
+            sv[:n].copy())

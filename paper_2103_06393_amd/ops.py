@@ -181,6 +181,22 @@ class AcaTuckerOperator:
         return X.reshape(-1) if vec else X.t()
 
 
+def aca_assemble(wl_dims, h, k0, basis, pos, ori, tol, hosvd_tol=0.0,
+                 rank_min=1, rank_cap=0, max_terms=64,
+                 precision: int = lib.TV_PREC_FP32):
+    """Algorithm 3 (Tucker-based ACA) on the device for point-current coil
+    elements: returns an AcaTuckerOperator (U as a Tucker plan, V on the GPU)
+    and a dict with r_c, convergence, the pivots and the norm estimates."""
+    q = 3 if basis == 0 else 12
+    grid = lib.make_grid(*wl_dims, q, int(pos.shape[0]))
+    h_plan, V, rc, conv, piv, s = lib.tv_aca_assemble(
+        grid, h, k0, basis, pos, ori, tol, hosvd_tol, rank_min, rank_cap,
+        max_terms, precision, _stream())
+    plan = TuckerPlan(h_plan)
+    op = AcaTuckerOperator(plan, torch.from_numpy(V.astype(np.complex64)).cuda())
+    return op, {"rc": rc, "converged": conv, "pivots": piv, "s": s, "V": V}
+
+
 class TuckerMatvec(torch.autograd.Function):
     """y = Z x with the hand-written Z^* kernel as the backward."""
 
