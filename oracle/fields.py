@@ -21,6 +21,11 @@ k = 4 c + l for field component c and basis function l.
 
 The physical E-field carries an extra constant 1/(i omega eps0); it scales
 every column alike and is left out.
+
+The magnetic coupling matrix Z_bc uses the K operator of eq. (5) instead,
+K(s) = curl of the g-weighted integral of s; for a point current that is
+curl(g p) = grad g x p = g (-i k0 - 1/R) Rhat x p (``point_hfield``).
+A workload selects it with ``operator = "K"``; the voxel bases are the same.
 """
 from __future__ import annotations
 
@@ -52,6 +57,20 @@ def point_field(points, src, p, k0: float):
                                        + (b * rp)[..., None] * rhat)
 
 
+def point_hfield(points, src, p, k0: float):
+    """K(p delta(r - src)) = grad g x p at ``points`` (..., 3), eq. (5)."""
+    d = np.asarray(points, dtype=np.float64) - np.asarray(src, np.float64)
+    R = np.sqrt(np.sum(d * d, axis=-1))
+    rhat = d / R[..., None]
+    g = np.asarray(scalar_green(R, k0))
+    dg = g * (-1j * k0 - 1.0 / R)                      # d g / d R
+    return dg[..., None] * np.cross(rhat, np.asarray(p, np.float64))
+
+
+def _field(wl):
+    return point_hfield if getattr(wl, "operator", "N") == "K" else point_field
+
+
 def voxel_centres(grid):
     """(n1, n2, n3, 3) array of voxel centres (domain centred at 0)."""
     x, y, z = (grid.axis(d) for d in range(3))
@@ -70,8 +89,9 @@ def column_tensors(wl, j: int) -> np.ndarray:
     """
     centres = voxel_centres(wl.grid)
     src, p, k0 = wl.pos[j], wl.ori[j], wl.k0
+    field = _field(wl)
     if wl.basis == "pwc":
-        E = point_field(centres, src, p, k0)            # (n1,n2,n3,3)
+        E = field(centres, src, p, k0)                  # (n1,n2,n3,3)
         return np.moveaxis(E, -1, 0).copy()
     h = wl.grid.h
     out = np.zeros((12,) + wl.grid.dims, dtype=np.complex128)
@@ -79,7 +99,7 @@ def column_tensors(wl, j: int) -> np.ndarray:
         for sy in (-1.0, 1.0):
             for sz in (-1.0, 1.0):
                 s = np.array([sx, sy, sz]) * _GL2
-                E = point_field(centres + s * h, src, p, k0)
+                E = field(centres + s * h, src, p, k0)
                 phi = (1.0, s[0], s[1], s[2])           # basis values
                 for c in range(3):
                     for l in range(4):
@@ -110,8 +130,9 @@ def row_vector(wl, i: int) -> np.ndarray:
     n1, n2 = wl.grid.n1, wl.grid.n2
     idx = (v % n1, (v // n1) % n2, v // (n1 * n2))
     centre = np.array([wl.grid.axis(d)[idx[d]] for d in range(3)])
+    field = _field(wl)
     if wl.basis == "pwc":
-        return point_field(centre, wl.pos, wl.ori, wl.k0)[:, k]
+        return field(centre, wl.pos, wl.ori, wl.k0)[:, k]
     c, l = divmod(k, 4)
     h = wl.grid.h
     out = np.zeros(wl.m, dtype=np.complex128)
@@ -119,7 +140,7 @@ def row_vector(wl, i: int) -> np.ndarray:
         for sy in (-1.0, 1.0):
             for sz in (-1.0, 1.0):
                 s = np.array([sx, sy, sz]) * _GL2
-                E = point_field(centre + s * h, wl.pos, wl.ori, wl.k0)
+                E = field(centre + s * h, wl.pos, wl.ori, wl.k0)
                 phi = (1.0, s[0], s[1], s[2])[l]
                 out += E[:, c] * (phi / 8.0)
     return out

@@ -171,3 +171,81 @@ def test_pwl_linear_moments_follow_field_gradient():
                 - fields.point_field(c - e, wl.pos[0], wl.ori[0], wl.k0)) / (2 * d)
         got = np.array([T[4 * cc + 1 + l, i1, i2, i3] for cc in range(3)])
         assert np.linalg.norm(got - h / 12 * grad) <= 0.05 * np.linalg.norm(h / 12 * grad)
+
+
+# ---- the K operator of eq. (5): H-field of a point current, curl(g p) ----
+
+def _fd_grad_g(x, src, k0, d):
+    e = np.eye(3) * d
+    g = lambda y: fields.scalar_green(np.linalg.norm(y - src), k0)  # noqa
+    return np.array([(g(x + e[a]) - g(x - e[a])) / (2 * d) for a in range(3)])
+
+
+def test_hfield_matches_finite_difference_curl():
+    """curl(g p) = grad g x p, with grad g by central differences of eq. (3)."""
+    for x in PTS:
+        ref = np.cross(_fd_grad_g(x, SRC, K0, 1e-4), P)
+        got = fields.point_hfield(x, SRC, P, K0)
+        assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_hfield_finite_difference_converges_second_order():
+    x = PTS[1]
+    ref = fields.point_hfield(x, SRC, P, K0)
+    errs = [np.linalg.norm(np.cross(_fd_grad_g(x, SRC, K0, d), P) - ref)
+            for d in (4e-3, 2e-3)]
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_hfield_orthogonal_and_divergence_free():
+    for x in PTS:
+        Hx = fields.point_hfield(x, SRC, P, K0)
+        rhat = (x - SRC) / np.linalg.norm(x - SRC)
+        assert abs(np.dot(Hx, rhat)) <= 1e-14 * np.linalg.norm(Hx)
+        assert abs(np.dot(Hx, P)) <= 1e-14 * np.linalg.norm(Hx)
+        d = 1e-4
+        e = np.eye(3) * d
+        div = sum((fields.point_hfield(x + e[a], SRC, P, K0)[a]
+                   - fields.point_hfield(x - e[a], SRC, P, K0)[a]) / (2 * d)
+                  for a in range(3))
+        R = np.linalg.norm(x - SRC)
+        assert abs(div) <= 1e-6 * np.linalg.norm(Hx) / R
+
+
+def test_curl_of_hfield_is_efield():
+    """N(p) = curl curl (g p) = curl K(p): eq. (2) is the curl of eq. (5)'s
+    field, by central differences."""
+    d = 1e-4
+    e = np.eye(3) * d
+    for x in PTS[:3]:
+        J = np.zeros((3, 3), np.complex128)    # J[a, b] = d H_a / d x_b
+        for b in range(3):
+            J[:, b] = (fields.point_hfield(x + e[b], SRC, P, K0)
+                       - fields.point_hfield(x - e[b], SRC, P, K0)) / (2 * d)
+        curl = np.array([J[2, 1] - J[1, 2], J[0, 2] - J[2, 0], J[1, 0] - J[0, 1]])
+        ref = fields.point_field(x, SRC, P, K0)
+        assert np.linalg.norm(curl - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+def test_hfield_static_limit_is_biot_savart():
+    k0 = 1e-9
+    for x in PTS:
+        r = x - SRC
+        R = np.linalg.norm(r)
+        ref = -np.cross(r / R, P) / (4 * math.pi * R * R)
+        got = fields.point_hfield(x, SRC, P, k0)
+        assert np.linalg.norm(got - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("basis", ["pwc", "pwl"])
+def test_hfield_rows_and_columns_agree(basis):
+    import dataclasses
+    wl = workloads.make("tiny" if basis == "pwc" else "tiny_pwl")
+    wl = dataclasses.replace(wl, operator="K")
+    for i in (0, 5, wl.rows // 2 + 3, wl.rows - 1):
+        r = fields.row_vector(wl, i)
+        c = np.array([fields.column_vector(wl, j)[i] for j in range(wl.m)])
+        assert np.array_equal(r, c)
+    # and the K columns differ from the N columns
+    wn = dataclasses.replace(wl, operator="N")
+    assert not np.allclose(fields.column_vector(wl, 0), fields.column_vector(wn, 0))

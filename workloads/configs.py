@@ -75,6 +75,7 @@ class Workload:
     nrhs: int = 1
     seed_x: int = 0
     seed_y: int = 0
+    operator: str = "N"         # 'N' (E-field, eq. 2) or 'K' (H-field, eq. 5)
 
     @property
     def q(self) -> int:
