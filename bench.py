@@ -155,7 +155,7 @@ def main(argv=None):
     log(f"[bench] workload {wl.name}: grid {wl.grid.dims}, q={wl.q}, m={wl.m}")
     t0 = time.perf_counter()
     plan = TuckerPlan.compress_dipoles(
-        wl.grid.dims, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1,
+        wl.grid.dims, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator),
         wl.pos, wl.ori, wl.tol, wl.rank_min, wl.rank_cap or 0, precision=prec)
     torch.cuda.synchronize()
     log(f"[bench] compressed on GPU in {time.perf_counter() - t0:.2f} s")
@@ -303,7 +303,7 @@ def bench_aca(args):
     rmin, rcap = (1, 0) if args.natural_ranks else (15, 18)
     t0 = time.perf_counter()
     plan = TuckerPlan.compress_dipoles(
-        wl.grid.dims, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1,
+        wl.grid.dims, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator),
         wl.pos[pick], wl.ori[pick], 3.0 * wl.tol, rmin, rcap, precision=prec)
     torch.cuda.synchronize()
     log(f"[aca] U compressed on GPU in {time.perf_counter() - t0:.2f} s")
@@ -446,7 +446,7 @@ def bench_assemble(args):
         f"m={wl.m}, {rc} steps")
     t0 = time.perf_counter()
     h_plan, V, n, conv, piv, s = lib.tv_aca_assemble(
-        grid, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1, wl.pos, wl.ori,
+        grid, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator), wl.pos, wl.ori,
         wl.tol, 0.0, 1, 0, rc, lib.TV_PREC_FP32, st)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0

@@ -64,6 +64,11 @@ typedef enum {
  * hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation. */
 typedef enum { TV_PREC_FP32 = 0, TV_PREC_BF16X3 = 1 } tv_precision;
 
+/* Flag ORed into the `basis` argument of the field entry points
+ * (tv_dipole_columns, tv_dipole_rows, tv_aca_assemble): the K operator of
+ * eq. (5) (magnetic field) instead of the N operator of eq. (2). */
+#define TV_FIELD_K 2
+
 /* Largest multilinear rank a plan may hold in any mode. */
 #define TV_MAX_RANK 64
 
@@ -167,6 +172,8 @@ tv_status tv_autotune(tv_plan plan, int32_t op, const char* cache_path,
  * basis 1 (PWL, q = 12): tensor 4c + l is (1/h^3) * integral over the voxel
  *   of field component c times phi_l, phi_0 = 1, phi_l = (x_l - centre_l)/h,
  *   by the 2x2x2 Gauss-Legendre rule.
+ * basis | TV_FIELD_K: the magnetic-field operator of eq. (5) instead (the
+ *   coupling matrix Z_bc): curl(g p) = g (-i k0 - 1/R) Rhat x p, same bases.
  * out: device complex128, ncols*q*nv values, column j's tensor k at
  *   out + 2*((j*q + k)*nv + v), v = i1 + n1*(i2 + n2*i3).  Runs on
  *   `stream` and synchronises it before returning (the inputs are staged

@@ -221,25 +221,32 @@ __global__ __launch_bounds__(kT) void to_c64_kernel(const double2* __restrict__ 
   y[e] = make_float2((float)x[e].x, (float)x[e].y);
 }
 
-// out = 2 Re sum_l conj(b_l) a_l with b_l = sum_n conj(V[n + ldv l]) y[n]:
-// one workgroup computes b_l for every l in turn and accumulates the term.
-__global__ __launch_bounds__(kT) void cross_kernel(const double2* __restrict__ V, int64_t ldv,
-                                                   const double2* __restrict__ y, int64_t m,
+// b[l] = sum_n conj(V[n + ldv l]) y[n] (V^* y), one workgroup per l.
+__global__ __launch_bounds__(kT) void vhy_kernel(const double2* __restrict__ V, int64_t ldv,
+                                                 const double2* __restrict__ y, int64_t m,
+                                                 double2* __restrict__ b) {
+  __shared__ double red[kT / 64];
+  const int64_t l = blockIdx.x;
+  double br = 0.0, bi = 0.0;
+  for (int64_t n = threadIdx.x; n < m; n += kT) {
+    const double2 v = V[n + ldv * l], w = y[n];
+    br += v.x * w.x + v.y * w.y;
+    bi += v.x * w.y - v.y * w.x;
+  }
+  br = block_sum(br, red);
+  bi = block_sum(bi, red);
+  if (threadIdx.x == 0) b[l] = make_double2(br, bi);
+}
+
+// out = 2 Re sum_l conj(b_l) a_l (the norm estimate's cross term), one
+// workgroup, fixed order.
+__global__ __launch_bounds__(kT) void cross_kernel(const double2* __restrict__ b,
                                                    const float2* __restrict__ a, int k,
                                                    double* __restrict__ out) {
   __shared__ double red[kT / 64];
   double acc = 0.0;
-  for (int l = 0; l < k; ++l) {
-    double br = 0.0, bi = 0.0;
-    for (int64_t n = threadIdx.x; n < m; n += kT) {
-      const double2 v = V[n + ldv * l], w = y[n];
-      br += v.x * w.x + v.y * w.y;
-      bi += v.x * w.y - v.y * w.x;
-    }
-    br = block_sum(br, red);
-    bi = block_sum(bi, red);
-    if (threadIdx.x == 0) acc += br * a[l].x + bi * a[l].y;  // Re(conj(b) a)
-  }
+  for (int l = threadIdx.x; l < k; l += kT) acc += b[l].x * a[l].x + b[l].y * a[l].y;
+  acc = block_sum(acc, red);
   if (threadIdx.x == 0) *out = 2.0 * acc;
 }
 
@@ -322,8 +329,8 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   const tv_grid g = *grid;
   if (g.n1 < 1 || g.n2 < 1 || g.n3 < 1 || g.m < 1)
     return set_error(TV_ERR_SHAPE, "grid sizes and m must be >= 1");
-  if (basis != 0 && basis != 1) return set_error(TV_ERR_INVALID_ARG, "basis must be 0 or 1");
-  if (g.q != (basis == 0 ? 3 : 12))
+  if (basis < 0 || basis > 3) return set_error(TV_ERR_INVALID_ARG, "basis must be in 0..3");
+  if (g.q != ((basis & 1) ? 12 : 3))
     return set_error(TV_ERR_SHAPE, "q must be 3 (PWC) or 12 (PWL) to match the basis");
   if (!(tol > 0.0) || !std::isfinite(tol)) return set_error(TV_ERR_INVALID_ARG, "tol must be > 0");
   if (!(h > 0.0) || !(k0 > 0.0)) return set_error(TV_ERR_INVALID_ARG, "h and k0 must be > 0");
@@ -342,13 +349,14 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   Buffers B;
   double *d_src, *d_bv, *d_scal;
   int64_t *d_bi, *d_row, *d_iscal;
-  double2 *d_r, *d_V, *d_t, *d_x;
+  double2 *d_r, *d_V, *d_t, *d_b, *d_x;
   float2 *d_w32, *d_x32, *d_u32, *d_a32;
   if ((s = B.alloc(&d_src, src.size())) != TV_OK || (s = B.alloc(&d_bv, 1024)) != TV_OK ||
       (s = B.alloc(&d_bi, 1024)) != TV_OK || (s = B.alloc(&d_scal, 4)) != TV_OK ||
       (s = B.alloc(&d_iscal, 2)) != TV_OK || (s = B.alloc(&d_row, 1)) != TV_OK ||
       (s = B.alloc(&d_r, m)) != TV_OK || (s = B.alloc(&d_V, (size_t)m * K)) != TV_OK ||
-      (s = B.alloc(&d_t, K)) != TV_OK || (s = B.alloc(&d_x, rows)) != TV_OK ||
+      (s = B.alloc(&d_t, K)) != TV_OK || (s = B.alloc(&d_b, K)) != TV_OK ||
+      (s = B.alloc(&d_x, rows)) != TV_OK ||
       (s = B.alloc(&d_w32, K)) != TV_OK || (s = B.alloc(&d_x32, rows)) != TV_OK ||
       (s = B.alloc(&d_u32, rows)) != TV_OK || (s = B.alloc(&d_a32, K)) != TV_OK)
     return s;
@@ -453,8 +461,8 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
       if ((s = last("to_c64_kernel")) != TV_OK) return fail(s);
       if ((s = tv_rmatvec(U, d_x32, rows, 1, d_a32, k, ws, ws_bytes, stream)) != TV_OK)
         return fail(s);
-      hipLaunchKernelGGL(cross_kernel, dim3(1), dim3(kT), 0, st, d_V, m, y, m, d_a32, k,
-                         d_scal + 2);
+      hipLaunchKernelGGL(vhy_kernel, dim3((unsigned)k), dim3(kT), 0, st, d_V, m, y, m, d_b);
+      hipLaunchKernelGGL(cross_kernel, dim3(1), dim3(kT), 0, st, d_b, d_a32, k, d_scal + 2);
       if ((s = last("cross_kernel")) != TV_OK) return fail(s);
       double cross = 0.0;
       e = hipMemcpyAsync(&cross, d_scal + 2, sizeof(double), hipMemcpyDeviceToHost, st);

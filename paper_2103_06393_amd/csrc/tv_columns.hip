@@ -8,6 +8,9 @@
 // with R = r - r_j, Rh = R / |R|.  PWC voxels take the value at the centre;
 // PWL voxels project on {1, (x - xc)/h, (y - yc)/h, (z - zc)/h} with the
 // 2x2x2 Gauss-Legendre rule, divided by the voxel volume.
+// The magnetic coupling matrix (K operator of eq. 5) takes instead
+//   H(r) = curl(g p) = grad g x p = g (-i k0 - 1/R) Rh x p
+// on the same voxel bases.  `basis` bit 0 selects PWL, bit 1 the K operator.
 #include "tv_internal.h"
 
 namespace tv {
@@ -16,6 +19,7 @@ struct ColParams {
   int n1, n2, n3;
   double h, k0;
   int basis;      // 0 PWC, 1 PWL
+  int op;         // 0 E-field (eq. 2), 1 H-field (eq. 5)
   int64_t ncols;
   const double* src;  // device [ncols][6]: position then orientation
   double2* out;
@@ -45,6 +49,30 @@ __device__ inline void point_field(double x, double y, double z, const double* s
   }
 }
 
+__device__ inline void point_hfield(double x, double y, double z, const double* s, double k0,
+                                    double2 H[3]) {
+  const double dx = x - s[0], dy = y - s[1], dz = z - s[2];
+  const double R = sqrt(dx * dx + dy * dy + dz * dz);
+  const double inv = 1.0 / R;
+  const double hx = dx * inv, hy = dy * inv, hz = dz * inv;
+  double sn, cs;
+  sincos(k0 * R, &sn, &cs);
+  const double amp = inv * 0.07957747154594767;  // 1/(4 pi R)
+  const double gr = amp * cs, gi = -amp * sn;
+  // dg/dR = g (-1/R - i k0)
+  const double dr = -gr * inv + gi * k0, di = -gi * inv - gr * k0;
+  const double w[3] = {hy * s[5] - hz * s[4], hz * s[3] - hx * s[5], hx * s[4] - hy * s[3]};
+  for (int c = 0; c < 3; ++c) H[c] = make_double2(dr * w[c], di * w[c]);
+}
+
+__device__ inline void field(int op, double x, double y, double z, const double* s, double k0,
+                             double2 F[3]) {
+  if (op == 0)
+    point_field(x, y, z, s, k0, F);
+  else
+    point_hfield(x, y, z, s, k0, F);
+}
+
 __global__ void columns_kernel(ColParams P) {
   const int64_t nv = (int64_t)P.n1 * P.n2 * P.n3;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,7 +89,7 @@ __global__ void columns_kernel(ColParams P) {
   __syncthreads();
   if (P.basis == 0) {
     double2 E[3];
-    point_field(cx, cy, cz, s, P.k0, E);
+    field(P.op, cx, cy, cz, s, P.k0, E);
     for (int c = 0; c < 3; ++c) P.out[(j * 3 + c) * nv + v] = E[c];
     return;
   }
@@ -74,7 +102,7 @@ __global__ void columns_kernel(ColParams P) {
     const double uy = (q & 2) ? off : -off;
     const double uz = (q & 4) ? off : -off;
     double2 E[3];
-    point_field(cx + ux * P.h, cy + uy * P.h, cz + uz * P.h, s, P.k0, E);
+    field(P.op, cx + ux * P.h, cy + uy * P.h, cz + uz * P.h, s, P.k0, E);
     const double phi[4] = {0.125, 0.125 * ux, 0.125 * uy, 0.125 * uz};
     for (int c = 0; c < 3; ++c)
       for (int l = 0; l < 4; ++l) {
@@ -106,7 +134,7 @@ __global__ void rows_kernel(ColParams P, const int64_t* rows) {
   double2* out = P.out + (int64_t)blockIdx.y * P.ncols + j;
   if (P.basis == 0) {
     double2 E[3];
-    point_field(cx, cy, cz, s, P.k0, E);
+    field(P.op, cx, cy, cz, s, P.k0, E);
     *out = E[k];
     return;
   }
@@ -116,7 +144,7 @@ __global__ void rows_kernel(ColParams P, const int64_t* rows) {
   for (int q = 0; q < 8; ++q) {
     const double u[3] = {(q & 1) ? off : -off, (q & 2) ? off : -off, (q & 4) ? off : -off};
     double2 E[3];
-    point_field(cx + u[0] * P.h, cy + u[1] * P.h, cz + u[2] * P.h, s, P.k0, E);
+    field(P.op, cx + u[0] * P.h, cy + u[1] * P.h, cz + u[2] * P.h, s, P.k0, E);
     const double phi = l == 0 ? 0.125 : 0.125 * u[l - 1];
     acc.x += E[c].x * phi;
     acc.y += E[c].y * phi;
@@ -151,7 +179,7 @@ tv_status launch_dipole_columns(int n1, int n2, int n3, double h, double k0, int
                                 int64_t ncols, const double* d_src, double2* out,
                                 hipStream_t st) {
   const int64_t nv = (int64_t)n1 * n2 * n3;
-  ColParams P{n1, n2, n3, h, k0, basis, ncols, d_src, out};
+  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, ncols, d_src, out};
   hipLaunchKernelGGL(columns_kernel, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
                      dim3(256), 0, st, P);
   hipError_t e = hipGetLastError();
@@ -161,7 +189,7 @@ tv_status launch_dipole_columns(int n1, int n2, int n3, double h, double k0, int
 tv_status launch_dipole_rows(int n1, int n2, int n3, double h, double k0, int basis,
                              int64_t nsrc, const double* d_src, int64_t nrows,
                              const int64_t* d_rows, double2* out, hipStream_t st) {
-  ColParams P{n1, n2, n3, h, k0, basis, nsrc, d_src, out};
+  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, nsrc, d_src, out};
   hipLaunchKernelGGL(rows_kernel, dim3((unsigned)((nsrc + 255) / 256), (unsigned)nrows),
                      dim3(256), 0, st, P, d_rows);
   hipError_t e = hipGetLastError();
@@ -180,11 +208,11 @@ extern "C" tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h
   if (n1 < 1 || n2 < 1 || n3 < 1 || nsrc < 1 || nrows < 0)
     return set_error(TV_ERR_SHAPE, "grid sizes and nsrc must be >= 1, nrows >= 0");
   if (!(h > 0.0) || !(k0 > 0.0)) return set_error(TV_ERR_INVALID_ARG, "h and k0 must be > 0");
-  if (basis != 0 && basis != 1) return set_error(TV_ERR_INVALID_ARG, "basis must be 0 or 1");
+  if (basis < 0 || basis > 3) return set_error(TV_ERR_INVALID_ARG, "basis must be in 0..3");
   if (nrows == 0) return TV_OK;
   if (!pos || !ori || !rows || !out) return set_error(TV_ERR_INVALID_ARG, "NULL pointer");
   if (nrows > 65535) return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 rows per call");
-  const int64_t total = (int64_t)(basis == 0 ? 3 : 12) * n1 * n2 * n3;
+  const int64_t total = (int64_t)((basis & 1) ? 12 : 3) * n1 * n2 * n3;
   for (int64_t r = 0; r < nrows; ++r)
     if (rows[r] < 0 || rows[r] >= total) return set_error(TV_ERR_SHAPE, "row index out of range");
   std::vector<double> src;
@@ -215,7 +243,7 @@ extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, doubl
   if (n1 < 1 || n2 < 1 || n3 < 1 || ncols < 0)
     return set_error(TV_ERR_SHAPE, "grid sizes must be >= 1 and ncols >= 0");
   if (!(h > 0.0) || !(k0 > 0.0)) return set_error(TV_ERR_INVALID_ARG, "h and k0 must be > 0");
-  if (basis != 0 && basis != 1) return set_error(TV_ERR_INVALID_ARG, "basis must be 0 or 1");
+  if (basis < 0 || basis > 3) return set_error(TV_ERR_INVALID_ARG, "basis must be in 0..3");
   if (ncols == 0) return TV_OK;
   if (!pos || !ori || !out) return set_error(TV_ERR_INVALID_ARG, "NULL pointer");
   if (ncols > 65535) return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 columns per call");
@@ -233,7 +261,7 @@ extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, doubl
     hipFreeAsync(d_src, st);
     return hip_error(e, "hipMemcpyAsync");
   }
-  ColParams P{n1, n2, n3, h, k0, basis, ncols, d_src, (double2*)out};
+  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, ncols, d_src, (double2*)out};
   hipLaunchKernelGGL(columns_kernel, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
                      dim3(256), 0, st, P);
   e = hipGetLastError();

@@ -31,6 +31,12 @@ STATUS = {0: "TV_OK", -1: "TV_ERR_INVALID_ARG", -2: "TV_ERR_SHAPE",
 TV_PREC_FP32 = 0
 TV_PREC_BF16X3 = 1
 TV_MAX_RANK = 64
+TV_FIELD_K = 2              # OR into `basis`: the H-field operator of eq. (5)
+
+
+def field_code(basis: str, operator: str = "N") -> int:
+    """`basis` argument of the field entry points: bit 0 PWL, bit 1 K."""
+    return (1 if basis == "pwl" else 0) | (TV_FIELD_K if operator == "K" else 0)
 
 
 class tv_grid(ctypes.Structure):

@@ -53,7 +53,7 @@ class TuckerPlan:
                          chunk: Optional[int] = None) -> "TuckerPlan":
         """Generate point-current columns on the device and compress them
         with the library's truncated HOSVD, a chunk of columns at a time."""
-        q = 3 if basis == 0 else 12
+        q = 12 if basis & 1 else 3
         m = int(pos.shape[0])
         nv = int(np.prod(dims))
         grid = lib.make_grid(*dims, q, m)
@@ -187,7 +187,7 @@ def aca_assemble(wl_dims, h, k0, basis, pos, ori, tol, hosvd_tol=0.0,
     """Algorithm 3 (Tucker-based ACA) on the device for point-current coil
     elements: returns an AcaTuckerOperator (U as a Tucker plan, V on the GPU)
     and a dict with r_c, convergence, the pivots and the norm estimates."""
-    q = 3 if basis == 0 else 12
+    q = 12 if basis & 1 else 3
     grid = lib.make_grid(*wl_dims, q, int(pos.shape[0]))
     h_plan, V, rc, conv, piv, s = lib.tv_aca_assemble(
         grid, h, k0, basis, pos, ori, tol, hosvd_tol, rank_min, rank_cap,

@@ -34,10 +34,12 @@ def _box(dims, h, basis="pwc", step=1):
 def test_rows_match_oracle(gpu_lib):
     import torch
     lib = gpu_lib
-    for wl in (workloads.make_bodycoil("aca_s"), _box((6, 5, 7), 0.02, "pwl", 4)):
+    import dataclasses
+    cases = (workloads.make_bodycoil("aca_s"), _box((6, 5, 7), 0.02, "pwl", 4))
+    for wl in cases + tuple(dataclasses.replace(w, operator="K") for w in cases):
         rows = np.array([0, 1, wl.rows // 3, wl.rows - 1, 777 % wl.rows], np.int64)
         out = torch.zeros((len(rows), wl.m), dtype=torch.complex128, device="cuda")
-        lib.tv_dipole_rows(*wl.grid.dims, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1,
+        lib.tv_dipole_rows(*wl.grid.dims, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator),
                            wl.pos, wl.ori, rows, out.data_ptr(),
                            torch.cuda.current_stream().cuda_stream)
         got = out.cpu().numpy()
@@ -47,8 +49,9 @@ def test_rows_match_oracle(gpu_lib):
 
 
 def _run(wl, tol, max_terms, hosvd_tol=0.0):
+    from paper_2103_06393_amd import lib
     from paper_2103_06393_amd.ops import aca_assemble
-    return aca_assemble(wl.grid.dims, wl.grid.h, wl.k0, 0 if wl.basis == "pwc" else 1,
+    return aca_assemble(wl.grid.dims, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator),
                         wl.pos, wl.ori, tol, hosvd_tol, max_terms=max_terms)
 
 

@@ -135,13 +135,14 @@ def test_dipole_columns_match_oracle(gpu_lib):
     import torch
     from paper_2103_06393_amd import lib
     from oracle import fields
-    for name in ("c1", "tiny_pwl"):
-        wl = workloads.make(name)
+    import dataclasses
+    for name, op in (("c1", "N"), ("tiny_pwl", "N"), ("c1", "K"), ("tiny_pwl", "K")):
+        wl = dataclasses.replace(workloads.make(name), operator=op)
         cols = [0, 5 % wl.m, wl.m - 1]
         out = torch.empty(len(cols) * wl.q * wl.grid.nv * 2, dtype=torch.float64,
                           device="cuda")
         lib.tv_dipole_columns(*wl.grid.dims, wl.grid.h, wl.k0,
-                              0 if wl.basis == "pwc" else 1, wl.pos[cols],
+                              lib.field_code(wl.basis, wl.operator), wl.pos[cols],
                               wl.ori[cols], out.data_ptr(),
                               torch.cuda.current_stream().cuda_stream)
         got = out.cpu().numpy().view(np.complex128).reshape(len(cols), -1)

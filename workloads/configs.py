@@ -197,7 +197,7 @@ FREQ_3T = 123.0e6           # Sec. IV.B.2 operating frequency, Hz
 def _bodycoil(name, dims, h, m, basis, tol, seed_geo, seed_x, seed_y,
               rank_min=1, cap=None) -> Workload:
     """Body-coil stand-in for Sec. IV.B.2 with point currents in place of
-    the RWG functions: 32 legs (radius 35.5 cm, length 45 cm, z-directed),
+    the RWG functions, magnetic coupling matrix Z_bc (K operator, eq. 5): 32 legs (radius 35.5 cm, length 45 cm, z-directed),
     two end rings (phi-directed) and a conductive shield (radius 37.2 cm,
     length 1.5 m, tangential currents at seeded random positions and
     angles), all centred at the origin around the voxel box.  A quarter of
@@ -231,7 +231,7 @@ def _bodycoil(name, dims, h, m, basis, tol, seed_geo, seed_x, seed_y,
     grid = Grid(dims[0], dims[1], dims[2], h)
     return Workload(name, grid, basis, FREQ_3T, np.asarray(pos, np.float64),
                     np.asarray(ori, np.float64), tol, rank_min, cap, 1,
-                    seed_x, seed_y)
+                    seed_x, seed_y, operator="K")
 
 
 # Body-coil workloads: the box of Sec. IV.B.2 (81 x 44 x 108 voxels at 5 mm,
