@@ -40,6 +40,12 @@ MEASURED_TRAFFIC = {
         "sha256": "445803172685202790421745ad3263a637dd9c270cce35e2892f0a98b7a0314b",
         "profile": "profiles/ws_fused_c2_fp32_pmc.md",
     },
+    ("aca2-pwc", "fp32", "adjoint"): {
+        "bytes": 3657544232,
+        "source": "paper_2103_06393_amd/csrc/tv_fused_ws.hip",
+        "sha256": "445803172685202790421745ad3263a637dd9c270cce35e2892f0a98b7a0314b",
+        "profile": "profiles/aca_tucker_aca2_pwc_pmc.md",
+    },
 }
 
 
@@ -391,7 +397,10 @@ def bench_aca(args):
         "paper_table9_s": PAPER_TABLE9_S.get((wl.name, args.basis)),
         "roofline": {"kernel": f"{kname} ({dom})", "bound": "mfma",
                      "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak, "traffic": None},
+                     "frac": ach / peak,
+                     "traffic": None if args.natural_ranks else measured_traffic(
+                         f"{wl.name}-{args.basis}", "fp32" if prec == lib.TV_PREC_FP32
+                         else "bf16x3", dom)},
         "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
                    "splits": list(info.splits)},
     }
