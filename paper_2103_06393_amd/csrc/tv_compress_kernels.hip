@@ -451,6 +451,7 @@ __global__ __launch_bounds__(256) void zgemm_batched_kernel(
 __global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int n, int l,
                                                    int64_t stride) {
   __shared__ double2 c[64];
+  __shared__ double2 cpart[4][64];
   __shared__ double red[256];
   double2* Zb = Z + blockIdx.x * stride;
   const int tid = threadIdx.x;
@@ -469,15 +470,23 @@ __global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int 
     const double nrm0 = sqrt(red[0]);
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-      if (tid < j) {
+      // c[k] = sum_i conj(Q[i,k]) z[i] for k < j: thread (part, kk) sums the
+      // rows i = part mod 4, then the four parts are added in order
+      {
+        const int kk = tid & 63, part = tid >> 6;
         double2 a = make_double2(0.0, 0.0);
-        for (int i = 0; i < n; ++i) {
-          const double2 q = Zb[(int64_t)i * l + tid], z = Zb[(int64_t)i * l + j];
-          a.x += q.x * z.x + q.y * z.y;  // conj(q) z
-          a.y += q.x * z.y - q.y * z.x;
-        }
-        c[tid] = a;
+        if (kk < j)
+          for (int i = part; i < n; i += 4) {
+            const double2 q = Zb[(int64_t)i * l + kk], z = Zb[(int64_t)i * l + j];
+            a.x += q.x * z.x + q.y * z.y;  // conj(q) z
+            a.y += q.x * z.y - q.y * z.x;
+          }
+        cpart[part][kk] = a;
       }
+      __syncthreads();
+      if (tid < j)
+        c[tid] = make_double2(cpart[0][tid].x + cpart[1][tid].x + cpart[2][tid].x + cpart[3][tid].x,
+                              cpart[0][tid].y + cpart[1][tid].y + cpart[2][tid].y + cpart[3][tid].y);
       __syncthreads();
       for (int i = tid; i < n; i += 256) {
         double2 z = Zb[(int64_t)i * l + j];
