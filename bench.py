@@ -111,6 +111,9 @@ def main(argv=None):
                          "body-coil grids")
     ap.add_argument("--basis", default="pwc", choices=("pwc", "pwl"),
                     help="voxel basis of the aca* workloads")
+    ap.add_argument("--gemm-reference", action="store_true",
+                    help="time the stacked mode-1 GEMM alone with B materialised in HBM "
+                         "(library complex GEMM at the workload's shapes)")
     ap.add_argument("--assemble", action="store_true",
                     help="aca* workloads: time Algorithm 3 (tv_aca_assemble) for r_c "
                          "steps instead of the products")
@@ -154,6 +157,8 @@ def main(argv=None):
         return 0
     if args.workload == "c4":
         return bench_batch(args)
+    if args.gemm_reference:
+        return bench_gemm_reference(args)
     if args.workload.startswith("aca"):
         return bench_assemble(args) if args.assemble else bench_aca(args)
     prec = lib.TV_PREC_BF16X3 if args.precision == "bf16x3" else lib.TV_PREC_FP32
@@ -270,6 +275,62 @@ def main(argv=None):
         log(f"[bench] oracle {cb['value']:.4f} matvecs/s on {cb['cores']} threads; "
             f"rel err fwd {out['rel_err_fwd']:.2e} adj {out['rel_err_adj']:.2e}")
     plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_gemm_reference(args):
+    """The stacked mode-1 product Y^k_(1) = A_k B_k of one Z x with B
+    materialised: per component, A_k (n1 x R_k, the stacked U1 factors) times
+    B_k (R_k x n2 n3, every tensor's core applied in modes 2 and 3), R_k the
+    plan's mean rows per component, complex64, as one batched library GEMM
+    (rocBLAS through torch).  A reference point for the fused kernels, which
+    never write B: its flops are the dominant term of theirs."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+
+    wl = workloads.make(args.workload)
+    plan = TuckerPlan.compress_dipoles(
+        wl.grid.dims, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator),
+        wl.pos, wl.ori, wl.tol, wl.rank_min, wl.rank_cap or 0)
+    info = plan.info
+    q, n1 = wl.q, wl.grid.n1
+    ncols = wl.grid.n2 * wl.grid.n3
+    R = int(round(info.sum_r1 / q))
+    plan.close()
+    g = torch.Generator(device="cuda").manual_seed(81)
+    A = torch.randn((q, n1, R), dtype=torch.complex64, device="cuda", generator=g)
+    B = torch.randn((q, R, ncols), dtype=torch.complex64, device="cuda", generator=g)
+    C = torch.empty((q, n1, ncols), dtype=torch.complex64, device="cuda")
+    for _ in range(args.warmup):
+        torch.bmm(A, B, out=C)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        torch.bmm(A, B, out=C)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    flops = 8.0 * q * n1 * R * ncols
+    tf = flops / (ms * 1e-3) / 1e12
+    b_bytes = 8 * q * R * ncols
+    log(f"[gemm] {q} x ({n1} x {R}) @ ({R} x {ncols}) complex64: {ms:.4f} ms, {tf:.1f} TFLOP/s "
+        f"({100 * tf / PEAK_FP32_MFMA:.1f}% of FP32 peak), B {b_bytes / 1e6:.1f} MB")
+    out = {
+        "metric": "stacked mode-1 GEMM with B materialised (library complex GEMM)",
+        "value": tf, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (f32)", "data": "synthetic",
+        "config": {"workload": f"{wl.name}: q={q} components of ({n1} x {R}) @ ({R} x {ncols})",
+                   "b_bytes": b_bytes, "flops": flops},
+        "frac_fp32_peak": tf / PEAK_FP32_MFMA,
+    }
     print(json.dumps(out), flush=True)
     return 0
 
