@@ -276,8 +276,9 @@ tv_status tv_aca_rmatvec(tv_plan plan, const void* v, int64_t m, int64_t ldv,
                          int64_t ldx, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Rows of the synthetic coupling matrix (the same point-current fields as
- * tv_dipole_columns): out[r*nsrc + j] = Z[rows[r], j], device complex128,
+ * Rows of the synthetic coupling matrix (the same point-current fields and
+ * `basis` codes as tv_dipole_columns): out[r*nsrc + j] = Z[rows[r], j],
+ * device complex128,
  * row = k nv + i1 + n1 (i2 + n2 i3) (Algorithm 1's row order), nrows <=
  * 65535, rows in [0, q nv).  Synchronous; allocates a small staging buffer.
  * ---------------------------------------------------------------------- */
@@ -303,9 +304,10 @@ tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h,
  * 1 if the stopping test was met; pivots (optional, host int64
  * [max_terms][2]) the pivot row i and column j of each step; s_out
  * (optional, host double[max_terms]) the estimate after each step.
- * basis 0 (PWC) needs q = 3, basis 1 (PWL) q = 12.  Synchronous; allocates
- * device memory for the duration of the call.  TV_ERR_NUMERIC if the first
- * pivot row of Z is zero.
+ * basis as for tv_dipole_columns (bit 0 PWL, TV_FIELD_K for the magnetic
+ * coupling matrix Z_bc); PWC needs grid->q = 3, PWL q = 12.  Synchronous;
+ * allocates device memory for the duration of the call.  TV_ERR_NUMERIC if
+ * the first pivot row of Z is zero.
  * ---------------------------------------------------------------------- */
 tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0,
                           int32_t basis, const double* pos, const double* ori,
