@@ -130,3 +130,35 @@ def test_argument_errors(gpu_lib):
     with pytest.raises(lib.TuckVsieError) as e:
         lib.tv_aca_assemble(g, wl.grid.h, wl.k0, 0, inside, wl.ori, 1e-3)
     assert e.value.status == -1 and "inside" in str(e.value)
+
+
+def test_algorithm3_k_operator_converges(gpu_lib):
+    """The magnetic coupling matrix Z_bc (K operator, eq. 5) on the 10 x 8 x
+    12 box: same comparison with the oracle as for the E-field matrix."""
+    import dataclasses
+    wl = dataclasses.replace(_box((10, 8, 12), 0.01), operator="K")
+    op, g, Z, err = _compare(wl, 1e-3, 100, 15)
+    assert g["converged"] and err <= 5e-3
+
+
+def test_algorithm3_bf16x3_products(gpu_lib):
+    """precision = BF16X3 runs the products with U in the BF16 split: the
+    leading pivots and the convergence agree with the FP32 run and the
+    approximation error stays within 1.5x."""
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import aca_assemble
+    wl = _box((10, 8, 12), 0.01)
+    args = (wl.grid.dims, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator),
+            wl.pos, wl.ori, 1e-3, 0.0)
+    op32, g32 = aca_assemble(*args, max_terms=100)
+    opbf, gbf = aca_assemble(*args, max_terms=100, precision=lib.TV_PREC_BF16X3)
+    assert gbf["converged"] and g32["converged"]
+    n = min(10, g32["rc"], gbf["rc"])
+    assert np.array_equal(g32["pivots"][:n], gbf["pivots"][:n])
+    Z = om.dense(wl)
+    errs = []
+    for op, g in ((op32, g32), (opbf, gbf)):
+        S = abi_to_struct(wl.grid.dims, wl.q, *op.plan.export_factors())
+        U = np.stack([om.column(S, l) for l in range(S.m)], axis=1)
+        errs.append(np.linalg.norm(Z - U @ g["V"].conj().T) / np.linalg.norm(Z))
+    assert errs[1] <= 1.5 * errs[0] + 1e-6
