@@ -10,9 +10,10 @@ voxel tensors and compressed at once by a truncated HOSVD of tolerance
 3 eps; a row of U is read by decompressing single elements (eq. 6), and
 products with U are Algorithms 1 and 2.
 
-``aca`` below takes Algorithm 3's steps in order for either storage of U:
-``DenseU`` (the traditional ACA the algorithm extends) or ``TuckerU``
-(Algorithm 3 proper).
+``aca`` below is the residual-cross iteration of the ACA for either storage
+of U: ``DenseU`` (the traditional ACA that Algorithm 3 extends) or
+``TuckerU`` (Algorithm 3 proper: compressed columns, single-element rows,
+products by Algorithms 1 and 2).
 
 Readings where the paper is silent or its printed formula is off:
 * the norm estimate's cross term is 2 Re sum_l conj((V^* y)_l) (U^* x)_l,
@@ -56,16 +57,13 @@ class DenseU:
         """Row i of U (length k)."""
         return np.array([c[i] for c in self.cols], np.complex128)
 
-    def alg1(self, w: np.ndarray) -> np.ndarray:
+    def times(self, w: np.ndarray) -> np.ndarray:
         """U w."""
-        out = np.zeros_like(self.cols[0])
-        for l, c in enumerate(self.cols):
-            out += c * w[l]
-        return out
+        return self.dense() @ np.asarray(w, np.complex128)
 
-    def alg2(self, x: np.ndarray) -> np.ndarray:
+    def adjoint_times(self, x: np.ndarray) -> np.ndarray:
         """U^* x."""
-        return np.array([np.vdot(c, x) for c in self.cols], np.complex128)
+        return self.dense().conj().T @ np.asarray(x, np.complex128)
 
     def append(self, x: np.ndarray) -> None:
         self.cols.append(np.array(x, np.complex128))
@@ -100,12 +98,12 @@ class TuckerU:
             t[l] = np.einsum("abc,a,b,c->", tk.G, U1[f1], U2[f2], U3[f3])
         return t
 
-    def alg1(self, w: np.ndarray) -> np.ndarray:
-        """U w by Algorithm 1."""
+    def times(self, w: np.ndarray) -> np.ndarray:
+        """U w (the product of Algorithm 1 with U's struct)."""
         return alg1(self.S, np.asarray(w).reshape(-1, 1))[:, 0]
 
-    def alg2(self, x: np.ndarray) -> np.ndarray:
-        """U^* x by Algorithm 2."""
+    def adjoint_times(self, x: np.ndarray) -> np.ndarray:
+        """U^* x (the product of Algorithm 2 with U's struct)."""
         return alg2(self.S, np.asarray(x).reshape(-1, 1))[:, 0]
 
     def append(self, x: np.ndarray) -> None:
@@ -137,50 +135,71 @@ class ACAResult:
         return self.V.shape[1]
 
 
+def _residual_row(row, U, V, i: int) -> np.ndarray:
+    """Row i of the residual Z - U V^*: Z's row minus (row i of U) V^*."""
+    r = np.array(row(i), np.complex128)
+    return r if U.k == 0 else r - V.conj() @ U.row(i)
+
+
+def _residual_col(col, U, V, j: int) -> np.ndarray:
+    """Column j of the residual Z - U V^*: Z's column minus U conj(V[j, :])."""
+    x = np.array(col(j), np.complex128)
+    return x if U.k == 0 else x - U.times(V[j, :].conj())
+
+
+def _norm2_with_cross(s: float, u: np.ndarray, v: np.ndarray, U, V) -> float:
+    """||U V^* + u v^*||_F^2 from s = ||U V^*||_F^2, by expanding the square:
+    ||A + u v^*||^2 = ||A||^2 + ||u||^2 ||v||^2 + 2 Re <A, u v^*>, where
+    <U V^*, u v^*> = trace(V U^* u v^*) = sum_l conj((V^* v)_l) (U^* u)_l."""
+    out = s + float(np.linalg.norm(u) * np.linalg.norm(v)) ** 2
+    if U.k:
+        out += 2.0 * float(np.real(np.vdot(V.conj().T @ v, U.adjoint_times(u))))
+    return out
+
+
 def aca(row: Callable[[int], np.ndarray], col: Callable[[int], np.ndarray],
         m1: int, m2: int, tol: float, U, max_rank: Optional[int] = None
         ) -> ACAResult:
-    """ACA with partial pivoting of Z (m1 x m2) given by its rows and
-    columns, Algorithm 3's steps in order; U is a DenseU or a TuckerU."""
-    eps = tol
-    i = 0
-    s = 0.0
-    Vcols: List[np.ndarray] = []
-    rows, cols, hist = [], [], []
+    """Adaptive cross approximation with partial pivoting (Sec. II.B.2) of
+    Z (m1 x m2), given by its rows and columns; U is a DenseU or a TuckerU
+    (Algorithm 3 runs this loop with U compressed, Sec. III.C).
+
+    Z ~= U V^* grows by one rank-1 cross u v^* per step, chosen on the
+    residual R = Z - U V^*: from the current pivot row i of R, the pivot
+    column j is its entry of largest modulus, and u = R[:, j],
+    v = conj(R[i, :] / R[i, j]), so that u v^* reproduces row i and column j
+    of R exactly.  The estimate s of ||U V^*||_F^2 follows the expansion in
+    _norm2_with_cross; the loop ends once ||u|| ||v|| <= tol sqrt(s), or at a
+    residual row that is exactly zero; otherwise the next pivot row is the
+    entry of u of largest modulus other than row i.
+    """
     kmax = min(m1, m2) if max_rank is None else min(m1, m2, max_rank)
+    V = np.zeros((m2, 0), np.complex128)
+    rows, cols, hist = [], [], []
+    s = 0.0
     converged = False
-    for k in range(kmax):
-        r = np.array(row(i), np.complex128)            # Z_{i:}
-        if k > 0:
-            V = np.stack(Vcols, axis=1)
-            t = U.row(i)                               # row i of U
-            r = r - V.conj() @ t                       # r -= t V^*
+    i = 0
+    while U.k < kmax:
+        r = _residual_row(row, U, V, i)
         j = int(np.argmax(np.abs(r)))
         if r[j] == 0:
             converged = True
             break
-        y = np.conj(r / r[j])
-        x = np.array(col(j), np.complex128)            # Z_{:j}
-        if k > 0:
-            x = x - U.alg1(V[j, :].conj())             # (U V^*)_{:j}
-        nxy = float(np.linalg.norm(x) * np.linalg.norm(y))
-        s_next = s + nxy * nxy
-        if k > 0:
-            s_next += 2.0 * float(np.sum((U.alg2(x) *
-                                          np.conj(V.conj().T @ y)).real))
-        U.append(x)
-        Vcols.append(y)
+        v = np.conj(r / r[j])
+        u = _residual_col(col, U, V, j)
+        s = _norm2_with_cross(s, u, v, U, V)
+        size = float(np.linalg.norm(u) * np.linalg.norm(v))
+        U.append(u)
+        V = np.column_stack([V, v])
         rows.append(i)
         cols.append(j)
-        s = s_next
         hist.append(s)
-        if nxy <= eps * math.sqrt(s):
+        if size <= tol * math.sqrt(s):
             converged = True
             break
-        xa = np.abs(x)
-        xa[i] = 0.0
-        i = int(np.argmax(xa))
-    V = np.stack(Vcols, axis=1) if Vcols else np.zeros((m2, 0), np.complex128)
+        mod = np.abs(u)
+        mod[i] = 0.0
+        i = int(np.argmax(mod))
     return ACAResult(U, V, rows, cols, hist, converged)
 
 

@@ -56,6 +56,20 @@ def matvec_flops(rank_array, dims, p: int = 1) -> float:
     return tot
 
 
+def rmatvec_flops(rank_array, dims) -> float:
+    """Real flops of one adjoint product Z^* y (p = 1): each tensor is
+    decompressed in modes 2 and 3 as for Z x, y's block is contracted with
+    U1^* (mode 1, r1 nv multiply-adds) and the result is dotted with the
+    conjugated mode-2/3 decompression (r1 n2 n3 multiply-adds): Algorithm 2's
+    inner product of the decompressed column with y, taken at the mode-1
+    output (Table III: the adjoint costs as much as the forward)."""
+    n1, n2, n3 = dims
+    tot = matvec_flops(rank_array, dims)
+    for r1, _, _ in np.asarray(rank_array).reshape(-1, 3):
+        tot += 8.0 * r1 * n2 * n3
+    return tot
+
+
 def aca_tucker_bytes(rank_array, dims, m: int, rc: int) -> int:
     """ACA+Tucker assembly, Table II: the q r_c Tucker tensors of U's
     columns plus V (m r_c entries)."""

@@ -8,8 +8,9 @@ column j and taking their conjugated inner product with X.  (:) is the
 column-major vectorisation, so row k nv + i1 + n1 (i2 + n2 i3) of Z holds
 voxel (i1, i2, i3) of component k.
 
-Everything is complex128 and follows the algorithms' loop order literally;
-nothing here is blocked or fused.
+Everything is complex128.  The products are computed from their definition
+(decompressed columns times the vectors, a library matrix product per block
+of columns); nothing is fused or reordered beyond that blocking.
 """
 from __future__ import annotations
 
@@ -76,25 +77,35 @@ def compress_columns(wl, cols: Optional[Iterable[int]] = None) -> TuckerStruct:
     return TuckerStruct(wl.grid.dims, wl.q, out)
 
 
+def _block(S: TuckerStruct) -> int:
+    """Columns of Z formed at once: about 2^22 complex entries (64 MiB)."""
+    return max(1, (1 << 22) // (S.q * S.nv))
+
+
 def alg1(S: TuckerStruct, X: np.ndarray) -> np.ndarray:
-    """Algorithm 1, Y = Z X.  X is m x p; returns q nv x p."""
+    """Y = Z X, the product Algorithm 1 computes, from its definition: the
+    columns of Z are the decompressed tensors (eq. 6) stacked in component
+    order, and Y is the matrix product Z X, taken over blocks of columns so
+    that only a block of Z exists at a time.  X is m x p; returns q nv x p."""
     X = np.asarray(X, np.complex128).reshape(S.m, -1)
-    p = X.shape[1]
-    Yk = [np.zeros((S.nv, p), np.complex128) for _ in range(S.q)]
-    for j in range(S.m):
-        for k in range(S.q):
-            col = vec(S.t[j][k].full())              # decompress Z^{kj}
-            Yk[k] += np.outer(col, X[j, :])
-    return np.concatenate(Yk, axis=0)
+    Y = np.zeros((S.q * S.nv, X.shape[1]), np.complex128)
+    b = _block(S)
+    for j0 in range(0, S.m, b):
+        js = range(j0, min(S.m, j0 + b))
+        Y += np.stack([column(S, j) for j in js], axis=1) @ X[j0:j0 + len(js)]
+    return Y
 
 
 def alg2(S: TuckerStruct, X: np.ndarray) -> np.ndarray:
-    """Algorithm 2, Y = Z^* X.  X is q nv x p; returns m x p."""
+    """Y = Z^* X (conjugate transpose, Table I), the product Algorithm 2
+    computes, from its definition over blocks of decompressed columns as in
+    alg1.  X is q nv x p; returns m x p."""
     X = np.asarray(X, np.complex128).reshape(S.q * S.nv, -1)
     Y = np.zeros((S.m, X.shape[1]), np.complex128)
-    for j in range(S.m):
-        col = np.concatenate([vec(S.t[j][k].full()) for k in range(S.q)])
-        Y[j, :] = col.conj() @ X
+    b = _block(S)
+    for j0 in range(0, S.m, b):
+        js = range(j0, min(S.m, j0 + b))
+        Y[j0:j0 + len(js)] = np.stack([column(S, j) for j in js], axis=1).conj().T @ X
     return Y
 
 

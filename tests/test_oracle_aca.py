@@ -154,14 +154,11 @@ def test_compressed_columns_have_low_ranks():
 
 def test_table2_table3_counts():
     """Table II: ACA+Tucker memory is q (r^3 + 3 n r) r_c + m r_c entries for
-    equal ranks and sizes; Table III: the product adds r_c m p complex
-    multiply-adds to the Tucker product over r_c columns."""
+    equal ranks and sizes."""
     from oracle import accounting as acc
     q, n, r, rc, m = 3, 20, 4, 7, 50
     ranks = np.full((rc, q, 3), r)
     assert acc.aca_tucker_bytes(ranks, (n, n, n), m, rc) == \
         16 * (q * (r ** 3 + 3 * n * r) * rc + m * rc)
-    for p in (1, 3):
-        d = acc.aca_matvec_flops(ranks, (n, n, n), m, p) - \
-            acc.matvec_flops(ranks, (n, n, n), p)
-        assert d == 8.0 * rc * m * p
+    # the operation count is pinned against a literal count of multiply-adds
+    # in tests/test_oracle_accounting.py

@@ -144,3 +144,31 @@ def test_loss_central_difference_is_exact(struct_and_dense):
         t = np.linalg.norm(x) / np.linalg.norm(d)
         fd = (matvec.loss(S, x + t * d, b) - matvec.loss(S, x - t * d, b)) / (2 * t)
         assert abs(fd - np.vdot(g, d).real) <= 1e-11 * matvec.loss(S, x, b)
+
+
+@pytest.mark.parametrize("dims", [(6, 3, 2), (2, 6, 3), (3, 2, 6)])
+def test_truncation_bound_is_attained_with_one_truncated_mode(dims):
+    """When the rank cap truncates a single mode (the other two keep their
+    full size), the HOSVD reconstruction is an orthogonal projection in that
+    mode alone, so its squared error equals that mode's discarded energy
+    exactly: truncation_bound must equal (sum_k ||Z^kj - Zhat^kj||^2)^(1/2)
+    to rounding.  A bound without the square root, or one that drops a mode's
+    term, fails here."""
+    from oracle.hosvd import hosvd
+    rng = np.random.default_rng(sum(dims))
+    q, m = 2, 3
+    cols, errs = [], []
+    for _ in range(m):
+        col, e2 = [], 0.0
+        for _ in range(q):
+            A = rng.standard_normal(dims) + 1j * rng.standard_normal(dims)
+            t = hosvd(A, 0.0, 1, 3)          # cap 3: only the mode of length 6 is cut
+            assert sorted(t.ranks) == sorted(min(3, n) for n in dims)
+            e2 += float(np.linalg.norm(A - t.full()) ** 2)
+            col.append(t)
+        cols.append(col)
+        errs.append(np.sqrt(e2))
+    S = matvec.TuckerStruct(dims, q, cols)
+    bound = matvec.truncation_bound(S)
+    assert np.all(bound > 0)
+    assert np.allclose(bound, errs, rtol=1e-12, atol=0)
