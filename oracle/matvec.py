@@ -139,11 +139,29 @@ def entries(S: TuckerStruct, x: np.ndarray, rows: Sequence[int]) -> np.ndarray:
     return out
 
 
+def fibre(S: TuckerStruct, X: np.ndarray, k: int, i2: int, i3: int) -> np.ndarray:
+    """The n1 entries of Y = Z X along the mode-1 fibre (k, :, i2, i3): the
+    single-element decompression of Sec. III.C kept open in mode 1, i.e.
+    U1 (G x2 U2[i2,:] x3 U3[i3,:]) for every column j, weighted by X_{j,:}.
+    X is m x p (or length m); returns n1 x p (or n1)."""
+    x = np.asarray(X, np.complex128)
+    Xm = x.reshape(S.m, -1)
+    out = np.zeros((S.dims[0], Xm.shape[1]), np.complex128)
+    for j in range(S.m):
+        t = S.t[j][k]
+        g = np.einsum("abc,b,c->a", t.G, t.U[1][i2], t.U[2][i3])
+        out += np.outer(t.U[0] @ g, Xm[j])
+    return out[:, 0] if x.ndim == 1 else out
+
+
 def adjoint_entries(S: TuckerStruct, y: np.ndarray,
                     cols: Sequence[int]) -> np.ndarray:
-    """Selected entries of Z^* y: Algorithm 2's inner step for chosen j."""
-    y = np.asarray(y, np.complex128).reshape(-1)
-    return np.array([np.vdot(column(S, j), y) for j in cols])
+    """Selected entries of Z^* Y: Algorithm 2's inner step for chosen j.
+    Y is a vector (returns len(cols)) or q nv x p (returns len(cols) x p)."""
+    Y = np.asarray(y, np.complex128)
+    if Y.ndim == 1:
+        return np.array([np.vdot(column(S, j), Y) for j in cols])
+    return np.stack([column(S, j).conj() @ Y for j in cols])
 
 
 def dense(wl, cols: Optional[Iterable[int]] = None) -> np.ndarray:

@@ -474,7 +474,7 @@ tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
   info->precision = p->precision;
   const int64_t K = (int64_t)p->grid.q * p->appended_or_all();
   double sum[3] = {0, 0, 0};
-  double fl = 0.0;
+  double fl = 0.0, dot = 0.0;
   const double n1 = p->grid.n1, n2 = p->grid.n2, n3 = p->grid.n3;
   for (int64_t t = 0; t < K; ++t) {
     const double r1 = p->ranks[3 * t], r2 = p->ranks[3 * t + 1], r3 = p->ranks[3 * t + 2];
@@ -486,11 +486,14 @@ tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
     info->sum_r1 += (int64_t)r1;
     // modes 2, 3 then 1 (Table III's decompression term r q nv m dominates)
     fl += 8.0 * (r1 * r2 * r3 * n2 + r1 * r3 * n2 * n3 + r1 * n1 * n2 * n3);
+    // the adjoint's inner product is taken at the mode-1 output: the
+    // conjugated mode-2/3 decompression (r1 x n2 n3) against U1^* y's block
+    dot += 8.0 * r1 * n2 * n3;
   }
   for (int d = 0; d < 3; ++d) info->mean_rank[d] = K ? sum[d] / (double)K : 0.0;
   info->device_bytes = p->device_bytes;
   info->flops_matvec = fl;
-  info->flops_rmatvec = fl + 8.0 * (double)K * n1 * n2 * n3;
+  info->flops_rmatvec = fl + dot;
   for (int o = 0; o < 2; ++o) {
     const Tiling& T = o == 0 ? p->tiling : p->tiling_a;
     info->tile_t2[o] = T.t2;

@@ -22,6 +22,44 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+def _check_operand(t: torch.Tensor, rows: int, name: str) -> int:
+    """Validate a product operand before its pointer reaches the C ABI:
+    complex64, on the current CUDA device, shaped (rows,) or (rows, p).
+    Returns p.  Raises ValueError otherwise (no kernel is launched)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.complex64:
+        raise ValueError(f"{name} must be complex64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor, got {t.device}")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} must be on the current CUDA device "
+                         f"(cuda:{torch.cuda.current_device()}), got {t.device}")
+    if t.dim() not in (1, 2) or t.shape[0] != rows or (t.dim() == 2 and t.shape[1] < 1):
+        raise ValueError(f"{name} must be shaped ({rows},) or ({rows}, p), "
+                         f"got {tuple(t.shape)}")
+    return 1 if t.dim() == 1 else int(t.shape[1])
+
+
+def _check_out(out: torch.Tensor, p: int, rows: int, device) -> torch.Tensor:
+    """The output buffer of a product, returned as the (p, rows) view the
+    C ABI writes (column-major rows x p): complex64 on the operand's device,
+    either contiguous with p * rows elements or a (rows, p) column-major view."""
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.complex64:
+        raise ValueError("out must be a complex64 tensor")
+    if out.device != device:
+        raise ValueError(f"out must be on {device}, got {out.device}")
+    buf = out
+    if out.dim() == 2 and tuple(out.shape) == (rows, p) and out.stride() == (1, rows):
+        buf = out.t()
+    shape_ok = (buf.dim() == 1 and p == 1) or tuple(buf.shape) == (p, rows)
+    if not shape_ok or not buf.is_contiguous() or buf.numel() != p * rows:
+        raise ValueError(f"out must be contiguous with {p * rows} elements or a "
+                         f"({rows}, {p}) column-major view, got shape "
+                         f"{tuple(out.shape)} strides {out.stride()}")
+    return buf.view(p, rows)
+
+
 class TuckerPlan:
     def __init__(self, handle: int):
         self.handle = handle
@@ -98,11 +136,11 @@ class TuckerPlan:
 
     def matvec(self, x: torch.Tensor, out: Optional[torch.Tensor] = None):
         """Y = Z X for x of shape (m,) or (m, p), complex64 on the GPU."""
+        p = _check_operand(x, self.m, "x")
         vec = x.dim() == 1
         X = x.reshape(self.m, -1)
-        p = X.shape[1]
         Xc = X.t().contiguous()                  # column-major m x p
-        Y = out if out is not None else torch.empty(
+        Y = _check_out(out, p, self.rows, x.device) if out is not None else torch.empty(
             (p, self.rows), dtype=torch.complex64, device=x.device)
         ws = self.workspace(0, p)
         lib.tv_matvec(self.handle, Xc.data_ptr(), self.m, p, Y.data_ptr(),
@@ -111,11 +149,11 @@ class TuckerPlan:
 
     def rmatvec(self, y: torch.Tensor, out: Optional[torch.Tensor] = None):
         """X = Z^* Y for y of shape (q nv,) or (q nv, p), complex64."""
+        p = _check_operand(y, self.rows, "y")
         vec = y.dim() == 1
         Yv = y.reshape(self.rows, -1)
-        p = Yv.shape[1]
         Yc = Yv.t().contiguous()
-        X = out if out is not None else torch.empty(
+        X = _check_out(out, p, self.m, y.device) if out is not None else torch.empty(
             (p, self.m), dtype=torch.complex64, device=y.device)
         ws = self.workspace(1, p)
         lib.tv_rmatvec(self.handle, Yc.data_ptr(), self.rows, p, X.data_ptr(),
@@ -137,8 +175,10 @@ class AcaTuckerOperator:
     Z^* Y = V (U^* Y) through tv_aca_matvec / tv_aca_rmatvec (Sec. III.B)."""
 
     def __init__(self, plan: TuckerPlan, V: torch.Tensor):
-        if V.dim() != 2 or V.shape[1] != plan.m:
+        if not isinstance(V, torch.Tensor) or V.dim() != 2 or V.shape[1] != plan.m:
             raise ValueError("V must be m x r_c with r_c = the plan's columns")
+        if not V.is_cuda:
+            raise ValueError("V must be on the GPU")
         self.plan = plan
         self.m = int(V.shape[0])
         self.rows = plan.rows
@@ -156,9 +196,9 @@ class AcaTuckerOperator:
 
     def matvec(self, x: torch.Tensor) -> torch.Tensor:
         """Y = U (V^* X) for x of shape (m,) or (m, p)."""
+        p = _check_operand(x, self.m, "x")
         vec = x.dim() == 1
         X = x.reshape(self.m, -1)
-        p = X.shape[1]
         Xc = X.t().contiguous()
         Y = torch.empty((p, self.rows), dtype=torch.complex64, device=x.device)
         ws = self.workspace(0, p)
@@ -169,9 +209,9 @@ class AcaTuckerOperator:
 
     def rmatvec(self, y: torch.Tensor) -> torch.Tensor:
         """X = V (U^* Y) for y of shape (q nv,) or (q nv, p)."""
+        p = _check_operand(y, self.rows, "y")
         vec = y.dim() == 1
         Yv = y.reshape(self.rows, -1)
-        p = Yv.shape[1]
         Yc = Yv.t().contiguous()
         X = torch.empty((p, self.m), dtype=torch.complex64, device=y.device)
         ws = self.workspace(1, p)

@@ -13,7 +13,7 @@ import pytest
 import workloads
 from oracle import aca as oaca
 from oracle import matvec as om
-from tests.plans import random_struct, rel_err, struct_to_abi
+from tests.plans import assert_close, random_struct, rel_err, struct_to_abi
 
 pytestmark = pytest.mark.gpu
 TOL_FP32 = 1e-5
@@ -64,12 +64,12 @@ def test_algorithm3_factors(gpu_lib, alg3):
     ref_y = oaca.aca_matvec(S, V, X)
     ref_x = oaca.aca_rmatvec(S, V, Y)
     for c in range(3):
-        assert rel_err(got_y[:, c], ref_y[:, c]) <= TOL_FP32
+        assert_close(got_y[:, c], ref_y[:, c], TOL_FP32)
     for c in range(2):
-        assert rel_err(got_x[:, c], ref_x[:, c]) <= TOL_FP32
+        assert_close(got_x[:, c], ref_x[:, c], TOL_FP32)
     # one right-hand side through the vector form
     g1 = op.matvec(_cuda(X[:, 0])).cpu().numpy()
-    assert rel_err(g1, ref_y[:, 0]) <= TOL_FP32
+    assert_close(g1, ref_y[:, 0], TOL_FP32)
 
 
 @pytest.mark.parametrize("dims,q,rc,m,rmax,nrhs,seed", [
@@ -118,8 +118,8 @@ def test_shapes_and_leading_dimensions(gpu_lib, dims, q, rc, m, rmax, nrhs,
     ref_y = oaca.aca_matvec(S, V, X)
     ref_x = oaca.aca_rmatvec(S, V, Y)
     for c in range(nrhs):
-        assert rel_err(gy[c, :rows], ref_y[:, c]) <= TOL_FP32
-        assert rel_err(gx[c, :m], ref_x[:, c]) <= TOL_FP32
+        assert_close(gy[c, :rows], ref_y[:, c], TOL_FP32)
+        assert_close(gx[c, :m], ref_x[:, c], TOL_FP32)
         assert np.all(gy[c, rows:] == sentinel)      # padding untouched
         assert np.all(gx[c, m:] == sentinel)
 
@@ -131,10 +131,8 @@ def test_bf16x3_plan(gpu_lib):
     op = AcaTuckerOperator(_plan(S, precision=1), _cuda(V))
     x = _up(workloads.complex_normal(500, 92))
     y = _up(workloads.complex_normal(S.q * S.nv, 93))
-    assert rel_err(op.matvec(_cuda(x)).cpu().numpy(),
-                   oaca.aca_matvec(S, V, x)[:, 0]) <= TOL_BF16X3
-    assert rel_err(op.rmatvec(_cuda(y)).cpu().numpy(),
-                   oaca.aca_rmatvec(S, V, y)[:, 0]) <= TOL_BF16X3
+    assert_close(op.matvec(_cuda(x)).cpu().numpy(), oaca.aca_matvec(S, V, x)[:, 0], TOL_BF16X3)
+    assert_close(op.rmatvec(_cuda(y)).cpu().numpy(), oaca.aca_rmatvec(S, V, y)[:, 0], TOL_BF16X3)
 
 
 def test_argument_errors(gpu_lib):
@@ -180,10 +178,8 @@ def test_body_coil_5mm_full(gpu_lib):
     op = AcaTuckerOperator(P, _cuda(V))
     x = _up(workloads.complex_normal(m, 23))
     y = _up(workloads.complex_normal(S.q * S.nv, 24))
-    assert rel_err(op.matvec(_cuda(x)).cpu().numpy(),
-                   oaca.aca_matvec(S, V, x)[:, 0]) <= TOL_FP32
-    assert rel_err(op.rmatvec(_cuda(y)).cpu().numpy(),
-                   oaca.aca_rmatvec(S, V, y)[:, 0]) <= TOL_FP32
+    assert_close(op.matvec(_cuda(x)).cpu().numpy(), oaca.aca_matvec(S, V, x)[:, 0], TOL_FP32)
+    assert_close(op.rmatvec(_cuda(y)).cpu().numpy(), oaca.aca_rmatvec(S, V, y)[:, 0], TOL_FP32)
 
 
 def test_body_coil_1mm_sampled(gpu_lib):

@@ -11,7 +11,7 @@ import pytest
 
 import workloads
 from oracle import matvec as om
-from tests.plans import rel_err, struct_to_abi
+from tests.plans import assert_close, rel_err, struct_to_abi
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +44,7 @@ def test_gradient_matches_oracle(gpu_lib, c1_plan):
     L.backward()
     g = x.grad.cpu().numpy()
     ref = om.loss_grad(S, x_np, b_np)
-    assert rel_err(g, ref) <= 1e-5
+    assert_close(g, ref, 1e-5)
     assert abs(L.item() - om.loss(S, x_np, b_np)) <= 1e-5 * om.loss(S, x_np, b_np)
 
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import matvec as om
-from tests.plans import random_struct, rel_err, struct_to_abi
+from tests.plans import assert_close, random_struct, rel_err, struct_to_abi
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +23,8 @@ def test_autotune_keeps_results_and_caches(gpu_lib, tmp_path):
     cache = tmp_path / "tune.json"
     P = TuckerPlan.from_factors(S.dims, S.q, S.m, *abi)
     P.autotune(2, str(cache))
-    assert rel_err(P.matvec(cx(x)).cpu().numpy(), om.alg1(S, x)[:, 0]) <= 1e-5
-    assert rel_err(P.rmatvec(cx(y)).cpu().numpy(), om.alg2(S, y)[:, 0]) <= 1e-5
+    assert_close(P.matvec(cx(x)).cpu().numpy(), om.alg1(S, x)[:, 0], 1e-5)
+    assert_close(P.rmatvec(cx(y)).cpu().numpy(), om.alg2(S, y)[:, 0], 1e-5)
     entries = json.loads(cache.read_text())
     assert len(entries) == 2
     Q = TuckerPlan.from_factors(S.dims, S.q, S.m, *abi)
@@ -60,7 +60,7 @@ def test_adjoint_row_block_caps(gpu_lib, tmp_path, cap, t2):
     assert info.tile_t2[1] == t2 and info.splits[1] == 2
     y = workloads_cn(S.q * S.nv, 42)
     got = Q.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
-    assert rel_err(got, om.alg2(S, y.astype(np.complex64).astype(np.complex128))[:, 0]) <= 1e-5
+    assert_close(got, om.alg2(S, y.astype(np.complex64).astype(np.complex128))[:, 0], 1e-5)
 
 
 def workloads_cn(n, seed):

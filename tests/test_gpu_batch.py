@@ -9,7 +9,7 @@ import pytest
 
 import workloads
 from oracle import matvec as om
-from tests.plans import rel_err, struct_to_abi
+from tests.plans import assert_close, rel_err, struct_to_abi
 
 pytestmark = pytest.mark.gpu
 
@@ -60,8 +60,8 @@ def test_batch_forward_and_adjoint(gpu_lib, c4s):
     got_f = _run(plans, 0, [cx(x) for x in X], nrhs)
     got_a = _run(plans, 1, [cx(y) for y in Y], nrhs)
     for c, S in enumerate(structs):
-        assert rel_err(got_f[c], om.alg1(S, X[c])) <= 1e-5
-        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5
+        assert_close(got_f[c], om.alg1(S, X[c]), 1e-5)
+        assert_close(got_a[c], om.alg2(S, Y[c]), 1e-5)
 
 
 def test_batch_graph_replay(gpu_lib, c4s):
@@ -94,7 +94,7 @@ def test_batch_graph_replay(gpu_lib, c4s):
             assert np.array_equal(y.cpu().numpy(), e), rep
     lib.tv_batch_destroy(b)
     for c, S in enumerate(structs):
-        assert rel_err(eager[c], om.alg1(S, X[c].cpu().numpy())) <= 1e-5
+        assert_close(eager[c], om.alg1(S, X[c].cpu().numpy()), 1e-5)
 
 
 # Shapes chosen to reach every batched kernel: forward with n1p32 / 32 = 3,
@@ -129,8 +129,8 @@ def test_batch_kernels_against_oracle(gpu_lib, dims, q, ms, rmax, seed):
     got_f = _run(plans, 0, [cx(x) for x in X], nrhs)
     got_a = _run(plans, 1, [cx(y) for y in Y], nrhs)
     for c, S in enumerate(structs):
-        assert rel_err(got_f[c], om.alg1(S, X[c])) <= 1e-5, ("forward", c)
-        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
+        assert_close(got_f[c], om.alg1(S, X[c]), 1e-5, what=("forward", c))
+        assert_close(got_a[c], om.alg2(S, Y[c]), 1e-5, what=("adjoint", c))
 
 
 def test_batch_adjoint_items_span_tiles(gpu_lib):
@@ -150,8 +150,8 @@ def test_batch_adjoint_items_span_tiles(gpu_lib):
     got_f = _run(plans, 0, [cx(x) for x in X], nrhs)
     got_a = _run(plans, 1, [cx(y) for y in Y], nrhs)
     for c, S in enumerate(structs):
-        assert rel_err(got_f[c], om.alg1(S, X[c])) <= 1e-5, ("forward", c)
-        assert rel_err(got_a[c], om.alg2(S, Y[c])) <= 1e-5, ("adjoint", c)
+        assert_close(got_f[c], om.alg1(S, X[c]), 1e-5, what=("forward", c))
+        assert_close(got_a[c], om.alg2(S, Y[c]), 1e-5, what=("adjoint", c))
 
 
 def test_batch_bf16x3(gpu_lib):

@@ -10,7 +10,7 @@ import pytest
 
 import workloads
 from oracle import matvec as om
-from tests.plans import abi_to_struct, random_struct, rel_err, struct_to_abi
+from tests.plans import assert_close, abi_to_struct, random_struct, rel_err, struct_to_abi
 
 pytestmark = pytest.mark.gpu
 TOL_BF16 = 1e-3
@@ -81,5 +81,5 @@ def test_device_compression_bf16_plan(gpu_lib):
                                     precision=lib.TV_PREC_BF16X3)
     S = abi_to_struct(wl.grid.dims, wl.q, *P.export_factors())
     x, y = wl.x()[:, 0], wl.y()[:, 0]
-    assert rel_err(P.matvec(_cuda(x)).cpu().numpy(), om.alg1(S, x)[:, 0]) <= TOL_BF16
-    assert rel_err(P.rmatvec(_cuda(y)).cpu().numpy(), om.alg2(S, y)[:, 0]) <= TOL_BF16
+    assert_close(P.matvec(_cuda(x)).cpu().numpy(), om.alg1(S, x)[:, 0], TOL_BF16)
+    assert_close(P.rmatvec(_cuda(y)).cpu().numpy(), om.alg2(S, y)[:, 0], TOL_BF16)

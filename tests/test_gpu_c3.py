@@ -3,8 +3,10 @@ currents on 8 rings, columns compressed on the GPU at tolerance 1e-4 with
 ranks capped at 32 (modes of length 128 use the subspace eigensolver).
 
 The BF16X3 plan is checked against the FP64 oracle on the plan's own
-factors on sampled rows (single-element decompression) and sampled columns
-(Algorithm 2's inner step), with the FP32 plan on the same factors beside it;
+factors on whole mode-1 fibres on the edges of the first and last column
+tiles (12 components in turn) and on the columns on both sides of every split
+of the adjoint's column ranges (Algorithm 2's inner step), entry by entry,
+with the FP32 plan on the same factors beside it;
 compression is checked on sampled columns against the oracle's SVD-based
 HOSVD of the closed-form tensors.
 """
@@ -13,7 +15,8 @@ import pytest
 
 import workloads
 from oracle import fields, matvec as om
-from tests.plans import abi_to_struct, rel_err
+from tests.plans import (abi_to_struct, abs_struct, assert_close, boundary_fibres,
+                         fibre_check, split_boundary_columns)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,18 +43,26 @@ def _cuda(a):
 def test_c3_products_bf16_and_fp32(gpu_lib, c3):
     wl, P16, P32, S = c3
     x, y = wl.x()[:, 0], wl.y()[:, 0]
-    rows = np.random.default_rng(31).integers(0, wl.rows, size=24)
-    cols = [0, 255, 511]
-    ref_y = om.entries(S, x, rows)
-    ref_x = om.adjoint_entries(S, y, cols)
+    ranks = P32.export_factors()[0]
     errs = {}
-    for name, P in (("bf16x3", P16), ("fp32", P32)):
+    for name, P, tol in (("bf16x3", P16, 1e-3), ("fp32", P32, 1e-5)):
+        info = P.info
+        cols = sorted(set(split_boundary_columns(ranks, wl.q, wl.m, info.splits[1]))
+                      | {255})
+        ref_x = om.adjoint_entries(S, y, cols)
+        terms_x = np.abs(om.adjoint_entries(abs_struct(S), np.abs(y), cols))
         gy = P.matvec(_cuda(x)).cpu().numpy()
         gx = P.rmatvec(_cuda(y)).cpu().numpy()
-        errs[name] = (rel_err(gy[rows], ref_y), rel_err(gx[cols], ref_x))
-    print(f"C3 sampled rel err: {errs}")
-    assert max(errs["bf16x3"]) <= 1e-3
-    assert max(errs["fp32"]) <= 1e-5
+        ex = assert_close(gx[cols], ref_x, tol, terms=terms_x, what=f"{name} Z^* y")
+        ey = 0.0
+        # whole fibres on the edges of the first and last column tiles; the
+        # 12 components of the PWL basis in turn
+        for n, (i2, i3) in enumerate(boundary_fibres(wl.grid.dims, info.tile_t2[0],
+                                                     info.tile_t3[0])):
+            for k in (n % wl.q, (n + 6) % wl.q):
+                ey = max(ey, fibre_check(S, gy, x, k, i2, i3, tol, what=f"{name} Z x"))
+        errs[name] = (ey, ex)
+    print(f"C3 sampled rel err (fibres, columns): {errs}")
 
 
 def test_c3_compression_sampled(gpu_lib, c3):

@@ -5,15 +5,19 @@
 L(x) = ||Z x - b||^2 with b complex normal; its gradient is taken by the
 adjoint kernel as the backward of TuckerMatvec.  Checked against central
 differences on 8 random directions (exact for a quadratic up to rounding)
-and, on sampled columns, against the oracle's 2 Z^* (Z x - b) on the plan's
-own factors (the full oracle product would take hours on a CPU).
+and against the oracle's 2 Z^* (Z x - b) on the plan's own factors at the
+columns on both sides of every split of the adjoint's column ranges; the
+forward product is checked on whole mode-1 fibres on the edges of the first
+and last column tiles, every component, entry by entry (the full oracle
+product would take hours on a CPU).
 """
 import numpy as np
 import pytest
 
 import workloads
 from oracle import matvec as om
-from tests.plans import abi_to_struct
+from tests.plans import (abi_to_struct, abs_struct, assert_close, boundary_fibres,
+                         fibre_check, split_boundary_columns)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,11 +62,15 @@ def test_c5_gradient(gpu_lib, c5):
         r = (TuckerMatvec.apply(x, P) - b).cpu().numpy().astype(np.complex128)
     ranks, G, U1, U2, U3 = P.export_factors()
     S = abi_to_struct(wl.grid.dims, wl.q, ranks, G, U1, U2, U3)
-    cols = [0, 777, 2047]
+    info = P.info
+    cols = sorted(set(split_boundary_columns(ranks, wl.q, wl.m, info.splits[1]))
+                  | {777})
     ref = 2.0 * om.adjoint_entries(S, r, cols)
-    assert np.linalg.norm(g[cols] - ref) <= 1e-5 * np.linalg.norm(ref)
-    # sampled rows of the forward product against single-element decompression
-    rows = np.random.default_rng(5).integers(0, wl.rows, size=16)
+    terms = 2.0 * np.abs(om.adjoint_entries(abs_struct(S), np.abs(r), cols))
+    assert_close(g[cols], ref, 1e-5, terms=terms, what="gradient columns")
+    # whole mode-1 fibres on the edges of the first and last column tiles of
+    # the forward's tiling, every component
     y = P.matvec(x.detach()).cpu().numpy()
-    ref_y = om.entries(S, x_np, rows)
-    assert np.linalg.norm(y[rows] - ref_y) <= 1e-5 * np.linalg.norm(ref_y)
+    for i2, i3 in boundary_fibres(wl.grid.dims, info.tile_t2[0], info.tile_t3[0]):
+        for k in range(wl.q):
+            fibre_check(S, y, x_np, k, i2, i3, 1e-5, what="c5 Z x")

@@ -97,6 +97,21 @@ def test_single_entries(struct_and_dense):
                        (Z.conj().T @ y)[[1, 4]], atol=1e-11, rtol=0)
 
 
+def test_fibres(struct_and_dense):
+    S, Z = struct_and_dense
+    n1, n2, n3 = S.dims
+    X = crandn(S.m, 2)
+    Y = Z @ X
+    for k, i2, i3 in [(0, 0, 0), (1, n2 - 1, 2), (2, 3, n3 - 1)]:
+        rows = [k * S.nv + i1 + n1 * (i2 + n2 * i3) for i1 in range(n1)]
+        assert np.allclose(matvec.fibre(S, X, k, i2, i3), Y[rows], atol=1e-11, rtol=0)
+        assert np.allclose(matvec.fibre(S, X[:, 0], k, i2, i3), Y[rows, 0],
+                           atol=1e-11, rtol=0)
+    W = crandn(Z.shape[0], 3)
+    assert np.allclose(matvec.adjoint_entries(S, W, [0, 2]),
+                       (Z.conj().T @ W)[[0, 2]], atol=1e-11, rtol=0)
+
+
 def test_compressed_matvec_within_truncation_bound():
     wl = workloads.make("tiny")
     Zd = matvec.dense(wl)
