@@ -3,10 +3,10 @@
 MI355X: compressed matvecs/s, counting both Z x and Z^* y.
 
 One step = one Z x (Algorithm 1) and one Z^* y (Algorithm 2) on the default
-workload: a 64^3 voxel grid, 3 field components, 256 point currents on two
-rings, columns compressed on the GPU at tolerance 1e-4 with ranks capped at
-24, complex64 vectors, FP32 MFMA arithmetic.  Inputs are resident in HBM
-before the timed region; compression is set-up, not timed.
+workload: a 256^3 voxel grid (1 mm voxels), 3 field components, 2048 point
+currents on 16 rings, columns compressed on the GPU at tolerance 1e-4 with
+ranks capped at 32, complex64 vectors, FP32 MFMA arithmetic.  Inputs are
+resident in HBM before the timed region; compression is set-up, not timed.
 
 Prints one JSON line on stdout (progress goes to stderr).
 """
@@ -63,6 +63,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, plan, x_np, y_np, budget_s: float):
     """Time the FP64 oracle (Algorithms 1 and 2) on the plan's own factors,
     on a column subset sized to about ``budget_s`` seconds, scaled to one
@@ -93,7 +104,7 @@ def cpu_baseline(wl, plan, x_np, y_np, budget_s: float):
                   if i.get("user_api") == "blas") or 1
     return {
         "value": 2.0 / per_pair, "unit": "matvecs/s", "cores": threads,
-        "kind": "oracle",
+        "kind": "oracle", "cpu_model": cpu_model(),
         "sample": f"{len(cols)} of {m} columns of the same plan (FP64 "
                   f"Algorithms 1 and 2 on the GPU plan's factors), scaled "
                   f"by {scale:.2f} to one Z x and one Z^* y",
@@ -103,10 +114,10 @@ def cpu_baseline(wl, plan, x_np, y_np, budget_s: float):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2",
-                    help="c1, c2 (default), c3, c5, c4 for the batched path, or "
+    ap.add_argument("--workload", default="c5",
+                    help="c1, c2, c3, c5 (default), c4 for the batched path, or "
                          "aca5 / aca2 / aca1 for the ACA+Tucker products on the "
                          "body-coil grids")
     ap.add_argument("--basis", default="pwc", choices=("pwc", "pwl"),
@@ -234,6 +245,7 @@ def main(argv=None):
     ach = tf_a if dom == "adjoint" else tf_f
     # the BF16 split executes 3 MFMA products per algorithmic one
     peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
+    mode1 = 8.0 * wl.grid.n1 * wl.grid.n2 * wl.grid.n3 * info.sum_r1
     out = {
         "metric": "compressed VSIE matvecs/s (Zx and Z^H y), TFLOP/s and % MFMA peak",
         "value": value, "unit": "matvecs/s", "n_gpus": 1, "steps": K,
@@ -257,7 +269,13 @@ def main(argv=None):
         "roofline": {"kernel": f"{kname} ({dom})", "bound": "mfma",
                      "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                      "frac": ach / peak,
-                     "traffic": measured_traffic(wl.name, pname, dom)},
+                     "traffic": measured_traffic(wl.name, pname, dom),
+                     # the stacked mode-1 product alone (8 nv sum r1 flops, all
+                     # on the matrix cores) over the same duration
+                     "mode1_achieved": mode1 / ((adj_ms if dom == "adjoint" else fwd_ms)
+                                                * 1e-3) / 1e12,
+                     "mode1_frac": mode1 / ((adj_ms if dom == "adjoint" else fwd_ms)
+                                            * 1e-3) / 1e12 / peak},
         "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
                    "splits": list(info.splits),
                    "kernel": ["warp-specialised" if v else "phased" for v in info.kernel]},
@@ -434,6 +452,7 @@ def bench_aca(args):
     kname = "tv::ws_fused" if info.kernel[d] else "tv::fused_f32"
     ach = tf_a if dom == "adjoint" else tf_f
     peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
+    mode1 = 8.0 * wl.grid.n1 * wl.grid.n2 * wl.grid.n3 * info.sum_r1
     out = {
         "metric": "ACA+Tucker coupling-matrix products/s (U (V^* x) and V (U^* y))",
         "value": 2.0 * K / (total_ms / 1e3), "unit": "matvecs/s", "n_gpus": 1,

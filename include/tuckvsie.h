@@ -92,7 +92,9 @@ typedef struct {
   double flops_rmatvec;    /* algorithmic real flops of one Z^* y (p = 1)  */
   /* launch configuration of the fused kernels, [0] forward, [1] adjoint:
    * tile extent along i2 and i3, column splits, and the kernel family
-   * (0: phased, 1: warp-specialised producer/consumer)                     */
+   * (0: phased, 1: warp-specialised producer/consumer, 2: decompress-then-
+   * GEMM, for which tile_t2 is the i3 values per slab, tile_t3 the GEMM's
+   * column blocks per wave and splits its k-step split count)              */
   int32_t tile_t2[2], tile_t3[2], splits[2], kernel[2];
 } tv_plan_info_t;
 
@@ -150,9 +152,37 @@ tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
                      void* x, int64_t ldx, void* ws, size_t ws_bytes,
                      void* stream);
 
-/* Pick the fastest workgroup column tile and column split of the fused
- * kernels for this plan by timing every candidate on the device (HIP
- * events, `stream`), for op 0 (tv_matvec), 1 (tv_rmatvec) or 2 (both).
+/* Launch configuration of one direction of a plan's products (what the
+ * autotuner chooses; set-up call, not thread-safe against concurrent
+ * products on the same plan).
+ *   path 0: the fused kernels (Algorithms 1/2 with decompression inside the
+ *     mode-1 product): tile_t2 = i2 extent of a workgroup tile (0: the tile
+ *     covering the fewest columns), splits = column-range splits (split-K
+ *     over j), row_cap = row blocks per consumer wave (forward 8; adjoint 2
+ *     or 3).
+ *   path 1 (FP32 plans): decompress-then-GEMM: per slab of slab_i3 values
+ *     of i3 (0: all), modes 3 and 2 of every tensor are decompressed into
+ *     the stacked operand B_k = [x_1 M_1; ...] (unscaled for the adjoint) in
+ *     the workspace, then the forward runs Y^k_(1) = A_k B_k as one MFMA
+ *     GEMM per component (gemm_nbw = 2 or 4 column blocks per wave, splits
+ *     k-step splits), the adjoint W = A_k^* Y^k_(1) with the conjugated dot
+ *     against B_k in the GEMM's epilogue (splits 1, gemm_nbw 2) and a
+ *     fixed-order FP64 sum per column (Algorithms 1 and 2, Sec. III.B).
+ * TV_ERR_INVALID_ARG / TV_ERR_NOT_SUPPORTED for a configuration the plan
+ * cannot run; the previous configuration is then kept.  Afterwards
+ * tv_workspace_bytes reflects the configuration. */
+typedef struct {
+  int32_t path;
+  int32_t tile_t2, splits, row_cap;
+  int32_t slab_i3, gemm_nbw;
+} tv_launch_config;
+tv_status tv_plan_configure(tv_plan plan, int32_t op, const tv_launch_config* cfg);
+
+/* Pick the fastest launch configuration (tv_launch_config: fused-kernel
+ * tiles, splits and row caps, and for the forward also the
+ * decompress-then-GEMM path with its slab and tile) for this plan by timing
+ * every candidate on the device (HIP events, `stream`), for op 0
+ * (tv_matvec), 1 (tv_rmatvec) or 2 (both).
  * Results are cached in the JSON file cache_path (NULL: no cache), keyed by
  * device architecture, grid, q, m, precision and a hash of the ranks; a
  * cached entry is applied without timing.  Allocates and synchronises (a

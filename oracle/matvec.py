@@ -77,32 +77,34 @@ def compress_columns(wl, cols: Optional[Iterable[int]] = None) -> TuckerStruct:
     return TuckerStruct(wl.grid.dims, wl.q, out)
 
 
-def _block(S: TuckerStruct) -> int:
-    """Columns of Z formed at once: about 2^22 complex entries (64 MiB)."""
-    return max(1, (1 << 22) // (S.q * S.nv))
+def _block(S: TuckerStruct, entries: int = 1 << 22) -> int:
+    """Columns of Z formed at once: about ``entries`` complex entries
+    (default 2^22, 64 MiB)."""
+    return max(1, entries // (S.q * S.nv))
 
 
-def alg1(S: TuckerStruct, X: np.ndarray) -> np.ndarray:
+def alg1(S: TuckerStruct, X: np.ndarray, block_entries: int = 1 << 22) -> np.ndarray:
     """Y = Z X, the product Algorithm 1 computes, from its definition: the
     columns of Z are the decompressed tensors (eq. 6) stacked in component
     order, and Y is the matrix product Z X, taken over blocks of columns so
-    that only a block of Z exists at a time.  X is m x p; returns q nv x p."""
+    that only a block of Z (about ``block_entries`` entries) exists at a time.
+    X is m x p; returns q nv x p."""
     X = np.asarray(X, np.complex128).reshape(S.m, -1)
     Y = np.zeros((S.q * S.nv, X.shape[1]), np.complex128)
-    b = _block(S)
+    b = _block(S, block_entries)
     for j0 in range(0, S.m, b):
         js = range(j0, min(S.m, j0 + b))
         Y += np.stack([column(S, j) for j in js], axis=1) @ X[j0:j0 + len(js)]
     return Y
 
 
-def alg2(S: TuckerStruct, X: np.ndarray) -> np.ndarray:
+def alg2(S: TuckerStruct, X: np.ndarray, block_entries: int = 1 << 22) -> np.ndarray:
     """Y = Z^* X (conjugate transpose, Table I), the product Algorithm 2
     computes, from its definition over blocks of decompressed columns as in
     alg1.  X is q nv x p; returns m x p."""
     X = np.asarray(X, np.complex128).reshape(S.q * S.nv, -1)
     Y = np.zeros((S.m, X.shape[1]), np.complex128)
-    b = _block(S)
+    b = _block(S, block_entries)
     for j0 in range(0, S.m, b):
         js = range(j0, min(S.m, j0 + b))
         Y[j0:j0 + len(js)] = np.stack([column(S, j) for j in js], axis=1).conj().T @ X

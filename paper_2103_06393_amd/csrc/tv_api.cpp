@@ -128,6 +128,10 @@ static void free_device(tv_plan_s* p) {
   hipFree(p->d_apack_koff);
   hipFree(p->d_split_f);
   hipFree(p->d_split_a);
+  hipFree(p->d_apack4);
+  hipFree(p->d_apackh);
+  p->d_apack4 = nullptr;
+  p->d_apackh = nullptr;
   p->d_meta = nullptr;
   p->d_cores = p->d_u1t = p->d_u2t = p->d_u3t = nullptr;
   p->d_apack = nullptr;
@@ -376,6 +380,10 @@ static tv_status pack_and_upload(tv_plan_s* p) {
     free_device(p);
     return st;
   }
+  if (!bf && (st = dtg_pack(p, meta)) != TV_OK) {
+    free_device(p);
+    return st;
+  }
   p->finalized = true;
   return TV_OK;
 }
@@ -500,6 +508,12 @@ tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
     info->tile_t3[o] = T.t3;
     info->splits[o] = o == 0 ? p->split_f : p->split_a;
     info->kernel[o] = (p->finalized && p->kernel_ws[o] && ws_supported(p, T, o == 1)) ? 1 : 0;
+    if (p->use_dtg[o] && dtg_supported(p)) {
+      info->kernel[o] = 2;
+      info->splits[o] = o == 0 ? p->dtg_split : 1;
+      info->tile_t2[o] = std::min(o == 0 ? p->dtg_s3 : p->dtg_s3_a, p->grid.n3);  // slab
+      info->tile_t3[o] = o == 0 ? p->dtg_nbw : 2;
+    }
   }
   return TV_OK;
 }
@@ -525,7 +539,9 @@ tv_status tv_workspace_bytes(tv_plan p, int32_t op, int32_t nrhs, size_t* bytes)
   if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
   const tv_grid& g = p->grid;
   const int64_t nv = (int64_t)g.n1 * g.n2 * g.n3;
-  if (op == 0)
+  if (p->use_dtg[op] && dtg_supported(p))
+    *bytes = dtg_workspace_bytes(p, op);
+  else if (op == 0)
     *bytes = p->split_f > 1 ? (size_t)8 * p->split_f * g.q * nv : 0;
   else
     *bytes = (size_t)8 * g.q * p->tiling_a.tiles * g.m;
@@ -573,7 +589,9 @@ tv_status tv_matvec(tv_plan p, const void* x, int64_t ldx, int32_t nrhs, void* y
   for (int32_t c = 0; c < nrhs; ++c) {
     const float2* xc = (const float2*)x + (int64_t)c * ldx;
     float2* yc = (float2*)y + (int64_t)c * ldy;
-    if (p->split_f > 1) {
+    if (p->use_dtg[0] && dtg_supported(p)) {
+      st = launch_dtg_forward(p, xc, yc, ws, s);
+    } else if (p->split_f > 1) {
       st = launch_forward_f32(p, xc, (float2*)ws, p->split_f, p->d_split_f, rows, s);
       if (st == TV_OK) st = launch_sum_partials((const float2*)ws, p->split_f, rows, yc, s);
     } else {
@@ -595,6 +613,11 @@ tv_status tv_rmatvec(tv_plan p, const void* y, int64_t ldy, int32_t nrhs, void* 
   for (int32_t c = 0; c < nrhs; ++c) {
     const float2* yc = (const float2*)y + (int64_t)c * ldy;
     float2* xc = (float2*)x + (int64_t)c * ldx;
+    if (p->use_dtg[1] && dtg_supported(p)) {
+      st = launch_dtg_adjoint(p, yc, xc, ws, s);
+      if (st != TV_OK) return st;
+      continue;
+    }
     st = launch_adjoint_f32(p, yc, (float2*)ws, p->split_a, p->d_split_a, s);
     if (st == TV_OK)
       st = launch_reduce_adjoint((const float2*)ws, p->grid.q, p->tiling_a.tiles, p->grid.m, xc,

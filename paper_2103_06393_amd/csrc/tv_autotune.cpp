@@ -1,8 +1,10 @@
-// Autotuner for the fused single-vector kernels: per plan and direction it
-// times every workgroup column tile (t2 x t3), column split count and (for
-// the adjoint) row-block cap per wave on the device with HIP events and keeps
-// the fastest; results are cached in a small JSON file keyed by device, grid,
-// precision and a hash of the ranks.
+// Autotuner for the single-vector products: per plan and direction it times
+// every workgroup column tile (t2 x t3), column split count and (for the
+// adjoint) row-block cap per wave of the fused kernels, and for the forward
+// the decompress-then-GEMM path over its slab sizes, GEMM tiles and k-step
+// splits, on the device with HIP events, and keeps the fastest; results are
+// cached in a small JSON file keyed by device, grid, precision and a hash of
+// the ranks.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -27,7 +29,7 @@ static std::string plan_key(const tv_plan_s* p, int op) {
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "k4|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k5|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -35,13 +37,9 @@ static std::string plan_key(const tv_plan_s* p, int op) {
   return buf;
 }
 
-struct TuneChoice {
-  int t2, split, cap;
-};
-
-// The cache is a flat JSON object {"key": [t2, split, cap], ...}.
-static std::map<std::string, TuneChoice> read_cache(const char* path) {
-  std::map<std::string, TuneChoice> out;
+// The cache is a flat JSON object {"key": [path, t2, split, cap, slab, nbw], ...}.
+static std::map<std::string, tv_launch_config> read_cache(const char* path) {
+  std::map<std::string, tv_launch_config> out;
   if (!path) return out;
   std::ifstream f(path);
   if (!f) return out;
@@ -56,15 +54,16 @@ static std::map<std::string, TuneChoice> read_cache(const char* path) {
     if (q1 == std::string::npos) break;
     const size_t b0 = s.find('[', q1), b1 = s.find(']', q1);
     if (b0 == std::string::npos || b1 == std::string::npos) break;
-    int t2 = 0, sp = 0, cap = 0;
-    if (sscanf(s.c_str() + b0 + 1, "%d , %d , %d", &t2, &sp, &cap) == 3)
-      out[s.substr(q0 + 1, q1 - q0 - 1)] = {t2, sp, cap};
+    tv_launch_config c{};
+    if (sscanf(s.c_str() + b0 + 1, "%d , %d , %d , %d , %d , %d", &c.path, &c.tile_t2,
+               &c.splits, &c.row_cap, &c.slab_i3, &c.gemm_nbw) == 6)
+      out[s.substr(q0 + 1, q1 - q0 - 1)] = c;
     pos = b1 + 1;
   }
   return out;
 }
 
-static void write_cache(const char* path, const std::map<std::string, TuneChoice>& m) {
+static void write_cache(const char* path, const std::map<std::string, tv_launch_config>& m) {
   if (!path) return;
   const std::string tmp = std::string(path) + ".tmp";
   {
@@ -73,17 +72,41 @@ static void write_cache(const char* path, const std::map<std::string, TuneChoice
     f << "{\n";
     size_t i = 0;
     for (const auto& kv : m) {
-      f << "  \"" << kv.first << "\": [" << kv.second.t2 << ", " << kv.second.split << ", "
-        << kv.second.cap << "]" << (++i < m.size() ? ",\n" : "\n");
+      const tv_launch_config& c = kv.second;
+      f << "  \"" << kv.first << "\": [" << c.path << ", " << c.tile_t2 << ", " << c.splits
+        << ", " << c.row_cap << ", " << c.slab_i3 << ", " << c.gemm_nbw << "]"
+        << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
   }
   std::rename(tmp.c_str(), path);
 }
 
-static tv_status apply_config(tv_plan_s* p, int op, int t2, int split, int cap) {
+static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
+  if (c.path == 1) {
+    if (!dtg_supported(p)) return set_error(TV_ERR_NOT_SUPPORTED, "plan has no GEMM operand");
+    if (c.slab_i3 < 0) return set_error(TV_ERR_INVALID_ARG, "slab_i3 must be >= 0");
+    const int slab = c.slab_i3 ? std::min(c.slab_i3, p->grid.n3) : p->grid.n3;
+    if (op == 1) {
+      if (c.splits != 1 || c.gemm_nbw != 2)
+        return set_error(TV_ERR_INVALID_ARG, "the adjoint GEMM takes splits 1 and gemm_nbw 2");
+      p->dtg_s3_a = slab;
+      p->use_dtg[1] = true;
+      return TV_OK;
+    }
+    if (c.gemm_nbw != 2 && c.gemm_nbw != 4) return set_error(TV_ERR_INVALID_ARG, "gemm_nbw");
+    if (c.splits < 1 || c.splits > 64) return set_error(TV_ERR_INVALID_ARG, "GEMM splits");
+    p->dtg_nbw = c.gemm_nbw;
+    p->dtg_split = c.splits;
+    p->dtg_s3 = slab;
+    p->use_dtg[0] = true;
+    return TV_OK;
+  }
+  if (c.path != 0) return set_error(TV_ERR_INVALID_ARG, "path must be 0 or 1");
+  const int t2 = c.tile_t2, split = c.splits, cap = c.row_cap;
   if (op == 0 && cap != nb_cap(p, 0)) return set_error(TV_ERR_INVALID_ARG, "forward cap");
   if (op == 1 && cap != 2 && cap != 3) return set_error(TV_ERR_INVALID_ARG, "adjoint cap");
+  if (split < 1) return set_error(TV_ERR_INVALID_ARG, "splits must be >= 1");
   Tiling T;
   tv_status s = make_tiling(p->grid, t2, cap, &T);
   if (s != TV_OK) return s;
@@ -98,12 +121,39 @@ static tv_status apply_config(tv_plan_s* p, int op, int t2, int split, int cap) 
     p->tiling_a = T;
     p->nbcap_a = cap;
   }
+  p->use_dtg[op] = false;
   return TV_OK;
+}
+
+static tv_launch_config current_config(const tv_plan_s* p, int op) {
+  tv_launch_config c{};
+  if (p->use_dtg[op]) {
+    c.path = 1;
+    c.splits = op == 0 ? p->dtg_split : 1;
+    c.slab_i3 = op == 0 ? p->dtg_s3 : p->dtg_s3_a;
+    c.gemm_nbw = op == 0 ? p->dtg_nbw : 2;
+    return c;
+  }
+  c.tile_t2 = op == 0 ? p->tiling.t2 : p->tiling_a.t2;
+  c.splits = op == 0 ? p->split_f : p->split_a;
+  c.row_cap = nb_cap(p, op);
+  return c;
 }
 
 }  // namespace tv
 
 using namespace tv;
+
+extern "C" tv_status tv_plan_configure(tv_plan p, int32_t op, const tv_launch_config* cfg) {
+  clear_error();
+  if (!p || !cfg) return set_error(TV_ERR_INVALID_ARG, "plan and cfg must be non-NULL");
+  if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  if (op != 0 && op != 1) return set_error(TV_ERR_INVALID_ARG, "op must be 0 or 1");
+  const tv_launch_config keep = current_config(p, op);
+  tv_status s = apply_config(p, op, *cfg);
+  if (s != TV_OK) apply_config(p, op, keep);  // keeps the error message of the refusal
+  return s;
+}
 
 extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, void* stream) {
   clear_error();
@@ -119,12 +169,15 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     if (op != 2 && op != o) continue;
     const std::string key = plan_key(p, o);
     auto it = cache.find(key);
-    if (it != cache.end() &&
-        apply_config(p, o, it->second.t2, it->second.split, it->second.cap) == TV_OK)
-      continue;
-    // candidates: (cap, t2) pairs, then column splits
-    std::vector<std::pair<int, int>> shapes;
+    if (it != cache.end() && apply_config(p, o, it->second) == TV_OK) continue;
+    std::vector<tv_launch_config> cands;
+    // fused kernels: (cap, t2) pairs times column splits
     std::vector<int> splits;
+    const int smax = o == 0 ? 16 : 64;
+    for (int sp = 1; sp <= smax && sp <= g.m; sp *= 2) {
+      if (o == 0 && sp > 1 && (double)sp * rows * 8 > 2e9) break;  // forward partials
+      splits.push_back(sp);
+    }
     int prev_nb = -1, prev_wm = -1;
     for (int cap : (o == 0 ? std::vector<int>{nb_cap(p, 0)} : std::vector<int>{2, 3})) {
       Tiling T0;
@@ -133,20 +186,55 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
       if (T0.nb == prev_nb && T0.wm == prev_wm) continue;  // same tiling as the last cap
       prev_nb = T0.nb;
       prev_wm = T0.wm;
-      for (int t2 = T0.nwg; t2 >= 2; t2 /= 2) shapes.push_back({cap, t2});
+      for (int t2 = T0.nwg; t2 >= 2; t2 /= 2)
+        for (int sp : splits) {
+          tv_launch_config c{};
+          c.tile_t2 = t2;
+          c.splits = sp;
+          c.row_cap = cap;
+          cands.push_back(c);
+        }
     }
-    const int smax = o == 0 ? 16 : 64;
-    for (int sp = 1; sp <= smax && sp <= g.m; sp *= 2) {
-      if (o == 0 && sp > 1 && (double)sp * rows * 8 > 2e9) break;  // forward partials
-      splits.push_back(sp);
+    // decompress-then-GEMM: slabs of B within 16 GiB; forward GEMM tiles and
+    // k-step splits while the launch has fewer than 1024 workgroups
+    if (dtg_supported(p)) {
+      for (int slab = g.n3; slab >= 1; slab = (slab + 1) / 2) {
+        for (int nbw : (o == 0 ? std::vector<int>{2, 4} : std::vector<int>{2})) {
+          tv_launch_config c{};
+          c.path = 1;
+          c.slab_i3 = slab;
+          c.gemm_nbw = nbw;
+          c.splits = 1;
+          const tv_launch_config keep = current_config(p, o);
+          if (apply_config(p, o, c) != TV_OK) continue;
+          const size_t need = dtg_workspace_bytes(p, o);
+          apply_config(p, o, keep);
+          if (need > ((size_t)16 << 30)) continue;
+          if (o == 1) {
+            cands.push_back(c);
+            continue;
+          }
+          const int64_t tiles = dtg_launch_tiles(p, slab, nbw);
+          for (int sp = 1; sp <= 16; sp *= 2) {
+            if (sp > 1 && tiles * (sp / 2) >= 1024) break;
+            if (sp > 1 && (double)sp * rows * 8 > 2e9) break;
+            c.splits = sp;
+            cands.push_back(c);
+          }
+        }
+        if (slab <= 8 || (int64_t)g.n2 * slab < 4096) break;
+      }
     }
     // buffers sized for the largest candidate
     size_t wsb = 16;
-    for (const auto& sh : shapes) {
-      Tiling T;
-      if (make_tiling(g, sh.second, sh.first, &T) != TV_OK) continue;
-      const size_t b = o == 0 ? (size_t)8 * splits.back() * rows : (size_t)8 * g.q * T.tiles * g.m;
-      wsb = std::max(wsb, b);
+    {
+      const tv_launch_config keep = current_config(p, o);
+      for (const auto& c : cands) {
+        if (apply_config(p, o, c) != TV_OK) continue;
+        size_t b = 0;
+        if (tv_workspace_bytes(p, o, 1, &b) == TV_OK) wsb = std::max(wsb, b);
+      }
+      apply_config(p, o, keep);
     }
     void *x = nullptr, *y = nullptr, *ws = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -157,46 +245,41 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     if (e == hipSuccess) e = hipMemsetAsync(y, 0, (size_t)8 * rows, st);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    const int keep_t2 = o == 0 ? p->tiling.t2 : p->tiling_a.t2;
-    const int keep_sp = o == 0 ? p->split_f : p->split_a;
-    const int keep_cap = nb_cap(p, o);
+    const tv_launch_config keep = current_config(p, o);
     float best = -1.f;
-    int best_t2 = keep_t2, best_sp = keep_sp, best_cap = keep_cap;
-    for (size_t a = 0; e == hipSuccess && a < shapes.size(); ++a)
-      for (size_t b = 0; e == hipSuccess && b < splits.size(); ++b) {
-        if (apply_config(p, o, shapes[a].second, splits[b], shapes[a].first) != TV_OK) continue;
-        auto run = [&]() {
-          return o == 0 ? tv_matvec(p, x, g.m, 1, y, rows, ws, wsb, stream)
-                        : tv_rmatvec(p, y, rows, 1, x, g.m, ws, wsb, stream);
-        };
-        bool ok = true;
-        for (int w = 0; w < 2 && ok; ++w) ok = run() == TV_OK;
-        if (!ok) continue;
-        e = hipEventRecord(e0, st);
-        for (int r = 0; r < 5 && ok && e == hipSuccess; ++r) ok = run() == TV_OK;
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (ok && e == hipSuccess && (best < 0.f || ms < best)) {
-          best = ms;
-          best_t2 = shapes[a].second;
-          best_sp = splits[b];
-          best_cap = shapes[a].first;
-        }
+    tv_launch_config best_c = keep;
+    for (size_t a = 0; e == hipSuccess && a < cands.size(); ++a) {
+      if (apply_config(p, o, cands[a]) != TV_OK) continue;
+      auto run = [&]() {
+        return o == 0 ? tv_matvec(p, x, g.m, 1, y, rows, ws, wsb, stream)
+                      : tv_rmatvec(p, y, rows, 1, x, g.m, ws, wsb, stream);
+      };
+      bool ok = true;
+      for (int w = 0; w < 2 && ok; ++w) ok = run() == TV_OK;
+      if (!ok) continue;
+      e = hipEventRecord(e0, st);
+      for (int r = 0; r < 5 && ok && e == hipSuccess; ++r) ok = run() == TV_OK;
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (ok && e == hipSuccess && (best < 0.f || ms < best)) {
+        best = ms;
+        best_c = cands[a];
       }
+    }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     hipFree(x);
     hipFree(y);
     hipFree(ws);
     if (e != hipSuccess) {
-      apply_config(p, o, keep_t2, keep_sp, keep_cap);
+      apply_config(p, o, keep);
       return hip_error(e, "tv_autotune");
     }
-    tv_status s = apply_config(p, o, best_t2, best_sp, best_cap);
+    tv_status s = apply_config(p, o, best_c);
     if (s != TV_OK) return s;
-    cache[key] = {best_t2, best_sp, best_cap};
+    cache[key] = best_c;
     dirty = true;
   }
   if (dirty) write_cache(cache_path, cache);

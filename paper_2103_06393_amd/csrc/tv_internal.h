@@ -71,6 +71,20 @@ struct tv_plan_s {
   int32_t* d_split_f = nullptr;    // [q][split+1] first column per split
   int32_t* d_split_a = nullptr;
   size_t device_bytes = 0;
+  // decompress-then-GEMM form of the forward product (large grids)
+  float* d_apack4 = nullptr;       // stacked U1 in 4-k-step groups (FP32 plans)
+  int dtg_nbtp = 0;                // 32-row blocks per k-step, padded to the GEMM tile
+  std::vector<int64_t> dtg_rpad;   // rows of A_k padded to 16, per component
+  std::vector<int64_t> dtg_a4off;  // float offset of component k in d_apack4
+  int64_t dtg_rows = 0;            // sum of dtg_rpad
+  float* d_apackh = nullptr;       // adjoint operand: U1^* real-embedded, 4-voxel-row groups
+  std::vector<int> dtg_mbh;        // 32-row blocks of the adjoint operand per component
+  std::vector<int64_t> dtg_ahoff;  // float offset of component k in d_apackh
+  bool use_dtg[2] = {false, false};
+  int dtg_s3 = 1 << 30;            // i3 values per slab of B (forward)
+  int dtg_s3_a = 1 << 30;          // i3 values per slab of B (adjoint)
+  int dtg_nbw = 2;                 // 32-column blocks per wave of the GEMM tile
+  int dtg_split = 1;               // k-step splits of the GEMM
   int max_r[3] = {0, 0, 0};
   int nbt_pack = 0;      // 32-row blocks per stacked A row in the packed layout
   int max_r12 = 0;       // largest r1 r2
@@ -107,6 +121,15 @@ tv_status make_tiling(const tv_grid& g, int t2, int nbcap, Tiling* T);
 int nb_cap(const tv_plan_s* p, int op);
 // (re)build and upload the column split table of one direction
 tv_status set_split(tv_plan_s* p, int op, int S);
+// decompress-then-GEMM forward (tv_dtg.hip)
+tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta);
+bool dtg_supported(const tv_plan_s* p);
+size_t dtg_workspace_bytes(const tv_plan_s* p, int op);
+int64_t dtg_launch_tiles(const tv_plan_s* p, int s3, int nbw);  // workgroups of one GEMM launch
+tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, void* ws,
+                             hipStream_t st);
+tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,
+                             hipStream_t st);
 // point-current fields (tv_columns.hip): sources as device [n][6]
 tv_status stage_sources(int n1, int n2, int n3, double h, int64_t n, const double* pos,
                         const double* ori, std::vector<double>& src);

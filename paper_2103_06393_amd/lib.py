@@ -53,6 +53,11 @@ class tv_plan_info_t(ctypes.Structure):
                 ("tile_t3", c_i32 * 2), ("splits", c_i32 * 2), ("kernel", c_i32 * 2)]
 
 
+class tv_launch_config(ctypes.Structure):
+    _fields_ = [("path", c_i32), ("tile_t2", c_i32), ("splits", c_i32),
+                ("row_cap", c_i32), ("slab_i3", c_i32), ("gemm_nbw", c_i32)]
+
+
 class TuckVsieError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -91,6 +96,8 @@ _tv_compress_append = _sig("tv_compress_append", [c_vp, c_vp, c_i64, c_vp])
 _tv_plan_finalize = _sig("tv_plan_finalize", [c_vp, c_vp])
 _tv_compress_discarded = _sig("tv_compress_discarded", [c_vp, _dp])
 _tv_autotune = _sig("tv_autotune", [c_vp, c_i32, ctypes.c_char_p, c_vp])
+_tv_plan_configure = _sig("tv_plan_configure",
+                          [c_vp, c_i32, ctypes.POINTER(tv_launch_config)])
 _tv_batch_create = _sig("tv_batch_create", [c_i32, ctypes.POINTER(c_vp), c_i32,
                                             _ip, ctypes.POINTER(c_vp)])
 _tv_batch_workspace_bytes = _sig("tv_batch_workspace_bytes",
@@ -121,7 +128,7 @@ EXPORTED = ("tv_plan_from_factors", "tv_plan_destroy", "tv_plan_info",
             "tv_plan_export_factors", "tv_workspace_bytes", "tv_matvec",
             "tv_rmatvec", "tv_dipole_columns", "tv_compress_begin",
             "tv_compress_append", "tv_plan_finalize", "tv_compress_discarded",
-            "tv_autotune", "tv_batch_create", "tv_batch_workspace_bytes", "tv_batch_run",
+            "tv_autotune", "tv_plan_configure", "tv_batch_create", "tv_batch_workspace_bytes", "tv_batch_run",
             "tv_batch_destroy", "tv_aca_workspace_bytes", "tv_aca_matvec",
             "tv_aca_rmatvec", "tv_dipole_rows", "tv_aca_assemble",
             "tv_status_string", "tv_last_error")
@@ -275,6 +282,14 @@ def tv_batch_run(batch, in_ptrs, ld_in, out_ptrs, ld_out, ws_ptr, ws_bytes,
 
 def tv_batch_destroy(batch: int) -> None:
     _check(_tv_batch_destroy(batch), "tv_batch_destroy")
+
+
+def tv_plan_configure(plan: int, op: int, path: int = 0, tile_t2: int = 0,
+                      splits: int = 1, row_cap: int = 0, slab_i3: int = 0,
+                      gemm_nbw: int = 2) -> None:
+    cfg = tv_launch_config(int(path), int(tile_t2), int(splits), int(row_cap),
+                           int(slab_i3), int(gemm_nbw))
+    _check(_tv_plan_configure(plan, int(op), ctypes.byref(cfg)), "tv_plan_configure")
 
 
 def tv_autotune(plan: int, op: int = 2, cache_path=None, stream=None) -> None:

@@ -1,0 +1,120 @@
+"""The decompress-then-GEMM form of Algorithms 1 and 2 (slabs of the stacked
+operand B written by the decompression kernel, then one MFMA GEMM per
+component; the adjoint's conjugated dot in the GEMM's epilogue) against the
+FP64 oracle, in every configuration the autotuner may choose: slab sizes
+(ragged last slab), GEMM tiles, k-step splits, ragged voxel rows and columns,
+ranks up to 32 and single-column plans."""
+import numpy as np
+import pytest
+
+from oracle import matvec as om
+from tests.plans import adj_terms, assert_close, fwd_terms, random_struct, struct_to_abi
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _plan(S):
+    from paper_2103_06393_amd.ops import TuckerPlan
+    return TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S))
+
+
+@pytest.mark.parametrize("dims,q,m,rmax,seed,slab,nbw,splits", [
+    ((20, 13, 7), 2, 5, 5, 1, 0, 2, 1),       # n1 = 20: one 4-block row tile, ragged
+    ((64, 32, 24), 3, 9, 12, 2, 8, 2, 1),     # three slabs
+    ((64, 32, 24), 3, 9, 12, 2, 5, 4, 3),     # ragged last slab, wide tile, 3 splits
+    ((96, 40, 33), 3, 6, 20, 4, 16, 4, 1),    # 6 blocks padded to 8, i2 ragged
+    ((130, 24, 10), 1, 7, 32, 5, 0, 2, 2),    # n1 > 128: 2 row tiles, ranks to 32
+    ((256, 16, 9), 3, 4, 10, 6, 3, 2, 1),     # 16 row blocks
+    ((17, 9, 5), 12, 1, 4, 7, 2, 4, 1),       # q = 12, one column, odd n1
+])
+def test_dtg_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, splits):
+    import torch
+    from paper_2103_06393_amd import lib
+    S = random_struct(dims, q, m, rmax, seed)
+    P = _plan(S)
+    lib.tv_plan_configure(P.handle, 0, path=1, splits=splits, slab_i3=slab, gemm_nbw=nbw)
+    P._ws.clear()
+    info = P.info
+    assert info.kernel[0] == 2 and info.splits[0] == splits and info.tile_t3[0] == nbw
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    got = P.matvec(torch.from_numpy(x.astype(np.complex64)).cuda()).cpu().numpy()
+    assert_close(got, om.alg1(S, x)[:, 0], TOL, terms=fwd_terms(S, x), what="GEMM path Z x")
+    # a second call reuses the workspace (stale B rows must not leak in)
+    x2 = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    got2 = P.matvec(torch.from_numpy(x2.astype(np.complex64)).cuda()).cpu().numpy()
+    assert_close(got2, om.alg1(S, x2)[:, 0], TOL, terms=fwd_terms(S, x2), what="second call")
+    # the adjoint on the same path and slab
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2)
+    P._ws.clear()
+    assert P.info.kernel[1] == 2
+    for rep in range(2):
+        y = rng.standard_normal(S.q * S.nv) + 1j * rng.standard_normal(S.q * S.nv)
+        gx = P.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
+        assert_close(gx, om.alg2(S, y)[:, 0], TOL, terms=adj_terms(S, y),
+                     what=f"GEMM path Z^* y, call {rep}")
+
+
+def test_dtg_workspace_poisoned_and_multi_rhs(gpu_lib):
+    """NaN-filled workspace (the decompression must overwrite or zero every
+    element the GEMM reads) and several right-hand sides with leading dims."""
+    import torch
+    from paper_2103_06393_amd import lib
+    S = random_struct((48, 20, 12), 3, 6, 9, 11)
+    P = _plan(S)
+    lib.tv_plan_configure(P.handle, 0, path=1, splits=1, slab_i3=5, gemm_nbw=2)
+    p = 3
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((S.m, p)) + 1j * rng.standard_normal((S.m, p))
+    nb = lib.tv_workspace_bytes(P.handle, 0, p)
+    ws = torch.full((nb // 4,), float("nan"), dtype=torch.float32, device="cuda")
+    ldx, ldy = S.m + 2, S.q * S.nv + 4
+    xb = np.zeros((p, ldx), np.complex64)
+    xb[:, :S.m] = X.T
+    xd = torch.from_numpy(xb).cuda()
+    yd = torch.zeros((p, ldy), dtype=torch.complex64, device="cuda")
+    lib.tv_matvec(P.handle, xd.data_ptr(), ldx, p, yd.data_ptr(), ldy, ws.data_ptr(), nb,
+                  torch.cuda.current_stream().cuda_stream)
+    got = yd.cpu().numpy()[:, :S.q * S.nv].T
+    assert_close(got, om.alg1(S, X), TOL, terms=fwd_terms(S, X), what="GEMM path, 3 RHS")
+
+
+def test_dtg_adjoint_poisoned_workspace_and_multi_rhs(gpu_lib):
+    import torch
+    from paper_2103_06393_amd import lib
+    S = random_struct((50, 20, 12), 3, 6, 9, 12)       # even n1: paired y loads
+    T = random_struct((33, 9, 7), 2, 4, 7, 13)          # odd n1: single loads
+    for R, slab in ((S, 5), (T, 0)):
+        P = _plan(R)
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2)
+        p = 2
+        rng = np.random.default_rng(5)
+        Y = rng.standard_normal((R.q * R.nv, p)) + 1j * rng.standard_normal((R.q * R.nv, p))
+        nb = lib.tv_workspace_bytes(P.handle, 1, p)
+        ws = torch.full((nb // 4,), float("nan"), dtype=torch.float32, device="cuda")
+        ldy, ldx = R.q * R.nv + 2, R.m + 3
+        yb = np.zeros((p, ldy), np.complex64)
+        yb[:, :R.q * R.nv] = Y.T
+        yd = torch.from_numpy(yb).cuda()
+        xd = torch.zeros((p, ldx), dtype=torch.complex64, device="cuda")
+        lib.tv_rmatvec(P.handle, yd.data_ptr(), ldy, p, xd.data_ptr(), ldx, ws.data_ptr(), nb,
+                       torch.cuda.current_stream().cuda_stream)
+        got = xd.cpu().numpy()[:, :R.m].T
+        assert_close(got, om.alg2(R, Y), TOL, terms=adj_terms(R, Y), what="GEMM adjoint, 2 RHS")
+
+
+def test_dtg_refused_configurations(gpu_lib):
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    S = random_struct((20, 13, 7), 2, 3, 5, 1)
+    P = _plan(S)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=2, gemm_nbw=2)
+    Q = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
+                                precision=lib.TV_PREC_BF16X3)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(Q.handle, 0, path=1, splits=1, gemm_nbw=2)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=3)
+    assert P.info.kernel[0] != 2 and P.info.kernel[1] != 2   # refusals left no trace
