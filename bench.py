@@ -240,7 +240,10 @@ def main(argv=None):
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
     d = 1 if dom == "adjoint" else 0
     info = plan.info  # after autotuning: the launch configuration in use
-    kname = "tv::ws_fused" if info.kernel[d] else "tv::fused_f32"
+    kname = {0: "tv::fused_f32", 1: "tv::ws_fused",
+             2: ("tv_matvec call: dtg_decomp_kernel + dtg_gemm_kernel" if d == 0 else
+                 "tv_rmatvec call: dtg_decomp_kernel + dtg_adjoint_kernel + "
+                 "dtg_adjoint_reduce_kernel")}[info.kernel[d]]
     pname = "fp32" if prec == lib.TV_PREC_FP32 else "bf16x3"
     ach = tf_a if dom == "adjoint" else tf_f
     # the BF16 split executes 3 MFMA products per algorithmic one
@@ -278,7 +281,8 @@ def main(argv=None):
                                             * 1e-3) / 1e12 / peak},
         "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
                    "splits": list(info.splits),
-                   "kernel": ["warp-specialised" if v else "phased" for v in info.kernel]},
+                   "kernel": [{0: "phased", 1: "warp-specialised",
+                               2: "decompress-then-GEMM"}[v] for v in info.kernel]},
     }
     if not args.no_cpu:
         cb, cols, y_ref, x_ref = cpu_baseline(wl, plan, x_np, y_np, args.cpu_budget)
@@ -449,7 +453,10 @@ def bench_aca(args):
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
     d = 1 if dom == "adjoint" else 0
     info = plan.info
-    kname = "tv::ws_fused" if info.kernel[d] else "tv::fused_f32"
+    kname = {0: "tv::fused_f32", 1: "tv::ws_fused",
+             2: ("tv_matvec call: dtg_decomp_kernel + dtg_gemm_kernel" if d == 0 else
+                 "tv_rmatvec call: dtg_decomp_kernel + dtg_adjoint_kernel + "
+                 "dtg_adjoint_reduce_kernel")}[info.kernel[d]]
     ach = tf_a if dom == "adjoint" else tf_f
     peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
     mode1 = 8.0 * wl.grid.n1 * wl.grid.n2 * wl.grid.n3 * info.sum_r1
@@ -534,9 +541,11 @@ def bench_assemble(args):
     log(f"[alg3] workload {wl.name} ({args.basis}): grid {wl.grid.dims}, q={wl.q}, "
         f"m={wl.m}, {rc} steps")
     t0 = time.perf_counter()
+    ws = torch.empty(lib.tv_aca_assemble_workspace_bytes(grid, rc, wl.tol), dtype=torch.uint8,
+                     device="cuda")
     h_plan, V, n, conv, piv, s = lib.tv_aca_assemble(
         grid, wl.grid.h, wl.k0, lib.field_code(wl.basis, wl.operator), wl.pos, wl.ori,
-        wl.tol, 0.0, 1, 0, rc, lib.TV_PREC_FP32, st)
+        wl.tol, 0.0, 1, 0, rc, lib.TV_PREC_FP32, st, ws.data_ptr(), ws.numel())
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     info = lib.tv_plan_info(h_plan)
@@ -571,7 +580,7 @@ def bench_batch(args):
     import torch
     import workloads
     from paper_2103_06393_amd import lib
-    from paper_2103_06393_amd.ops import TuckerPlan
+    from paper_2103_06393_amd.ops import TuckerPlan, batch_create
     wls = workloads.make_batch("c4")
     t0 = time.perf_counter()
     bf = args.precision == "bf16x3"
@@ -588,8 +597,8 @@ def bench_batch(args):
     Xo = [torch.empty((p, P.m), dtype=torch.complex64, device="cuda").t() for P in plans]
     hs = [P.handle for P in plans]
     t0 = time.perf_counter()
-    bf = lib.tv_batch_create(hs, 0, [p] * len(plans))
-    ba = lib.tv_batch_create(hs, 1, [p] * len(plans))
+    bf, bf_arena = batch_create(hs, 0, [p] * len(plans))
+    ba, ba_arena = batch_create(hs, 1, [p] * len(plans))
     log(f"[bench] batch objects (work queues, packed operands) built in "
         f"{time.perf_counter() - t0:.1f} s")
     wsf = torch.empty(lib.tv_batch_workspace_bytes(bf), dtype=torch.uint8, device="cuda")

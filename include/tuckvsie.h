@@ -107,16 +107,30 @@ typedef struct {
  * u1, u2, u3 : host complex128, the factors concatenated in tensor order;
  *         U_n of tensor t is n_n x r_n column-major, U[i,a] at i + n_n*a.
  * The library copies and repacks the factors (FP64 -> FP32 round to
- * nearest even) into device memory it allocates; the host arrays may be
- * freed on return.  Synchronous.  Returns TV_ERR_RANK for a rank outside
- * [1, min(n_n, TV_MAX_RANK)], TV_ERR_NUMERIC for non-finite values.
+ * nearest even) on the host; the host arrays may be freed on return.  The
+ * plan holds no device memory until tv_plan_bind_arena.  Host-only.
+ * Returns TV_ERR_RANK for a rank outside [1, min(n_n, TV_MAX_RANK)],
+ * TV_ERR_NUMERIC for non-finite values.
  * ---------------------------------------------------------------------- */
 tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks,
                                const double* cores, const double* u1,
                                const double* u2, const double* u3,
                                tv_precision precision, tv_plan* out);
 
-/* Release a plan and its device memory.  NULL is accepted. */
+/* Device memory of a plan (Table II's Tucker entries in the packed layouts
+ * of the kernels: FP32 cores and factors, the stacked U1 operands, split
+ * tables) is owned by the caller: tv_plan_required_bytes gives the size of
+ * the arena a finalized plan needs, tv_plan_bind_arena copies the packed
+ * plan into the caller's device buffer [arena, arena + bytes) (256-byte
+ * aligned) on `stream` and waits for the copies (set-up call), after which
+ * the plan's products and autotuning may run.  The arena must stay
+ * allocated and unmodified while the plan is used; a plan binds once.
+ * TV_ERR_WORKSPACE (before any device work) if bytes is short. */
+tv_status tv_plan_required_bytes(tv_plan plan, size_t* bytes);
+tv_status tv_plan_bind_arena(tv_plan plan, void* arena, size_t bytes, void* stream);
+
+/* Release a plan (host memory only; its arena belongs to the caller).
+ * NULL is accepted. */
 tv_status tv_plan_destroy(tv_plan plan);
 
 /* Sizes, ranks and operation counts of a plan. */
@@ -206,8 +220,8 @@ tv_status tv_autotune(tv_plan plan, int32_t op, const char* cache_path,
  *   coupling matrix Z_bc): curl(g p) = g (-i k0 - 1/R) Rhat x p, same bases.
  * out: device complex128, ncols*q*nv values, column j's tensor k at
  *   out + 2*((j*q + k)*nv + v), v = i1 + n1*(i2 + n2*i3).  Runs on
- *   `stream` and synchronises it before returning (the inputs are staged
- *   through a temporary device buffer that is freed on return).
+ *   `stream` and synchronises it before returning; the sources reach the
+ *   kernels through their launch arguments (no device allocation).
  * ---------------------------------------------------------------------- */
 tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h,
                             double k0, int32_t basis, int64_t ncols,
@@ -223,16 +237,21 @@ tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h,
  * values and clamped to [rank_min, min(rank_cap, n_n, TV_MAX_RANK)]
  * (rank_cap <= 0 means no cap).
  * tv_compress_append compresses the next ncols columns, given as device
- * complex128 in the layout written by tv_dipole_columns; work happens on
- * `stream`, and the call synchronises it before returning.
+ * complex128 in the layout written by tv_dipole_columns, with the caller's
+ * device workspace ws (256-byte aligned, at least
+ * tv_compress_workspace_bytes(plan, ncols) bytes: Gram matrices,
+ * eigenpairs, factors and partial projections of the call; TV_ERR_WORKSPACE
+ * before any device work if short); work happens on `stream`, and the call
+ * synchronises it before returning.  The factors are kept on the host.
  * tv_plan_finalize packs the plan for the products once all m columns are
- * in; only then may it be used with tv_matvec / tv_rmatvec.
+ * in; after tv_plan_bind_arena it may be used with tv_matvec / tv_rmatvec.
  * ---------------------------------------------------------------------- */
 tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min,
                             int32_t rank_cap, tv_precision precision,
                             tv_plan* out);
+tv_status tv_compress_workspace_bytes(tv_plan plan, int64_t ncols, size_t* bytes);
 tv_status tv_compress_append(tv_plan plan, const void* cols, int64_t ncols,
-                             void* stream);
+                             void* ws, size_t ws_bytes, void* stream);
 tv_status tv_plan_finalize(tv_plan plan, void* stream);
 
 /* Largest singular-value tail discarded per mode for every tensor appended
@@ -251,9 +270,13 @@ tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
  * directions apply with the BF16 hi/lo split (FP32 accumulation).  With all
  * ranks <= 32 (and, forward, n1 <= 96) the decompression runs on MFMA too,
  * from G x3 U3 precomputed per (tensor, i3) into the workspace.
- * tv_batch_create builds the work queue and the packed operands (device
- * memory it owns, queue ordered longest job first) and is synchronous;
- * plans must outlive the batch.
+ * tv_batch_create builds the work queue (longest job first) and the packed
+ * operands on the host (host-only; the plans must be bound to their arenas
+ * and outlive the batch); tv_batch_required_bytes gives the device arena
+ * the batch needs and tv_batch_bind_arena copies the queue and operands
+ * into the caller's buffer (256-byte aligned; set-up call, synchronous;
+ * TV_ERR_WORKSPACE before any device work if short).  A batch binds once
+ * and its arena must stay allocated while it is used.
  * tv_batch_run queues a counter-reset kernel, (MFMA path) the mode-3
  * kernel, the persistent kernel and (op 1) a reduction kernel on `stream`:
  * no allocation, no synchronisation and no memset, so it may be captured
@@ -268,6 +291,8 @@ tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
 typedef struct tv_batch_s* tv_batch;
 tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op,
                           const int32_t* nrhs, tv_batch* out);
+tv_status tv_batch_required_bytes(tv_batch batch, size_t* bytes);
+tv_status tv_batch_bind_arena(tv_batch batch, void* arena, size_t bytes, void* stream);
 tv_status tv_batch_workspace_bytes(tv_batch batch, size_t* bytes);
 tv_status tv_batch_run(tv_batch batch, const void* const* in,
                        const int64_t* ld_in, void* const* out,
@@ -310,7 +335,8 @@ tv_status tv_aca_rmatvec(tv_plan plan, const void* v, int64_t m, int64_t ldv,
  * `basis` codes as tv_dipole_columns): out[r*nsrc + j] = Z[rows[r], j],
  * device complex128,
  * row = k nv + i1 + n1 (i2 + n2 i3) (Algorithm 1's row order), nrows <=
- * 65535, rows in [0, q nv).  Synchronous; allocates a small staging buffer.
+ * 65535, rows in [0, q nv).  Synchronous; sources and row indices reach
+ * the kernels through their launch arguments (no device allocation).
  * ---------------------------------------------------------------------- */
 tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h,
                          double k0, int32_t basis, int64_t nsrc,
@@ -329,22 +355,32 @@ tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h,
  * ||U V^*||_F^2, with the cross term 2 Re sum conj(V^* y) (U^* x)), when a
  * residual row is exactly zero, or after max_terms steps.
  * Outputs: *u_out a finalized plan of the r_c columns of U (grid m = r_c;
- * release with tv_plan_destroy); v_out host complex128 m x max_terms,
+ * not bound: bind it with tv_plan_bind_arena before its products; release
+ * with tv_plan_destroy); v_out host complex128 m x max_terms,
  * column-major, first r_c columns written; *rc_out = r_c; *converged_out =
  * 1 if the stopping test was met; pivots (optional, host int64
  * [max_terms][2]) the pivot row i and column j of each step; s_out
  * (optional, host double[max_terms]) the estimate after each step.
  * basis as for tv_dipole_columns (bit 0 PWL, TV_FIELD_K for the magnetic
- * coupling matrix Z_bc); PWC needs grid->q = 3, PWL q = 12.  Synchronous;
- * allocates device memory for the duration of the call.  TV_ERR_NUMERIC if
- * the first pivot row of Z is zero.
+ * coupling matrix Z_bc); PWC needs grid->q = 3, PWL q = 12.  Synchronous.
+ * ws: the caller's device workspace (256-byte aligned) of at least
+ * tv_aca_assemble_workspace_bytes(grid, max_terms, tol, hosvd_tol,
+ * rank_min, rank_cap, precision) bytes: the row, column and V buffers, one
+ * column's compression scratch, U's device arena at max_terms columns of the
+ * largest ranks the HOSVD clamps allow (rank_cap bounds it) and the products'
+ * workspace; TV_ERR_WORKSPACE before any device work if short.
+ * TV_ERR_NUMERIC if the first pivot row of Z is zero.
  * ---------------------------------------------------------------------- */
+tv_status tv_aca_assemble_workspace_bytes(const tv_grid* grid, int32_t max_terms,
+                                          double tol, double hosvd_tol,
+                                          int32_t rank_min, int32_t rank_cap,
+                                          tv_precision precision, size_t* bytes);
 tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0,
                           int32_t basis, const double* pos, const double* ori,
                           double tol, double hosvd_tol, int32_t rank_min,
                           int32_t rank_cap, int32_t max_terms,
-                          tv_precision precision, tv_plan* u_out,
-                          double* v_out, int32_t* rc_out,
+                          tv_precision precision, void* ws, size_t ws_bytes,
+                          tv_plan* u_out, double* v_out, int32_t* rc_out,
                           int32_t* converged_out, int64_t* pivots,
                           double* s_out, void* stream);
 

@@ -86,6 +86,7 @@ tv_status aca_check(tv_plan p, const void* v, int64_t m, int64_t ldv, const void
                     int64_t rows_out, int op, const void* ws, size_t ws_bytes) {
   if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
   if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  if (!p->bound) return set_error(TV_ERR_INVALID_ARG, "plan has no device arena (tv_plan_bind_arena)");
   if (!v || !in || !out) return set_error(TV_ERR_INVALID_ARG, "V and vectors must be non-NULL");
   if (m < 1 || m > ((int64_t)1 << 31)) return set_error(TV_ERR_SHAPE, "m must be in [1, 2^31]");
   if (ldv < m) return set_error(TV_ERR_SHAPE, "ldv smaller than m");

@@ -257,21 +257,84 @@ tv_status last(const char* what) {
   return e == hipSuccess ? TV_OK : hip_error(e, what);
 }
 
-// Device buffers of one assembly, released on every exit path.
+// Device buffers of one assembly, carved from the caller's workspace
+// (256-byte aligned, in call order); with base == nullptr only the size is
+// accumulated.
 struct Buffers {
-  std::vector<void*> ptrs;
-  ~Buffers() {
-    for (void* q : ptrs) hipFree(q);
-  }
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
   template <typename T>
   tv_status alloc(T** p, size_t count) {
-    *p = nullptr;
-    hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
-    if (e != hipSuccess) return hip_error(e, "hipMalloc (ACA assembly)");
-    ptrs.push_back(*p);
+    off = (off + 255) & ~(size_t)255;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (base && off + bytes > cap) return set_error(TV_ERR_WORKSPACE, "ACA assembly workspace");
+    *p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
     return TV_OK;
   }
 };
+
+// Largest rank per mode a new column of U may keep (the HOSVD's clamps).
+void rank_bounds(const tv_grid& g, int rank_cap, int rmax[3]) {
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  for (int d = 0; d < 3; ++d) {
+    int r = std::min(dims[d], std::min(64, TV_MAX_RANK));
+    if (rank_cap > 0) r = std::min(r, rank_cap);
+    rmax[d] = std::max(r, 1);
+  }
+}
+
+// Sizes of the regions of the assembly's workspace (see tv_aca_assemble):
+// fixed buffers, one column's compression scratch, U's arena at K columns of
+// the largest ranks, and the product workspace.
+struct AcaSizes {
+  size_t fixed, comp, uarena, prod, total;
+};
+AcaSizes aca_sizes(const tv_grid& g, int K, double htol, int rank_min, int rank_cap,
+                   tv_precision prec) {
+  AcaSizes z{};
+  const int64_t nv = (int64_t)g.n1 * g.n2 * g.n3, rows = (int64_t)g.q * nv, m = g.m;
+  Buffers B;
+  double *d1;
+  int64_t* i1;
+  double2* z2;
+  float2* f2;
+  B.alloc(&d1, (size_t)6 * m);
+  B.alloc(&d1, 1024);
+  B.alloc(&i1, 1024);
+  B.alloc(&d1, 4);
+  B.alloc(&i1, 2);
+  B.alloc(&i1, 1);
+  B.alloc(&z2, m);
+  B.alloc(&z2, (size_t)m * K);
+  B.alloc(&z2, K);
+  B.alloc(&z2, K);
+  B.alloc(&z2, rows);
+  B.alloc(&f2, K);
+  B.alloc(&f2, rows);
+  B.alloc(&f2, rows);
+  B.alloc(&f2, K);
+  z.fixed = (B.off + 255) & ~(size_t)255;
+  tv_grid g1 = g;
+  g1.m = 1;
+  tv_plan cp = nullptr;
+  if (tv_compress_begin(&g1, htol, rank_min, rank_cap, prec, &cp) == TV_OK) {
+    z.comp = compress_scratch_bytes(cp, g.q);
+    tv_plan_destroy(cp);
+  }
+  int rmax[3];
+  rank_bounds(g, rank_cap, rmax);
+  tv_grid gk = g;
+  gk.m = K;
+  z.uarena = plan_arena_bound(gk, rmax, prec);
+  // forward split partials (at most 8 by default) or the adjoint's partial
+  // inner products per (component, tile, column)
+  Tiling Ta;
+  make_tiling(g, 0, 2, &Ta);
+  z.prod = std::max((size_t)8 * 8 * rows, (size_t)8 * g.q * Ta.tiles * K);
+  z.total = z.fixed + z.comp + z.uarena + z.prod + 4 * 256;
+  return z;
+}
 
 // Host copies of U's Tucker factors in the layout of tv_plan_from_factors.
 struct HostFactors {
@@ -282,13 +345,14 @@ struct HostFactors {
 // Truncated HOSVD of one column (q tensors) on the device, factors appended
 // to the host copies.
 tv_status compress_column(const tv_grid& grid, const double2* d_x, double tol, int rank_min,
-                          int rank_cap, tv_precision prec, HostFactors& F, void* stream) {
+                          int rank_cap, tv_precision prec, HostFactors& F, void* cws,
+                          size_t cws_bytes, void* stream) {
   tv_grid g1 = grid;
   g1.m = 1;
   tv_plan cp = nullptr;
   tv_status s = tv_compress_begin(&g1, tol, rank_min, rank_cap, prec, &cp);
   if (s != TV_OK) return s;
-  s = tv_compress_append(cp, d_x, 1, stream);
+  s = tv_compress_append(cp, d_x, 1, cws, cws_bytes, stream);
   std::vector<int32_t> rk((size_t)3 * grid.q);
   if (s == TV_OK) s = tv_plan_export_factors(cp, rk.data(), nullptr, nullptr, nullptr, nullptr);
   if (s == TV_OK) {
@@ -316,12 +380,27 @@ tv_status compress_column(const tv_grid& grid, const double2* d_x, double tol, i
 
 using namespace tv;
 
+extern "C" tv_status tv_aca_assemble_workspace_bytes(const tv_grid* grid, int32_t max_terms,
+                                                     double tol, double hosvd_tol,
+                                                     int32_t rank_min, int32_t rank_cap,
+                                                     tv_precision precision, size_t* bytes) {
+  clear_error();
+  if (!grid || !bytes) return set_error(TV_ERR_INVALID_ARG, "NULL argument");
+  if (grid->n1 < 1 || grid->n2 < 1 || grid->n3 < 1 || grid->m < 1 || grid->q < 1)
+    return set_error(TV_ERR_SHAPE, "grid sizes and m must be >= 1");
+  if (max_terms < 1) return set_error(TV_ERR_INVALID_ARG, "max_terms must be >= 1");
+  const double htol = hosvd_tol > 0.0 ? hosvd_tol : 3.0 * tol;
+  *bytes = aca_sizes(*grid, max_terms, htol, rank_min, rank_cap, precision).total;
+  return TV_OK;
+}
+
 extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, int32_t basis,
                                      const double* pos, const double* ori, double tol,
                                      double hosvd_tol, int32_t rank_min, int32_t rank_cap,
-                                     int32_t max_terms, tv_precision precision, tv_plan* u_out,
-                                     double* v_out, int32_t* rc_out, int32_t* converged_out,
-                                     int64_t* pivots, double* s_out, void* stream) {
+                                     int32_t max_terms, tv_precision precision, void* ws,
+                                     size_t ws_bytes, tv_plan* u_out, double* v_out,
+                                     int32_t* rc_out, int32_t* converged_out, int64_t* pivots,
+                                     double* s_out, void* stream) {
   clear_error();
   if (!grid || !pos || !ori || !u_out || !v_out || !rc_out || !converged_out)
     return set_error(TV_ERR_INVALID_ARG, "NULL argument");
@@ -346,7 +425,22 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   const unsigned nb_rows = std::min<unsigned>(1024, blocks(rows));
   const unsigned nb_m = std::min<unsigned>(1024, blocks(m));
 
+  const AcaSizes Z = aca_sizes(g, K, htol, rank_min, rank_cap, precision);
+  if (!ws || ws_bytes < Z.total) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "assembly workspace of %zu bytes needed, %zu given", Z.total,
+             ws ? ws_bytes : (size_t)0);
+    return set_error(TV_ERR_WORKSPACE, buf);
+  }
+  if ((uintptr_t)ws % 256) return set_error(TV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  // regions: fixed buffers | column compression | U's arena | product workspace
+  char* const wsb = (char*)ws;
+  void* const cws = wsb + Z.fixed;
+  char* const uarena = wsb + Z.fixed + Z.comp;
+  void* const pws = uarena + Z.uarena;
   Buffers B;
+  B.base = wsb;
+  B.cap = Z.fixed;
   double *d_src, *d_bv, *d_scal;
   int64_t *d_bi, *d_row, *d_iscal;
   double2 *d_r, *d_V, *d_t, *d_b, *d_x;
@@ -363,8 +457,6 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   hipError_t e =
       hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_error(e, "source upload");
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
 
   // scalar results back to the host: (value, index) of an argmax, or a sum
   auto argmax = [&](const double2* x, int64_t n, int64_t skip, unsigned nb, double* v,
@@ -390,10 +482,9 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   };
 
   HostFactors F;
-  tv_plan U = nullptr;  // the compressed U of the steps so far
+  tv_plan U = nullptr;  // the compressed U of the steps so far (bound to uarena)
   auto fail = [&](tv_status r) {
     if (U) tv_plan_destroy(U);
-    hipFree(ws);
     return r;
   };
   int64_t i = 0;
@@ -434,19 +525,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     if (k > 0) {
       hipLaunchKernelGGL(conj_row_kernel, dim3(blocks(k)), dim3(kT), 0, st, d_V, m, j, k, d_w32);
       if ((s = last("conj_row_kernel")) != TV_OK) return fail(s);
-      size_t need = 0, need_a = 0;
-      if ((s = tv_workspace_bytes(U, 0, 1, &need)) != TV_OK ||
-          (s = tv_workspace_bytes(U, 1, 1, &need_a)) != TV_OK)
-        return fail(s);
-      need = std::max(need, need_a);
-      if (need > ws_bytes) {
-        hipFree(ws);
-        ws = nullptr;
-        e = hipMalloc(&ws, need);
-        if (e != hipSuccess) return fail(hip_error(e, "hipMalloc (product workspace)"));
-        ws_bytes = need;
-      }
-      if ((s = tv_matvec(U, d_w32, k, 1, d_u32, rows, ws, ws_bytes, stream)) != TV_OK)
+      if ((s = tv_matvec(U, d_w32, k, 1, d_u32, rows, pws, Z.prod, stream)) != TV_OK)
         return fail(s);
       hipLaunchKernelGGL(sub_kernel, dim3(blocks(rows)), dim3(kT), 0, st, d_x, d_u32, rows);
       if ((s = last("sub_kernel")) != TV_OK) return fail(s);
@@ -459,7 +538,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     if (k > 0) {
       hipLaunchKernelGGL(to_c64_kernel, dim3(blocks(rows)), dim3(kT), 0, st, d_x, d_x32, rows);
       if ((s = last("to_c64_kernel")) != TV_OK) return fail(s);
-      if ((s = tv_rmatvec(U, d_x32, rows, 1, d_a32, k, ws, ws_bytes, stream)) != TV_OK)
+      if ((s = tv_rmatvec(U, d_x32, rows, 1, d_a32, k, pws, Z.prod, stream)) != TV_OK)
         return fail(s);
       hipLaunchKernelGGL(vhy_kernel, dim3((unsigned)k), dim3(kT), 0, st, d_V, m, y, m, d_b);
       hipLaunchKernelGGL(cross_kernel, dim3(1), dim3(kT), 0, st, d_b, d_a32, k, d_scal + 2);
@@ -471,15 +550,22 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
       s_next += cross;
     }
     // U = [U HOSVD(x)] and V = [V y] (y is already in place)
-    if ((s = compress_column(g, d_x, htol, rank_min, rank_cap, precision, F, stream)) != TV_OK)
+    if ((s = compress_column(g, d_x, htol, rank_min, rank_cap, precision, F, cws, Z.comp,
+                             stream)) != TV_OK)
       return fail(s);
     tv_grid gk = g;
     gk.m = k + 1;
     tv_plan U2 = nullptr;
-    if ((s = tv_plan_from_factors(&gk, F.ranks.data(), F.cores.data(), F.u1.data(), F.u2.data(),
-                                  F.u3.data(), precision, &U2)) != TV_OK)
+    if ((s = plan_from_factors_ex(&gk, F.ranks.data(), F.cores.data(), F.u1.data(),
+                                  F.u2.data(), F.u3.data(), precision, false, &U2)) != TV_OK)
       return fail(s);
+    // the previous U is no longer read: its arena region takes the new one
     if (U) tv_plan_destroy(U);
+    U = nullptr;
+    if ((s = tv_plan_bind_arena(U2, uarena, Z.uarena, stream)) != TV_OK) {
+      tv_plan_destroy(U2);
+      return fail(s);
+    }
     U = U2;
     if (pivots) {
       pivots[2 * k] = i;
@@ -499,8 +585,6 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     if (!(xmax >= 0.0) || inext >= rows) break;
     i = inext;
   }
-  hipFree(ws);
-  ws = nullptr;
   if (rc == 0) {
     // the first row was zero: no term; report an empty approximation
     *rc_out = 0;
@@ -509,7 +593,18 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   }
   e = hipMemcpy(v_out, d_V, sizeof(double2) * (size_t)m * rc, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(hip_error(e, "V readback"));
-  *u_out = U;
+  // the returned plan is unbound: the caller binds it to an arena of its own
+  tv_plan Uout = nullptr;
+  {
+    tv_grid gk = g;
+    gk.m = rc;
+    s = tv_plan_from_factors(&gk, F.ranks.data(), F.cores.data(), F.u1.data(), F.u2.data(),
+                             F.u3.data(), precision, &Uout);
+    if (s != TV_OK) return fail(s);
+  }
+  tv_plan_destroy(U);
+  U = nullptr;
+  *u_out = Uout;
   *rc_out = rc;
   *converged_out = converged ? 1 : 0;
   return TV_OK;

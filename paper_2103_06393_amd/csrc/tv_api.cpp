@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "tv_internal.h"
 
@@ -97,48 +98,43 @@ static tv_status validate_grid(const tv_grid* g) {
   return TV_OK;
 }
 
-template <typename T>
-static tv_status dev_alloc(T** p, size_t count, size_t* total) {
-  *p = nullptr;
-  if (count == 0) return TV_OK;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return hip_error(e, "hipMalloc");
-  }
-  *total += count * sizeof(T);
-  return TV_OK;
+// Device arena of a plan: every packed array at a 256-byte aligned offset, in
+// a fixed order.  With base == nullptr only the size is computed; otherwise
+// the plan's device pointers are set into [base, base + size).
+static size_t arena_layout(tv_plan_s* p, char* base) {
+  size_t off = 0;
+  auto carve = [&](auto** ptr, size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    typedef typename std::remove_reference<decltype(**ptr)>::type T;
+    if (base) *ptr = bytes ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+  };
+  const HostPack& h = p->hp;
+  const size_t splits = (size_t)p->grid.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t);
+  carve(&p->d_meta, h.meta.size() * sizeof(TensorMeta));
+  carve(&p->d_cores, h.cores.size() * sizeof(float2));
+  carve(&p->d_u1t, h.u1t.size() * sizeof(float2));
+  carve(&p->d_u2t, h.u2t.size() * sizeof(float2));
+  carve(&p->d_u3t, h.u3t.size() * sizeof(float2));
+  carve(&p->d_apack, h.apack.size() * sizeof(float));
+  carve(&p->d_apack_bf, h.apack_bf.size() * sizeof(uint4));
+  carve(&p->d_apack_koff, p->apack_koff.size() * sizeof(int64_t));
+  carve(&p->d_split_f, splits);
+  carve(&p->d_split_a, splits);
+  carve(&p->d_apack4, h.a4.size() * sizeof(float));
+  carve(&p->d_apackh, h.ah.size() * sizeof(float));
+  return (off + 255) & ~(size_t)255;
 }
 
-template <typename T>
-static tv_status upload(T* d, const std::vector<T>& h) {
-  if (h.empty()) return TV_OK;
-  hipError_t e = hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
-  return e == hipSuccess ? TV_OK : hip_error(e, "hipMemcpy to device");
-}
-
-static void free_device(tv_plan_s* p) {
-  hipFree(p->d_meta);
-  hipFree(p->d_cores);
-  hipFree(p->d_u1t);
-  hipFree(p->d_u2t);
-  hipFree(p->d_u3t);
-  hipFree(p->d_apack);
-  hipFree(p->d_apack_bf);
-  hipFree(p->d_apack_koff);
-  hipFree(p->d_split_f);
-  hipFree(p->d_split_a);
-  hipFree(p->d_apack4);
-  hipFree(p->d_apackh);
-  p->d_apack4 = nullptr;
-  p->d_apackh = nullptr;
+static void clear_device_pointers(tv_plan_s* p) {
   p->d_meta = nullptr;
   p->d_cores = p->d_u1t = p->d_u2t = p->d_u3t = nullptr;
   p->d_apack = nullptr;
   p->d_apack_bf = nullptr;
   p->d_apack_koff = nullptr;
   p->d_split_f = p->d_split_a = nullptr;
-  p->device_bytes = 0;
+  p->d_apack4 = p->d_apackh = nullptr;
+  p->bound = false;
 }
 
 // Offsets of every tensor's factors in the concatenated host arrays.
@@ -197,30 +193,28 @@ static std::vector<int32_t> make_split(const tv_plan_s* p, int S) {
 }
 
 tv_status set_split(tv_plan_s* p, int op, int S) {
-  S = (int)std::max<int64_t>(1, std::min<int64_t>(S, p->grid.m));
-  std::vector<int32_t> sp = make_split(p, S);
-  int32_t* d = nullptr;
-  hipError_t e = hipMalloc((void**)&d, sp.size() * sizeof(int32_t));
-  if (e == hipSuccess)
-    e = hipMemcpy(d, sp.data(), sp.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    hipFree(d);
-    return hip_error(e, "split table upload");
+  S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(S, TV_SPLIT_MAX), p->grid.m));
+  if (p->bound) {
+    // the table of S + 1 entries per component, at a stride of TV_SPLIT_MAX + 1
+    std::vector<int32_t> sp = make_split(p, S);
+    std::vector<int32_t> tab((size_t)p->grid.q * (TV_SPLIT_MAX + 1), 0);
+    for (int k = 0; k < p->grid.q; ++k)
+      std::copy(sp.begin() + (size_t)k * (S + 1), sp.begin() + (size_t)(k + 1) * (S + 1),
+                tab.begin() + (size_t)k * (TV_SPLIT_MAX + 1));
+    hipError_t e = hipMemcpy(op == 0 ? p->d_split_f : p->d_split_a, tab.data(),
+                             tab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "split table upload");
   }
-  if (op == 0) {
-    hipFree(p->d_split_f);
-    p->d_split_f = d;
+  if (op == 0)
     p->split_f = S;
-  } else {
-    hipFree(p->d_split_a);
-    p->d_split_a = d;
+  else
     p->split_a = S;
-  }
   return TV_OK;
 }
 
-// Pack the FP64 host factors into the device layouts of the fused kernels.
-static tv_status pack_and_upload(tv_plan_s* p) {
+// Pack the FP64 host factors into the device layouts of the kernels (host
+// side; the device copy is made by tv_plan_bind_arena).
+static tv_status pack_plan(tv_plan_s* p) {
   const tv_grid& g = p->grid;
   const int64_t K = (int64_t)g.q * g.m;
   tv_status st = make_tiling(g, 0, nb_cap(p, 0), &p->tiling);
@@ -348,43 +342,56 @@ static tv_status pack_and_upload(tv_plan_s* p) {
   const int64_t base_f = (int64_t)g.q * p->tiling.tiles, base_a = (int64_t)g.q * p->tiling_a.tiles;
   int sf = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + base_f - 1) / base_f));
   int sa = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + base_a - 1) / base_a));
-  sf = (int)std::max<int64_t>(1, std::min<int64_t>(sf, g.m));
-  sa = (int)std::max<int64_t>(1, std::min<int64_t>(sa, g.m));
-  p->split_f = sf;
-  p->split_a = sa;
-  std::vector<int32_t> spf = make_split(p, sf), spa = make_split(p, sa);
+  p->split_f = (int)std::max<int64_t>(1, std::min<int64_t>(sf, g.m));
+  p->split_a = (int)std::max<int64_t>(1, std::min<int64_t>(sa, g.m));
 
-  free_device(p);
-  size_t tot = 0;
-  if ((st = dev_alloc(&p->d_meta, meta.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_cores, cores.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_u1t, u1t.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_u2t, u2t.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_u3t, u3t.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_apack, apack.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_apack_bf, apack_bf.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_apack_koff, p->apack_koff.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_split_f, spf.size(), &tot)) != TV_OK ||
-      (st = dev_alloc(&p->d_split_a, spa.size(), &tot)) != TV_OK) {
-    free_device(p);
-    return st;
-  }
-  p->device_bytes = tot;
-  if ((st = upload(p->d_meta, meta)) != TV_OK || (st = upload(p->d_cores, cores)) != TV_OK ||
-      (st = upload(p->d_u1t, u1t)) != TV_OK || (st = upload(p->d_u2t, u2t)) != TV_OK ||
-      (st = upload(p->d_u3t, u3t)) != TV_OK ||
-      (st = upload(p->d_apack, apack)) != TV_OK ||
-      (st = upload(p->d_apack_bf, apack_bf)) != TV_OK ||
-      (st = upload(p->d_apack_koff, p->apack_koff)) != TV_OK ||
-      (st = upload(p->d_split_f, spf)) != TV_OK || (st = upload(p->d_split_a, spa)) != TV_OK) {
-    free_device(p);
-    return st;
-  }
-  if (!bf && (st = dtg_pack(p, meta)) != TV_OK) {
-    free_device(p);
-    return st;
-  }
+  clear_device_pointers(p);
+  p->hp.meta = std::move(meta);
+  p->hp.cores = std::move(cores);
+  p->hp.u1t = std::move(u1t);
+  p->hp.u2t = std::move(u2t);
+  p->hp.u3t = std::move(u3t);
+  p->hp.apack = std::move(apack);
+  p->hp.apack_bf = std::move(apack_bf);
+  if (!bf && p->with_dtg && (st = dtg_pack(p, p->hp.meta)) != TV_OK) return st;
+  p->device_bytes = arena_layout(p, nullptr);
   p->finalized = true;
+  return TV_OK;
+}
+
+// Upload the packed plan into [arena, arena + bytes) (set-up call; waits for
+// the copies, then releases the host-side packed copies).
+static tv_status bind_arena(tv_plan_s* p, void* arena, size_t bytes, hipStream_t st) {
+  arena_layout(p, (char*)arena);
+  const HostPack& h = p->hp;
+  hipError_t e = hipSuccess;
+  auto put = [&](void* d, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(d, src, n, hipMemcpyHostToDevice, st);
+  };
+  put(p->d_meta, h.meta.data(), h.meta.size() * sizeof(TensorMeta));
+  put(p->d_cores, h.cores.data(), h.cores.size() * sizeof(float2));
+  put(p->d_u1t, h.u1t.data(), h.u1t.size() * sizeof(float2));
+  put(p->d_u2t, h.u2t.data(), h.u2t.size() * sizeof(float2));
+  put(p->d_u3t, h.u3t.data(), h.u3t.size() * sizeof(float2));
+  put(p->d_apack, h.apack.data(), h.apack.size() * sizeof(float));
+  put(p->d_apack_bf, h.apack_bf.data(), h.apack_bf.size() * sizeof(uint4));
+  put(p->d_apack_koff, p->apack_koff.data(), p->apack_koff.size() * sizeof(int64_t));
+  put(p->d_apack4, h.a4.data(), h.a4.size() * sizeof(float));
+  put(p->d_apackh, h.ah.data(), h.ah.size() * sizeof(float));
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    clear_device_pointers(p);
+    return hip_error(e, "plan upload");
+  }
+  (void)bytes;
+  p->bound = true;
+  tv_status s = set_split(p, 0, p->split_f);
+  if (s == TV_OK) s = set_split(p, 1, p->split_a);
+  if (s != TV_OK) {
+    clear_device_pointers(p);
+    return s;
+  }
+  p->hp = HostPack();
   return TV_OK;
 }
 
@@ -394,7 +401,7 @@ static bool all_finite(const double* v, size_t n) {
   return true;
 }
 
-tv_status finalize_plan(tv_plan_s* p) { return pack_and_upload(p); }
+tv_status finalize_plan(tv_plan_s* p) { return pack_plan(p); }
 
 tv_status validate_ranks_and_offsets(tv_plan_s* p) { return compute_offsets(p); }
 
@@ -424,6 +431,16 @@ const char* tv_last_error(void) { return g_last_error.c_str(); }
 tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const double* cores,
                                const double* u1, const double* u2, const double* u3,
                                tv_precision precision, tv_plan* out) {
+  return plan_from_factors_ex(grid, ranks, cores, u1, u2, u3, precision, true, out);
+}
+
+}  // extern "C"
+
+namespace tv {
+
+tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const double* cores,
+                               const double* u1, const double* u2, const double* u3,
+                               tv_precision precision, bool with_dtg, tv_plan* out) {
   clear_error();
   if (!out) return set_error(TV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -437,6 +454,7 @@ tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const 
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = *grid;
   p->precision = precision;
+  p->with_dtg = with_dtg;
   p->appended = grid->m;
   const int64_t K = (int64_t)grid->q * grid->m;
   p->ranks.assign(ranks, ranks + 3 * K);
@@ -458,7 +476,7 @@ tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const 
     delete p;
     return set_error(TV_ERR_NUMERIC, "non-finite factor values");
   }
-  if ((st = pack_and_upload(p)) != TV_OK) {
+  if ((st = pack_plan(p)) != TV_OK) {
     delete p;
     return st;
   }
@@ -466,12 +484,66 @@ tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const 
   return TV_OK;
 }
 
+size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision) {
+  // the packed U1 rows hold the larger row-block count of the default
+  // forward (8 blocks per wave) and adjoint (2) tilings
+  Tiling Tf, Ta;
+  if (make_tiling(g, 0, 8, &Tf) != TV_OK || make_tiling(g, 0, 2, &Ta) != TV_OK) return 0;
+  const int nbt = std::max(Tf.nbt, Ta.nbt);
+  const size_t K = (size_t)g.q * g.m;
+  const size_t r1 = rmax[0], r2 = rmax[1], r3 = rmax[2];
+  size_t off = 0;
+  auto carve = [&](size_t bytes) { off = ((off + 255) & ~(size_t)255) + bytes; };
+  carve(K * sizeof(TensorMeta));
+  carve(K * r1 * r2 * r3 * sizeof(float2));
+  carve(K * g.n1 * r1 * sizeof(float2));
+  carve(K * g.n2 * r2 * sizeof(float2));
+  carve(K * g.n3 * r3 * sizeof(float2));
+  if (precision == TV_PREC_BF16X3) {
+    carve(0);
+    carve(K * ((r1 + 7) / 8) * nbt * 128 * sizeof(uint4));
+  } else {
+    carve(K * r1 * nbt * 64 * sizeof(float));
+    carve(0);
+  }
+  carve((size_t)(g.q + 1) * sizeof(int64_t));
+  carve((size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
+  carve((size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
+  return (off + 255) & ~(size_t)255;
+}
+
+}  // namespace tv
+
+extern "C" {
+
 tv_status tv_plan_destroy(tv_plan p) {
   clear_error();
   if (!p) return TV_OK;
-  free_device(p);
-  delete p;
+  delete p;  // the device arena belongs to the caller
   return TV_OK;
+}
+
+tv_status tv_plan_required_bytes(tv_plan p, size_t* bytes) {
+  clear_error();
+  if (!p || !bytes) return set_error(TV_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
+  if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  *bytes = p->device_bytes;
+  return TV_OK;
+}
+
+tv_status tv_plan_bind_arena(tv_plan p, void* arena, size_t bytes, void* stream) {
+  clear_error();
+  if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
+  if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  if (p->bound) return set_error(TV_ERR_INVALID_ARG, "plan is already bound to an arena");
+  if (!arena) return set_error(TV_ERR_INVALID_ARG, "arena is NULL");
+  if ((uintptr_t)arena % 256) return set_error(TV_ERR_INVALID_ARG, "arena must be 256-byte aligned");
+  if (bytes < p->device_bytes) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "arena of %zu bytes needed, %zu given", p->device_bytes, bytes);
+    return set_error(TV_ERR_WORKSPACE, buf);
+  }
+  return bind_arena(p, arena, bytes, (hipStream_t)stream);
 }
 
 tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
@@ -553,6 +625,8 @@ static tv_status check_call(tv_plan p, const void* in, int64_t ldin, int64_t row
                             int op, const void* ws, size_t ws_bytes) {
   if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
   if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
+  if (!p->bound)
+    return set_error(TV_ERR_INVALID_ARG, "plan has no device arena (tv_plan_bind_arena)");
   if (!in || !out) return set_error(TV_ERR_INVALID_ARG, "vector pointers must be non-NULL");
   if (nrhs < 1) return set_error(TV_ERR_INVALID_ARG, "nrhs must be >= 1");
   if (ldin < rows_in || ldout < rows_out)

@@ -21,6 +21,8 @@
 //   [Yr | Yi] = [Tr Ti] [[Xr, Xi], [-Xi, Xr]]
 //   [Wr; Wi]  = [[Yr^T, -Yi^T], [Yi^T, Yr^T]] [Tr; -Ti].
 #include <algorithm>
+#include <cstdio>
+#include <type_traits>
 #include <climits>
 #include <new>
 
@@ -1049,18 +1051,40 @@ struct tv_batch_s {
   float* d_u1p = nullptr;
   float* d_u2p = nullptr;
   int2* d_tlist = nullptr;
+  // host copies awaiting tv_batch_bind_arena (the arena is the caller's)
+  std::vector<BTensor> h_bt;
+  std::vector<size_t> h_bt_off;      // first record of each plan in h_bt
+  std::vector<float> h_u1p, h_u2p;
+  std::vector<int2> h_tlist;
+  std::vector<BatchStatic> h_plans;
+  std::vector<int4> h_items, h_red_out;
+  std::vector<int> h_red_list;
+  bool bound = false;
+  size_t arena_bytes = 0;
 };
 
-static void batch_free(tv_batch_s* b) {
-  hipFree(b->d_plans);
-  hipFree(b->d_items);
-  hipFree(b->d_red_list);
-  hipFree(b->d_red_out);
-  hipFree(b->d_bt);
-  hipFree(b->d_u1p);
-  hipFree(b->d_u2p);
-  hipFree(b->d_tlist);
-  delete b;
+static void batch_free(tv_batch_s* b) { delete b; }
+
+// Device arena of a batch object: the per-plan records, work items,
+// reduction lists and packed operands at 256-byte aligned offsets.  With
+// base == nullptr only the size is computed.
+static size_t batch_layout(tv_batch_s* b, char* base) {
+  size_t off = 0;
+  auto carve = [&](auto** ptr, size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    typedef typename std::remove_reference<decltype(**ptr)>::type T;
+    if (base) *ptr = bytes ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+  };
+  carve(&b->d_plans, b->h_plans.size() * sizeof(BatchStatic));
+  carve(&b->d_items, b->h_items.size() * sizeof(int4));
+  carve(&b->d_red_list, b->h_red_list.size() * sizeof(int));
+  carve(&b->d_red_out, b->h_red_out.size() * sizeof(int4));
+  carve(&b->d_bt, b->h_bt.size() * sizeof(BTensor));
+  carve(&b->d_u1p, b->h_u1p.size() * sizeof(float));
+  carve(&b->d_u2p, b->h_u2p.size() * sizeof(float));
+  carve(&b->d_tlist, b->h_tlist.size() * sizeof(int2));
+  return (off + 255) & ~(size_t)255;
 }
 
 static size_t batch_hcache_offset(const tv_batch_s* b) {
@@ -1080,8 +1104,8 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   if (!plans || !nrhs) return set_error(TV_ERR_INVALID_ARG, "plans and nrhs must be non-NULL");
   if (op != 0 && op != 1) return set_error(TV_ERR_INVALID_ARG, "op must be 0 or 1");
   for (int c = 0; c < nplans; ++c) {
-    if (!plans[c] || !plans[c]->finalized)
-      return set_error(TV_ERR_INVALID_ARG, "every plan must be finalized");
+    if (!plans[c] || !plans[c]->finalized || !plans[c]->bound)
+      return set_error(TV_ERR_INVALID_ARG, "every plan must be finalized and bound to its arena");
     if (nrhs[c] < 1 || nrhs[c] > (1 << 20)) return set_error(TV_ERR_INVALID_ARG, "nrhs < 1");
     const tv_grid& g0 = plans[0]->grid;
     const tv_grid& g = plans[c]->grid;
@@ -1269,44 +1293,23 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   for (int c = 0; c < nplans; ++c)
     st[c] = BatchStatic{plans[c]->d_meta, plans[c]->d_cores, plans[c]->d_u1t, plans[c]->d_u2t,
                         plans[c]->d_u3t, plans[c]->grid.m, nullptr};
-  hipError_t e = hipSuccess;
   if (b->mfma) {
-    size_t nbt = 0;
-    for (int c = 0; c < nplans; ++c) nbt += bts[c].size();
-    e = hipMalloc((void**)&b->d_bt, nbt * sizeof(BTensor));
-    size_t o = 0;
-    for (int c = 0; c < nplans && e == hipSuccess; ++c) {
-      st[c].bt = b->d_bt + o;
-      e = hipMemcpy(b->d_bt + o, bts[c].data(), bts[c].size() * sizeof(BTensor),
-                    hipMemcpyHostToDevice);
-      o += bts[c].size();
+    for (int c = 0; c < nplans; ++c) {
+      b->h_bt_off.push_back(b->h_bt.size());
+      b->h_bt.insert(b->h_bt.end(), bts[c].begin(), bts[c].end());
     }
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_u1p, u1p.size() * sizeof(float));
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_u1p, u1p.data(), u1p.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_u2p, u2p.size() * sizeof(float));
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_u2p, u2p.data(), u2p.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_tlist, tlist.size() * sizeof(int2));
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_tlist, tlist.data(), tlist.size() * sizeof(int2), hipMemcpyHostToDevice);
+    b->h_u1p = std::move(u1p);
+    b->h_u2p = std::move(u2p);
+    b->h_tlist = std::move(tlist);
   }
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_plans, st.size() * sizeof(BatchStatic));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_items, items.size() * sizeof(int4));
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_plans, st.data(), st.size() * sizeof(BatchStatic), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
-  if (e == hipSuccess && op == 1) {
-    e = hipMalloc((void**)&b->d_red_list, red_list.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_red_out, red_out.size() * sizeof(int4));
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_red_list, red_list.data(), red_list.size() * sizeof(int),
-                    hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_red_out, red_out.data(), red_out.size() * sizeof(int4),
-                    hipMemcpyHostToDevice);
+  b->h_plans = std::move(st);
+  b->h_items = std::move(items);
+  if (op == 1) {
+    b->h_red_list = std::move(red_list);
+    b->h_red_out = std::move(red_out);
   }
+  b->arena_bytes = batch_layout(b, nullptr);
+  hipError_t e = hipSuccess;
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)b->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)b->lds);
@@ -1321,6 +1324,56 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
   }
   b->grid_blocks = std::max(1, std::min(b->nitems, cus * std::max(per_cu, 1)));
   *out = b;
+  return TV_OK;
+}
+
+tv_status tv_batch_required_bytes(tv_batch b, size_t* bytes) {
+  clear_error();
+  if (!b || !bytes) return set_error(TV_ERR_INVALID_ARG, "batch and bytes must be non-NULL");
+  *bytes = b->arena_bytes;
+  return TV_OK;
+}
+
+tv_status tv_batch_bind_arena(tv_batch b, void* arena, size_t bytes, void* stream) {
+  clear_error();
+  if (!b) return set_error(TV_ERR_INVALID_ARG, "batch is NULL");
+  if (b->bound) return set_error(TV_ERR_INVALID_ARG, "batch is already bound to an arena");
+  if (!arena) return set_error(TV_ERR_INVALID_ARG, "arena is NULL");
+  if ((uintptr_t)arena % 256) return set_error(TV_ERR_INVALID_ARG, "arena must be 256-byte aligned");
+  if (bytes < b->arena_bytes) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "arena of %zu bytes needed, %zu given", b->arena_bytes, bytes);
+    return set_error(TV_ERR_WORKSPACE, buf);
+  }
+  batch_layout(b, (char*)arena);
+  for (size_t c = 0; c < b->h_bt_off.size(); ++c) b->h_plans[c].bt = b->d_bt + b->h_bt_off[c];
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  auto put = [&](void* d, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(d, src, n, hipMemcpyHostToDevice, st);
+  };
+  put(b->d_plans, b->h_plans.data(), b->h_plans.size() * sizeof(BatchStatic));
+  put(b->d_items, b->h_items.data(), b->h_items.size() * sizeof(int4));
+  put(b->d_red_list, b->h_red_list.data(), b->h_red_list.size() * sizeof(int));
+  put(b->d_red_out, b->h_red_out.data(), b->h_red_out.size() * sizeof(int4));
+  put(b->d_bt, b->h_bt.data(), b->h_bt.size() * sizeof(BTensor));
+  put(b->d_u1p, b->h_u1p.data(), b->h_u1p.size() * sizeof(float));
+  put(b->d_u2p, b->h_u2p.data(), b->h_u2p.size() * sizeof(float));
+  put(b->d_tlist, b->h_tlist.data(), b->h_tlist.size() * sizeof(int2));
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_error(e, "batch upload");
+  b->bound = true;
+  b->h_bt.clear();
+  b->h_u1p.clear();
+  b->h_u2p.clear();
+  b->h_tlist.clear();
+  b->h_items.clear();
+  b->h_red_list.clear();
+  b->h_red_out.clear();
+  b->h_bt.shrink_to_fit();
+  b->h_u1p.shrink_to_fit();
+  b->h_u2p.shrink_to_fit();
+  b->h_items.shrink_to_fit();
   return TV_OK;
 }
 
@@ -1340,6 +1393,7 @@ tv_status tv_batch_run(tv_batch b, const void* const* in, const int64_t* ld_in, 
   clear_error();
   if (!b || !in || !ld_in || !out || !ld_out)
     return set_error(TV_ERR_INVALID_ARG, "NULL argument");
+  if (!b->bound) return set_error(TV_ERR_INVALID_ARG, "batch has no device arena (tv_batch_bind_arena)");
   size_t need = 0;
   tv_batch_workspace_bytes(b, &need);
   if (!ws || ws_bytes < need || (uintptr_t)ws % 16)

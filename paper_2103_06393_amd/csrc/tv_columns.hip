@@ -11,6 +11,8 @@
 // The magnetic coupling matrix (K operator of eq. 5) takes instead
 //   H(r) = curl(g p) = grad g x p = g (-i k0 - 1/R) Rh x p
 // on the same voxel bases.  `basis` bit 0 selects PWL, bit 1 the K operator.
+#include <algorithm>
+
 #include "tv_internal.h"
 
 namespace tv {
@@ -23,6 +25,7 @@ struct ColParams {
   int64_t ncols;
   const double* src;  // device [ncols][6]: position then orientation
   double2* out;
+  int64_t ldo;        // rows kernel: output stride between rows
 };
 
 __device__ inline void point_field(double x, double y, double z, const double* s, double k0,
@@ -73,7 +76,16 @@ __device__ inline void field(int op, double x, double y, double z, const double*
     point_hfield(x, y, z, s, k0, F);
 }
 
-__global__ void columns_kernel(ColParams P) {
+// Up to kChunk sources (and rows) passed by value in the kernel arguments,
+// so that the public entry points need no device staging buffer.
+constexpr int kChunk = 32;
+struct SrcChunk {
+  double src[kChunk * 6];
+  int64_t rows[kChunk];
+};
+
+template <bool ARGS>
+__global__ void columns_kernel(ColParams P, SrcChunk C) {
   const int64_t nv = (int64_t)P.n1 * P.n2 * P.n3;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
@@ -85,7 +97,7 @@ __global__ void columns_kernel(ColParams P) {
   const double cy = (i2 - 0.5 * (P.n2 - 1)) * P.h;
   const double cz = (i3 - 0.5 * (P.n3 - 1)) * P.h;
   __shared__ double s[6];
-  if (threadIdx.x < 6) s[threadIdx.x] = P.src[j * 6 + threadIdx.x];
+  if (threadIdx.x < 6) s[threadIdx.x] = ARGS ? C.src[j * 6 + threadIdx.x] : P.src[j * 6 + threadIdx.x];
   __syncthreads();
   if (P.basis == 0) {
     double2 E[3];
@@ -116,11 +128,12 @@ __global__ void columns_kernel(ColParams P) {
 // Row `row` of the coupling matrix, one source j per lane: the field of
 // every coil element at one voxel v and tensor index k (row = k nv + v, the
 // row order of Algorithm 1).  Same closed form and quadrature as the columns.
-__global__ void rows_kernel(ColParams P, const int64_t* rows) {
+template <bool ARGS>
+__global__ void rows_kernel(ColParams P, const int64_t* rows, SrcChunk C) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= P.ncols) return;
   const int64_t nv = (int64_t)P.n1 * P.n2 * P.n3;
-  const int64_t row = rows[blockIdx.y];
+  const int64_t row = ARGS ? C.rows[blockIdx.y] : rows[blockIdx.y];
   const int k = (int)(row / nv);
   const int64_t v = row - (int64_t)k * nv;
   const int i1 = (int)(v % P.n1);
@@ -130,8 +143,8 @@ __global__ void rows_kernel(ColParams P, const int64_t* rows) {
   const double cy = (i2 - 0.5 * (P.n2 - 1)) * P.h;
   const double cz = (i3 - 0.5 * (P.n3 - 1)) * P.h;
   double s[6];
-  for (int c = 0; c < 6; ++c) s[c] = P.src[j * 6 + c];
-  double2* out = P.out + (int64_t)blockIdx.y * P.ncols + j;
+  for (int c = 0; c < 6; ++c) s[c] = ARGS ? C.src[j * 6 + c] : P.src[j * 6 + c];
+  double2* out = P.out + (int64_t)blockIdx.y * P.ldo + j;
   if (P.basis == 0) {
     double2 E[3];
     field(P.op, cx, cy, cz, s, P.k0, E);
@@ -179,9 +192,10 @@ tv_status launch_dipole_columns(int n1, int n2, int n3, double h, double k0, int
                                 int64_t ncols, const double* d_src, double2* out,
                                 hipStream_t st) {
   const int64_t nv = (int64_t)n1 * n2 * n3;
-  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, ncols, d_src, out};
-  hipLaunchKernelGGL(columns_kernel, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
-                     dim3(256), 0, st, P);
+  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, ncols, d_src, out, 0};
+  SrcChunk C{};
+  hipLaunchKernelGGL(columns_kernel<false>, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
+                     dim3(256), 0, st, P, C);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? TV_OK : hip_error(e, "columns kernel launch");
 }
@@ -189,9 +203,10 @@ tv_status launch_dipole_columns(int n1, int n2, int n3, double h, double k0, int
 tv_status launch_dipole_rows(int n1, int n2, int n3, double h, double k0, int basis,
                              int64_t nsrc, const double* d_src, int64_t nrows,
                              const int64_t* d_rows, double2* out, hipStream_t st) {
-  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, nsrc, d_src, out};
-  hipLaunchKernelGGL(rows_kernel, dim3((unsigned)((nsrc + 255) / 256), (unsigned)nrows),
-                     dim3(256), 0, st, P, d_rows);
+  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, nsrc, d_src, out, nsrc};
+  SrcChunk C{};
+  hipLaunchKernelGGL(rows_kernel<false>, dim3((unsigned)((nsrc + 255) / 256), (unsigned)nrows),
+                     dim3(256), 0, st, P, d_rows, C);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? TV_OK : hip_error(e, "rows kernel launch");
 }
@@ -219,21 +234,24 @@ extern "C" tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h
   tv_status s = stage_sources(n1, n2, n3, h, nsrc, pos, ori, src);
   if (s != TV_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  double* d_src = nullptr;
-  int64_t* d_rows = nullptr;
-  hipError_t e = hipMalloc((void**)&d_src, src.size() * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&d_rows, (size_t)nrows * sizeof(int64_t));
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_rows, rows, (size_t)nrows * sizeof(int64_t), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    s = launch_dipole_rows(n1, n2, n3, h, k0, basis, nsrc, d_src, nrows, d_rows, (double2*)out, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFree(d_src);
-  hipFree(d_rows);
-  if (e != hipSuccess) return hip_error(e, "tv_dipole_rows");
-  return s;
+  // sources and rows in chunks of kChunk through the kernel arguments
+  for (int64_t r0 = 0; r0 < nrows; r0 += kChunk) {
+    const int nr = (int)std::min<int64_t>(kChunk, nrows - r0);
+    for (int64_t j0 = 0; j0 < nsrc; j0 += kChunk) {
+      const int nj = (int)std::min<int64_t>(kChunk, nsrc - j0);
+      SrcChunk C{};
+      std::copy(src.begin() + 6 * j0, src.begin() + 6 * (j0 + nj), C.src);
+      std::copy(rows + r0, rows + r0 + nr, C.rows);
+      ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, nj, nullptr,
+                  (double2*)out + r0 * nsrc + j0, nsrc};
+      hipLaunchKernelGGL(rows_kernel<true>, dim3(1, (unsigned)nr), dim3(kChunk), 0, st, P,
+                         (const int64_t*)nullptr, C);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_error(e, "rows kernel launch");
+    }
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  return e == hipSuccess ? TV_OK : hip_error(e, "tv_dipole_rows");
 }
 
 extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h, double k0,
@@ -252,23 +270,20 @@ extern "C" tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, doubl
   std::vector<double> src;
   tv_status s0 = stage_sources(n1, n2, n3, h, ncols, pos, ori, src);
   if (s0 != TV_OK) return s0;
-  double* d_src = nullptr;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMallocAsync((void**)&d_src, src.size() * sizeof(double), st);
-  if (e != hipSuccess) return hip_error(e, "hipMallocAsync");
-  e = hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) {
-    hipFreeAsync(d_src, st);
-    return hip_error(e, "hipMemcpyAsync");
+  // sources in chunks of kChunk through the kernel arguments
+  for (int64_t j0 = 0; j0 < ncols; j0 += kChunk) {
+    const int nj = (int)std::min<int64_t>(kChunk, ncols - j0);
+    SrcChunk C{};
+    std::copy(src.begin() + 6 * j0, src.begin() + 6 * (j0 + nj), C.src);
+    ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, nj, nullptr,
+                (double2*)out + j0 * ((basis & 1) ? 12 : 3) * nv, 0};
+    hipLaunchKernelGGL(columns_kernel<true>, dim3((unsigned)((nv + 255) / 256), (unsigned)nj),
+                       dim3(256), 0, st, P, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "columns kernel launch");
   }
-  ColParams P{n1, n2, n3, h, k0, basis & 1, basis >> 1, ncols, d_src, (double2*)out};
-  hipLaunchKernelGGL(columns_kernel, dim3((unsigned)((nv + 255) / 256), (unsigned)ncols),
-                     dim3(256), 0, st, P);
-  e = hipGetLastError();
-  hipFreeAsync(d_src, st);
-  // the host staging vector must outlive the async copy
-  hipError_t e2 = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_error(e, "columns kernel launch");
-  if (e2 != hipSuccess) return hip_error(e2, "hipStreamSynchronize");
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   return TV_OK;
 }

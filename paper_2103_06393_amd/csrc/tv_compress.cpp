@@ -12,6 +12,7 @@
 // clamp to [rank_min, min(rank_cap, n, TV_MAX_RANK)].
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -32,24 +33,60 @@ tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, dou
 tv_status finalize_plan(tv_plan_s* p);
 tv_status validate_ranks_and_offsets(tv_plan_s* p);
 
-// Device scratch of one append call, released on every exit path.
+// Device scratch of one append call, carved from the caller's workspace
+// (256-byte aligned pieces, in call order).  With base == nullptr only the
+// size is accumulated.
 struct DevScratch {
-  std::vector<void*> ptrs;
-  ~DevScratch() {
-    for (void* q : ptrs) hipFree(q);
-  }
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
   template <typename T>
   tv_status alloc(T** p, size_t count) {
-    *p = nullptr;
-    hipError_t e = hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
-    if (e != hipSuccess) {
-      *p = nullptr;
-      return hip_error(e, "hipMalloc (compression scratch)");
-    }
-    ptrs.push_back(*p);
+    off = (off + 255) & ~(size_t)255;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (base && off + bytes > cap) return set_error(TV_ERR_WORKSPACE, "compression workspace");
+    *p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
     return TV_OK;
   }
 };
+
+// Upper bound of the scratch of one append call of T tensors: Gram
+// matrices, eigenpairs (and the subspace solver's work arrays for modes
+// longer than 64), factors at the largest rank a mode can keep, and the
+// partial projections and cores of the core computation.
+size_t compress_scratch_bytes(const tv_plan_s* p, int T) {
+  const tv_grid& g = p->grid;
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  const int nmax = std::max(g.n1, std::max(g.n2, g.n3));
+  int rmax[3];
+  for (int d = 0; d < 3; ++d) {
+    int r = std::min(dims[d], std::min(64, TV_MAX_RANK));
+    if (p->rank_cap > 0) r = std::min(r, (int)p->rank_cap);
+    rmax[d] = std::max(r, 1);
+  }
+  DevScratch ds;
+  double2* z2;
+  double* z1;
+  int64_t* zi;
+  int* zk;
+  ds.alloc(&z2, (size_t)3 * T * nmax * nmax);
+  for (int d = 0; d < 3; ++d) {
+    const int n = dims[d], L = n <= 64 ? n : 64;
+    ds.alloc(&z2, (size_t)T * n * L);
+    ds.alloc(&z1, (size_t)T * L);
+    if (n > 64) {
+      ds.alloc(&z1, (size_t)T);
+      ds.alloc(&z2, (size_t)T * (3 * (size_t)n * 64 + 64 * 64));
+    }
+  }
+  for (int d = 0; d < 3; ++d) ds.alloc(&z2, (size_t)T * dims[d] * rmax[d]);
+  ds.alloc(&z2, (size_t)T * rmax[0] * g.n2 * g.n3);
+  ds.alloc(&z2, (size_t)T * rmax[0] * rmax[1] * g.n3);
+  ds.alloc(&z2, (size_t)T * rmax[0] * rmax[1] * rmax[2]);
+  ds.alloc(&zi, (size_t)4 * T);
+  ds.alloc(&zk, (size_t)3 * T);
+  return (ds.off + 255) & ~(size_t)255;
+}
 
 // Rank of one mode from its leading eigenvalues lam (descending, L of the
 // n_full eigenvalues of the Gram matrix) and the Gram trace: the tail of
@@ -119,7 +156,17 @@ tv_status tv_compress_begin(const tv_grid* grid, double tol, int32_t rank_min, i
   return TV_OK;
 }
 
-tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* stream) {
+tv_status tv_compress_workspace_bytes(tv_plan p, int64_t ncols, size_t* bytes) {
+  clear_error();
+  if (!p || !bytes) return set_error(TV_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
+  if (ncols < 0 || ncols * p->grid.q > 65535)
+    return set_error(TV_ERR_NOT_SUPPORTED, "at most 65535 tensors per append call");
+  *bytes = ncols ? compress_scratch_bytes(p, (int)(ncols * p->grid.q)) : 0;
+  return TV_OK;
+}
+
+tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* ws,
+                             size_t ws_bytes, void* stream) {
   clear_error();
   if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
   if (p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is already finalized");
@@ -136,7 +183,17 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* s
   const int T = (int)(ncols * g.q);
   hipStream_t st = (hipStream_t)stream;
   const double2* A = (const double2*)cols;
+  const size_t need = compress_scratch_bytes(p, T);
+  if (!ws || ws_bytes < need) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "compression workspace of %zu bytes needed, %zu given", need,
+             ws ? ws_bytes : (size_t)0);
+    return set_error(TV_ERR_WORKSPACE, buf);
+  }
+  if ((uintptr_t)ws % 256) return set_error(TV_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   DevScratch ds;
+  ds.base = (char*)ws;
+  ds.cap = ws_bytes;
   tv_status s;
 
   // 1. Gram matrices S_d (mode-major) and their (leading) eigenpairs: the

@@ -567,17 +567,7 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
           }
       }
     }
-  hipFree(p->d_apack4);
-  p->d_apack4 = nullptr;
-  hipError_t e = hipMalloc((void**)&p->d_apack4, a4.size() * sizeof(float));
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_apack4, a4.data(), a4.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    hipFree(p->d_apack4);
-    p->d_apack4 = nullptr;
-    return hip_error(e, "decompress-then-GEMM operand upload");
-  }
-  p->device_bytes += a4.size() * sizeof(float);
+  p->hp.a4 = std::move(a4);
   int64_t rp = 0;
   for (int k = 0; k < g.q; ++k) rp += p->dtg_rpad[k];
   p->dtg_rows = rp;
@@ -612,23 +602,13 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
         }
       }
     }
-  hipFree(p->d_apackh);
-  p->d_apackh = nullptr;
-  e = hipMalloc((void**)&p->d_apackh, ah.size() * sizeof(float));
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_apackh, ah.data(), ah.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    hipFree(p->d_apackh);
-    p->d_apackh = nullptr;
-    return hip_error(e, "adjoint GEMM operand upload");
-  }
-  p->device_bytes += ah.size() * sizeof(float);
+  p->hp.ah = std::move(ah);
+  p->dtg_packed = true;
   return TV_OK;
 }
 
 bool dtg_supported(const tv_plan_s* p) {
-  return p->d_apack4 != nullptr && p->d_apackh != nullptr && p->grid.q <= DTG_MAXQ &&
-         p->precision == TV_PREC_FP32;
+  return p->dtg_packed && p->grid.q <= DTG_MAXQ && p->precision == TV_PREC_FP32;
 }
 
 // 32-column blocks of one slab's B rows (a multiple of the widest tile)

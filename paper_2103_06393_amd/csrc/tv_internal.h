@@ -33,6 +33,18 @@ struct Tiling {
   int64_t tiles;   // per component
 };
 
+// Host-side packed form of a plan, kept from packing until the plan is bound
+// to its device arena.
+struct HostPack {
+  std::vector<TensorMeta> meta;
+  std::vector<float2> cores, u1t, u2t, u3t;
+  std::vector<float> apack, a4, ah;
+  std::vector<uint4> apack_bf;
+};
+
+// column-split tables hold up to this many splits per component
+constexpr int TV_SPLIT_MAX = 64;
+
 }  // namespace tv
 
 struct tv_plan_s {
@@ -70,7 +82,9 @@ struct tv_plan_s {
   bool kernel_ws[2] = {true, true};  // warp-specialised kernel (when the tile allows)
   int32_t* d_split_f = nullptr;    // [q][split+1] first column per split
   int32_t* d_split_a = nullptr;
-  size_t device_bytes = 0;
+  size_t device_bytes = 0;          // bytes the plan needs in its device arena
+  tv::HostPack hp;                   // packed data awaiting tv_plan_bind_arena
+  bool bound = false;                // device pointers point into the caller's arena
   // decompress-then-GEMM form of the forward product (large grids)
   float* d_apack4 = nullptr;       // stacked U1 in 4-k-step groups (FP32 plans)
   int dtg_nbtp = 0;                // 32-row blocks per k-step, padded to the GEMM tile
@@ -80,6 +94,8 @@ struct tv_plan_s {
   float* d_apackh = nullptr;       // adjoint operand: U1^* real-embedded, 4-voxel-row groups
   std::vector<int> dtg_mbh;        // 32-row blocks of the adjoint operand per component
   std::vector<int64_t> dtg_ahoff;  // float offset of component k in d_apackh
+  bool with_dtg = true;             // pack the GEMM operands (FP32 plans)
+  bool dtg_packed = false;          // the GEMM operands are part of the plan
   bool use_dtg[2] = {false, false};
   int dtg_s3 = 1 << 30;            // i3 values per slab of B (forward)
   int dtg_s3_a = 1 << 30;          // i3 values per slab of B (adjoint)
@@ -130,6 +146,15 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
                              hipStream_t st);
 tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,
                              hipStream_t st);
+// plan creation without the decompress-then-GEMM operands (plans rebuilt
+// inside Algorithm 3), and an upper bound of the device arena of a plan of
+// grid g whose ranks are at most rmax (that packing)
+tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const double* cores,
+                               const double* u1, const double* u2, const double* u3,
+                               tv_precision precision, bool with_dtg, tv_plan* out);
+size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision);
+// compression scratch of one append call of T tensors (tv_compress.cpp)
+size_t compress_scratch_bytes(const tv_plan_s* p, int T);
 // point-current fields (tv_columns.hip): sources as device [n][6]
 tv_status stage_sources(int n1, int n2, int n3, double h, int64_t n, const double* pos,
                         const double* ori, std::vector<double>& src);

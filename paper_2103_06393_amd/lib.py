@@ -92,7 +92,13 @@ _tv_dipole_columns = _sig("tv_dipole_columns",
 _tv_compress_begin = _sig("tv_compress_begin",
                           [ctypes.POINTER(tv_grid), c_dbl, c_i32, c_i32,
                            ctypes.c_int, ctypes.POINTER(c_vp)])
-_tv_compress_append = _sig("tv_compress_append", [c_vp, c_vp, c_i64, c_vp])
+_tv_compress_append = _sig("tv_compress_append", [c_vp, c_vp, c_i64, c_vp, c_sz, c_vp])
+_tv_compress_workspace_bytes = _sig("tv_compress_workspace_bytes",
+                                    [c_vp, c_i64, ctypes.POINTER(c_sz)])
+_tv_plan_required_bytes = _sig("tv_plan_required_bytes", [c_vp, ctypes.POINTER(c_sz)])
+_tv_plan_bind_arena = _sig("tv_plan_bind_arena", [c_vp, c_vp, c_sz, c_vp])
+_tv_batch_required_bytes = _sig("tv_batch_required_bytes", [c_vp, ctypes.POINTER(c_sz)])
+_tv_batch_bind_arena = _sig("tv_batch_bind_arena", [c_vp, c_vp, c_sz, c_vp])
 _tv_plan_finalize = _sig("tv_plan_finalize", [c_vp, c_vp])
 _tv_compress_discarded = _sig("tv_compress_discarded", [c_vp, _dp])
 _tv_autotune = _sig("tv_autotune", [c_vp, c_i32, ctypes.c_char_p, c_vp])
@@ -118,19 +124,26 @@ _tv_dipole_rows = _sig("tv_dipole_rows", [c_i32, c_i32, c_i32, c_dbl, c_dbl, c_i
                                           ctypes.POINTER(c_i64), c_vp, c_vp])
 _tv_aca_assemble = _sig("tv_aca_assemble",
                         [ctypes.POINTER(tv_grid), c_dbl, c_dbl, c_i32, _dp, _dp,
-                         c_dbl, c_dbl, c_i32, c_i32, c_i32, ctypes.c_int,
+                         c_dbl, c_dbl, c_i32, c_i32, c_i32, ctypes.c_int, c_vp, c_sz,
                          ctypes.POINTER(c_vp), _dp, _ip, _ip,
                          ctypes.POINTER(c_i64), _dp, c_vp])
+_tv_aca_assemble_workspace_bytes = _sig("tv_aca_assemble_workspace_bytes",
+                                        [ctypes.POINTER(tv_grid), c_i32, c_dbl, c_dbl, c_i32,
+                                         c_i32, ctypes.c_int, ctypes.POINTER(c_sz)])
 _tv_status_string = _sig("tv_status_string", [ctypes.c_int], ctypes.c_char_p)
 _tv_last_error = _sig("tv_last_error", [], ctypes.c_char_p)
 
-EXPORTED = ("tv_plan_from_factors", "tv_plan_destroy", "tv_plan_info",
+EXPORTED = ("tv_plan_from_factors", "tv_plan_required_bytes", "tv_plan_bind_arena",
+            "tv_plan_destroy", "tv_plan_info",
             "tv_plan_export_factors", "tv_workspace_bytes", "tv_matvec",
             "tv_rmatvec", "tv_dipole_columns", "tv_compress_begin",
-            "tv_compress_append", "tv_plan_finalize", "tv_compress_discarded",
-            "tv_autotune", "tv_plan_configure", "tv_batch_create", "tv_batch_workspace_bytes", "tv_batch_run",
+            "tv_compress_workspace_bytes", "tv_compress_append", "tv_plan_finalize",
+            "tv_compress_discarded",
+            "tv_autotune", "tv_plan_configure", "tv_batch_create", "tv_batch_required_bytes", "tv_batch_bind_arena",
+            "tv_batch_workspace_bytes", "tv_batch_run",
             "tv_batch_destroy", "tv_aca_workspace_bytes", "tv_aca_matvec",
-            "tv_aca_rmatvec", "tv_dipole_rows", "tv_aca_assemble",
+            "tv_aca_rmatvec", "tv_dipole_rows", "tv_aca_assemble_workspace_bytes",
+            "tv_aca_assemble",
             "tv_status_string", "tv_last_error")
 TV_BATCH_MAX_PLANS = 32
 
@@ -239,9 +252,36 @@ def tv_compress_begin(grid: tv_grid, tol: float, rank_min: int, rank_cap: int,
     return h.value
 
 
-def tv_compress_append(plan, cols_ptr, ncols, stream):
-    _check(_tv_compress_append(plan, cols_ptr, int(ncols), stream),
+def tv_compress_workspace_bytes(plan, ncols) -> int:
+    n = c_sz()
+    _check(_tv_compress_workspace_bytes(plan, int(ncols), ctypes.byref(n)),
+           "tv_compress_workspace_bytes")
+    return n.value
+
+
+def tv_compress_append(plan, cols_ptr, ncols, ws_ptr, ws_bytes, stream):
+    _check(_tv_compress_append(plan, cols_ptr, int(ncols), ws_ptr, int(ws_bytes), stream),
            "tv_compress_append")
+
+
+def tv_plan_required_bytes(plan) -> int:
+    n = c_sz()
+    _check(_tv_plan_required_bytes(plan, ctypes.byref(n)), "tv_plan_required_bytes")
+    return n.value
+
+
+def tv_plan_bind_arena(plan, arena_ptr, nbytes, stream):
+    _check(_tv_plan_bind_arena(plan, arena_ptr, int(nbytes), stream), "tv_plan_bind_arena")
+
+
+def tv_batch_required_bytes(batch) -> int:
+    n = c_sz()
+    _check(_tv_batch_required_bytes(batch, ctypes.byref(n)), "tv_batch_required_bytes")
+    return n.value
+
+
+def tv_batch_bind_arena(batch, arena_ptr, nbytes, stream):
+    _check(_tv_batch_bind_arena(batch, arena_ptr, int(nbytes), stream), "tv_batch_bind_arena")
 
 
 def tv_plan_finalize(plan, stream):
@@ -328,11 +368,24 @@ def tv_dipole_rows(n1, n2, n3, h, k0, basis, pos, ori, rows, out_ptr, stream):
                            out_ptr, stream), "tv_dipole_rows")
 
 
+def tv_aca_assemble_workspace_bytes(grid: tv_grid, max_terms, tol, hosvd_tol=0.0,
+                                    rank_min=1, rank_cap=0,
+                                    precision=TV_PREC_FP32) -> int:
+    n = c_sz()
+    _check(_tv_aca_assemble_workspace_bytes(ctypes.byref(grid), int(max_terms), float(tol),
+                                            float(hosvd_tol), int(rank_min), int(rank_cap),
+                                            int(precision), ctypes.byref(n)),
+           "tv_aca_assemble_workspace_bytes")
+    return n.value
+
+
 def tv_aca_assemble(grid: tv_grid, h, k0, basis, pos, ori, tol, hosvd_tol=0.0,
                     rank_min=1, rank_cap=0, max_terms=64,
-                    precision=TV_PREC_FP32, stream=None):
-    """Algorithm 3 on the device.  Returns (plan handle, V complex128
-    (m x r_c), r_c, converged, pivots int64 (r_c x 2), s float64 (r_c,))."""
+                    precision=TV_PREC_FP32, stream=None, ws_ptr=None, ws_bytes=0):
+    """Algorithm 3 on the device, with the caller's device workspace
+    (tv_aca_assemble_workspace_bytes).  Returns (plan handle (unbound),
+    V complex128 (m x r_c), r_c, converged, pivots int64 (r_c x 2),
+    s float64 (r_c,))."""
     pos = np.ascontiguousarray(pos, np.float64)
     ori = np.ascontiguousarray(ori, np.float64)
     m, K = int(grid.m), int(max_terms)
@@ -345,6 +398,7 @@ def tv_aca_assemble(grid: tv_grid, h, k0, basis, pos, ori, tol, hosvd_tol=0.0,
     _check(_tv_aca_assemble(ctypes.byref(grid), float(h), float(k0), int(basis),
                             _dptr(pos), _dptr(ori), float(tol), float(hosvd_tol),
                             int(rank_min), int(rank_cap), K, int(precision),
+                            ws_ptr, int(ws_bytes),
                             ctypes.byref(h_plan), _dptr(V), ctypes.byref(rc),
                             ctypes.byref(conv),
                             piv.ctypes.data_as(ctypes.POINTER(c_i64)), _dptr(sv),

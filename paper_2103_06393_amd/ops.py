@@ -1,9 +1,9 @@
 """Torch-facing wrappers over the C ABI.
 
-``TuckerPlan`` holds a device plan and runs Y = Z X / X = Z^* Y on torch
-complex64 CUDA tensors through ``tv_matvec`` / ``tv_rmatvec``; outputs and
-workspaces come from torch's caching allocator, the library itself never
-allocates on these calls.  ``TuckerMatvec`` is the autograd Function whose
+``TuckerPlan`` holds a plan and runs Y = Z X / X = Z^* Y on torch complex64
+CUDA tensors through ``tv_matvec`` / ``tv_rmatvec``; the plan's device arena,
+compression scratch, outputs and workspaces all come from torch's caching
+allocator: the library itself never allocates device memory for them.  ``TuckerMatvec`` is the autograd Function whose
 backward is the adjoint kernel: for the linear map y = Z x the
 vector-Jacobian product is Z^* g (the conjugate transpose needed by the GMT
 cost gradient, Sec. II.A.2).
@@ -60,9 +60,38 @@ def _check_out(out: torch.Tensor, p: int, rows: int, device) -> torch.Tensor:
     return buf.view(p, rows)
 
 
+def _device_bytes(n: int) -> torch.Tensor:
+    """A device buffer of at least n bytes (torch's allocator aligns to 512)."""
+    return torch.empty(max(int(n), 256), dtype=torch.uint8, device="cuda")
+
+
+def batch_create(handles, op: int, nrhs):
+    """tv_batch_create plus its device arena: returns (batch handle, arena);
+    the arena tensor must outlive the batch."""
+    b = lib.tv_batch_create(handles, op, nrhs)
+    try:
+        nb = lib.tv_batch_required_bytes(b)
+        arena = _device_bytes(nb)
+        lib.tv_batch_bind_arena(b, arena.data_ptr(), arena.numel(), _stream())
+    except Exception:
+        lib.tv_batch_destroy(b)
+        raise
+    return b, arena
+
+
 class TuckerPlan:
     def __init__(self, handle: int):
         self.handle = handle
+        # the plan's packed factors live in a device arena from torch
+        try:
+            nb = lib.tv_plan_required_bytes(handle)
+            self._arena = _device_bytes(nb)
+            lib.tv_plan_bind_arena(handle, self._arena.data_ptr(), self._arena.numel(),
+                                   _stream())
+        except Exception:
+            lib.tv_plan_destroy(handle)
+            self.handle = 0
+            raise
         g = self.info.grid
         self.dims = (g.n1, g.n2, g.n3)
         self.q = g.q
@@ -101,13 +130,15 @@ class TuckerPlan:
                 chunk = max(1, min(m, (2 << 30) // (16 * q * nv), 65535 // q))
             buf = torch.empty(chunk * q * nv * 2, dtype=torch.float64,
                               device="cuda")
+            ws = _device_bytes(lib.tv_compress_workspace_bytes(h_plan, chunk))
             st = _stream()
             for j0 in range(0, m, chunk):
                 n = min(chunk, m - j0)
                 lib.tv_dipole_columns(*dims, h, k0, basis, pos[j0:j0 + n],
                                       ori[j0:j0 + n], buf.data_ptr(), st)
-                lib.tv_compress_append(h_plan, buf.data_ptr(), n, st)
-            del buf
+                lib.tv_compress_append(h_plan, buf.data_ptr(), n, ws.data_ptr(),
+                                       ws.numel(), st)
+            del buf, ws
             lib.tv_plan_finalize(h_plan, st)
         except Exception:
             lib.tv_plan_destroy(h_plan)
@@ -229,9 +260,12 @@ def aca_assemble(wl_dims, h, k0, basis, pos, ori, tol, hosvd_tol=0.0,
     and a dict with r_c, convergence, the pivots and the norm estimates."""
     q = 12 if basis & 1 else 3
     grid = lib.make_grid(*wl_dims, q, int(pos.shape[0]))
+    ws = _device_bytes(lib.tv_aca_assemble_workspace_bytes(
+        grid, max_terms, tol, hosvd_tol, rank_min, rank_cap, precision))
     h_plan, V, rc, conv, piv, s = lib.tv_aca_assemble(
         grid, h, k0, basis, pos, ori, tol, hosvd_tol, rank_min, rank_cap,
-        max_terms, precision, _stream())
+        max_terms, precision, _stream(), ws.data_ptr(), ws.numel())
+    del ws
     plan = TuckerPlan(h_plan)
     op = AcaTuckerOperator(plan, torch.from_numpy(V.astype(np.complex64)).cuda())
     return op, {"rc": rc, "converged": conv, "pivots": piv, "s": s, "V": V}

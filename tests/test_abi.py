@@ -106,3 +106,71 @@ def test_aca_entry_points_reject_null_plan():
         with pytest.raises(lib.TuckVsieError) as e:
             f(None, None, 1, 1, None, 1, 1, None, 1, None, 0, None)
         assert e.value.status == -1 and "plan is NULL" in str(e.value)
+
+
+def test_plan_arena_is_the_callers():
+    """Plans are packed on the host; their device memory is an arena the
+    caller binds.  A short or misaligned arena is refused before any device
+    work, and an unbound plan refuses products."""
+    from paper_2103_06393_amd import lib
+    dims = (8, 6, 5)
+    g = lib.make_grid(*dims, 3, 2)
+    ranks = np.full((6, 3), 2, np.int32)
+    h = lib.tv_plan_from_factors(g, ranks, *_factors(dims, ranks))
+    try:
+        need = lib.tv_plan_required_bytes(h)
+        assert need > 0 and need % 256 == 0
+        assert lib.tv_plan_info(h).device_bytes == need
+        with pytest.raises(lib.TuckVsieError) as e:
+            lib.tv_plan_bind_arena(h, 1 << 20, need - 256, None)       # short
+        assert e.value.status == -8
+        with pytest.raises(lib.TuckVsieError) as e:
+            lib.tv_plan_bind_arena(h, (1 << 20) + 16, need, None)      # misaligned
+        assert e.value.status == -1
+        with pytest.raises(lib.TuckVsieError) as e:
+            lib.tv_plan_bind_arena(h, None, need, None)
+        assert e.value.status == -1
+        # products and autotuning need the arena
+        assert lib._tv_matvec(h, 8, 2, 1, 4096, 3 * 240, 0, 0, None) == -1
+        assert "arena" in lib.tv_last_error()
+        with pytest.raises(lib.TuckVsieError):
+            lib.tv_autotune(h, 2, None, None)
+        with pytest.raises(lib.TuckVsieError):
+            lib.tv_batch_create([h], 0, [1])
+    finally:
+        lib.tv_plan_destroy(h)
+
+
+def test_compression_workspace_is_the_callers():
+    from paper_2103_06393_amd import lib
+    g = lib.make_grid(12, 10, 9, 3, 4)
+    h = lib.tv_compress_begin(g, 1e-3, 1, 6)
+    try:
+        need = lib.tv_compress_workspace_bytes(h, 2)
+        assert need > 0 and need % 256 == 0
+        assert lib.tv_compress_workspace_bytes(h, 4) > need
+        # a short workspace is refused before any device work
+        with pytest.raises(lib.TuckVsieError) as e:
+            lib.tv_compress_append(h, 1 << 20, 2, 1 << 24, need - 256, None)
+        assert e.value.status == -8
+        with pytest.raises(lib.TuckVsieError) as e:
+            lib.tv_compress_append(h, 1 << 20, 2, None, need, None)
+        assert e.value.status == -8
+    finally:
+        lib.tv_plan_destroy(h)
+
+
+def test_aca_assembly_workspace_is_the_callers():
+    from paper_2103_06393_amd import lib
+    g = lib.make_grid(6, 5, 4, 3, 10)
+    ang = np.linspace(0, 2 * np.pi, 10, endpoint=False)
+    pos = np.stack([0.2 * np.cos(ang), 0.2 * np.sin(ang), np.zeros(10)], axis=1)
+    ori = np.stack([-np.sin(ang), np.cos(ang), np.zeros(10)], axis=1)
+    need = lib.tv_aca_assemble_workspace_bytes(g, 4, 1e-3)
+    assert need > 0 and need % 256 == 0
+    assert lib.tv_aca_assemble_workspace_bytes(g, 4, 1e-3, rank_cap=2) < need
+    for ws, nb in ((None, need), (1 << 24, need - 256)):
+        with pytest.raises(lib.TuckVsieError) as e:
+            lib.tv_aca_assemble(g, 0.01, 6.0, 0, pos, ori, 1e-3, max_terms=4,
+                                ws_ptr=ws, ws_bytes=nb)
+        assert e.value.status == -8

@@ -33,7 +33,8 @@ def _ld(t):
 def _run(plans, op, inputs, nrhs):
     import torch
     from paper_2103_06393_amd import lib
-    b = lib.tv_batch_create([p.handle for p in plans], op, nrhs)
+    from paper_2103_06393_amd.ops import batch_create
+    b, b_arena = batch_create([p.handle for p in plans], op, nrhs)
     try:
         rows = [p.rows for p in plans]
         outs = [torch.zeros((r if op == 0 else p.m, n), dtype=torch.complex64,
@@ -72,7 +73,8 @@ def test_batch_graph_replay(gpu_lib, c4s):
     X = [torch.from_numpy(workloads.complex_normal((S.m, 8), 210 + c).astype(np.complex64))
          .cuda().t().contiguous().t() for c, S in enumerate(structs)]
     outs = [torch.zeros((8, p.rows), dtype=torch.complex64, device="cuda").t() for p in plans]
-    b = lib.tv_batch_create([p.handle for p in plans], 0, nrhs)
+    from paper_2103_06393_amd.ops import batch_create
+    b, b_arena = batch_create([p.handle for p in plans], 0, nrhs)
     ws = torch.empty(lib.tv_batch_workspace_bytes(b), dtype=torch.uint8, device="cuda")
     args = ([x.data_ptr() for x in X], [_ld(x) for x in X],
             [y.data_ptr() for y in outs], [_ld(y) for y in outs], ws.data_ptr(), ws.numel())

@@ -25,7 +25,7 @@ P_RHS = 32
 def c4_run():
     import torch
     from paper_2103_06393_amd import lib
-    from paper_2103_06393_amd.ops import TuckerPlan
+    from paper_2103_06393_amd.ops import TuckerPlan, batch_create
     wls = workloads.make_batch("c4")
     plans = [TuckerPlan.compress_dipoles(w.grid.dims, w.grid.h, w.k0, 0, w.pos, w.ori,
                                          w.tol, w.rank_min, w.rank_cap) for w in wls]
@@ -33,7 +33,7 @@ def c4_run():
     Y = [w.y(P_RHS) for w in wls]
     outs = {}
     for op, ins in ((0, X), (1, Y)):
-        b = lib.tv_batch_create([P.handle for P in plans], op, [P_RHS] * len(plans))
+        b, b_arena = batch_create([P.handle for P in plans], op, [P_RHS] * len(plans))
         try:
             # column-major (rows x 32) device operands
             dev_in = [torch.from_numpy(np.ascontiguousarray(a.T.astype(np.complex64)))
