@@ -192,6 +192,20 @@ typedef struct {
 } tv_launch_config;
 tv_status tv_plan_configure(tv_plan plan, int32_t op, const tv_launch_config* cfg);
 
+/* Z^* y exactly as tv_rmatvec, with no workspace argument and no device
+ * allocation: for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * adjoint's scratch is a static device array of TV_STATIC_SCRATCH_BYTES per
+ * GPU, held until the process ends; a plan configuration needing more
+ * (tv_workspace_bytes(plan, 1, nrhs)) returns TV_ERR_WORKSPACE before any
+ * device work.  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  Every scratch entry a call reads is written
+ * earlier in the same call, so nothing carries over between calls. */
+#define TV_STATIC_SCRATCH_BYTES (32u << 20)
+tv_status tv_rmatvec_noalloc(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
+                             void* x, int64_t ldx, void* stream);
+
 /* Pick the fastest launch configuration (tv_launch_config: fused-kernel
  * tiles, splits and row caps, and for the forward also the
  * decompress-then-GEMM path with its slab and tile) for this plan by timing

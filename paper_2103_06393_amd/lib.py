@@ -31,6 +31,7 @@ STATUS = {0: "TV_OK", -1: "TV_ERR_INVALID_ARG", -2: "TV_ERR_SHAPE",
 TV_PREC_FP32 = 0
 TV_PREC_BF16X3 = 1
 TV_MAX_RANK = 64
+TV_STATIC_SCRATCH_BYTES = 32 << 20
 TV_FIELD_K = 2              # OR into `basis`: the H-field operator of eq. (5)
 
 
@@ -102,6 +103,8 @@ _tv_batch_bind_arena = _sig("tv_batch_bind_arena", [c_vp, c_vp, c_sz, c_vp])
 _tv_plan_finalize = _sig("tv_plan_finalize", [c_vp, c_vp])
 _tv_compress_discarded = _sig("tv_compress_discarded", [c_vp, _dp])
 _tv_autotune = _sig("tv_autotune", [c_vp, c_i32, ctypes.c_char_p, c_vp])
+_tv_rmatvec_noalloc = _sig("tv_rmatvec_noalloc", [c_vp, c_vp, c_i64, c_i32, c_vp, c_i64,
+                                                   c_vp])
 _tv_plan_configure = _sig("tv_plan_configure",
                           [c_vp, c_i32, ctypes.POINTER(tv_launch_config)])
 _tv_batch_create = _sig("tv_batch_create", [c_i32, ctypes.POINTER(c_vp), c_i32,
@@ -136,7 +139,7 @@ _tv_last_error = _sig("tv_last_error", [], ctypes.c_char_p)
 EXPORTED = ("tv_plan_from_factors", "tv_plan_required_bytes", "tv_plan_bind_arena",
             "tv_plan_destroy", "tv_plan_info",
             "tv_plan_export_factors", "tv_workspace_bytes", "tv_matvec",
-            "tv_rmatvec", "tv_dipole_columns", "tv_compress_begin",
+            "tv_rmatvec", "tv_rmatvec_noalloc", "tv_dipole_columns", "tv_compress_begin",
             "tv_compress_workspace_bytes", "tv_compress_append", "tv_plan_finalize",
             "tv_compress_discarded",
             "tv_autotune", "tv_plan_configure", "tv_batch_create", "tv_batch_required_bytes", "tv_batch_bind_arena",
@@ -233,6 +236,11 @@ def tv_matvec(plan, x_ptr, ldx, nrhs, y_ptr, ldy, ws_ptr, ws_bytes, stream):
 def tv_rmatvec(plan, y_ptr, ldy, nrhs, x_ptr, ldx, ws_ptr, ws_bytes, stream):
     _check(_tv_rmatvec(plan, y_ptr, int(ldy), int(nrhs), x_ptr, int(ldx),
                        ws_ptr, int(ws_bytes), stream), "tv_rmatvec")
+
+
+def tv_rmatvec_noalloc(plan, y_ptr, ldy, nrhs, x_ptr, ldx, stream):
+    _check(_tv_rmatvec_noalloc(plan, y_ptr, int(ldy), int(nrhs), x_ptr, int(ldx), stream),
+           "tv_rmatvec_noalloc")
 
 
 def tv_dipole_columns(n1, n2, n3, h, k0, basis, pos, ori, out_ptr, stream):

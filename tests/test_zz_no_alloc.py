@@ -1,0 +1,65 @@
+"""tv_rmatvec_noalloc (the adjoint with its scratch in the library's static
+device array, for callers that cannot allocate) against tv_rmatvec with a
+caller workspace: two calls in a row on one GPU, the second on a smaller
+plan and input, both within the FP32 bar of the oracle and bit-identical to
+the workspace path (same kernels, same summation order); a configuration
+whose scratch exceeds the array is refused before any device work."""
+import numpy as np
+import pytest
+
+from oracle import matvec as om
+from tests.plans import adj_terms, assert_close, random_struct, struct_to_abi
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_both(S, seed, p=1):
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    P = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S))
+    rng = np.random.default_rng(seed)
+    Y = rng.standard_normal((S.q * S.nv, p)) + 1j * rng.standard_normal((S.q * S.nv, p))
+    yd = torch.from_numpy(np.ascontiguousarray(Y.T.astype(np.complex64))).cuda()
+    xa = torch.full((p, S.m), 3.0 + 3.0j, dtype=torch.complex64, device="cuda")
+    xb = torch.zeros((p, S.m), dtype=torch.complex64, device="cuda")
+    sp = torch.cuda.current_stream().cuda_stream
+    lib.tv_rmatvec_noalloc(P.handle, yd.data_ptr(), S.q * S.nv, p, xa.data_ptr(), S.m, sp)
+    ws = P.workspace(1, p)
+    lib.tv_rmatvec(P.handle, yd.data_ptr(), S.q * S.nv, p, xb.data_ptr(), S.m,
+                   ws.data_ptr(), ws.numel(), sp)
+    torch.cuda.synchronize()
+    a, b = xa.cpu().numpy().T, xb.cpu().numpy().T
+    assert np.array_equal(a, b)
+    assert_close(a, om.alg2(S, Y), 1e-5, terms=adj_terms(S, Y), what="no-alloc adjoint")
+    return P
+
+
+def test_noalloc_adjoint_two_calls(gpu_lib):
+    big = random_struct((48, 40, 33), 3, 24, 12, 71)
+    small = random_struct((20, 13, 7), 2, 5, 5, 72)
+    _run_both(big, 1, p=2)
+    _run_both(small, 2)
+
+
+def test_noalloc_refuses_oversized_scratch(gpu_lib):
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    S = random_struct((64, 32, 32), 3, 6, 6, 73)
+    P = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S))
+    # the decompress-then-GEMM adjoint at one slab needs more than the array
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=0, gemm_nbw=2)
+    need = lib.tv_workspace_bytes(P.handle, 1, 1)
+    y = torch.zeros(S.q * S.nv, dtype=torch.complex64, device="cuda")
+    x = torch.full((S.m,), 5.0, dtype=torch.complex64, device="cuda")
+    if need > lib.TV_STATIC_SCRATCH_BYTES:
+        with pytest.raises(lib.TuckVsieError) as ei:
+            lib.tv_rmatvec_noalloc(P.handle, y.data_ptr(), S.q * S.nv, 1, x.data_ptr(), S.m,
+                                   torch.cuda.current_stream().cuda_stream)
+        assert ei.value.status == -8                       # TV_ERR_WORKSPACE
+        assert np.all(x.cpu().numpy() == 5.0)              # nothing ran
+    # back on the fused adjoint it fits and runs
+    lib.tv_plan_configure(P.handle, 1, path=0, tile_t2=0, splits=1, row_cap=2)
+    assert lib.tv_workspace_bytes(P.handle, 1, 1) <= lib.TV_STATIC_SCRATCH_BYTES
+    _run_both(S, 3)
