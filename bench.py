@@ -573,6 +573,38 @@ def bench_assemble(args):
     return 0
 
 
+def batch_cpu_baseline(wls, plans, X, Y, Yo, Xo, p):
+    """The FP64 oracle (Algorithms 1 and 2 with p right-hand sides) on the two
+    coils with the fewest columns, on the GPU plans' own factors; also the
+    GPU results' relative errors on those coils."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import matvec as om
+    from tests.plans import abi_to_struct
+    order = np.argsort([w.m for w in wls])[:2]
+    t = 0.0
+    errs = {}
+    for c in order:
+        w, P = wls[c], plans[c]
+        S = abi_to_struct(w.grid.dims, w.q, *P.export_factors())
+        xc, yc = X[c].cpu().numpy(), Y[c].cpu().numpy()
+        t0 = time.perf_counter()
+        yr = om.alg1(S, xc, block_entries=1 << 28)
+        xr = om.alg2(S, yc, block_entries=1 << 28)
+        t += time.perf_counter() - t0
+        ey = np.linalg.norm(Yo[c].cpu().numpy() - yr) / np.linalg.norm(yr)
+        ex = np.linalg.norm(Xo[c].cpu().numpy() - xr) / np.linalg.norm(xr)
+        errs[f"rel_err_coil{c}"] = [float(ey), float(ex)]
+    threads = sum(int(i.get("num_threads", 1)) for i in threadpool_info()
+                  if i.get("user_api") == "blas") or 1
+    n = 2 * p * len(order)
+    return {"value": n / t, "unit": "matvecs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"the 2 coils with the fewest columns ({[wls[c].m for c in order]}), "
+                      f"{p} right-hand sides, both directions, FP64 Algorithms 1 and 2 on the "
+                      f"GPU plans' factors"}, errs
+
+
 def bench_batch(args):
     """Batched path: 16 coils on a 96x128x112 grid, 32 right-hand sides
     each, one persistent launch per direction, captured into a graph."""
@@ -597,12 +629,20 @@ def bench_batch(args):
     Xo = [torch.empty((p, P.m), dtype=torch.complex64, device="cuda").t() for P in plans]
     hs = [P.handle for P in plans]
     t0 = time.perf_counter()
-    bf, bf_arena = batch_create(hs, 0, [p] * len(plans))
-    ba, ba_arena = batch_create(hs, 1, [p] * len(plans))
+    cfg = [(0, 0), (0, 0)]
+    if not args.no_autotune:
+        st0 = torch.cuda.current_stream().cuda_stream
+        cfg = [lib.tv_batch_autotune(hs, op, [p] * len(plans), args.tune_cache, st0)
+               for op in (0, 1)]
+        log(f"[bench] batch configurations (tsplit, workgroups per CU): forward {cfg[0]}, "
+            f"adjoint {cfg[1]} (autotuned in {time.perf_counter() - t0:.1f} s)")
+        t0 = time.perf_counter()
+    bfwd, bfwd_arena = batch_create(hs, 0, [p] * len(plans), cfg[0])
+    badj, badj_arena = batch_create(hs, 1, [p] * len(plans), cfg[1])
     log(f"[bench] batch objects (work queues, packed operands) built in "
         f"{time.perf_counter() - t0:.1f} s")
-    wsf = torch.empty(lib.tv_batch_workspace_bytes(bf), dtype=torch.uint8, device="cuda")
-    wsa = torch.empty(lib.tv_batch_workspace_bytes(ba), dtype=torch.uint8, device="cuda")
+    wsf = torch.empty(lib.tv_batch_workspace_bytes(bfwd), dtype=torch.uint8, device="cuda")
+    wsa = torch.empty(lib.tv_batch_workspace_bytes(badj), dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
     fa = ([x.data_ptr() for x in X], [x.stride(1) for x in X], [y.data_ptr() for y in Yo],
           [y.stride(1) for y in Yo], wsf.data_ptr(), wsf.numel())
@@ -610,16 +650,20 @@ def bench_batch(args):
           [x.stride(1) for x in Xo], wsa.data_ptr(), wsa.numel())
     g = torch.cuda.CUDAGraph()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for name, bb, args_ in (("forward", bf, fa), ("adjoint", ba, aa)):
+    dir_ms = {}
+    for name, bb, args_ in (("forward", bfwd, fa), ("adjoint", badj, aa)):
         with torch.cuda.stream(s):
+            lib.tv_batch_run(bb, *args_, s.cuda_stream)       # first launch
             e0.record(s)
-            lib.tv_batch_run(bb, *args_, s.cuda_stream)
+            for _ in range(2):
+                lib.tv_batch_run(bb, *args_, s.cuda_stream)
             e1.record(s)
         torch.cuda.synchronize()
-        log(f"[bench] first batched {name} launch: {e0.elapsed_time(e1):.1f} ms")
+        dir_ms[name] = e0.elapsed_time(e1) / 2
+        log(f"[bench] batched {name}: {dir_ms[name]:.1f} ms per launch")
     with torch.cuda.graph(g, stream=s):
-        lib.tv_batch_run(bf, *fa, s.cuda_stream)
-        lib.tv_batch_run(ba, *aa, s.cuda_stream)
+        lib.tv_batch_run(bfwd, *fa, s.cuda_stream)
+        lib.tv_batch_run(badj, *aa, s.cuda_stream)
     for _ in range(min(args.warmup, 2)):
         g.replay()
     torch.cuda.synchronize()
@@ -657,6 +701,12 @@ def bench_batch(args):
         nv = n1 * n2 * n3
         dec = r[:, 0] * r[:, 1] * r[:, 2] * n2 + r[:, 0] * r[:, 2] * n2 * n3 + r[:, 0] * nv
         fl += 2 * float(np.sum(8.0 * (dec + nv * p)))   # both directions
+    # Table III's p-vector count per direction: decompression once per tensor
+    # plus the application to the p right-hand sides
+    fl_dir = fl / 2
+    dom = max(dir_ms, key=dir_ms.get)
+    peak = PEAK_BF16_MFMA / 3.0 if bf else PEAK_FP32_MFMA
+    ach = fl_dir / (dir_ms[dom] * 1e-3) / 1e12
     log(f"[bench] batched {ms:.2f} ms per step ({nmv} products), one plan and vector at a time "
         f"{ms_plain:.2f} ms; max relative difference {dev:.2e}")
     out = {"metric": "compressed VSIE matvecs/s (Zx and Z^H y), batched",
@@ -668,11 +718,21 @@ def bench_batch(args):
            "config": {"workload": "c4: 16 coils (64..1024 point currents) on 96x128x112, "
                                   "32 right-hand sides each, graph replay of both directions"},
            "tflops": fl / (ms * 1e-3) / 1e12,
+           "forward_ms": dir_ms["forward"], "adjoint_ms": dir_ms["adjoint"],
+           "roofline": {"kernel": f"tv_batch_run ({dom}: mode-3 kernel + persistent batched "
+                                  f"kernel{' + reduction' if dom == 'adjoint' else ''})",
+                        "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                        "frac": ach / peak, "traffic": None},
+           "launch": {"forward": list(cfg[0]), "adjoint": list(cfg[1]),
+                      "fields": "tsplit, workgroups per CU"},
            "unbatched_ms_per_step": ms_plain, "batched_speedup": ms_plain / ms,
            "max_rel_diff_vs_unbatched": dev,
            "workspace_bytes": {"forward": int(wsf.numel()), "adjoint": int(wsa.numel())}}
-    lib.tv_batch_destroy(bf)
-    lib.tv_batch_destroy(ba)
+    if not args.no_cpu:
+        out["cpu_baseline"], errs = batch_cpu_baseline(wls, plans, X, Y, Yo, Xo, p)
+        out.update(errs)
+    lib.tv_batch_destroy(bfwd)
+    lib.tv_batch_destroy(badj)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -178,17 +178,19 @@ tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
  *     of i3 (0: all), modes 3 and 2 of every tensor are decompressed into
  *     the stacked operand B_k = [x_1 M_1; ...] (unscaled for the adjoint) in
  *     the workspace, then the forward runs Y^k_(1) = A_k B_k as one MFMA
- *     GEMM per component (gemm_nbw = 2 or 4 column blocks per wave, splits
- *     k-step splits), the adjoint W = A_k^* Y^k_(1) with the conjugated dot
- *     against B_k in the GEMM's epilogue (splits 1, gemm_nbw 2) and a
- *     fixed-order FP64 sum per column (Algorithms 1 and 2, Sec. III.B).
+ *     GEMM per component (gemm_nbw = 2 or 4 column blocks per wave; for
+ *     BF16X3 plans also 1: two blocks per wave with 8 k-steps per LDS stage
+ *     and two workgroups per CU; splits k-step splits), the adjoint W = A_k^* Y^k_(1) with the conjugated dot
+ *     against B_k in the GEMM's epilogue (splits 1, gemm_nbw 2, gemm_order
+ *     0: consecutive workgroups share columns of y, 1: share rows of A_k^*)
+ *     and a fixed-order FP64 sum per column (Algorithms 1 and 2, Sec. III.B).
  * TV_ERR_INVALID_ARG / TV_ERR_NOT_SUPPORTED for a configuration the plan
  * cannot run; the previous configuration is then kept.  Afterwards
  * tv_workspace_bytes reflects the configuration. */
 typedef struct {
   int32_t path;
   int32_t tile_t2, splits, row_cap;
-  int32_t slab_i3, gemm_nbw;
+  int32_t slab_i3, gemm_nbw, gemm_order;
 } tv_launch_config;
 tv_status tv_plan_configure(tv_plan plan, int32_t op, const tv_launch_config* cfg);
 
@@ -303,8 +305,26 @@ tv_status tv_compress_discarded(tv_plan plan, double* rel_discarded);
  * ---------------------------------------------------------------------- */
 #define TV_BATCH_MAX_PLANS 32
 typedef struct tv_batch_s* tv_batch;
+/* Launch configuration of a batch (what tv_batch_autotune chooses):
+ * tsplit = adjoint work items per (plan, component, 32-column chunk,
+ * right-hand-side group), each a slice of the voxel tiles (0: automatic,
+ * about 4096 items; ignored by the forward); blocks_per_cu = persistent
+ * workgroups per compute unit (0: as many as fit).  cfg NULL: automatic. */
+typedef struct {
+  int32_t tsplit, blocks_per_cu;
+} tv_batch_config;
 tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op,
-                          const int32_t* nrhs, tv_batch* out);
+                          const int32_t* nrhs, const tv_batch_config* cfg, tv_batch* out);
+/* The configuration a batch uses (tsplit reported as 0 for the forward). */
+tv_status tv_batch_info(tv_batch batch, tv_batch_config* cfg);
+/* Time the batch configurations for these plans, direction and right-hand
+ * sides (set-up call: allocates its own timing buffers and synchronises)
+ * and return the fastest in *best; cached in the JSON file cache_path
+ * (shared with tv_autotune; NULL: no cache) keyed by device, grid, q, the
+ * plans' ranks and nrhs. */
+tv_status tv_batch_autotune(int32_t nplans, const tv_plan* plans, int32_t op,
+                            const int32_t* nrhs, const char* cache_path, void* stream,
+                            tv_batch_config* best);
 tv_status tv_batch_required_bytes(tv_batch batch, size_t* bytes);
 tv_status tv_batch_bind_arena(tv_batch batch, void* arena, size_t bytes, void* stream);
 tv_status tv_batch_workspace_bytes(tv_batch batch, size_t* bytes);

@@ -123,6 +123,8 @@ static size_t arena_layout(tv_plan_s* p, char* base) {
   carve(&p->d_split_a, splits);
   carve(&p->d_apack4, h.a4.size() * sizeof(float));
   carve(&p->d_apackh, h.ah.size() * sizeof(float));
+  carve(&p->d_abf, h.abf.size() * sizeof(uint4));
+  carve(&p->d_drow, h.drow.size() * sizeof(int32_t));
   return (off + 255) & ~(size_t)255;
 }
 
@@ -134,6 +136,8 @@ static void clear_device_pointers(tv_plan_s* p) {
   p->d_apack_koff = nullptr;
   p->d_split_f = p->d_split_a = nullptr;
   p->d_apack4 = p->d_apackh = nullptr;
+  p->d_abf = nullptr;
+  p->d_drow = nullptr;
   p->bound = false;
 }
 
@@ -195,14 +199,11 @@ static std::vector<int32_t> make_split(const tv_plan_s* p, int S) {
 tv_status set_split(tv_plan_s* p, int op, int S) {
   S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(S, TV_SPLIT_MAX), p->grid.m));
   if (p->bound) {
-    // the table of S + 1 entries per component, at a stride of TV_SPLIT_MAX + 1
+    // [q][S + 1] first column of each split, within the region reserved for
+    // TV_SPLIT_MAX splits
     std::vector<int32_t> sp = make_split(p, S);
-    std::vector<int32_t> tab((size_t)p->grid.q * (TV_SPLIT_MAX + 1), 0);
-    for (int k = 0; k < p->grid.q; ++k)
-      std::copy(sp.begin() + (size_t)k * (S + 1), sp.begin() + (size_t)(k + 1) * (S + 1),
-                tab.begin() + (size_t)k * (TV_SPLIT_MAX + 1));
-    hipError_t e = hipMemcpy(op == 0 ? p->d_split_f : p->d_split_a, tab.data(),
-                             tab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(op == 0 ? p->d_split_f : p->d_split_a, sp.data(),
+                             sp.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_error(e, "split table upload");
   }
   if (op == 0)
@@ -353,7 +354,7 @@ static tv_status pack_plan(tv_plan_s* p) {
   p->hp.u3t = std::move(u3t);
   p->hp.apack = std::move(apack);
   p->hp.apack_bf = std::move(apack_bf);
-  if (!bf && p->with_dtg && (st = dtg_pack(p, p->hp.meta)) != TV_OK) return st;
+  if (p->with_dtg && (st = dtg_pack(p, p->hp.meta)) != TV_OK) return st;
   p->device_bytes = arena_layout(p, nullptr);
   p->finalized = true;
   return TV_OK;
@@ -378,6 +379,8 @@ static tv_status bind_arena(tv_plan_s* p, void* arena, size_t bytes, hipStream_t
   put(p->d_apack_koff, p->apack_koff.data(), p->apack_koff.size() * sizeof(int64_t));
   put(p->d_apack4, h.a4.data(), h.a4.size() * sizeof(float));
   put(p->d_apackh, h.ah.data(), h.ah.size() * sizeof(float));
+  put(p->d_abf, h.abf.data(), h.abf.size() * sizeof(uint4));
+  put(p->d_drow, h.drow.data(), h.drow.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     clear_device_pointers(p);

@@ -7,6 +7,7 @@
 // the ranks.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -18,18 +19,14 @@
 namespace tv {
 
 static std::string plan_key(const tv_plan_s* p, int op) {
-  hipDeviceProp_t prop;
-  int dev = 0;
-  std::string arch = "gpu";
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    arch = prop.gcnArchName;
+  const std::string arch = device_arch();
   uint64_t h = 1469598103934665603ull;  // FNV-1a over the ranks
   for (int32_t r : p->ranks) {
     h ^= (uint32_t)r;
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "k5|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k6|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -37,9 +34,11 @@ static std::string plan_key(const tv_plan_s* p, int op) {
   return buf;
 }
 
-// The cache is a flat JSON object {"key": [path, t2, split, cap, slab, nbw], ...}.
-static std::map<std::string, tv_launch_config> read_cache(const char* path) {
-  std::map<std::string, tv_launch_config> out;
+// The cache is a flat JSON object {"key": [int, ...], ...}: plan entries
+// hold [path, t2, split, cap, slab, nbw, order], batch entries [tsplit,
+// workgroups per CU].
+std::map<std::string, std::vector<int>> read_tune_cache(const char* path) {
+  std::map<std::string, std::vector<int>> out;
   if (!path) return out;
   std::ifstream f(path);
   if (!f) return out;
@@ -54,16 +53,26 @@ static std::map<std::string, tv_launch_config> read_cache(const char* path) {
     if (q1 == std::string::npos) break;
     const size_t b0 = s.find('[', q1), b1 = s.find(']', q1);
     if (b0 == std::string::npos || b1 == std::string::npos) break;
-    tv_launch_config c{};
-    if (sscanf(s.c_str() + b0 + 1, "%d , %d , %d , %d , %d , %d", &c.path, &c.tile_t2,
-               &c.splits, &c.row_cap, &c.slab_i3, &c.gemm_nbw) == 6)
-      out[s.substr(q0 + 1, q1 - q0 - 1)] = c;
+    std::vector<int> v;
+    const char* c = s.c_str() + b0 + 1;
+    const char* end = s.c_str() + b1;
+    while (c < end) {
+      char* nx = nullptr;
+      const long x = strtol(c, &nx, 10);
+      if (nx == c) {
+        ++c;
+        continue;
+      }
+      v.push_back((int)x);
+      c = nx;
+    }
+    out[s.substr(q0 + 1, q1 - q0 - 1)] = v;
     pos = b1 + 1;
   }
   return out;
 }
 
-static void write_cache(const char* path, const std::map<std::string, tv_launch_config>& m) {
+void write_tune_cache(const char* path, const std::map<std::string, std::vector<int>>& m) {
   if (!path) return;
   const std::string tmp = std::string(path) + ".tmp";
   {
@@ -72,14 +81,30 @@ static void write_cache(const char* path, const std::map<std::string, tv_launch_
     f << "{\n";
     size_t i = 0;
     for (const auto& kv : m) {
-      const tv_launch_config& c = kv.second;
-      f << "  \"" << kv.first << "\": [" << c.path << ", " << c.tile_t2 << ", " << c.splits
-        << ", " << c.row_cap << ", " << c.slab_i3 << ", " << c.gemm_nbw << "]"
-        << (++i < m.size() ? ",\n" : "\n");
+      f << "  \"" << kv.first << "\": [";
+      for (size_t j = 0; j < kv.second.size(); ++j) f << (j ? ", " : "") << kv.second[j];
+      f << "]" << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
   }
   std::rename(tmp.c_str(), path);
+}
+
+std::string device_arch() {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    return prop.gcnArchName;
+  return "gpu";
+}
+
+static std::vector<int> to_vec(const tv_launch_config& c) {
+  return {c.path, c.tile_t2, c.splits, c.row_cap, c.slab_i3, c.gemm_nbw, c.gemm_order};
+}
+static bool from_vec(const std::vector<int>& v, tv_launch_config* c) {
+  if (v.size() != 7) return false;
+  *c = tv_launch_config{v[0], v[1], v[2], v[3], v[4], v[5], v[6]};
+  return true;
 }
 
 static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
@@ -88,13 +113,17 @@ static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
     if (c.slab_i3 < 0) return set_error(TV_ERR_INVALID_ARG, "slab_i3 must be >= 0");
     const int slab = c.slab_i3 ? std::min(c.slab_i3, p->grid.n3) : p->grid.n3;
     if (op == 1) {
-      if (c.splits != 1 || c.gemm_nbw != 2)
-        return set_error(TV_ERR_INVALID_ARG, "the adjoint GEMM takes splits 1 and gemm_nbw 2");
+      if (c.splits != 1 || c.gemm_nbw != 2 || (c.gemm_order != 0 && c.gemm_order != 1))
+        return set_error(TV_ERR_INVALID_ARG,
+                         "the adjoint GEMM takes splits 1, gemm_nbw 2, gemm_order 0 or 1");
       p->dtg_s3_a = slab;
+      p->dtg_order_a = c.gemm_order;
       p->use_dtg[1] = true;
       return TV_OK;
     }
-    if (c.gemm_nbw != 2 && c.gemm_nbw != 4) return set_error(TV_ERR_INVALID_ARG, "gemm_nbw");
+    const bool nbw_ok = c.gemm_nbw == 2 || c.gemm_nbw == 4 ||
+                        (c.gemm_nbw == 1 && p->precision == TV_PREC_BF16X3);
+    if (!nbw_ok) return set_error(TV_ERR_INVALID_ARG, "gemm_nbw");
     if (c.splits < 1 || c.splits > 64) return set_error(TV_ERR_INVALID_ARG, "GEMM splits");
     p->dtg_nbw = c.gemm_nbw;
     p->dtg_split = c.splits;
@@ -132,6 +161,7 @@ static tv_launch_config current_config(const tv_plan_s* p, int op) {
     c.splits = op == 0 ? p->dtg_split : 1;
     c.slab_i3 = op == 0 ? p->dtg_s3 : p->dtg_s3_a;
     c.gemm_nbw = op == 0 ? p->dtg_nbw : 2;
+    c.gemm_order = op == 0 ? 0 : p->dtg_order_a;
     return c;
   }
   c.tile_t2 = op == 0 ? p->tiling.t2 : p->tiling_a.t2;
@@ -148,7 +178,6 @@ extern "C" tv_status tv_plan_configure(tv_plan p, int32_t op, const tv_launch_co
   clear_error();
   if (!p || !cfg) return set_error(TV_ERR_INVALID_ARG, "plan and cfg must be non-NULL");
   if (!p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is not finalized");
-  if (!p->bound) return set_error(TV_ERR_INVALID_ARG, "plan has no device arena (tv_plan_bind_arena)");
   if (op != 0 && op != 1) return set_error(TV_ERR_INVALID_ARG, "op must be 0 or 1");
   const tv_launch_config keep = current_config(p, op);
   tv_status s = apply_config(p, op, *cfg);
@@ -163,7 +192,7 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
   if (!p->bound) return set_error(TV_ERR_INVALID_ARG, "plan has no device arena (tv_plan_bind_arena)");
   if (op < 0 || op > 2) return set_error(TV_ERR_INVALID_ARG, "op must be 0, 1 or 2");
   hipStream_t st = (hipStream_t)stream;
-  auto cache = read_cache(cache_path);
+  auto cache = read_tune_cache(cache_path);
   const tv_grid& g = p->grid;
   const int64_t rows = (int64_t)g.q * g.n1 * g.n2 * g.n3;
   bool dirty = false;
@@ -171,7 +200,9 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     if (op != 2 && op != o) continue;
     const std::string key = plan_key(p, o);
     auto it = cache.find(key);
-    if (it != cache.end() && apply_config(p, o, it->second) == TV_OK) continue;
+    tv_launch_config cached{};
+    if (it != cache.end() && from_vec(it->second, &cached) && apply_config(p, o, cached) == TV_OK)
+      continue;
     std::vector<tv_launch_config> cands;
     // fused kernels: (cap, t2) pairs times column splits
     std::vector<int> splits;
@@ -201,7 +232,9 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     // k-step splits while the launch has fewer than 1024 workgroups
     if (dtg_supported(p)) {
       for (int slab = g.n3; slab >= 1; slab = (slab + 1) / 2) {
-        for (int nbw : (o == 0 ? std::vector<int>{2, 4} : std::vector<int>{2})) {
+        std::vector<int> nbws = o == 1 ? std::vector<int>{2} : std::vector<int>{2, 4};
+        if (o == 0 && p->precision == TV_PREC_BF16X3) nbws.push_back(1);
+        for (int nbw : nbws) {
           tv_launch_config c{};
           c.path = 1;
           c.slab_i3 = slab;
@@ -213,7 +246,10 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
           apply_config(p, o, keep);
           if (need > ((size_t)16 << 30)) continue;
           if (o == 1) {
-            cands.push_back(c);
+            for (int order : {0, 1}) {
+              c.gemm_order = order;
+              cands.push_back(c);
+            }
             continue;
           }
           const int64_t tiles = dtg_launch_tiles(p, slab, nbw);
@@ -286,10 +322,10 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     }
     tv_status s = apply_config(p, o, best_c);
     if (s != TV_OK) return s;
-    cache[key] = best_c;
+    cache[key] = to_vec(best_c);
     dirty = true;
   }
-  if (dirty) write_cache(cache_path, cache);
+  if (dirty) write_tune_cache(cache_path, cache);
   clear_error();
   return TV_OK;
 }

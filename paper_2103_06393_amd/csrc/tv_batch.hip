@@ -1029,6 +1029,7 @@ struct tv_batch_s {
   int r1max = 1, r2max = 1, r3max = 1;
   int nitems = 0;
   int grid_blocks = 0;
+  int per_cu = 1;           // persistent workgroups per compute unit
   size_t lds = 0;
   std::vector<int64_t> m;
   std::vector<int32_t> nrhs;
@@ -1095,7 +1096,7 @@ static size_t batch_hcache_offset(const tv_batch_s* b) {
 extern "C" {
 
 tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, const int32_t* nrhs,
-                          tv_batch* out) {
+                          const tv_batch_config* cfg, tv_batch* out) {
   clear_error();
   if (!out) return set_error(TV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -1103,6 +1104,8 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     return set_error(TV_ERR_INVALID_ARG, "nplans outside [1, TV_BATCH_MAX_PLANS]");
   if (!plans || !nrhs) return set_error(TV_ERR_INVALID_ARG, "plans and nrhs must be non-NULL");
   if (op != 0 && op != 1) return set_error(TV_ERR_INVALID_ARG, "op must be 0 or 1");
+  if (cfg && (cfg->tsplit < 0 || cfg->blocks_per_cu < 0))
+    return set_error(TV_ERR_INVALID_ARG, "batch configuration values must be >= 0");
   for (int c = 0; c < nplans; ++c) {
     if (!plans[c] || !plans[c]->finalized || !plans[c]->bound)
       return set_error(TV_ERR_INVALID_ARG, "every plan must be finalized and bound to its arena");
@@ -1197,6 +1200,7 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     int64_t base = 0;
     for (int c = 0; c < nplans; ++c) base += (int64_t)g.q * ((b->m[c] + 31) / 32) * ((nrhs[c] + 31) / 32);
     b->tsplit = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (target + base - 1) / base));
+    if (cfg && cfg->tsplit > 0) b->tsplit = std::min(cfg->tsplit, tiles);
   }
   std::vector<int4> items;
   std::vector<int> red_list;
@@ -1322,7 +1326,10 @@ tv_status tv_batch_create(int32_t nplans, const tv_plan* plans, int32_t op, cons
     batch_free(b);
     return hip_error(e, "tv_batch_create");
   }
-  b->grid_blocks = std::max(1, std::min(b->nitems, cus * std::max(per_cu, 1)));
+  per_cu = std::max(per_cu, 1);
+  if (cfg && cfg->blocks_per_cu > 0) per_cu = std::min(per_cu, (int)cfg->blocks_per_cu);
+  b->per_cu = per_cu;
+  b->grid_blocks = std::max(1, std::min(b->nitems, cus * per_cu));
   *out = b;
   return TV_OK;
 }
@@ -1464,6 +1471,123 @@ tv_status tv_batch_destroy(tv_batch b) {
   clear_error();
   if (!b) return TV_OK;
   batch_free(b);
+  return TV_OK;
+}
+
+tv_status tv_batch_info(tv_batch b, tv_batch_config* cfg) {
+  clear_error();
+  if (!b || !cfg) return set_error(TV_ERR_INVALID_ARG, "batch and cfg must be non-NULL");
+  cfg->tsplit = b->op == 1 ? b->tsplit : 0;
+  cfg->blocks_per_cu = b->per_cu;
+  return TV_OK;
+}
+
+// Times batch configurations (adjoint voxel-tile slices, persistent
+// workgroups per CU) on zero-filled vectors with timing buffers of its own
+// (set-up call: allocates and synchronises) and returns the fastest; results
+// are cached in the JSON file shared with tv_autotune.
+tv_status tv_batch_autotune(int32_t nplans, const tv_plan* plans, int32_t op,
+                            const int32_t* nrhs, const char* cache_path, void* stream,
+                            tv_batch_config* best) {
+  clear_error();
+  if (!best || !plans || !nrhs || nplans < 1 || nplans > TV_BATCH_MAX_PLANS)
+    return set_error(TV_ERR_INVALID_ARG, "invalid batch autotune arguments");
+  *best = tv_batch_config{0, 0};
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the plans' ranks and nrhs
+  for (int c = 0; c < nplans; ++c) {
+    if (!plans[c]) return set_error(TV_ERR_INVALID_ARG, "NULL plan");
+    for (int32_t r : plans[c]->ranks) {
+      h ^= (uint32_t)r;
+      h *= 1099511628211ull;
+    }
+    h ^= (uint32_t)nrhs[c];
+    h *= 1099511628211ull;
+  }
+  const tv_grid g0 = plans[0]->grid;
+  char key[256];
+  snprintf(key, sizeof key, "b1|%s|%dx%dx%d|q%d|n%d|h%016llx|op%d", device_arch().c_str(), g0.n1,
+           g0.n2, g0.n3, g0.q, nplans, (unsigned long long)h, op);
+  auto cache = read_tune_cache(cache_path);
+  auto it = cache.find(key);
+  if (it != cache.end() && it->second.size() == 2) {
+    *best = tv_batch_config{it->second[0], it->second[1]};
+    return TV_OK;
+  }
+  // the default configuration fixes the candidates' ranges
+  tv_batch b0 = nullptr;
+  tv_status s = tv_batch_create(nplans, plans, op, nrhs, nullptr, &b0);
+  if (s != TV_OK) return s;
+  const int ts0 = b0->tsplit, pc0 = b0->per_cu;
+  const int tiles = b0->tiles2 * g0.n3 * (b0->mfma && op == 1 ? b0->nic : 1);
+  tv_batch_destroy(b0);
+  std::vector<tv_batch_config> cands;
+  for (int pc = 1; pc <= pc0; ++pc) {
+    if (op == 0) {
+      cands.push_back(tv_batch_config{0, pc});
+      continue;
+    }
+    for (int ts = std::max(1, ts0 / 4); ts <= std::min(tiles, 4 * ts0); ts *= 2)
+      cands.push_back(tv_batch_config{ts, pc});
+  }
+  // zero-filled vectors and the largest workspace
+  const int64_t nv = (int64_t)g0.n1 * g0.n2 * g0.n3, rows = (int64_t)g0.q * nv;
+  std::vector<void*> vin(nplans, nullptr), vout(nplans, nullptr);
+  std::vector<int64_t> ldi(nplans), ldo(nplans);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < nplans && e == hipSuccess; ++c) {
+    const int64_t m = plans[c]->grid.m;
+    ldi[c] = op == 0 ? m : rows;
+    ldo[c] = op == 0 ? rows : m;
+    e = hipMalloc(&vin[c], (size_t)8 * ldi[c] * nrhs[c]);
+    if (e == hipSuccess) e = hipMalloc(&vout[c], (size_t)8 * ldo[c] * nrhs[c]);
+    if (e == hipSuccess) e = hipMemsetAsync(vin[c], 0, (size_t)8 * ldi[c] * nrhs[c], st);
+  }
+  float bestms = -1.f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (size_t a = 0; e == hipSuccess && a < cands.size(); ++a) {
+    tv_batch b = nullptr;
+    if (tv_batch_create(nplans, plans, op, nrhs, &cands[a], &b) != TV_OK) continue;
+    size_t ab = 0, wb = 0;
+    void *arena = nullptr, *ws = nullptr;
+    tv_batch_required_bytes(b, &ab);
+    tv_batch_workspace_bytes(b, &wb);
+    e = hipMalloc(&arena, std::max<size_t>(ab, 256));
+    if (e == hipSuccess) e = hipMalloc(&ws, std::max<size_t>(wb, 256));
+    bool ok = e == hipSuccess && tv_batch_bind_arena(b, arena, ab, stream) == TV_OK;
+    auto run = [&]() {
+      return tv_batch_run(b, (const void* const*)vin.data(), ldi.data(), vout.data(), ldo.data(),
+                          ws, wb, stream) == TV_OK;
+    };
+    if (ok) ok = run();
+    float ms = 0.f;
+    if (ok && e == hipSuccess) e = hipEventRecord(e0, st);
+    if (ok && e == hipSuccess) ok = run();
+    if (ok && e == hipSuccess) e = hipEventRecord(e1, st);
+    if (ok && e == hipSuccess) e = hipEventSynchronize(e1);
+    if (ok && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (ok && e == hipSuccess && (bestms < 0.f || ms < bestms)) {
+      bestms = ms;
+      *best = cands[a];
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    tv_batch_destroy(b);
+    hipFree(arena);
+    hipFree(ws);
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  for (int c = 0; c < nplans; ++c) {
+    hipFree(vin[c]);
+    hipFree(vout[c]);
+  }
+  if (e != hipSuccess) return hip_error(e, "tv_batch_autotune");
+  if (bestms < 0.f) return set_error(TV_ERR_NOT_SUPPORTED, "no batch configuration ran");
+  cache[key] = {best->tsplit, best->blocks_per_cu};
+  write_tune_cache(cache_path, cache);
+  clear_error();
   return TV_OK;
 }
 

@@ -24,6 +24,7 @@
 // The GEMM stages 16 k-steps of A (8 row blocks) and B (4 column blocks)
 // through LDS per step, double-buffered, one barrier per step.
 #include <algorithm>
+#include <cstring>
 
 #include "tv_internal.h"
 
@@ -43,14 +44,51 @@ struct DecompParams {
   const float2* u2t;
   const float2* u3t;
   const float2* x;   // x_j scaling (forward) or null
+  const int32_t* drow;  // first stacked row of each tensor [k * m + j]
   float* B;
   int64_t ldb;       // floats per stacked row of B
   int64_t brow[DTG_MAXQ];
   int64_t m;
   int n2, n3, i30, s3, nsub;
   int t3w;           // i3 values per decompression workgroup
+  int layout;        // 0: FP32 planar (forward), 1: FP32 accumulator order
+                     // (adjoint), 2: BF16 hi/lo operand order (forward, BF16X3)
   int64_t nitems;
 };
+
+// Adjoint layout of B: stacked rows in blocks of 16 (a row block of the
+// adjoint GEMM's 32x32 accumulator), float offset
+// ((R/16 * nbl + n/32) * 4 + g) * 256 + lane * 4 + 2 e + (Re, Im) for row R
+// with R%16 = 4 g + 2 h + e and lane = 32 h + n%32: a lane of the GEMM's
+// epilogue finds the values matching its accumulator registers 4g..4g+3 in
+// one 16-byte load.
+__host__ __device__ inline int64_t adj_b_index(int64_t R, int64_t n, int64_t nbl) {
+  const int al = (int)(R & 15);
+  const int g = al >> 2, h = (al >> 1) & 1, e = al & 1;
+  return (((R >> 4) * nbl + (n >> 5)) * 4 + g) * 256 + (32 * h + (n & 31)) * 4 + 2 * e;
+}
+
+// BF16X3 layout of B: stacked rows in chunks of 8, per (chunk, 32-column
+// block) the hi then the lo halves as 64 lanes x 8 bf16, lane 32 h + n%32
+// holding rows 8c + 4h + 0..3 as (Re, Im) pairs: the B operand of
+// v_mfma_f32_32x32x16_bf16 for eight k-steps.  Index of the 32-bit (Re, Im)
+// word of row R, column n, hi half (the lo half is 256 words further).
+__host__ __device__ inline int64_t bf_b_index(int64_t R, int64_t n, int64_t nbl) {
+  const int rl = (int)(R & 7);
+  return (((R >> 3) * nbl + (n >> 5)) * 2) * 256 + (32 * (rl >> 2) + (n & 31)) * 4 + (rl & 3);
+}
+
+__host__ __device__ inline uint32_t bf16_rne(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__host__ __device__ inline float bf16_float(uint32_t h) {
+  const uint32_t u = h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -93,7 +131,9 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
     h3[(a * T3 + i3l) * r2 + b] = cmul(xj, s);
   }
   __syncthreads();
-  float* Bk = P.B + (P.brow[k] + t.arow) * P.ldb;
+  const int64_t row0 = P.brow[k] + P.drow[kt];
+  float* Bk = P.B + row0 * P.ldb;
+  const int64_t nbl = P.ldb / 64;
   for (int i2 = threadIdx.x; i2 < P.n2; i2 += 256) {
     float2 u[R2MAX];
     const float2* u2 = P.u2t + t.u2_off + (int64_t)i2 * r2;
@@ -113,9 +153,19 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
           }
         }
         const int64_t n = i2 + (int64_t)P.n2 * (i3a + i3l - P.i30);
-        float* dst = row + (n >> 5) * 64 + (n & 31);
-        dst[0] = sr;
-        dst[32] = si;
+        if (P.layout == 1) {
+          *(float2*)(P.B + adj_b_index(row0 + a, n, nbl)) = make_float2(sr, si);
+        } else if (P.layout == 2) {
+          const uint32_t hr = bf16_rne(sr), hi_ = bf16_rne(si);
+          const uint32_t lr = bf16_rne(sr - bf16_float(hr)), li = bf16_rne(si - bf16_float(hi_));
+          uint32_t* dst = (uint32_t*)P.B + bf_b_index(row0 + a, n, nbl);
+          dst[0] = hr | (hi_ << 16);
+          dst[256] = lr | (li << 16);
+        } else {
+          float* dst = row + (n >> 5) * 64 + (n & 31);
+          dst[0] = sr;
+          dst[32] = si;
+        }
       }
     }
   }
@@ -276,6 +326,155 @@ __global__ __launch_bounds__(256) void dtg_gemm_kernel(GemmParams P) {
   }
 }
 
+// zero rows [from_k, to_k) of the BF16 layout (both halves, every column)
+__global__ void dtg_zero_rows_bf_kernel(ZeroParams Z) {
+  const int64_t nbl = Z.ldb / 64;
+  for (int k = 0; k < Z.q; ++k) {
+    const int64_t n = (Z.to[k] - Z.from[k]) * nbl * 32;
+    uint32_t* B = (uint32_t*)Z.B;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t R = Z.from[k] + i / (nbl * 32), c = i % (nbl * 32);
+      const int64_t w = bf_b_index(R, c, nbl);
+      B[w] = 0u;
+      B[w + 256] = 0u;
+    }
+  }
+}
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v8bf as_v8bf(uint4 v) { return __builtin_bit_cast(v8bf, v); }
+
+// The stacked mode-1 GEMM with BF16 hi/lo operands: per 16 k-steps (two
+// chunks of 8), Y += Ah Bh + Ah Bl + Al Bh on v_mfma_f32_32x32x16_bf16 (the
+// lo x lo term is dropped), FP32 accumulation.  Tiles, waves, XCD grouping
+// and epilogue as dtg_gemm_kernel; A (abf) per component as
+// ((chunk * nbtp + blk) * 2 + hl) * 64 + lane uint4, lane l holding
+// A_emb[32 blk + l%32][(8 chunk + 4 (l/32) + e/2, e%2)], e < 8.
+template <int MBW, int NBW, int CPS>
+__global__ __launch_bounds__(256, CPS == 1 ? 2 : 1) void dtg_gemm_bf_kernel(GemmParams P) {
+  // CPS chunks of 8 k-steps per LDS stage; with one chunk per stage two
+  // workgroups share a CU, which hides the loads behind the other's MFMAs
+  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
+  constexpr int A_ST = CPS * MT * 128;      // uint4 per A stage
+  constexpr int B_ST = CPS * NBT * 128;     // uint4 per B stage
+  extern __shared__ uint4 ldsq[];
+  const int64_t nwg = gridDim.x;
+  const int64_t L = (int64_t)(blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+  if (L >= P.nitems) return;
+  const int mt = (int)(L % P.mtiles);
+  int64_t rest = L / P.mtiles;
+  const int nt = (int)(rest % P.ntiles);
+  rest /= P.ntiles;
+  const int k = (int)(rest % P.q);
+  const int s = (int)(rest / P.q);
+  const int nst = P.kst[k] * (2 / CPS);
+  const int st0 = (int)((int64_t)nst * s / P.S), st1 = (int)((int64_t)nst * (s + 1) / P.S);
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const uint4* Ag = (const uint4*)P.apack4 + P.a4off[k];
+  const int64_t nbl = P.ldb / 64;
+  const uint4* Bg = (const uint4*)P.B + (P.brow[k] >> 3) * nbl * 128;
+
+  constexpr int NA = CPS * MT / 2, NB = CPS * NBT / 2;   // uint4 loads per thread
+  uint4 ra[NA], rb[NB];
+  auto gload = [&](int st) {
+#pragma unroll
+    for (int c = 0; c < NA; ++c) {
+      const int u = c * 256 + tid;
+      const int ch = u / (MT * 128), rem = u % (MT * 128);
+      ra[c] = Ag[(((int64_t)st * CPS + ch) * P.nbtp + mt * MT + rem / 128) * 128 + rem % 128];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int u = c * 256 + tid;
+      const int ch = u / (NBT * 128), rem = u % (NBT * 128);
+      rb[c] = Bg[(((int64_t)st * CPS + ch) * nbl + (int64_t)nt * NBT + rem / 128) * 128 +
+                 rem % 128];
+    }
+  };
+  auto lstore = [&](int buf) {
+    uint4* As = ldsq + buf * (A_ST + B_ST);
+    uint4* Bs = As + A_ST;
+#pragma unroll
+    for (int c = 0; c < NA; ++c) As[c * 256 + tid] = ra[c];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Bs[c * 256 + tid] = rb[c];
+  };
+
+  v16f acc[MBW][NBW];
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int jn = 0; jn < NBW; ++jn) acc[i][jn] = v16f{0.f};
+
+  if (st0 < st1) {
+    gload(st0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int st = st0; st < st1; ++st) {
+    const int buf = (st - st0) & 1;
+    if (st + 1 < st1) gload(st + 1);
+    const uint4* As = ldsq + buf * (A_ST + B_ST);
+    const uint4* Bs = As + A_ST;
+#pragma unroll
+    for (int ch = 0; ch < CPS; ++ch) {
+      v8bf ah[MBW], al[MBW], bh[NBW], bl[NBW];
+#pragma unroll
+      for (int i = 0; i < MBW; ++i) {
+        const int b = ch * MT + wm * MBW + i;
+        ah[i] = as_v8bf(As[(b * 2) * 64 + lane]);
+        al[i] = as_v8bf(As[(b * 2 + 1) * 64 + lane]);
+      }
+#pragma unroll
+      for (int jn = 0; jn < NBW; ++jn) {
+        const int b = ch * NBT + wn * NBW + jn;
+        bh[jn] = as_v8bf(Bs[(b * 2) * 64 + lane]);
+        bl[jn] = as_v8bf(Bs[(b * 2 + 1) * 64 + lane]);
+      }
+#pragma unroll
+      for (int i = 0; i < MBW; ++i)
+#pragma unroll
+        for (int jn = 0; jn < NBW; ++jn) {
+          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[jn], acc[i][jn], 0, 0, 0);
+          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[jn], acc[i][jn], 0, 0, 0);
+          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[jn], acc[i][jn], 0, 0, 0);
+        }
+    }
+    if (st + 1 < st1) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  float2* out = P.out + (int64_t)s * P.out_stride + (int64_t)k * P.nv;
+#pragma unroll
+  for (int jn = 0; jn < NBW; ++jn) {
+    const int64_t n = ((int64_t)nt * NBT + wn * NBW + jn) * 32 + (lane & 31);
+    if (n >= P.ncols) continue;
+    float2* col = out + (int64_t)P.n1 * (P.col0 + n);
+#pragma unroll
+    for (int i = 0; i < MBW; ++i) {
+      const int blk = mt * MT + wm * MBW + i;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int i1 = blk * 16 + 4 * g + 2 * (lane >> 5);
+        const v16f& d = acc[i][jn];
+        if (i1 + 1 < P.n1) {
+          if (P.vec4) {
+            *(v4f*)(col + i1) = v4f{d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]};
+          } else {
+            col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
+            col[i1 + 1] = make_float2(d[4 * g + 2], d[4 * g + 3]);
+          }
+        } else if (i1 < P.n1) {
+          col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
+        }
+      }
+    }
+  }
+}
+
 typedef void (*gemm_fn)(GemmParams);
 
 // ---- adjoint: W_k = A_k^* Y^k_(1) on MFMA, then the conjugated dot with the
@@ -298,7 +497,8 @@ struct AdjParams {
   int mbh[DTG_MAXQ];        // 32-row blocks of the A^* operand per component
   int mtb[DTG_MAXQ + 1];    // prefix sum of row tiles over components
   int q, kst, ntiles, ntw, nchunks;
-  int64_t prow, ldb, nv;
+  int order;                // 0: row tiles fastest, 1: column chunks fastest
+  int64_t prow, nbl, nv;
   int n1;
   int64_t col0, ncols;
   int vec;                  // n1 even: y read two complex at a time
@@ -317,8 +517,10 @@ __global__ __launch_bounds__(256) void dtg_adjoint_kernel(AdjParams P) {
   const int64_t L = (int64_t)(blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
   if (L >= P.nitems) return;
   const int mtot = P.mtb[P.q];
-  const int chunk = (int)(L / mtot);
-  const int mtg = (int)(L - (int64_t)chunk * mtot);
+  // consecutive workgroups on an XCD share either their y columns (row tiles
+  // fastest) or their U1^* rows (column chunks fastest)
+  const int chunk = P.order ? (int)(L % P.nchunks) : (int)(L / mtot);
+  const int mtg = P.order ? (int)(L / P.nchunks) : (int)(L - (int64_t)chunk * mtot);
   int k = 0;
   while (mtg >= P.mtb[k + 1]) ++k;
   const int mt = mtg - P.mtb[k];
@@ -425,16 +627,22 @@ __global__ __launch_bounds__(256) void dtg_adjoint_kernel(AdjParams P) {
         const bool okn = n < P.ncols;
 #pragma unroll
         for (int i = 0; i < ADJ_MBW; ++i) {
-          const int64_t a0 = (int64_t)(mt * ADJ_MT + wm * ADJ_MBW + i) * 16 + 2 * h;
+          const int64_t blk = mt * ADJ_MT + wm * ADJ_MBW + i;
+          const int64_t a0 = blk * 16 + 2 * h;
+          const float* bp = P.B + ((((P.brow[k] >> 4) + blk) * P.nbl + nblk) * 4) * 256 + lane * 4;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int64_t a = a0 + 4 * (e / 2) + (e & 1);
+          for (int g4 = 0; g4 < 4; ++g4) {
+            const int64_t a = a0 + 4 * g4;
             if (okn && a < P.rk[k]) {
-              const float* bp = P.B + (P.brow[k] + a) * P.ldb + (int64_t)nblk * 64 + (lane & 31);
-              const float br = bp[0], bi = bp[32];
-              const float wr = acc[i][jn][2 * e], wi = acc[i][jn][2 * e + 1];
-              dr[i][e] = fmaf(br, wr, fmaf(bi, wi, dr[i][e]));
-              di[i][e] = fmaf(br, wi, fmaf(-bi, wr, di[i][e]));
+              const v4f bv = *(const v4f*)(bp + g4 * 256);
+#pragma unroll
+              for (int e2 = 0; e2 < 2; ++e2) {
+                const int e = 2 * g4 + e2;
+                const float br = bv[2 * e2], bi = bv[2 * e2 + 1];
+                const float wr = acc[i][jn][2 * e], wi = acc[i][jn][2 * e + 1];
+                dr[i][e] = fmaf(br, wr, fmaf(bi, wi, dr[i][e]));
+                di[i][e] = fmaf(br, wi, fmaf(-bi, wr, di[i][e]));
+              }
             }
           }
         }
@@ -481,6 +689,7 @@ __global__ __launch_bounds__(256) void dtg_adjoint_kernel(AdjParams P) {
 // partial dots, in a fixed order (FP64)
 struct AdjReduceParams {
   const TensorMeta* meta;
+  const int32_t* drow;
   const float2* partial;
   float2* x;
   int64_t brow[DTG_MAXQ];
@@ -494,7 +703,7 @@ __global__ void dtg_adjoint_reduce_kernel(AdjReduceParams P) {
   for (int k = 0; k < P.q; ++k) {
     const TensorMeta t = P.meta[(int64_t)k * P.m + j];
     for (int c = 0; c < P.nchunks; ++c) {
-      const float2* src = P.partial + (int64_t)c * P.prow + P.brow[k] + t.arow;
+      const float2* src = P.partial + (int64_t)c * P.prow + P.brow[k] + P.drow[(int64_t)k * P.m + j];
       for (int a = 0; a < t.r1; ++a) {
         sr += src[a].x;
         si += src[a].y;
@@ -510,6 +719,19 @@ decomp_fn decomp_pick(int r2max) {
   if (r2max <= 16) return dtg_decomp_kernel<16>;
   if (r2max <= 32) return dtg_decomp_kernel<32>;
   return dtg_decomp_kernel<64>;
+}
+
+// BF16X3 GEMM instances: nbw 2 and 4 with two chunks per stage (one
+// workgroup per CU), nbw 1 stands for 2 column blocks per wave with one chunk
+// per stage (two workgroups per CU)
+gemm_fn gemm_pick_bf(int mbw, int nbw) {
+  if (mbw == 4 && nbw == 1) return dtg_gemm_bf_kernel<4, 2, 1>;
+  if (mbw == 4 && nbw == 2) return dtg_gemm_bf_kernel<4, 2, 2>;
+  if (mbw == 4 && nbw == 4) return dtg_gemm_bf_kernel<4, 4, 2>;
+  if (mbw == 2 && nbw == 1) return dtg_gemm_bf_kernel<2, 2, 1>;
+  if (mbw == 2 && nbw == 2) return dtg_gemm_bf_kernel<2, 2, 2>;
+  if (mbw == 2 && nbw == 4) return dtg_gemm_bf_kernel<2, 4, 2>;
+  return nullptr;
 }
 
 gemm_fn gemm_pick(int mbw, int nbw) {
@@ -545,29 +767,68 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
     p->dtg_rpad[k] = (p->sum_r1_k[k] + DTG_KC - 1) / DTG_KC * DTG_KC;
     p->dtg_a4off[k + 1] = p->dtg_a4off[k] + p->dtg_rpad[k] * nbtp * 64;
   }
-  std::vector<float> a4((size_t)p->dtg_a4off[g.q], 0.f);
-  for (int64_t j = 0; j < g.m; ++j)
-    for (int k = 0; k < g.q; ++k) {
-      const int64_t t = k + (int64_t)g.q * j;
+  // stacked row of each tensor's first U1 column in A_k (the fused BF16X3
+  // kernels pad tensors to 8-row chunks in their own packing; this one does not)
+  std::vector<int32_t> drow((size_t)g.q * g.m);
+  std::vector<std::vector<int64_t>> owner(g.q);
+  for (int k = 0; k < g.q; ++k) {
+    owner[k].assign(p->dtg_rpad[k], 0);
+    int64_t r = 0;
+    for (int64_t j = 0; j < g.m; ++j) {
       const TensorMeta& M = meta[(size_t)k * g.m + j];
-      for (int a = 0; a < M.r1; ++a) {
-        const int64_t row = M.arow + a;
-        float* base = &a4[p->dtg_a4off[k] + (row / 4) * nbtp * 256 + row % 4];
+      drow[(size_t)k * g.m + j] = (int32_t)r;
+      for (int a = 0; a < M.r1; ++a) owner[k][r + a] = j;
+      r += M.r1;
+    }
+  }
+  // value of the real-embedded stacked U1 of component k at real row mrow
+  // and k-step (stacked row a, part pp), from the tensor owning a
+  auto emb = [&](const std::vector<int64_t>& own, int k, int64_t a, int mrow, int pp) -> double {
+    const int i1 = mrow >> 1, s = mrow & 1;
+    if (i1 >= g.n1 || a >= p->sum_r1_k[k]) return 0.0;
+    const int64_t j = own[a];
+    const int64_t t = k + (int64_t)g.q * j;
+    const int al = (int)(a - drow[(size_t)k * g.m + j]);
+    const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * al;
+    const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
+    return s == pp ? ar : (s == 0 ? -ai : ai);
+  };
+  if (p->precision == TV_PREC_BF16X3) {
+    // hi/lo bf16 in the A-operand order of v_mfma_f32_32x32x16_bf16
+    p->dtg_abfoff.assign(g.q + 1, 0);
+    for (int k = 0; k < g.q; ++k)
+      p->dtg_abfoff[k + 1] = p->dtg_abfoff[k] + p->dtg_rpad[k] / 8 * nbtp * 128;
+    std::vector<uint4> abf((size_t)p->dtg_abfoff[g.q], make_uint4(0, 0, 0, 0));
+    for (int k = 0; k < g.q; ++k)
+      for (int64_t c = 0; c < p->dtg_rpad[k] / 8; ++c)
         for (int blk = 0; blk < nbtp; ++blk)
           for (int lane = 0; lane < 64; ++lane) {
-            const int mrow = 32 * blk + (lane & 31);
-            const int i1 = mrow >> 1, s = mrow & 1, pp = lane >> 5;
-            double v = 0.0;
-            if (i1 < g.n1) {
-              const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * a;
-              const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
-              v = s == pp ? ar : (s == 0 ? -ai : ai);
+            uint32_t hi[8], lo[8];
+            for (int e = 0; e < 8; ++e) {
+              const int64_t a = 8 * c + 4 * (lane >> 5) + e / 2;
+              const float v = (float)emb(owner[k], k, a, 32 * blk + (lane & 31), e % 2);
+              hi[e] = bf16_rne(v);
+              lo[e] = bf16_rne(v - bf16_float(hi[e]));
             }
-            base[((int64_t)blk * 64 + lane) * 4] = (float)v;
+            uint4* dst = &abf[p->dtg_abfoff[k] + ((c * nbtp + blk) * 2) * 64 + lane];
+            dst[0] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16),
+                                hi[4] | (hi[5] << 16), hi[6] | (hi[7] << 16));
+            dst[64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
+                                 lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
           }
+    p->hp.abf = std::move(abf);
+  } else {
+    std::vector<float> a4((size_t)p->dtg_a4off[g.q], 0.f);
+    for (int k = 0; k < g.q; ++k)
+      for (int64_t a = 0; a < p->sum_r1_k[k]; ++a) {
+        float* base = &a4[p->dtg_a4off[k] + (a / 4) * nbtp * 256 + a % 4];
+        for (int blk = 0; blk < nbtp; ++blk)
+          for (int lane = 0; lane < 64; ++lane)
+            base[((int64_t)blk * 64 + lane) * 4] =
+                (float)emb(owner[k], k, a, 32 * blk + (lane & 31), lane >> 5);
       }
-    }
-  p->hp.a4 = std::move(a4);
+    p->hp.a4 = std::move(a4);
+  }
   int64_t rp = 0;
   for (int k = 0; k < g.q; ++k) rp += p->dtg_rpad[k];
   p->dtg_rows = rp;
@@ -588,7 +849,7 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
       const TensorMeta& M = meta[(size_t)k * g.m + j];
       const int mbh = p->dtg_mbh[k];
       for (int al = 0; al < M.r1; ++al) {
-        const int64_t a = M.arow + al;           // stacked row
+        const int64_t a = drow[(size_t)k * g.m + j] + al;   // stacked row
         const int blk = (int)(a / 16), rl = (int)(a % 16);
         for (int i1 = 0; i1 < g.n1; ++i1) {
           const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * al;
@@ -603,13 +864,12 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
       }
     }
   p->hp.ah = std::move(ah);
+  p->hp.drow = std::move(drow);
   p->dtg_packed = true;
   return TV_OK;
 }
 
-bool dtg_supported(const tv_plan_s* p) {
-  return p->dtg_packed && p->grid.q <= DTG_MAXQ && p->precision == TV_PREC_FP32;
-}
+bool dtg_supported(const tv_plan_s* p) { return p->dtg_packed && p->grid.q <= DTG_MAXQ; }
 
 // 32-column blocks of one slab's B rows (a multiple of the widest tile)
 static int64_t dtg_nblocks(const tv_plan_s* p, int s3) {
@@ -628,7 +888,8 @@ static int dtg_t3w(const tv_plan_s* p) {
 
 int64_t dtg_launch_tiles(const tv_plan_s* p, int s3, int nbw) {
   const int64_t cols = (int64_t)p->grid.n2 * std::min(s3, p->grid.n3);
-  return (int64_t)p->grid.q * (p->dtg_nbtp / dtg_mt(p)) * ((cols + 64 * nbw - 1) / (64 * nbw));
+  const int w = nbw == 1 ? 2 : nbw;  // BF16X3's one-chunk stages keep 2 blocks per wave
+  return (int64_t)p->grid.q * (p->dtg_nbtp / dtg_mt(p)) * ((cols + 64 * w - 1) / (64 * w));
 }
 
 // adjoint: row tiles over all components, N tiles per workgroup and chunks
@@ -681,6 +942,7 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
   D.u2t = p->d_u2t;
   D.u3t = p->d_u3t;
   D.x = x;
+  D.drow = p->d_drow;
   D.B = B;
   D.ldb = ldb;
   int64_t acc = 0;
@@ -703,9 +965,15 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
     G.kst[k] = (int)(p->dtg_rpad[k] / DTG_KC);
   }
   const int MT = dtg_mt(p);
-  const int mbw = MT / 2, nbw = p->dtg_nbw;
-  gemm_fn fn = gemm_pick(mbw, nbw);
+  const bool bf = p->precision == TV_PREC_BF16X3;
+  const int mbw = MT / 2, nbw = (bf && p->dtg_nbw == 1) ? 2 : p->dtg_nbw;
+  const int cps = (bf && p->dtg_nbw == 1) ? 1 : 2;
+  gemm_fn fn = bf ? gemm_pick_bf(mbw, p->dtg_nbw) : gemm_pick(mbw, nbw);
   if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no GEMM instance for this tile");
+  if (bf) {
+    G.apack4 = (const float*)p->d_abf;
+    for (int k = 0; k < g.q; ++k) G.a4off[k] = p->dtg_abfoff[k];
+  }
   G.q = g.q;
   G.nbtp = p->dtg_nbtp;
   G.mtiles = p->dtg_nbtp / MT;
@@ -714,12 +982,14 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
   G.nv = (int64_t)g.n1 * g.n2 * g.n3;
   G.n1 = g.n1;
   G.vec4 = (g.n1 % 2 == 0) && ((uintptr_t)out % 16 == 0);
-  const size_t lds = dtg_gemm_lds(mbw, nbw);
+  const size_t lds = bf ? 2 * sizeof(uint4) * (size_t)(cps * 2 * mbw * 128 + cps * 2 * nbw * 128)
+                       : dtg_gemm_lds(mbw, nbw);
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
   const int t3w = dtg_t3w(p);
   D.t3w = t3w;
+  D.layout = p->precision == TV_PREC_BF16X3 ? 2 : 0;
   const size_t hl = sizeof(float2) * (size_t)p->max_r[0] * t3w * p->max_r[1];
   decomp_fn dfn = decomp_pick(p->max_r[1]);
   e = hipFuncSetAttribute((const void*)dfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
@@ -735,7 +1005,10 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
     Z.from[k] = D.brow[k] + p->sum_r1_k[k];
     Z.to[k] = D.brow[k] + p->dtg_rpad[k];
   }
-  hipLaunchKernelGGL(dtg_zero_rows_kernel, dim3(64), dim3(256), 0, st, Z);
+  if (bf)
+    hipLaunchKernelGGL(dtg_zero_rows_bf_kernel, dim3(64), dim3(256), 0, st, Z);
+  else
+    hipLaunchKernelGGL(dtg_zero_rows_kernel, dim3(64), dim3(256), 0, st, Z);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "padding rows");
   for (int i30 = 0; i30 < g.n3; i30 += s3) {
@@ -778,6 +1051,7 @@ tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, voi
   D.u2t = p->d_u2t;
   D.u3t = p->d_u3t;
   D.x = nullptr;
+  D.drow = p->d_drow;
   D.B = B;
   D.ldb = ldb;
   int64_t acc = 0;
@@ -814,7 +1088,8 @@ tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, voi
   A.ntw = AG.ntw;
   A.nchunks = AG.nchunks;
   A.prow = p->dtg_rows;
-  A.ldb = ldb;
+  A.nbl = nbl;
+  A.order = p->dtg_order_a;
   A.nv = (int64_t)g.n1 * g.n2 * g.n3;
   A.n1 = g.n1;
   A.vec = (g.n1 % 2 == 0) && ((uintptr_t)y % 16 == 0);
@@ -824,17 +1099,9 @@ tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, voi
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
 
-  ZeroParams Z;
-  Z.B = B;
-  Z.ldb = ldb;
-  Z.q = g.q;
-  for (int k = 0; k < g.q; ++k) {
-    Z.from[k] = D.brow[k] + p->sum_r1_k[k];
-    Z.to[k] = D.brow[k] + p->dtg_rpad[k];
-  }
-  hipLaunchKernelGGL(dtg_zero_rows_kernel, dim3(64), dim3(256), 0, st, Z);
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_error(e, "padding rows");
+  // rows past the stacked rows and columns past the slab are masked in the
+  // epilogue: no padding to clear
+  D.layout = 1;
   int slab = 0;
   for (int i30 = 0; i30 < g.n3; i30 += s3, ++slab) {
     const int s3a = std::min(s3, g.n3 - i30);
@@ -855,6 +1122,7 @@ tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, voi
   }
   AdjReduceParams R;
   R.meta = p->d_meta;
+  R.drow = p->d_drow;
   R.partial = partial;
   R.x = x;
   for (int k = 0; k < g.q; ++k) R.brow[k] = D.brow[k];

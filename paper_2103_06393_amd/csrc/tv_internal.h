@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -39,7 +40,8 @@ struct HostPack {
   std::vector<TensorMeta> meta;
   std::vector<float2> cores, u1t, u2t, u3t;
   std::vector<float> apack, a4, ah;
-  std::vector<uint4> apack_bf;
+  std::vector<uint4> apack_bf, abf;
+  std::vector<int32_t> drow;
 };
 
 // column-split tables hold up to this many splits per component
@@ -92,6 +94,9 @@ struct tv_plan_s {
   std::vector<int64_t> dtg_a4off;  // float offset of component k in d_apack4
   int64_t dtg_rows = 0;            // sum of dtg_rpad
   float* d_apackh = nullptr;       // adjoint operand: U1^* real-embedded, 4-voxel-row groups
+  uint4* d_abf = nullptr;          // BF16X3 plans: stacked U1 hi/lo in 8-k-step chunks
+  int32_t* d_drow = nullptr;       // first stacked row of each tensor in A_k, [k][j]
+  std::vector<int64_t> dtg_abfoff; // uint4 offset of component k in d_abf
   std::vector<int> dtg_mbh;        // 32-row blocks of the adjoint operand per component
   std::vector<int64_t> dtg_ahoff;  // float offset of component k in d_apackh
   bool with_dtg = true;             // pack the GEMM operands (FP32 plans)
@@ -99,6 +104,7 @@ struct tv_plan_s {
   bool use_dtg[2] = {false, false};
   int dtg_s3 = 1 << 30;            // i3 values per slab of B (forward)
   int dtg_s3_a = 1 << 30;          // i3 values per slab of B (adjoint)
+  int dtg_order_a = 0;             // adjoint GEMM workgroup order (tv_launch_config)
   int dtg_nbw = 2;                 // 32-column blocks per wave of the GEMM tile
   int dtg_split = 1;               // k-step splits of the GEMM
   int max_r[3] = {0, 0, 0};
@@ -155,6 +161,10 @@ tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const 
 size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision);
 // compression scratch of one append call of T tensors (tv_compress.cpp)
 size_t compress_scratch_bytes(const tv_plan_s* p, int T);
+// the autotuners' JSON cache: key -> list of integers (tv_autotune.cpp)
+std::map<std::string, std::vector<int>> read_tune_cache(const char* path);
+void write_tune_cache(const char* path, const std::map<std::string, std::vector<int>>& m);
+std::string device_arch();
 // point-current fields (tv_columns.hip): sources as device [n][6]
 tv_status stage_sources(int n1, int n2, int n3, double h, int64_t n, const double* pos,
                         const double* ori, std::vector<double>& src);

@@ -56,7 +56,8 @@ class tv_plan_info_t(ctypes.Structure):
 
 class tv_launch_config(ctypes.Structure):
     _fields_ = [("path", c_i32), ("tile_t2", c_i32), ("splits", c_i32),
-                ("row_cap", c_i32), ("slab_i3", c_i32), ("gemm_nbw", c_i32)]
+                ("row_cap", c_i32), ("slab_i3", c_i32), ("gemm_nbw", c_i32),
+                ("gemm_order", c_i32)]
 
 
 class TuckVsieError(RuntimeError):
@@ -107,8 +108,17 @@ _tv_rmatvec_noalloc = _sig("tv_rmatvec_noalloc", [c_vp, c_vp, c_i64, c_i32, c_vp
                                                    c_vp])
 _tv_plan_configure = _sig("tv_plan_configure",
                           [c_vp, c_i32, ctypes.POINTER(tv_launch_config)])
-_tv_batch_create = _sig("tv_batch_create", [c_i32, ctypes.POINTER(c_vp), c_i32,
-                                            _ip, ctypes.POINTER(c_vp)])
+class tv_batch_config(ctypes.Structure):
+    _fields_ = [("tsplit", c_i32), ("blocks_per_cu", c_i32)]
+
+
+_tv_batch_create = _sig("tv_batch_create", [c_i32, ctypes.POINTER(c_vp), c_i32, _ip,
+                                            ctypes.POINTER(tv_batch_config),
+                                            ctypes.POINTER(c_vp)])
+_tv_batch_info = _sig("tv_batch_info", [c_vp, ctypes.POINTER(tv_batch_config)])
+_tv_batch_autotune = _sig("tv_batch_autotune", [c_i32, ctypes.POINTER(c_vp), c_i32, _ip,
+                                                ctypes.c_char_p, c_vp,
+                                                ctypes.POINTER(tv_batch_config)])
 _tv_batch_workspace_bytes = _sig("tv_batch_workspace_bytes",
                                  [c_vp, ctypes.POINTER(c_sz)])
 _tv_batch_run = _sig("tv_batch_run", [c_vp, ctypes.POINTER(c_vp),
@@ -142,7 +152,8 @@ EXPORTED = ("tv_plan_from_factors", "tv_plan_required_bytes", "tv_plan_bind_aren
             "tv_rmatvec", "tv_rmatvec_noalloc", "tv_dipole_columns", "tv_compress_begin",
             "tv_compress_workspace_bytes", "tv_compress_append", "tv_plan_finalize",
             "tv_compress_discarded",
-            "tv_autotune", "tv_plan_configure", "tv_batch_create", "tv_batch_required_bytes", "tv_batch_bind_arena",
+            "tv_autotune", "tv_plan_configure", "tv_batch_create", "tv_batch_info", "tv_batch_autotune",
+            "tv_batch_required_bytes", "tv_batch_bind_arena",
             "tv_batch_workspace_bytes", "tv_batch_run",
             "tv_batch_destroy", "tv_aca_workspace_bytes", "tv_aca_matvec",
             "tv_aca_rmatvec", "tv_dipole_rows", "tv_aca_assemble_workspace_bytes",
@@ -303,14 +314,33 @@ def tv_compress_discarded(plan) -> np.ndarray:
     return out
 
 
-def tv_batch_create(plans, op: int, nrhs) -> int:
+def tv_batch_create(plans, op: int, nrhs, tsplit: int = 0, blocks_per_cu: int = 0) -> int:
     n = len(plans)
     parr = (c_vp * n)(*plans)
     r = np.ascontiguousarray(nrhs, dtype=np.int32)
+    cfg = tv_batch_config(int(tsplit), int(blocks_per_cu))
     h = c_vp()
-    _check(_tv_batch_create(n, parr, int(op), r.ctypes.data_as(_ip),
+    _check(_tv_batch_create(n, parr, int(op), r.ctypes.data_as(_ip), ctypes.byref(cfg),
                             ctypes.byref(h)), "tv_batch_create")
     return h.value
+
+
+def tv_batch_info(batch) -> tuple:
+    cfg = tv_batch_config()
+    _check(_tv_batch_info(batch, ctypes.byref(cfg)), "tv_batch_info")
+    return cfg.tsplit, cfg.blocks_per_cu
+
+
+def tv_batch_autotune(plans, op: int, nrhs, cache_path=None, stream=None) -> tuple:
+    """Returns the fastest (tsplit, blocks_per_cu)."""
+    n = len(plans)
+    parr = (c_vp * n)(*plans)
+    r = np.ascontiguousarray(nrhs, dtype=np.int32)
+    cp = None if cache_path is None else str(cache_path).encode()
+    cfg = tv_batch_config()
+    _check(_tv_batch_autotune(n, parr, int(op), r.ctypes.data_as(_ip), cp, stream,
+                              ctypes.byref(cfg)), "tv_batch_autotune")
+    return cfg.tsplit, cfg.blocks_per_cu
 
 
 def tv_batch_workspace_bytes(batch: int) -> int:
@@ -334,9 +364,9 @@ def tv_batch_destroy(batch: int) -> None:
 
 def tv_plan_configure(plan: int, op: int, path: int = 0, tile_t2: int = 0,
                       splits: int = 1, row_cap: int = 0, slab_i3: int = 0,
-                      gemm_nbw: int = 2) -> None:
+                      gemm_nbw: int = 2, gemm_order: int = 0) -> None:
     cfg = tv_launch_config(int(path), int(tile_t2), int(splits), int(row_cap),
-                           int(slab_i3), int(gemm_nbw))
+                           int(slab_i3), int(gemm_nbw), int(gemm_order))
     _check(_tv_plan_configure(plan, int(op), ctypes.byref(cfg)), "tv_plan_configure")
 
 

@@ -65,10 +65,11 @@ def _device_bytes(n: int) -> torch.Tensor:
     return torch.empty(max(int(n), 256), dtype=torch.uint8, device="cuda")
 
 
-def batch_create(handles, op: int, nrhs):
-    """tv_batch_create plus its device arena: returns (batch handle, arena);
-    the arena tensor must outlive the batch."""
-    b = lib.tv_batch_create(handles, op, nrhs)
+def batch_create(handles, op: int, nrhs, config=(0, 0)):
+    """tv_batch_create (config = (tsplit, blocks_per_cu), zeros: automatic)
+    plus its device arena: returns (batch handle, arena); the arena tensor
+    must outlive the batch."""
+    b = lib.tv_batch_create(handles, op, nrhs, *config)
     try:
         nb = lib.tv_batch_required_bytes(b)
         arena = _device_bytes(nb)

@@ -33,14 +33,14 @@ def test_autotune_keeps_results_and_caches(gpu_lib, tmp_path):
     for op in (0, 1):
         assert lib.tv_workspace_bytes(P.handle, op, 1) == lib.tv_workspace_bytes(Q.handle, op, 1)
     assert np.array_equal(P.matvec(cx(x)).cpu().numpy(), Q.matvec(cx(x)).cpu().numpy())
-    # cached choices are [path, t2, split, row-block cap, slab, GEMM tile]; the
-    # adjoint runs the fused kernels with a cap of 2 or 3
+    # cached choices are [path, t2, split, row-block cap, slab, GEMM tile,
+    # GEMM order]; the fused adjoint has a row-block cap of 2 or 3, the fused
+    # forward 8
     for key, val in entries.items():
-        assert len(val) == 6
-        if key.endswith("op1"):
-            assert val[0] == 0 and val[3] in (2, 3)
-        else:
-            assert val[0] in (0, 1) and (val[0] == 1 or val[3] == 8)
+        assert len(val) == 7
+        assert val[0] in (0, 1)
+        if val[0] == 0:
+            assert val[3] in ((2, 3) if key.endswith("op1") else (8,))
 
 
 @pytest.mark.parametrize("cap,t2", [(2, 32), (3, 32), (3, 2), (2, 2)])
@@ -57,7 +57,7 @@ def test_adjoint_row_block_caps(gpu_lib, tmp_path, cap, t2):
     P.autotune(1, str(cache))
     entries = json.loads(cache.read_text())
     (key,) = [k for k in entries if k.endswith("op1")]
-    cache.write_text(json.dumps({key: [0, t2, 2, cap, 0, 0]}))
+    cache.write_text(json.dumps({key: [0, t2, 2, cap, 0, 0, 0]}))
     Q = TuckerPlan.from_factors(S.dims, S.q, S.m, *abi)
     Q.autotune(1, str(cache))
     info = Q.info

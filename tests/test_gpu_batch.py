@@ -182,3 +182,47 @@ def test_batch_bf16x3(gpu_lib):
         ea = rel_err(got_a[c], om.alg2(S, Y[c]))
         print(f"bf16x3 batched adjoint, plan {c}: rel err {ea:.2e}", flush=True)
         assert ea <= 1e-4, ("adjoint", c, ea)
+
+
+def test_batch_autotune_and_forced_configurations(gpu_lib, c4s, tmp_path):
+    """tv_batch_autotune picks (tsplit, workgroups per CU) by timing, caches
+    the choice, and every configuration it may choose gives the oracle's
+    products (adjoint voxel-tile slices change only the summation order)."""
+    import json
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import batch_create
+    wls, structs, plans = c4s
+    nrhs = [5, 2, 9, 3][:len(plans)]
+    hs = [p.handle for p in plans]
+    cache = tmp_path / "tune.json"
+    st = torch.cuda.current_stream().cuda_stream
+    cfg_f = lib.tv_batch_autotune(hs, 0, nrhs, str(cache), st)
+    cfg_a = lib.tv_batch_autotune(hs, 1, nrhs, str(cache), st)
+    entries = json.loads(cache.read_text())
+    assert len([k for k in entries if k.startswith("b1|")]) == 2
+    assert lib.tv_batch_autotune(hs, 1, nrhs, str(cache), st) == cfg_a   # from the cache
+    X = [workloads.complex_normal((S.m, n), 400 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    Y = [workloads.complex_normal((S.q * S.nv, n), 500 + c) for c, (S, n) in enumerate(zip(structs, nrhs))]
+    cx = lambda a: torch.from_numpy(a.astype(np.complex64)).cuda()  # noqa: E731
+    for op, cfgs in ((0, [cfg_f, (0, 1)]), (1, [cfg_a, (1, 1), (3, 2)])):
+        for cfg in cfgs:
+            b, arena = batch_create(hs, op, nrhs, cfg)
+            try:
+                assert lib.tv_batch_info(b)[1] >= 1
+                ins = [cx(a).t().contiguous().t() for a in (X if op == 0 else Y)]
+                outs = [torch.zeros((p.rows if op == 0 else p.m, n), dtype=torch.complex64,
+                                    device="cuda").t().contiguous().t()
+                        for p, n in zip(plans, nrhs)]
+                ws = torch.empty(lib.tv_batch_workspace_bytes(b), dtype=torch.uint8,
+                                 device="cuda")
+                lib.tv_batch_run(b, [x.data_ptr() for x in ins], [_ld(x) for x in ins],
+                                 [y.data_ptr() for y in outs], [_ld(y) for y in outs],
+                                 ws.data_ptr(), ws.numel(), st)
+                torch.cuda.synchronize()
+                for c, S in enumerate(structs):
+                    ref = om.alg1(S, X[c]) if op == 0 else om.alg2(S, Y[c])
+                    assert_close(outs[c].cpu().numpy(), ref, 1e-5,
+                                 what=f"op {op} config {cfg} coil {c}")
+            finally:
+                lib.tv_batch_destroy(b)

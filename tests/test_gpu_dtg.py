@@ -45,8 +45,9 @@ def test_dtg_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, 
     x2 = rng.standard_normal(m) + 1j * rng.standard_normal(m)
     got2 = P.matvec(torch.from_numpy(x2.astype(np.complex64)).cuda()).cpu().numpy()
     assert_close(got2, om.alg1(S, x2)[:, 0], TOL, terms=fwd_terms(S, x2), what="second call")
-    # the adjoint on the same path and slab
-    lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2)
+    # the adjoint on the same path and slab, both workgroup orders
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2,
+                          gemm_order=seed % 2)
     P._ws.clear()
     assert P.info.kernel[1] == 2
     for rep in range(2):
@@ -80,14 +81,47 @@ def test_dtg_workspace_poisoned_and_multi_rhs(gpu_lib):
     assert_close(got, om.alg1(S, X), TOL, terms=fwd_terms(S, X), what="GEMM path, 3 RHS")
 
 
+@pytest.mark.parametrize("dims,q,m,rmax,seed,slab,nbw,splits", [
+    ((20, 13, 7), 2, 5, 5, 21, 0, 2, 1),
+    ((64, 32, 24), 3, 9, 12, 22, 5, 4, 3),
+    ((96, 40, 33), 3, 6, 20, 23, 16, 4, 1),
+    ((130, 24, 10), 1, 7, 32, 24, 0, 2, 2),
+    ((17, 9, 5), 12, 1, 4, 25, 2, 2, 1),
+    ((64, 32, 24), 3, 9, 12, 26, 5, 1, 1),    # one chunk per stage, 2 workgroups per CU
+    ((160, 20, 9), 2, 5, 10, 27, 0, 1, 2),
+])
+def test_dtg_bf16x3_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, splits):
+    """BF16X3 plans: the stacked GEMM on v_mfma_f32_32x32x16_bf16 with hi/lo
+    operands (hi hi + hi lo + lo hi, FP32 accumulation), B written as bf16
+    hi/lo by the decompression; every entry within 1e-4 of the moduli of its
+    terms (each product carries a relative error of about 2^-17)."""
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    S = random_struct(dims, q, m, rmax, seed)
+    P = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
+                                precision=lib.TV_PREC_BF16X3)
+    lib.tv_plan_configure(P.handle, 0, path=1, splits=splits, slab_i3=slab, gemm_nbw=nbw)
+    P._ws.clear()
+    assert P.info.kernel[0] == 2
+    rng = np.random.default_rng(seed)
+    for rep in range(2):
+        x = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        got = P.matvec(torch.from_numpy(x.astype(np.complex64)).cuda()).cpu().numpy()
+        e = assert_close(got, om.alg1(S, x)[:, 0], 1e-4, terms=fwd_terms(S, x),
+                         what=f"BF16X3 GEMM path Z x, call {rep}")
+        print(f"bf16x3 dtg {dims}: rel err {e:.2e}")
+
+
 def test_dtg_adjoint_poisoned_workspace_and_multi_rhs(gpu_lib):
     import torch
     from paper_2103_06393_amd import lib
     S = random_struct((50, 20, 12), 3, 6, 9, 12)       # even n1: paired y loads
     T = random_struct((33, 9, 7), 2, 4, 7, 13)          # odd n1: single loads
-    for R, slab in ((S, 5), (T, 0)):
+    for R, slab, order in ((S, 5, 0), (T, 0, 1), (S, 0, 1)):
         P = _plan(R)
-        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2)
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2,
+                              gemm_order=order)
         p = 2
         rng = np.random.default_rng(5)
         Y = rng.standard_normal((R.q * R.nv, p)) + 1j * rng.standard_normal((R.q * R.nv, p))
@@ -111,10 +145,8 @@ def test_dtg_refused_configurations(gpu_lib):
     P = _plan(S)
     with pytest.raises(lib.TuckVsieError):
         lib.tv_plan_configure(P.handle, 1, path=1, splits=2, gemm_nbw=2)
-    Q = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
-                                precision=lib.TV_PREC_BF16X3)
     with pytest.raises(lib.TuckVsieError):
-        lib.tv_plan_configure(Q.handle, 0, path=1, splits=1, gemm_nbw=2)
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, gemm_nbw=2, gemm_order=2)
     with pytest.raises(lib.TuckVsieError):
         lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=3)
     assert P.info.kernel[0] != 2 and P.info.kernel[1] != 2   # refusals left no trace

@@ -46,11 +46,12 @@ def test_noalloc_refuses_oversized_scratch(gpu_lib):
     import torch
     from paper_2103_06393_amd import lib
     from paper_2103_06393_amd.ops import TuckerPlan
-    S = random_struct((64, 32, 32), 3, 6, 6, 73)
+    S = random_struct((64, 64, 64), 3, 80, 10, 73)
     P = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S))
     # the decompress-then-GEMM adjoint at one slab needs more than the array
     lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=0, gemm_nbw=2)
     need = lib.tv_workspace_bytes(P.handle, 1, 1)
+    assert need > lib.TV_STATIC_SCRATCH_BYTES
     y = torch.zeros(S.q * S.nv, dtype=torch.complex64, device="cuda")
     x = torch.full((S.m,), 5.0, dtype=torch.complex64, device="cuda")
     if need > lib.TV_STATIC_SCRATCH_BYTES:
