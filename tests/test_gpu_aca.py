@@ -13,7 +13,7 @@ import pytest
 import workloads
 from oracle import aca as oaca
 from oracle import matvec as om
-from tests.plans import assert_close, random_struct, rel_err, struct_to_abi
+from tests.plans import abs_struct, assert_close, random_struct, rel_err, struct_to_abi
 
 pytestmark = pytest.mark.gpu
 TOL_FP32 = 1e-5
@@ -218,6 +218,16 @@ def test_body_coil_1mm_sampled(gpu_lib):
     lhs = np.vdot(yv.cpu().numpy().astype(np.complex128), gy)
     rhs = np.vdot(got_x, x)
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    # U^* y itself on sampled columns against the oracle: with V the identity
+    # (m = r_c) the adjoint returns U^* y, whose entry l is Algorithm 2's inner
+    # product of U's column l with y
+    opI = AcaTuckerOperator(P, torch.eye(rc, dtype=torch.complex64, device="cuda"))
+    uy = opI.rmatvec(yv).cpu().numpy()
+    y64 = yv.cpu().numpy().astype(np.complex128)
+    cols = [0, rc // 2, rc - 1]
+    ref = om.adjoint_entries(S, y64, cols)
+    terms = np.abs(om.adjoint_entries(abs_struct(S), np.abs(y64), cols))
+    assert_close(uy[cols], ref, TOL_FP32, terms=terms, what="1 mm U^* y columns")
 
 
 def test_graph_replay(gpu_lib):

@@ -115,6 +115,25 @@ def test_algorithm3_stops_at_max_terms(gpu_lib):
     assert [tuple(int(v) for v in p) for p in g["pivots"][:8]] == piv_o
 
 
+def test_algorithm3_5mm_box_leading_steps(gpu_lib):
+    """The 5 mm body-coil box of Sec. IV.B.2 (81 x 44 x 108 voxels, PWC, 9450
+    coil elements) for its first steps: the same pivots as the oracle's
+    Algorithm 3 with the same step cap, the norm estimate to 1e-5 and the
+    first columns of V to 1e-4."""
+    wl = workloads.make_bodycoil("aca5", "pwc")
+    steps = 6
+    op, g = _run(wl, 1e-3, steps)
+    R = oaca.aca_tucker(wl, 1e-3, max_rank=steps)
+    assert g["rc"] == R.rc == steps
+    piv_o = list(zip(R.rows, R.cols))
+    assert [tuple(int(v) for v in p) for p in g["pivots"]] == piv_o
+    for k in range(steps):
+        assert abs(g["s"][k] - R.s[k]) <= 1e-5 * R.s[k], k
+    for k in range(3):
+        v_o, v_g = R.V[:, k], g["V"][:, k]
+        assert np.linalg.norm(v_g - v_o) <= 1e-4 * np.linalg.norm(v_o), k
+
+
 def test_argument_errors(gpu_lib):
     lib = gpu_lib
     wl = _box((6, 5, 8), 0.015)
