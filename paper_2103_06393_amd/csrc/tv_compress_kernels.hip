@@ -38,8 +38,11 @@ __device__ __forceinline__ int64_t unfold_index(int d, int64_t i, int64_t o, int
   return o + (int64_t)n1 * n2 * i;
 }
 
-// S_d = A_(d) A_(d)^*, one 64 x 64 tile of one (tensor, mode) per workgroup.
-// grid.x = tensors * 3 * tiles * tiles with tiles = ceil(nmax / 64).
+// S_d = A_(d) A_(d)^*, one 64 x 64 tile (ti <= tj: S is Hermitian, the tile
+// below the diagonal is written as the conjugate transpose) of one (tensor,
+// mode) per workgroup.  The unfolding streams through LDS 16 columns at a
+// time, the next 16 loaded into registers during the current ones' products.
+// grid.x = tensors * 3 * tiles (tiles + 1) / 2 with tiles = ceil(nmax / 64).
 __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A, int ntens,
                                                    int n1, int n2, int n3, int nmax,
                                                    double2* __restrict__ S) {
@@ -47,17 +50,22 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
   __shared__ double2 Xr[64][OC + 1];
   __shared__ double2 Xc[64][OC + 1];
   const int tiles = (nmax + 63) / 64;
+  const int pairs = tiles * (tiles + 1) / 2;
   int64_t b = blockIdx.x;
-  const int tj = (int)(b % tiles);
-  b /= tiles;
-  const int ti = (int)(b % tiles);
-  b /= tiles;
+  int pr = (int)(b % pairs);
+  b /= pairs;
   const int d = (int)(b % 3);
   const int t = (int)(b / 3);
   if (t >= ntens) return;
+  int ti = 0;
+  while (pr >= tiles - ti) {  // pair index -> (ti, tj), ti <= tj
+    pr -= tiles - ti;
+    ++ti;
+  }
+  const int tj = ti + pr;
   const int dims[3] = {n1, n2, n3};
   const int n = dims[d];
-  if (ti * 64 >= n || tj * 64 >= n) return;
+  if (tj * 64 >= n) return;
   const int64_t nv = (int64_t)n1 * n2 * n3;
   const int64_t no = nv / n;
   const double2* At = A + (int64_t)t * nv;
@@ -66,22 +74,41 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
   double2 acc[4][4];
   for (int u = 0; u < 4; ++u)
     for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
-  for (int64_t o0 = 0; o0 < no; o0 += OC) {
-    for (int e = tid; e < 64 * OC; e += 256) {
+  // element e of a stage: (row i, column oc), coalesced along the unfolding's
+  // contiguous index
+  auto coords = [&](int e, int& i, int& oc) {
+    if (d == 0) {
+      i = e % 64;
+      oc = e / 64;
+    } else {
+      oc = e % OC;
+      i = e / OC;
+    }
+  };
+  constexpr int PER = 64 * OC / 256;  // elements per thread per stage
+  double2 pr_r[PER], pr_c[PER];
+  auto gload = [&](int64_t o0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
       int i, oc;
-      if (d == 0) {
-        i = e % 64;
-        oc = e / 64;
-      } else {
-        oc = e % OC;
-        i = e / OC;
-      }
+      coords(tid + 256 * q, i, oc);
       const int64_t o = o0 + oc;
       const int ir = ti * 64 + i, ic = tj * 64 + i;
-      Xr[i][oc] = (ir < n && o < no) ? At[unfold_index(d, ir, o, n1, n2)] : make_double2(0, 0);
-      Xc[i][oc] = (ic < n && o < no) ? At[unfold_index(d, ic, o, n1, n2)] : make_double2(0, 0);
+      pr_r[q] = (ir < n && o < no) ? At[unfold_index(d, ir, o, n1, n2)] : make_double2(0, 0);
+      pr_c[q] = (ic < n && o < no) ? At[unfold_index(d, ic, o, n1, n2)] : make_double2(0, 0);
+    }
+  };
+  gload(0);
+  for (int64_t o0 = 0; o0 < no; o0 += OC) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int i, oc;
+      coords(tid + 256 * q, i, oc);
+      Xr[i][oc] = pr_r[q];
+      Xc[i][oc] = pr_c[q];
     }
     __syncthreads();
+    if (o0 + OC < no) gload(o0 + OC);
     for (int oc = 0; oc < OC; ++oc) {
       double2 a[4], c[4];
       for (int u = 0; u < 4; ++u) a[u] = Xr[r0 + u][oc];
@@ -95,7 +122,10 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
   for (int u = 0; u < 4; ++u)
     for (int v = 0; v < 4; ++v) {
       const int i = ti * 64 + r0 + u, j = tj * 64 + c0 + v;
-      if (i < n && j < n) St[(int64_t)i * n + j] = acc[u][v];
+      if (i < n && j < n) {
+        St[(int64_t)i * n + j] = acc[u][v];
+        if (ti != tj) St[(int64_t)j * n + i] = make_double2(acc[u][v].x, -acc[u][v].y);
+      }
     }
 }
 
@@ -329,7 +359,7 @@ static tv_status last(const char* what) {
 tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
                       hipStream_t st) {
   const int tiles = (nmax + 63) / 64;
-  const int64_t blocks = (int64_t)ntens * 3 * tiles * tiles;
+  const int64_t blocks = (int64_t)ntens * 3 * (tiles * (tiles + 1) / 2);
   hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, ntens, n1, n2,
                      n3, nmax, S);
   return last("gram_kernel");

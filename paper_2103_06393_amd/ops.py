@@ -127,8 +127,8 @@ class TuckerPlan:
         grid = lib.make_grid(*dims, q, m)
         h_plan = lib.tv_compress_begin(grid, tol, rank_min, rank_cap, precision)
         try:
-            if chunk is None:       # about 2 GiB of complex128 columns
-                chunk = max(1, min(m, (2 << 30) // (16 * q * nv), 65535 // q))
+            if chunk is None:       # about 24 GiB of complex128 columns (of 288 GB)
+                chunk = max(1, min(m, (24 << 30) // (16 * q * nv), 65535 // q))
             buf = torch.empty(chunk * q * nv * 2, dtype=torch.float64,
                               device="cuda")
             ws = _device_bytes(lib.tv_compress_workspace_bytes(h_plan, chunk))
