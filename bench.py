@@ -49,6 +49,21 @@ MEASURED_TRAFFIC = {
 }
 
 
+
+KERNEL_FAMILY = {0: "phased", 1: "warp-specialised", 2: "decompress-then-GEMM"}
+
+
+def kernel_label(family, d):
+    """Kernels one product call runs, for the roofline line (d: 0 forward, 1 adjoint)."""
+    if family == 0:
+        return "tv::fused_f32"
+    if family == 1:
+        return "tv::ws_fused"
+    if d == 0:
+        return "tv_matvec call: dtg_decomp_kernel + dtg_gemm_kernel"
+    return ("tv_rmatvec call: dtg_decomp_kernel + dtg_ypack_kernel + dtg_colgemm_kernel + "
+            "dtg_colgemm_reduce_kernel")
+
 def measured_traffic(workload: str, precision: str, direction: str):
     e = MEASURED_TRAFFIC.get((workload, precision, direction))
     if not e:
@@ -240,10 +255,7 @@ def main(argv=None):
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
     d = 1 if dom == "adjoint" else 0
     info = plan.info  # after autotuning: the launch configuration in use
-    kname = {0: "tv::fused_f32", 1: "tv::ws_fused",
-             2: ("tv_matvec call: dtg_decomp_kernel + dtg_gemm_kernel" if d == 0 else
-                 "tv_rmatvec call: dtg_decomp_kernel + dtg_adjoint_kernel + "
-                 "dtg_adjoint_reduce_kernel")}[info.kernel[d]]
+    kname = kernel_label(info.kernel[d], d)
     pname = "fp32" if prec == lib.TV_PREC_FP32 else "bf16x3"
     ach = tf_a if dom == "adjoint" else tf_f
     # the BF16 split executes 3 MFMA products per algorithmic one
@@ -281,8 +293,7 @@ def main(argv=None):
                                             * 1e-3) / 1e12 / peak},
         "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
                    "splits": list(info.splits),
-                   "kernel": [{0: "phased", 1: "warp-specialised",
-                               2: "decompress-then-GEMM"}[v] for v in info.kernel]},
+                   "kernel": [KERNEL_FAMILY[v] for v in info.kernel]},
     }
     if not args.no_cpu:
         cb, cols, y_ref, x_ref = cpu_baseline(wl, plan, x_np, y_np, args.cpu_budget)
@@ -453,10 +464,7 @@ def bench_aca(args):
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
     d = 1 if dom == "adjoint" else 0
     info = plan.info
-    kname = {0: "tv::fused_f32", 1: "tv::ws_fused",
-             2: ("tv_matvec call: dtg_decomp_kernel + dtg_gemm_kernel" if d == 0 else
-                 "tv_rmatvec call: dtg_decomp_kernel + dtg_adjoint_kernel + "
-                 "dtg_adjoint_reduce_kernel")}[info.kernel[d]]
+    kname = kernel_label(info.kernel[d], d)
     ach = tf_a if dom == "adjoint" else tf_f
     peak = PEAK_FP32_MFMA if prec == lib.TV_PREC_FP32 else PEAK_BF16_MFMA / 3.0
     mode1 = 8.0 * wl.grid.n1 * wl.grid.n2 * wl.grid.n3 * info.sum_r1

@@ -94,7 +94,8 @@ typedef struct {
    * tile extent along i2 and i3, column splits, and the kernel family
    * (0: phased, 1: warp-specialised producer/consumer, 2: decompress-then-
    * GEMM, for which tile_t2 is the i3 values per slab, tile_t3 the GEMM's
-   * column blocks per wave and splits its k-step split count)              */
+   * column blocks per wave (adjoint: row blocks) and splits its k-step
+   * (adjoint: column) split count)                                         */
   int32_t tile_t2[2], tile_t3[2], splits[2], kernel[2];
 } tv_plan_info_t;
 
@@ -180,10 +181,13 @@ tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
  *     the workspace, then the forward runs Y^k_(1) = A_k B_k as one MFMA
  *     GEMM per component (gemm_nbw = 2 or 4 column blocks per wave; for
  *     BF16X3 plans also 1: two blocks per wave with 8 k-steps per LDS stage
- *     and two workgroups per CU; splits k-step splits), the adjoint W = A_k^* Y^k_(1) with the conjugated dot
- *     against B_k in the GEMM's epilogue (splits 1, gemm_nbw 2, gemm_order
- *     0: consecutive workgroups share columns of y, 1: share rows of A_k^*)
- *     and a fixed-order FP64 sum per column (Algorithms 1 and 2, Sec. III.B).
+ *     and two workgroups per CU; splits k-step splits); the adjoint takes
+ *     Algorithm 2's sum over voxel columns first: Z_k = Y^k_(1) B_k^* as one
+ *     GEMM per slab over the slab's columns (gemm_nbw 2 or 4 blocks of 32
+ *     stacked rows per wave, splits 1..64 column splits, gemm_order 0:
+ *     workgroups sharing B rows adjacent, 1: sharing y columns adjacent),
+ *     one FP32 partial per slab and split, then x'_j = sum conj(U1_j) Z_k
+ *     with the partials summed in FP64 (Algorithms 1 and 2, Sec. III.B).
  * TV_ERR_INVALID_ARG / TV_ERR_NOT_SUPPORTED for a configuration the plan
  * cannot run; the previous configuration is then kept.  Afterwards
  * tv_workspace_bytes reflects the configuration. */

@@ -122,7 +122,6 @@ static size_t arena_layout(tv_plan_s* p, char* base) {
   carve(&p->d_split_f, splits);
   carve(&p->d_split_a, splits);
   carve(&p->d_apack4, h.a4.size() * sizeof(float));
-  carve(&p->d_apackh, h.ah.size() * sizeof(float));
   carve(&p->d_abf, h.abf.size() * sizeof(uint4));
   carve(&p->d_drow, h.drow.size() * sizeof(int32_t));
   return (off + 255) & ~(size_t)255;
@@ -135,7 +134,7 @@ static void clear_device_pointers(tv_plan_s* p) {
   p->d_apack_bf = nullptr;
   p->d_apack_koff = nullptr;
   p->d_split_f = p->d_split_a = nullptr;
-  p->d_apack4 = p->d_apackh = nullptr;
+  p->d_apack4 = nullptr;
   p->d_abf = nullptr;
   p->d_drow = nullptr;
   p->bound = false;
@@ -378,7 +377,6 @@ static tv_status bind_arena(tv_plan_s* p, void* arena, size_t bytes, hipStream_t
   put(p->d_apack_bf, h.apack_bf.data(), h.apack_bf.size() * sizeof(uint4));
   put(p->d_apack_koff, p->apack_koff.data(), p->apack_koff.size() * sizeof(int64_t));
   put(p->d_apack4, h.a4.data(), h.a4.size() * sizeof(float));
-  put(p->d_apackh, h.ah.data(), h.ah.size() * sizeof(float));
   put(p->d_abf, h.abf.data(), h.abf.size() * sizeof(uint4));
   put(p->d_drow, h.drow.data(), h.drow.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -585,9 +583,10 @@ tv_status tv_plan_info(tv_plan p, tv_plan_info_t* info) {
     info->kernel[o] = (p->finalized && p->kernel_ws[o] && ws_supported(p, T, o == 1)) ? 1 : 0;
     if (p->use_dtg[o] && dtg_supported(p)) {
       info->kernel[o] = 2;
-      info->splits[o] = o == 0 ? p->dtg_split : 1;
+      info->splits[o] = o == 0 ? p->dtg_split
+                               : dtg_colgemm_splits(p, std::min(p->dtg_s3_a, p->grid.n3));
       info->tile_t2[o] = std::min(o == 0 ? p->dtg_s3 : p->dtg_s3_a, p->grid.n3);  // slab
-      info->tile_t3[o] = o == 0 ? p->dtg_nbw : 2;
+      info->tile_t3[o] = o == 0 ? p->dtg_nbw : p->dtg_nbw_a;
     }
   }
   return TV_OK;

@@ -26,7 +26,7 @@ static std::string plan_key(const tv_plan_s* p, int op) {
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "k6|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k7|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -113,9 +113,14 @@ static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
     if (c.slab_i3 < 0) return set_error(TV_ERR_INVALID_ARG, "slab_i3 must be >= 0");
     const int slab = c.slab_i3 ? std::min(c.slab_i3, p->grid.n3) : p->grid.n3;
     if (op == 1) {
-      if (c.splits != 1 || c.gemm_nbw != 2 || (c.gemm_order != 0 && c.gemm_order != 1))
-        return set_error(TV_ERR_INVALID_ARG,
-                         "the adjoint GEMM takes splits 1, gemm_nbw 2, gemm_order 0 or 1");
+      if (c.gemm_nbw != 2 && c.gemm_nbw != 4)
+        return set_error(TV_ERR_INVALID_ARG, "the adjoint GEMM takes gemm_nbw 2 or 4");
+      if (c.splits < 1 || c.splits > 64)
+        return set_error(TV_ERR_INVALID_ARG, "the adjoint GEMM takes splits 1..64");
+      if (c.gemm_order != 0 && c.gemm_order != 1)
+        return set_error(TV_ERR_INVALID_ARG, "the adjoint GEMM takes gemm_order 0 or 1");
+      p->dtg_split_a = c.splits;
+      p->dtg_nbw_a = c.gemm_nbw;
       p->dtg_s3_a = slab;
       p->dtg_order_a = c.gemm_order;
       p->use_dtg[1] = true;
@@ -158,9 +163,9 @@ static tv_launch_config current_config(const tv_plan_s* p, int op) {
   tv_launch_config c{};
   if (p->use_dtg[op]) {
     c.path = 1;
-    c.splits = op == 0 ? p->dtg_split : 1;
+    c.splits = op == 0 ? p->dtg_split : p->dtg_split_a;
     c.slab_i3 = op == 0 ? p->dtg_s3 : p->dtg_s3_a;
-    c.gemm_nbw = op == 0 ? p->dtg_nbw : 2;
+    c.gemm_nbw = op == 0 ? p->dtg_nbw : p->dtg_nbw_a;
     c.gemm_order = op == 0 ? 0 : p->dtg_order_a;
     return c;
   }
@@ -246,9 +251,39 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
           apply_config(p, o, keep);
           if (need > ((size_t)16 << 30)) continue;
           if (o == 1) {
-            for (int order : {0, 1}) {
-              c.gemm_order = order;
-              cands.push_back(c);
+            // the column GEMM: both tiles and workgroup orders, column
+            // splits from the fewest giving 1024 workgroups to the fewest
+            // giving 4096 (as launched: at least the accumulation-chain
+            // minimum; the partials of Z within 4 GiB where that allows)
+            const int nslabs = (g.n3 + slab - 1) / slab;
+            for (int cnbw : {2, 4}) {
+              const int64_t tiles = dtg_colgemm_tiles(p, cnbw);
+              std::vector<int> sps;
+              int last = 0;
+              for (int sp = 1; sp <= 64; sp *= 2) {
+                const int keep_split = p->dtg_split_a;
+                p->dtg_split_a = sp;
+                const int eff = dtg_colgemm_splits(p, std::min(slab, g.n3));
+                p->dtg_split_a = keep_split;
+                if (eff == last) continue;
+                if (!sps.empty() && (double)nslabs * eff * p->dtg_rows * g.n1 * 8 >
+                                        4.0 * (1u << 30))
+                  break;
+                if (tiles * eff >= 1024 || sp == 64) {
+                  sps.push_back(sp);
+                  last = eff;
+                  if (tiles * eff >= 4096 || sp == 64) break;
+                }
+              }
+              if (sps.empty()) sps.push_back(1);
+              for (int sp : sps)
+                for (int order : {0, 1}) {
+                  tv_launch_config cc = c;
+                  cc.gemm_nbw = cnbw;
+                  cc.splits = sp;
+                  cc.gemm_order = order;
+                  cands.push_back(cc);
+                }
             }
             continue;
           }

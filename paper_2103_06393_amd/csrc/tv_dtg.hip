@@ -51,22 +51,9 @@ struct DecompParams {
   int64_t m;
   int n2, n3, i30, s3, nsub;
   int t3w;           // i3 values per decompression workgroup
-  int layout;        // 0: FP32 planar (forward), 1: FP32 accumulator order
-                     // (adjoint), 2: BF16 hi/lo operand order (forward, BF16X3)
+  int layout;        // 0: FP32 planar, 2: BF16 hi/lo operand order (BF16X3 forward)
   int64_t nitems;
 };
-
-// Adjoint layout of B: stacked rows in blocks of 16 (a row block of the
-// adjoint GEMM's 32x32 accumulator), float offset
-// ((R/16 * nbl + n/32) * 4 + g) * 256 + lane * 4 + 2 e + (Re, Im) for row R
-// with R%16 = 4 g + 2 h + e and lane = 32 h + n%32: a lane of the GEMM's
-// epilogue finds the values matching its accumulator registers 4g..4g+3 in
-// one 16-byte load.
-__host__ __device__ inline int64_t adj_b_index(int64_t R, int64_t n, int64_t nbl) {
-  const int al = (int)(R & 15);
-  const int g = al >> 2, h = (al >> 1) & 1, e = al & 1;
-  return (((R >> 4) * nbl + (n >> 5)) * 4 + g) * 256 + (32 * h + (n & 31)) * 4 + 2 * e;
-}
 
 // BF16X3 layout of B: stacked rows in chunks of 8, per (chunk, 32-column
 // block) the hi then the lo halves as 64 lanes x 8 bf16, lane 32 h + n%32
@@ -153,9 +140,7 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
           }
         }
         const int64_t n = i2 + (int64_t)P.n2 * (i3a + i3l - P.i30);
-        if (P.layout == 1) {
-          *(float2*)(P.B + adj_b_index(row0 + a, n, nbl)) = make_float2(sr, si);
-        } else if (P.layout == 2) {
+        if (P.layout == 2) {
           const uint32_t hr = bf16_rne(sr), hi_ = bf16_rne(si);
           const uint32_t lr = bf16_rne(sr - bf16_float(hr)), li = bf16_rne(si - bf16_float(hi_));
           uint32_t* dst = (uint32_t*)P.B + bf_b_index(row0 + a, n, nbl);
@@ -477,240 +462,279 @@ __global__ __launch_bounds__(256, CPS == 1 ? 2 : 1) void dtg_gemm_bf_kernel(Gemm
 
 typedef void (*gemm_fn)(GemmParams);
 
-// ---- adjoint: W_k = A_k^* Y^k_(1) on MFMA, then the conjugated dot with the
-// unscaled decompression B_k (Algorithm 2's inner products at the mode-1
-// output), summed per stacked row -------------------------------------------
+// ---- adjoint as a GEMM over voxel columns ---------------------------------
+// Algorithm 2's inner products with the sum over the columns (i2, i3) taken
+// first: Z_k = Y^k_(1) B_k^* (n1 x stacked rows, contraction over the slab's
+// columns, one partial per slab and column split), then x'_j = sum_k
+// sum_{a of j} sum_i1 conj(U1_j[i1][a]) Z_k[i1][row of a] with the partials
+// summed in FP64.  Z is a plain GEMM with the forward kernel's tile and stage
+// structure; the final sum is a small pass.
 //
-// A^* operand (apackh): per component, M = (a, s) rows (a stacked row of A_k,
-// s = Re/Im), K = (i1, t) (t = Re/Im of y); float index
-// ((i1/4 * mbh + blk) * 64 + lane) * 4 + i1%4 holds Ah_emb[32 blk + lane%32]
-// [(i1, lane/32)], Ah_emb[(a,s)][(i1,t)] = Ur if s == t, Ui if s = 0, t = 1,
-// -Ui if s = 1, t = 0 (U = U1[i1][a]): rows (a, Re), (a, Im) of U1^* y.
-struct AdjParams {
-  const float* apackh;
-  const float* B;
+// A operand (ypack, per slab): y^k real-embedded, M = (i1, s) rows
+// interleaved as in the forward, K = (column n, t = Re/Im):
+// [(i1,Re)][(n,Re)] = Re y, [(i1,Re)][(n,Im)] = Im y, [(i1,Im)][(n,Re)] =
+// Im y, [(i1,Im)][(n,Im)] = -Re y (so the accumulator holds Re and Im of
+// y conj(b)); float index ((n/4 * nbtp + blk) * 64 + lane) * 4 + n%4 per
+// component, the layout of the forward's A operand.
+// B operand: B_k as the forward writes it (row R, 32-column blocks of Re then
+// Im); lane 32 t + R%32 of an MFMA reads four consecutive columns of one row
+// with one 16-byte load, staged in LDS with a 32-float pad between k-step
+// groups (the global-to-LDS copy is then free of bank conflicts).
+struct YPackParams {
   const float2* y;
-  float2* partial;          // [chunk][prow] complex: sum over the chunk's columns
-  int64_t ahoff[DTG_MAXQ];
+  float* yp;
+  int64_t ystride;          // floats per component
+  int64_t nv;
+  int64_t col0, ncols, ngrp;  // slab's first column, width, 4-column groups packed
+  int n1, nbtp, q;
+};
+__global__ void dtg_ypack_kernel(YPackParams P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)P.q * P.ngrp * P.nbtp * 64;
+  if (idx >= total) return;
+  const int lane = (int)(idx & 63);
+  int64_t rest = idx >> 6;
+  const int blk = (int)(rest % P.nbtp);
+  rest /= P.nbtp;
+  const int64_t gq = rest % P.ngrp;
+  const int k = (int)(rest / P.ngrp);
+  const int mrow = 32 * blk + (lane & 31), i1 = mrow >> 1, s = mrow & 1, t = lane >> 5;
+  v4f v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t n = 4 * gq + e;
+    float val = 0.f;
+    if (n < P.ncols && i1 < P.n1) {
+      const float2 c = P.y[(int64_t)k * P.nv + (P.col0 + n) * P.n1 + i1];
+      val = s == 0 ? (t == 0 ? c.x : c.y) : (t == 0 ? c.y : -c.x);
+    }
+    v[e] = val;
+  }
+  *(v4f*)(P.yp + (int64_t)k * P.ystride + ((gq * P.nbtp + blk) * 64 + lane) * 4) = v;
+}
+
+struct ColGemmParams {
+  const float* ypack;
+  const float* B;
+  float2* z;                // this slab's [split][stacked row][i1] complex
+  int64_t ystride;          // floats per component of ypack
+  int64_t zsplit;           // complex per split of z
   int64_t brow[DTG_MAXQ];
-  int64_t rk[DTG_MAXQ];     // stacked rows of A_k
-  int mbh[DTG_MAXQ];        // 32-row blocks of the A^* operand per component
-  int mtb[DTG_MAXQ + 1];    // prefix sum of row tiles over components
-  int q, kst, ntiles, ntw, nchunks;
-  int order;                // 0: row tiles fastest, 1: column chunks fastest
-  int64_t prow, nbl, nv;
+  int64_t rk[DTG_MAXQ];
+  int ntb[DTG_MAXQ + 1];    // prefix sum over components of the N tiles
+  int q, nbtp, mtiles, S;
+  int order;                // 0: row tiles fastest, 1: N tiles fastest
+  int64_t ldb;
   int n1;
-  int64_t col0, ncols;
-  int vec;                  // n1 even: y read two complex at a time
+  int64_t ncols;            // columns of the slab
+  int vec4;
   int64_t nitems;
 };
+constexpr int COL_BPAD = 32;
 
-constexpr int ADJ_MBW = 4, ADJ_NBW = 2;
-constexpr int ADJ_MT = 2 * ADJ_MBW, ADJ_NBT = 2 * ADJ_NBW;
-constexpr int ADJ_YS = ADJ_NBT * 64 + 4;     // LDS row stride of the y stage (floats)
-constexpr int ADJ_A_ST = 4 * ADJ_MT * 64 * 4;
-constexpr int ADJ_Y_ST = DTG_KC * ADJ_YS;
-
-__global__ __launch_bounds__(256) void dtg_adjoint_kernel(AdjParams P) {
+template <int MBW, int NBW>
+__global__ __launch_bounds__(256) void dtg_colgemm_kernel(ColGemmParams P) {
+  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
+  constexpr int A_ST = 4 * MT * 64 * 4;
+  constexpr int KGS = NBT * 64 * 4 + COL_BPAD;   // floats per k-step group of B
+  constexpr int B_ST = 4 * KGS;
   extern __shared__ float lds[];
   const int64_t nwg = gridDim.x;
   const int64_t L = (int64_t)(blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
   if (L >= P.nitems) return;
-  const int mtot = P.mtb[P.q];
-  // consecutive workgroups on an XCD share either their y columns (row tiles
-  // fastest) or their U1^* rows (column chunks fastest)
-  const int chunk = P.order ? (int)(L % P.nchunks) : (int)(L / mtot);
-  const int mtg = P.order ? (int)(L / P.nchunks) : (int)(L - (int64_t)chunk * mtot);
+  const int ntot = P.ntb[P.q];
+  int mt, ntg;
+  int64_t rest;
+  if (P.order == 0) {
+    mt = (int)(L % P.mtiles);
+    rest = L / P.mtiles;
+    ntg = (int)(rest % ntot);
+    rest /= ntot;
+  } else {
+    ntg = (int)(L % ntot);
+    rest = L / ntot;
+    mt = (int)(rest % P.mtiles);
+    rest /= P.mtiles;
+  }
+  const int s = (int)rest;
   int k = 0;
-  while (mtg >= P.mtb[k + 1]) ++k;
-  const int mt = mtg - P.mtb[k];
-  const int nt0 = chunk * P.ntw, nt1 = min(P.ntiles, nt0 + P.ntw);
-  const int total = (nt1 - nt0) * P.kst;
+  while (ntg >= P.ntb[k + 1]) ++k;
+  const int nt = ntg - P.ntb[k];
+  const int nst = (int)((P.ncols + DTG_KC - 1) / DTG_KC);
+  const int st0 = (int)((int64_t)nst * s / P.S), st1 = (int)((int64_t)nst * (s + 1) / P.S);
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1, h = lane >> 5;
-  const float* Ag = P.apackh + P.ahoff[k];
-  const float2* yk = P.y + (int64_t)k * P.nv;
-  const int mbh = P.mbh[k];
+  const int wm = w >> 1, wn = w & 1;
+  const float* Ag = P.ypack + (int64_t)k * P.ystride;
+  const float* Bg = P.B + P.brow[k] * P.ldb;
+  const int64_t rk = P.rk[k];
 
-  v4f ra[ADJ_MT], ry[4];
-  auto gload = [&](int g) {
-    const int nt = nt0 + g / P.kst, st = g % P.kst;
+  v4f ra[MT], rb[NBT];
+  auto gload = [&](int st) {
 #pragma unroll
-    for (int c = 0; c < ADJ_MT; ++c) {
+    for (int c = 0; c < MT; ++c) {
       const int u = c * 256 + tid;
-      const int kg = u / (ADJ_MT * 64), rem = u % (ADJ_MT * 64);
-      ra[c] = *(const v4f*)(Ag + ((((int64_t)st * 4 + kg) * mbh + mt * ADJ_MT + rem / 64) * 64 +
+      const int kg = u / (MT * 64), rem = u % (MT * 64);
+      ra[c] = *(const v4f*)(Ag + ((((int64_t)st * 4 + kg) * P.nbtp + mt * MT + rem / 64) * 64 +
                                   rem % 64) * 4);
     }
+    // u = row-in-8 | kg | t | row-of-8: one instruction reads 8 rows x (Re,
+    // Im) x 16 columns, 64-byte runs
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NBT; ++c) {
       const int u = c * 256 + tid;
-      const int col = u / 8, i1 = st * DTG_KC + 2 * (u % 8);
-      const int64_t n = (int64_t)nt * (ADJ_NBT * 32) + col;
+      const int r8 = u & 7, kg = (u >> 3) & 3, t = (u >> 5) & 1;
+      const int64_t R = (int64_t)nt * (NBT * 32) + (u >> 6) * 8 + r8;
+      const int64_t n = (int64_t)st * DTG_KC + kg * 4;
       v4f v = v4f{0.f, 0.f, 0.f, 0.f};
-      if (n < P.ncols) {
-        const float2* src = yk + (int64_t)P.n1 * (P.col0 + n) + i1;
-        if (P.vec) {
-          if (i1 < P.n1) v = *(const v4f*)src;
+      if (R < rk) {
+        const float* src = Bg + R * P.ldb + (n >> 5) * 64 + t * 32 + (n & 31);
+        if (n + 4 <= P.ncols) {
+          v = *(const v4f*)src;
         } else {
-          if (i1 < P.n1) { const float2 a = src[0]; v[0] = a.x; v[1] = a.y; }
-          if (i1 + 1 < P.n1) { const float2 b = src[1]; v[2] = b.x; v[3] = b.y; }
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (n + e < P.ncols) v[e] = src[e];
         }
       }
-      ry[c] = v;
+      rb[c] = v;
     }
   };
   auto lstore = [&](int buf) {
-    float* As = lds + buf * (ADJ_A_ST + ADJ_Y_ST);
-    float* Ys = As + ADJ_A_ST;
+    float* As = lds + buf * (A_ST + B_ST);
+    float* Bs = As + A_ST;
 #pragma unroll
-    for (int c = 0; c < ADJ_MT; ++c) *(v4f*)(As + (c * 256 + tid) * 4) = ra[c];
+    for (int c = 0; c < MT; ++c) *(v4f*)(As + (c * 256 + tid) * 4) = ra[c];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NBT; ++c) {
       const int u = c * 256 + tid;
-      const int col = u / 8, r = 2 * (u % 8);
-      float* d = Ys + r * ADJ_YS + (col / 32) * 64 + (col & 31);
-      d[0] = ry[c][0];
-      d[32] = ry[c][1];
-      d[ADJ_YS] = ry[c][2];
-      d[ADJ_YS + 32] = ry[c][3];
+      const int r8 = u & 7, kg = (u >> 3) & 3, t = (u >> 5) & 1;
+      const int R = (u >> 6) * 8 + r8;
+      *(v4f*)(Bs + kg * KGS + ((R >> 5) * 64 + 32 * t + (R & 31)) * 4) = rb[c];
     }
   };
 
-  v16f acc[ADJ_MBW][ADJ_NBW];
-  float dr[ADJ_MBW][8], di[ADJ_MBW][8];   // per lane: rows 4g + 2h + e of each block
+  v16f acc[MBW][NBW];
 #pragma unroll
-  for (int i = 0; i < ADJ_MBW; ++i) {
+  for (int i = 0; i < MBW; ++i)
 #pragma unroll
-    for (int jn = 0; jn < ADJ_NBW; ++jn) acc[i][jn] = v16f{0.f};
-#pragma unroll
-    for (int e = 0; e < 8; ++e) dr[i][e] = di[i][e] = 0.f;
-  }
+    for (int jn = 0; jn < NBW; ++jn) acc[i][jn] = v16f{0.f};
 
-  if (total > 0) {
-    gload(0);
+  if (st0 < st1) {
+    gload(st0);
     lstore(0);
   }
   __syncthreads();
-  for (int g = 0; g < total; ++g) {
-    const int buf = g & 1;
-    if (g + 1 < total) gload(g + 1);
-    const float* As = lds + buf * (ADJ_A_ST + ADJ_Y_ST);
-    const float* Ys = As + ADJ_A_ST;
+  for (int st = st0; st < st1; ++st) {
+    const int buf = (st - st0) & 1;
+    if (st + 1 < st1) gload(st + 1);
+    const float* As = lds + buf * (A_ST + B_ST);
+    const float* Bs = As + A_ST;
 #pragma unroll
     for (int kg = 0; kg < 4; ++kg) {
-      v4f a[ADJ_MBW];
+      v4f a[MBW], b[NBW];
 #pragma unroll
-      for (int i = 0; i < ADJ_MBW; ++i)
-        a[i] = *(const v4f*)(As + ((kg * ADJ_MT + wm * ADJ_MBW + i) * 64 + lane) * 4);
+      for (int i = 0; i < MBW; ++i)
+        a[i] = *(const v4f*)(As + ((kg * MT + wm * MBW + i) * 64 + lane) * 4);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        float b[ADJ_NBW];
+      for (int jn = 0; jn < NBW; ++jn)
+        b[jn] = *(const v4f*)(Bs + kg * KGS + ((wn * NBW + jn) * 64 + lane) * 4);
 #pragma unroll
-        for (int jn = 0; jn < ADJ_NBW; ++jn)
-          b[jn] = Ys[(kg * 4 + kk) * ADJ_YS + (wn * ADJ_NBW + jn) * 64 + lane];
+      for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-        for (int i = 0; i < ADJ_MBW; ++i)
+        for (int i = 0; i < MBW; ++i)
 #pragma unroll
-          for (int jn = 0; jn < ADJ_NBW; ++jn)
-            acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[jn], acc[i][jn], 0, 0, 0);
-      }
+          for (int jn = 0; jn < NBW; ++jn)
+            acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[jn][kk], acc[i][jn], 0, 0, 0);
     }
-    if (g % P.kst == P.kst - 1) {
-      // the tile's W is complete: conjugated dot with B over its columns
-      const int nt = nt0 + g / P.kst;
-#pragma unroll
-      for (int jn = 0; jn < ADJ_NBW; ++jn) {
-        const int nblk = nt * ADJ_NBT + wn * ADJ_NBW + jn;
-        const int64_t n = (int64_t)nblk * 32 + (lane & 31);
-        const bool okn = n < P.ncols;
-#pragma unroll
-        for (int i = 0; i < ADJ_MBW; ++i) {
-          const int64_t blk = mt * ADJ_MT + wm * ADJ_MBW + i;
-          const int64_t a0 = blk * 16 + 2 * h;
-          const float* bp = P.B + ((((P.brow[k] >> 4) + blk) * P.nbl + nblk) * 4) * 256 + lane * 4;
-#pragma unroll
-          for (int g4 = 0; g4 < 4; ++g4) {
-            const int64_t a = a0 + 4 * g4;
-            if (okn && a < P.rk[k]) {
-              const v4f bv = *(const v4f*)(bp + g4 * 256);
-#pragma unroll
-              for (int e2 = 0; e2 < 2; ++e2) {
-                const int e = 2 * g4 + e2;
-                const float br = bv[2 * e2], bi = bv[2 * e2 + 1];
-                const float wr = acc[i][jn][2 * e], wi = acc[i][jn][2 * e + 1];
-                dr[i][e] = fmaf(br, wr, fmaf(bi, wi, dr[i][e]));
-                di[i][e] = fmaf(br, wi, fmaf(-bi, wr, di[i][e]));
-              }
-            }
-          }
-        }
-        // next tile starts from zero
-#pragma unroll
-        for (int i = 0; i < ADJ_MBW; ++i) acc[i][jn] = v16f{0.f};
-      }
-    }
-    if (g + 1 < total) lstore(buf ^ 1);
+    if (st + 1 < st1) lstore(buf ^ 1);
     __syncthreads();
   }
 
-  // sum over the 32 columns of each half-wave, then over the two waves along N
+  // accumulator rows (i1, Re/Im) pairs: registers 4g..4g+3 are (Re, Im) of
+  // i1, i1 + 1; column = stacked row R of component k
+  float2* zs = P.z + (int64_t)s * P.zsplit;
 #pragma unroll
-  for (int i = 0; i < ADJ_MBW; ++i)
+  for (int jn = 0; jn < NBW; ++jn) {
+    const int64_t R = ((int64_t)nt * NBT + wn * NBW + jn) * 32 + (lane & 31);
+    if (R >= rk) continue;
+    float2* col = zs + (P.brow[k] + R) * P.n1;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
+    for (int i = 0; i < MBW; ++i) {
+      const int blk = mt * MT + wm * MBW + i;
 #pragma unroll
-      for (int off = 16; off >= 1; off >>= 1) {
-        dr[i][e] += __shfl_xor(dr[i][e], off, 64);
-        di[i][e] += __shfl_xor(di[i][e], off, 64);
+      for (int g = 0; g < 4; ++g) {
+        const int i1 = blk * 16 + 4 * g + 2 * (lane >> 5);
+        const v16f& d = acc[i][jn];
+        if (i1 + 1 < P.n1 && P.vec4) {
+          *(v4f*)(col + i1) = v4f{d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]};
+        } else {
+          if (i1 < P.n1) col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
+          if (i1 + 1 < P.n1) col[i1 + 1] = make_float2(d[4 * g + 2], d[4 * g + 3]);
+        }
       }
-  float2* red = (float2*)lds;   // [wn][rows of the tile: 128 a]
-  if ((lane & 31) == 0) {
-#pragma unroll
-    for (int i = 0; i < ADJ_MBW; ++i)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int al = (wm * ADJ_MBW + i) * 16 + 2 * h + 4 * (e / 2) + (e & 1);
-        red[wn * (ADJ_MT * 16) + al] = make_float2(dr[i][e], di[i][e]);
-      }
-  }
-  __syncthreads();
-  if (tid < ADJ_MT * 16) {
-    const int64_t a = (int64_t)mt * ADJ_MT * 16 + tid;
-    if (a < P.rk[k]) {
-      const float2 u = red[tid], v = red[ADJ_MT * 16 + tid];
-      P.partial[(int64_t)chunk * P.prow + P.brow[k] + a] = make_float2(u.x + v.x, u.y + v.y);
     }
   }
 }
 
-// x'_j = sum over components, chunks and the tensor's stacked rows of the
-// partial dots, in a fixed order (FP64)
-struct AdjReduceParams {
+// x'_j = sum_k sum_{a < r1} sum_i1 conj(U1_j[i1][a]) sum_s Z_s[row a][i1]
+// over the partials s of every slab and split, in FP64, one workgroup per
+// column j, fixed order
+struct ColReduceParams {
   const TensorMeta* meta;
   const int32_t* drow;
-  const float2* partial;
+  const float2* u1t;
+  const float2* z;
   float2* x;
   int64_t brow[DTG_MAXQ];
-  int64_t prow, m;
-  int q, nchunks;
+  int64_t zsplit, m;
+  int q, S, n1;
 };
-__global__ void dtg_adjoint_reduce_kernel(AdjReduceParams P) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P.m) return;
+__global__ __launch_bounds__(256) void dtg_colgemm_reduce_kernel(ColReduceParams P) {
+  __shared__ double red[2][256];
+  const int64_t j = blockIdx.x;
   double sr = 0.0, si = 0.0;
   for (int k = 0; k < P.q; ++k) {
     const TensorMeta t = P.meta[(int64_t)k * P.m + j];
-    for (int c = 0; c < P.nchunks; ++c) {
-      const float2* src = P.partial + (int64_t)c * P.prow + P.brow[k] + P.drow[(int64_t)k * P.m + j];
+    const int64_t r0 = P.brow[k] + P.drow[(int64_t)k * P.m + j];
+    for (int i1 = threadIdx.x; i1 < P.n1; i1 += 256) {
+      const float2* u = P.u1t + t.u1_off + (int64_t)i1 * t.r1;
       for (int a = 0; a < t.r1; ++a) {
-        sr += src[a].x;
-        si += src[a].y;
+        double zr = 0.0, zi = 0.0;
+        for (int s = 0; s < P.S; ++s) {
+          const float2 z = P.z[(int64_t)s * P.zsplit + (r0 + a) * P.n1 + i1];
+          zr += z.x;
+          zi += z.y;
+        }
+        const double ur = u[a].x, ui = u[a].y;
+        sr += ur * zr + ui * zi;
+        si += ur * zi - ui * zr;
       }
     }
   }
-  P.x[j] = make_float2((float)sr, (float)si);
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = si;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) P.x[j] = make_float2((float)red[0][0], (float)red[1][0]);
+}
+
+typedef void (*colgemm_fn)(ColGemmParams);
+colgemm_fn colgemm_pick(int mbw, int nbw) {
+  if (mbw == 4 && nbw == 2) return dtg_colgemm_kernel<4, 2>;
+  if (mbw == 4 && nbw == 4) return dtg_colgemm_kernel<4, 4>;
+  if (mbw == 2 && nbw == 2) return dtg_colgemm_kernel<2, 2>;
+  if (mbw == 2 && nbw == 4) return dtg_colgemm_kernel<2, 4>;
+  return nullptr;
+}
+size_t colgemm_lds(int mbw, int nbw) {
+  return 2 * sizeof(float) * (size_t)(4 * 2 * mbw * 64 * 4 + 4 * (2 * nbw * 64 * 4 + COL_BPAD));
 }
 
 typedef void (*decomp_fn)(DecompParams);
@@ -753,8 +777,7 @@ size_t dtg_gemm_lds(int mbw, int nbw) {
   return 2 * sizeof(float) * (size_t)(4 * 2 * mbw * 64 * 4 + DTG_KC * 2 * nbw * 64);
 }
 
-// Pack A_k for the forward GEMM and A_k^* for the adjoint's (called at plan
-// finalisation, FP32 plans).
+// Pack A_k for the forward GEMM (called at plan finalisation).
 tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
   const tv_grid& g = p->grid;
   if (g.q > DTG_MAXQ) return TV_OK;
@@ -833,37 +856,6 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
   for (int k = 0; k < g.q; ++k) rp += p->dtg_rpad[k];
   p->dtg_rows = rp;
 
-  // A^* operand of the adjoint: 256-row tiles (128 stacked rows), K = n1
-  // padded to 16 voxel rows
-  const int n1p = (g.n1 + DTG_KC - 1) / DTG_KC * DTG_KC;
-  p->dtg_mbh.assign(g.q, 0);
-  p->dtg_ahoff.assign(g.q + 1, 0);
-  for (int k = 0; k < g.q; ++k) {
-    p->dtg_mbh[k] = (int)((2 * p->sum_r1_k[k] + 255) / 256 * 8);
-    p->dtg_ahoff[k + 1] = p->dtg_ahoff[k] + (int64_t)n1p * p->dtg_mbh[k] * 64;
-  }
-  std::vector<float> ah((size_t)p->dtg_ahoff[g.q], 0.f);
-  for (int64_t j = 0; j < g.m; ++j)
-    for (int k = 0; k < g.q; ++k) {
-      const int64_t t = k + (int64_t)g.q * j;
-      const TensorMeta& M = meta[(size_t)k * g.m + j];
-      const int mbh = p->dtg_mbh[k];
-      for (int al = 0; al < M.r1; ++al) {
-        const int64_t a = drow[(size_t)k * g.m + j] + al;   // stacked row
-        const int blk = (int)(a / 16), rl = (int)(a % 16);
-        for (int i1 = 0; i1 < g.n1; ++i1) {
-          const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * al;
-          const float ur = (float)p->u1[2 * src], ui = (float)p->u1[2 * src + 1];
-          float* base = &ah[p->dtg_ahoff[k] + (((int64_t)(i1 / 4) * mbh + blk) * 64) * 4 + i1 % 4];
-          for (int sidx = 0; sidx < 2; ++sidx)
-            for (int tt = 0; tt < 2; ++tt) {
-              const int lane = 32 * tt + 2 * rl + sidx;
-              base[lane * 4] = sidx == tt ? ur : (sidx == 0 ? ui : -ui);
-            }
-        }
-      }
-    }
-  p->hp.ah = std::move(ah);
   p->hp.drow = std::move(drow);
   p->dtg_packed = true;
   return TV_OK;
@@ -892,22 +884,27 @@ int64_t dtg_launch_tiles(const tv_plan_s* p, int s3, int nbw) {
   return (int64_t)p->grid.q * (p->dtg_nbtp / dtg_mt(p)) * ((cols + 64 * w - 1) / (64 * w));
 }
 
-// adjoint: row tiles over all components, N tiles per workgroup and chunks
-// per slab (about 2048 workgroups per launch)
-struct AdjGeom {
-  int mtot, ntiles, ntw, nchunks, nslabs;
-};
-static AdjGeom adj_geom(const tv_plan_s* p, int s3) {
-  AdjGeom G;
-  G.mtot = 0;
-  for (int k = 0; k < p->grid.q; ++k) G.mtot += p->dtg_mbh[k] / ADJ_MT;
+int64_t dtg_colgemm_tiles(const tv_plan_s* p, int nbw) {
+  int64_t nt = 0;
+  for (int k = 0; k < p->grid.q; ++k) nt += (p->sum_r1_k[k] + 64 * nbw - 1) / (64 * nbw);
+  return nt * (p->dtg_nbtp / dtg_mt(p));
+}
+
+// the column-contraction adjoint: ypack floats per component, z complex per split
+static int64_t col_ystride(const tv_plan_s* p, int s3) {
   const int64_t cols = (int64_t)p->grid.n2 * s3;
-  G.ntiles = (int)((cols + ADJ_NBT * 32 - 1) / (ADJ_NBT * 32));
-  const int64_t want = std::max<int64_t>(1, ((int64_t)G.ntiles * G.mtot + 2047) / 2048);
-  G.ntw = (int)std::min<int64_t>(want, G.ntiles);
-  G.nchunks = (G.ntiles + G.ntw - 1) / G.ntw;
-  G.nslabs = (p->grid.n3 + s3 - 1) / s3;
-  return G;
+  return (cols + DTG_KC - 1) / DTG_KC * DTG_KC / 4 * p->dtg_nbtp * 256;
+}
+static int64_t col_zsplit(const tv_plan_s* p) { return p->dtg_rows * p->grid.n1; }
+
+// column splits of the adjoint GEMM per slab of s3 values of i3: the
+// configured count, raised so that no FP32 accumulation chain spans more than
+// COL_CHAIN_STAGES LDS stages (2048 columns; the partials meet in FP64)
+constexpr int COL_CHAIN_STAGES = 128;
+int dtg_colgemm_splits(const tv_plan_s* p, int s3) {
+  const int64_t nst = ((int64_t)p->grid.n2 * s3 + DTG_KC - 1) / DTG_KC;
+  return (int)std::max<int64_t>(std::max(1, p->dtg_split_a),
+                                (nst + COL_CHAIN_STAGES - 1) / COL_CHAIN_STAGES);
 }
 
 size_t dtg_workspace_bytes(const tv_plan_s* p, int op) {
@@ -915,8 +912,9 @@ size_t dtg_workspace_bytes(const tv_plan_s* p, int op) {
   const int s3 = std::min(op == 0 ? p->dtg_s3 : p->dtg_s3_a, p->grid.n3);
   const size_t b = (size_t)p->dtg_rows * dtg_nblocks(p, s3) * 64 * sizeof(float);
   if (op == 1) {
-    const AdjGeom G = adj_geom(p, s3);
-    return b + (size_t)8 * G.nslabs * G.nchunks * p->dtg_rows;
+    const int64_t nslabs = (p->grid.n3 + s3 - 1) / s3;
+    return b + (size_t)p->grid.q * col_ystride(p, s3) * sizeof(float) +
+           (size_t)nslabs * dtg_colgemm_splits(p, s3) * col_zsplit(p) * sizeof(float2);
   }
   const int64_t rows = (int64_t)p->grid.q * p->grid.n1 * p->grid.n2 * p->grid.n3;
   const size_t part = p->dtg_split > 1 ? (size_t)8 * p->dtg_split * rows : 0;
@@ -1033,17 +1031,25 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
   return TV_OK;
 }
 
-tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,
-                             hipStream_t st) {
-  if (!dtg_supported(p)) return set_error(TV_ERR_NOT_SUPPORTED, "decompress-then-GEMM not packed");
+// Adjoint by the column contraction: per slab, the unscaled B_k (forward
+// layout), y packed as the GEMM's A operand, the slab's partials of Y B^*;
+// then the FP64 sum of all partials against conj(U1) per column.
+static tv_status launch_dtg_colgemm_adjoint(const tv_plan_s* p, const float2* y, float2* x,
+                                            void* ws, hipStream_t st) {
   const tv_grid& g = p->grid;
   const int s3 = std::min(p->dtg_s3_a, g.n3);
   const int64_t nbl = dtg_nblocks(p, s3);
   const int64_t ldb = nbl * 64;
   float* B = (float*)ws;
   const size_t bbytes = (size_t)p->dtg_rows * ldb * sizeof(float);
-  float2* partial = (float2*)((char*)ws + bbytes);
-  const AdjGeom AG = adj_geom(p, s3);
+  const int64_t ystride = col_ystride(p, s3);
+  float* yp = (float*)((char*)ws + bbytes);
+  float2* z = (float2*)((char*)yp + (size_t)g.q * ystride * sizeof(float));
+  const int S = dtg_colgemm_splits(p, s3);
+  const int MT = dtg_mt(p);
+  const int mbw = MT / 2, nbw = p->dtg_nbw_a;
+  colgemm_fn fn = colgemm_pick(mbw, nbw);
+  if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no adjoint GEMM instance for this tile");
 
   DecompParams D;
   D.meta = p->d_meta;
@@ -1064,44 +1070,48 @@ tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, voi
   D.n3 = g.n3;
   const int t3w = dtg_t3w(p);
   D.t3w = t3w;
+  D.layout = 0;
   const size_t hl = sizeof(float2) * (size_t)p->max_r[0] * t3w * p->max_r[1];
   decomp_fn dfn = decomp_pick(p->max_r[1]);
   hipError_t e = hipFuncSetAttribute((const void*)dfn,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
 
-  AdjParams A;
-  A.apackh = p->d_apackh;
-  A.B = B;
-  A.y = y;
-  A.q = g.q;
-  A.mtb[0] = 0;
+  YPackParams Y;
+  Y.y = y;
+  Y.yp = yp;
+  Y.ystride = ystride;
+  Y.nv = (int64_t)g.n1 * g.n2 * g.n3;
+  Y.n1 = g.n1;
+  Y.nbtp = p->dtg_nbtp;
+  Y.q = g.q;
+
+  ColGemmParams C;
+  C.ypack = yp;
+  C.B = B;
+  C.z = z;
+  C.ystride = ystride;
+  C.zsplit = col_zsplit(p);
+  C.ntb[0] = 0;
+  const int ntile_rows = 64 * nbw;
   for (int k = 0; k < g.q; ++k) {
-    A.ahoff[k] = p->dtg_ahoff[k];
-    A.brow[k] = D.brow[k];
-    A.rk[k] = p->sum_r1_k[k];
-    A.mbh[k] = p->dtg_mbh[k];
-    A.mtb[k + 1] = A.mtb[k] + p->dtg_mbh[k] / ADJ_MT;
+    C.brow[k] = D.brow[k];
+    C.rk[k] = p->sum_r1_k[k];
+    C.ntb[k + 1] = C.ntb[k] + (int)((p->sum_r1_k[k] + ntile_rows - 1) / ntile_rows);
   }
-  A.kst = (g.n1 + DTG_KC - 1) / DTG_KC;
-  A.ntiles = AG.ntiles;
-  A.ntw = AG.ntw;
-  A.nchunks = AG.nchunks;
-  A.prow = p->dtg_rows;
-  A.nbl = nbl;
-  A.order = p->dtg_order_a;
-  A.nv = (int64_t)g.n1 * g.n2 * g.n3;
-  A.n1 = g.n1;
-  A.vec = (g.n1 % 2 == 0) && ((uintptr_t)y % 16 == 0);
-  A.nitems = (int64_t)AG.mtot * AG.nchunks;
-  const size_t lds = 2 * sizeof(float) * (size_t)(ADJ_A_ST + ADJ_Y_ST);
-  e = hipFuncSetAttribute((const void*)dtg_adjoint_kernel,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  C.q = g.q;
+  C.nbtp = p->dtg_nbtp;
+  C.mtiles = p->dtg_nbtp / MT;
+  C.S = S;
+  C.order = p->dtg_order_a;
+  C.ldb = ldb;
+  C.n1 = g.n1;
+  C.vec4 = (g.n1 % 2 == 0) && ((uintptr_t)z % 16 == 0);
+  C.nitems = (int64_t)C.mtiles * C.ntb[g.q] * S;
+  const size_t lds = colgemm_lds(mbw, nbw);
+  e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
 
-  // rows past the stacked rows and columns past the slab are masked in the
-  // epilogue: no padding to clear
-  D.layout = 1;
   int slab = 0;
   for (int i30 = 0; i30 < g.n3; i30 += s3, ++slab) {
     const int s3a = std::min(s3, g.n3 - i30);
@@ -1112,28 +1122,42 @@ tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, voi
     hipLaunchKernelGGL(dfn, dim3((unsigned)D.nitems), dim3(256), hl, st, D);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "slab decompression launch");
-    A.col0 = (int64_t)g.n2 * i30;
-    A.ncols = (int64_t)g.n2 * s3a;
-    A.partial = partial + (int64_t)slab * AG.nchunks * p->dtg_rows;
-    const int64_t grid = (A.nitems + 7) / 8 * 8;
-    hipLaunchKernelGGL(dtg_adjoint_kernel, dim3((unsigned)grid), dim3(256), lds, st, A);
+    const int64_t ncols = (int64_t)g.n2 * s3a;
+    Y.col0 = (int64_t)g.n2 * i30;
+    Y.ncols = ncols;
+    Y.ngrp = (ncols + DTG_KC - 1) / DTG_KC * DTG_KC / 4;
+    const int64_t yth = (int64_t)g.q * Y.ngrp * Y.nbtp * 64;
+    hipLaunchKernelGGL(dtg_ypack_kernel, dim3((unsigned)((yth + 255) / 256)), dim3(256), 0, st, Y);
     e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(e, "adjoint GEMM launch");
+    if (e != hipSuccess) return hip_error(e, "adjoint operand packing launch");
+    C.ncols = ncols;
+    C.z = z + (int64_t)slab * S * C.zsplit;
+    const int64_t grid = (C.nitems + 7) / 8 * 8;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(256), lds, st, C);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "adjoint column GEMM launch");
   }
-  AdjReduceParams R;
+  ColReduceParams R;
   R.meta = p->d_meta;
   R.drow = p->d_drow;
-  R.partial = partial;
+  R.u1t = p->d_u1t;
+  R.z = z;
   R.x = x;
   for (int k = 0; k < g.q; ++k) R.brow[k] = D.brow[k];
-  R.prow = p->dtg_rows;
+  R.zsplit = C.zsplit;
   R.m = g.m;
   R.q = g.q;
-  R.nchunks = AG.nslabs * AG.nchunks;
-  hipLaunchKernelGGL(dtg_adjoint_reduce_kernel, dim3((unsigned)((g.m + 255) / 256)), dim3(256), 0,
-                     st, R);
+  R.S = slab * S;
+  R.n1 = g.n1;
+  hipLaunchKernelGGL(dtg_colgemm_reduce_kernel, dim3((unsigned)g.m), dim3(256), 0, st, R);
   e = hipGetLastError();
   return e == hipSuccess ? TV_OK : hip_error(e, "adjoint reduction launch");
+}
+
+tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,
+                             hipStream_t st) {
+  if (!dtg_supported(p)) return set_error(TV_ERR_NOT_SUPPORTED, "decompress-then-GEMM not packed");
+  return launch_dtg_colgemm_adjoint(p, y, x, ws, st);
 }
 
 }  // namespace tv

@@ -39,7 +39,7 @@ struct Tiling {
 struct HostPack {
   std::vector<TensorMeta> meta;
   std::vector<float2> cores, u1t, u2t, u3t;
-  std::vector<float> apack, a4, ah;
+  std::vector<float> apack, a4;
   std::vector<uint4> apack_bf, abf;
   std::vector<int32_t> drow;
 };
@@ -93,18 +93,17 @@ struct tv_plan_s {
   std::vector<int64_t> dtg_rpad;   // rows of A_k padded to 16, per component
   std::vector<int64_t> dtg_a4off;  // float offset of component k in d_apack4
   int64_t dtg_rows = 0;            // sum of dtg_rpad
-  float* d_apackh = nullptr;       // adjoint operand: U1^* real-embedded, 4-voxel-row groups
   uint4* d_abf = nullptr;          // BF16X3 plans: stacked U1 hi/lo in 8-k-step chunks
   int32_t* d_drow = nullptr;       // first stacked row of each tensor in A_k, [k][j]
   std::vector<int64_t> dtg_abfoff; // uint4 offset of component k in d_abf
-  std::vector<int> dtg_mbh;        // 32-row blocks of the adjoint operand per component
-  std::vector<int64_t> dtg_ahoff;  // float offset of component k in d_apackh
   bool with_dtg = true;             // pack the GEMM operands (FP32 plans)
   bool dtg_packed = false;          // the GEMM operands are part of the plan
   bool use_dtg[2] = {false, false};
   int dtg_s3 = 1 << 30;            // i3 values per slab of B (forward)
   int dtg_s3_a = 1 << 30;          // i3 values per slab of B (adjoint)
   int dtg_order_a = 0;             // adjoint GEMM workgroup order (tv_launch_config)
+  int dtg_split_a = 1;             // column splits of the adjoint's column GEMM
+  int dtg_nbw_a = 4;               // 32-row blocks per wave along N of that GEMM
   int dtg_nbw = 2;                 // 32-column blocks per wave of the GEMM tile
   int dtg_split = 1;               // k-step splits of the GEMM
   int max_r[3] = {0, 0, 0};
@@ -148,6 +147,8 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta);
 bool dtg_supported(const tv_plan_s* p);
 size_t dtg_workspace_bytes(const tv_plan_s* p, int op);
 int64_t dtg_launch_tiles(const tv_plan_s* p, int s3, int nbw);  // workgroups of one GEMM launch
+int64_t dtg_colgemm_tiles(const tv_plan_s* p, int nbw);  // adjoint column GEMM tiles per split
+int dtg_colgemm_splits(const tv_plan_s* p, int s3);     // its column splits as launched
 tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, void* ws,
                              hipStream_t st);
 tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,

@@ -1,6 +1,7 @@
 """The decompress-then-GEMM form of Algorithms 1 and 2 (slabs of the stacked
 operand B written by the decompression kernel, then one MFMA GEMM per
-component; the adjoint's conjugated dot in the GEMM's epilogue) against the
+component; the adjoint's contraction over voxel columns as its own GEMM
+followed by the FP64 sum against conj(U1)) against the
 FP64 oracle, in every configuration the autotuner may choose: slab sizes
 (ragged last slab), GEMM tiles, k-step splits, ragged voxel rows and columns,
 ranks up to 32 and single-column plans."""
@@ -45,8 +46,8 @@ def test_dtg_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, 
     x2 = rng.standard_normal(m) + 1j * rng.standard_normal(m)
     got2 = P.matvec(torch.from_numpy(x2.astype(np.complex64)).cuda()).cpu().numpy()
     assert_close(got2, om.alg1(S, x2)[:, 0], TOL, terms=fwd_terms(S, x2), what="second call")
-    # the adjoint on the same path and slab, both workgroup orders
-    lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2,
+    # the adjoint on the same path and slab, tile and splits, both workgroup orders
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=splits, slab_i3=slab, gemm_nbw=nbw,
                           gemm_order=seed % 2)
     P._ws.clear()
     assert P.info.kernel[1] == 2
@@ -55,6 +56,38 @@ def test_dtg_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, 
         gx = P.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
         assert_close(gx, om.alg2(S, y)[:, 0], TOL, terms=adj_terms(S, y),
                      what=f"GEMM path Z^* y, call {rep}")
+
+
+@pytest.mark.parametrize("dims,q,m,rmax,seed,slab,nbw,splits,order", [
+    ((20, 13, 7), 2, 5, 5, 31, 0, 2, 1, 0),     # 91 columns: a ragged 4-column group
+    ((64, 32, 24), 3, 9, 12, 32, 5, 4, 3, 1),   # five slabs (ragged last), 3 splits each
+    ((96, 40, 33), 3, 6, 20, 33, 16, 4, 2, 0),  # last slab of 40 columns, 6 blocks padded to 8
+    ((130, 24, 10), 1, 7, 32, 34, 0, 2, 5, 1),  # n1 > 128: 2 row tiles, ranks to 32
+    ((256, 16, 9), 3, 4, 10, 35, 3, 4, 1, 0),   # 16 row blocks
+    ((17, 9, 5), 12, 1, 4, 36, 2, 2, 64, 1),    # q = 12, one column, splits past the stages
+    ((33, 9, 7), 2, 4, 7, 37, 0, 4, 2, 0),      # odd n1: element-wise partial stores
+])
+def test_dtg_column_adjoint_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, splits,
+                                           order):
+    """The adjoint with the sum over voxel columns first (Z_k = Y B_k^* as a
+    GEMM over the slab's columns, one partial per slab and split, then the
+    FP64 sum against conj(U1)) in every tile, split and order the autotuner
+    may choose, two calls on one workspace."""
+    import torch
+    from paper_2103_06393_amd import lib
+    S = random_struct(dims, q, m, rmax, seed)
+    P = _plan(S)
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=splits, slab_i3=slab, gemm_nbw=nbw,
+                          gemm_order=order)
+    P._ws.clear()
+    info = P.info
+    assert info.kernel[1] == 2 and info.splits[1] == splits and info.tile_t3[1] == nbw
+    rng = np.random.default_rng(seed)
+    for rep in range(2):
+        y = rng.standard_normal(S.q * S.nv) + 1j * rng.standard_normal(S.q * S.nv)
+        gx = P.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
+        assert_close(gx, om.alg2(S, y)[:, 0], TOL, terms=adj_terms(S, y),
+                     what=f"column-GEMM adjoint Z^* y, call {rep}")
 
 
 def test_dtg_workspace_poisoned_and_multi_rhs(gpu_lib):
@@ -118,9 +151,10 @@ def test_dtg_adjoint_poisoned_workspace_and_multi_rhs(gpu_lib):
     from paper_2103_06393_amd import lib
     S = random_struct((50, 20, 12), 3, 6, 9, 12)       # even n1: paired y loads
     T = random_struct((33, 9, 7), 2, 4, 7, 13)          # odd n1: single loads
-    for R, slab, order in ((S, 5, 0), (T, 0, 1), (S, 0, 1)):
+    for R, slab, order, nbw, splits in ((S, 5, 0, 2, 1), (T, 0, 1, 2, 1), (S, 0, 1, 2, 1),
+                                        (S, 5, 0, 4, 3), (T, 0, 1, 4, 2)):
         P = _plan(R)
-        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, slab_i3=slab, gemm_nbw=2,
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=splits, slab_i3=slab, gemm_nbw=nbw,
                               gemm_order=order)
         p = 2
         rng = np.random.default_rng(5)
@@ -144,9 +178,11 @@ def test_dtg_refused_configurations(gpu_lib):
     S = random_struct((20, 13, 7), 2, 3, 5, 1)
     P = _plan(S)
     with pytest.raises(lib.TuckVsieError):
-        lib.tv_plan_configure(P.handle, 1, path=1, splits=2, gemm_nbw=2)
-    with pytest.raises(lib.TuckVsieError):
         lib.tv_plan_configure(P.handle, 1, path=1, splits=1, gemm_nbw=2, gemm_order=2)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, gemm_nbw=3, gemm_order=0)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=65, gemm_nbw=4, gemm_order=1)
     with pytest.raises(lib.TuckVsieError):
         lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=3)
     assert P.info.kernel[0] != 2 and P.info.kernel[1] != 2   # refusals left no trace
