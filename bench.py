@@ -39,12 +39,28 @@ MEASURED_TRAFFIC = {
         "source": "paper_2103_06393_amd/csrc/tv_fused_ws.hip",
         "sha256": "445803172685202790421745ad3263a637dd9c270cce35e2892f0a98b7a0314b",
         "profile": "profiles/ws_fused_c2_fp32_pmc.md",
+        "launch": {"kernel": 1},
+    },
+    ("c5", "fp32", "adjoint"): {
+        "bytes": 143918913172,
+        "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
+        "sha256": "9049465408b4a2b7e9fb9b75addaea219f3d5346e76b6936ecc4460ad5428e1b",
+        "profile": "profiles/dtg_c5_fp32_pmc.md",
+        "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 16},
+    },
+    ("c5", "fp32", "forward"): {
+        "bytes": 58639544760,
+        "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
+        "sha256": "9049465408b4a2b7e9fb9b75addaea219f3d5346e76b6936ecc4460ad5428e1b",
+        "profile": "profiles/dtg_c5_fp32_pmc.md",
+        "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 1},
     },
     ("aca2-pwc", "fp32", "adjoint"): {
         "bytes": 3657544232,
         "source": "paper_2103_06393_amd/csrc/tv_fused_ws.hip",
         "sha256": "445803172685202790421745ad3263a637dd9c270cce35e2892f0a98b7a0314b",
         "profile": "profiles/aca_tucker_aca2_pwc_pmc.md",
+        "launch": {"kernel": 1},
     },
 }
 
@@ -64,12 +80,20 @@ def kernel_label(family, d):
     return ("tv_rmatvec call: dtg_decomp_kernel + dtg_ypack_kernel + dtg_colgemm_kernel + "
             "dtg_colgemm_reduce_kernel")
 
-def measured_traffic(workload: str, precision: str, direction: str):
+def measured_traffic(workload: str, precision: str, direction: str, info=None):
+    """HBM bytes per call from the committed counter profile, or None when
+    the kernel source or the launch configuration differs from the profiled one."""
     e = MEASURED_TRAFFIC.get((workload, precision, direction))
     if not e:
         return None
     with open(os.path.join(ROOT, e["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != e["sha256"]:
+            return None
+    if info is not None:
+        d = 1 if direction == "adjoint" else 0
+        have = {"kernel": info.kernel[d], "tile_t2": info.tile_t2[d],
+                "tile_t3": info.tile_t3[d], "splits": info.splits[d]}
+        if any(have[k] != v for k, v in e["launch"].items()):
             return None
     return e["bytes"]
 
@@ -284,7 +308,7 @@ def main(argv=None):
         "roofline": {"kernel": f"{kname} ({dom})", "bound": "mfma",
                      "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                      "frac": ach / peak,
-                     "traffic": measured_traffic(wl.name, pname, dom),
+                     "traffic": measured_traffic(wl.name, pname, dom, info),
                      # the stacked mode-1 product alone (8 nv sum r1 flops, all
                      # on the matrix cores) over the same duration
                      "mode1_achieved": mode1 / ((adj_ms if dom == "adjoint" else fwd_ms)
@@ -495,7 +519,7 @@ def bench_aca(args):
                      "frac": ach / peak,
                      "traffic": None if args.natural_ranks else measured_traffic(
                          f"{wl.name}-{args.basis}", "fp32" if prec == lib.TV_PREC_FP32
-                         else "bf16x3", dom)},
+                         else "bf16x3", dom, info)},
         "launch": {"tile_t2": list(info.tile_t2), "tile_t3": list(info.tile_t3),
                    "splits": list(info.splits)},
     }
