@@ -46,7 +46,16 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* Enumerations are int32 in C and C++ alike; in C++ the fixed underlying
+ * type makes every int32 value a valid enumerator value, so an unknown value
+ * passed by a caller is refused instead of being undefined behaviour. */
+#ifdef __cplusplus
+#define TV_ENUM(tag) enum tag : int32_t
+#else
+#define TV_ENUM(tag) enum tag
+#endif
+
+typedef TV_ENUM(tv_status_e) {
   TV_OK = 0,
   TV_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad enum    */
   TV_ERR_SHAPE = -2,         /* grid / leading dimension inconsistent    */
@@ -62,7 +71,7 @@ typedef enum {
  * FP32 MFMA with FP32 accumulation.  BF16X3: every FP32 operand x is split
  * into bf16 hi = rn(x), lo = rn(x - hi) and a*b is formed as
  * hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation. */
-typedef enum { TV_PREC_FP32 = 0, TV_PREC_BF16X3 = 1 } tv_precision;
+typedef TV_ENUM(tv_precision_e) { TV_PREC_FP32 = 0, TV_PREC_BF16X3 = 1 } tv_precision;
 
 /* Flag ORed into the `basis` argument of the field entry points
  * (tv_dipole_columns, tv_dipole_rows, tv_aca_assemble): the K operator of
@@ -140,7 +149,9 @@ tv_status tv_plan_info(tv_plan plan, tv_plan_info_t* info);
 /* Copy the ranks (int32[q*m][3]) and, if the pointers are non-NULL, the
  * complex128 factors of a plan back to host arrays in the layout of
  * tv_plan_from_factors (sizes from tv_plan_info / the ranks).  Synchronous.
- * Factors are returned as stored (FP32 values widened to FP64). */
+ * Factors are returned in FP64 as the plan keeps them on the host (the
+ * values given to tv_plan_from_factors, or the compression's FP64 factors);
+ * the products use their FP32 rounding. */
 tv_status tv_plan_export_factors(tv_plan plan, int32_t* ranks, double* cores,
                                  double* u1, double* u2, double* u3);
 

@@ -17,16 +17,27 @@ def _info(kernel, t2, t3, splits):
                                  splits=[splits, splits])
 
 
-def test_traffic_only_for_the_profiled_launch():
-    e = bench.MEASURED_TRAFFIC[("c5", "fp32", "adjoint")]
-    L = e["launch"]
+def test_traffic_only_for_the_profiled_launch(monkeypatch):
+    import hashlib
+    src = "paper_2103_06393_amd/csrc/tv_dtg.hip"
+    cur = hashlib.sha256((ROOT / src).read_bytes()).hexdigest()
+    L = {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 16}
+    table = {("w", "fp32", "adjoint"): {"bytes": 123, "source": src, "sha256": cur,
+                                         "profile": "profiles/dtg_c5_fp32_pmc.md",
+                                         "launch": L},
+             ("w", "fp32", "forward"): {"bytes": 456, "source": src, "sha256": "0" * 64,
+                                         "profile": "profiles/dtg_c5_fp32_pmc.md",
+                                         "launch": L}}
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", table)
     ok = _info(L["kernel"], L["tile_t2"], L["tile_t3"], L["splits"])
-    assert bench.measured_traffic("c5", "fp32", "adjoint", ok) == e["bytes"]
+    assert bench.measured_traffic("w", "fp32", "adjoint", ok) == 123
     other = _info(L["kernel"], L["tile_t2"], L["tile_t3"], L["splits"] * 2)
-    assert bench.measured_traffic("c5", "fp32", "adjoint", other) is None
+    assert bench.measured_traffic("w", "fp32", "adjoint", other) is None
     fused = _info(1, L["tile_t2"], L["tile_t3"], L["splits"])
-    assert bench.measured_traffic("c5", "fp32", "adjoint", fused) is None
-    assert bench.measured_traffic("c5", "bf16x3", "adjoint", ok) is None
+    assert bench.measured_traffic("w", "fp32", "adjoint", fused) is None
+    assert bench.measured_traffic("w", "bf16x3", "adjoint", ok) is None
+    # a changed kernel source voids the figure
+    assert bench.measured_traffic("w", "fp32", "forward", ok) is None
 
 
 def test_profiles_named_by_the_entries_exist():
