@@ -462,6 +462,182 @@ __global__ __launch_bounds__(256, CPS == 1 ? 2 : 1) void dtg_gemm_bf_kernel(Gemm
 
 typedef void (*gemm_fn)(GemmParams);
 
+// ---- BF16X3 GEMM on the FP32 stacked operand ------------------------------
+// The forward GEMM of BF16X3 plans: A_k hi/lo from the plan (8-k-step chunks
+// in the A-operand order of v_mfma_f32_32x32x16_bf16), B_k FP32 as the
+// decompression writes it for FP32 plans, split into bf16 hi/lo while the
+// MFMA operands are built (hi = rn(b), lo = rn(b - hi)); Ah Bh + Ah Bl + Al Bh
+// with FP32 accumulation.  One LDS stage is one chunk (8 stacked rows, 16
+// real k-steps).  Loads are staged through two register sets: the global
+// loads of chunk c + 2 are in flight while chunk c is multiplied from LDS and
+// chunk c + 1 (loaded one step earlier) is stored to the other LDS buffer,
+// one barrier per chunk.  B rows are padded by 8 floats in LDS so that the
+// operand reads of the two half-waves (rows 4 apart) fall on disjoint banks.
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+constexpr int BF2_RPAD = 8;        // floats of padding per B row in LDS
+
+__device__ __forceinline__ uint32_t bf2_pack(float a, float b) {
+  const v2bf h = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, h);
+}
+
+// one chunk (16 real k-steps) of the BF16X3 GEMM from LDS buffer `buf`
+template <int MBW, int NBW>
+__device__ __forceinline__ void bf2_compute(const float* lds, int buf, int lane, int wm, int wn,
+                                            v16f (&acc)[MBW][NBW]) {
+  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
+  constexpr int RS = NBT * 64 + BF2_RPAD;
+  constexpr int A_ST = MT * 2 * 64 * 4;
+  constexpr int ST = A_ST + 8 * RS;
+  const int h = lane >> 5, ln = lane & 31;
+  const float* As = lds + buf * ST;
+  const float* Bs = As + A_ST;
+  v8bf ah[MBW], al[MBW], bh[NBW], bl[NBW];
+#pragma unroll
+  for (int ii = 0; ii < MBW; ++ii) {
+    const int b = wm * MBW + ii;
+    ah[ii] = as_v8bf(*(const uint4*)(As + ((b * 2) * 64 + lane) * 4));
+    al[ii] = as_v8bf(*(const uint4*)(As + ((b * 2 + 1) * 64 + lane) * 4));
+  }
+#pragma unroll
+  for (int jn = 0; jn < NBW; ++jn) {
+    const float* bp = Bs + (4 * h) * RS + (wn * NBW + jn) * 64 + ln;
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float re = bp[r * RS], im = bp[r * RS + 32];
+      hw[r] = bf2_pack(re, im);
+      const float hre = __builtin_bit_cast(float, hw[r] << 16);
+      const float him = __builtin_bit_cast(float, hw[r] & 0xFFFF0000u);
+      lw[r] = bf2_pack(re - hre, im - him);
+    }
+    bh[jn] = as_v8bf(make_uint4(hw[0], hw[1], hw[2], hw[3]));
+    bl[jn] = as_v8bf(make_uint4(lw[0], lw[1], lw[2], lw[3]));
+  }
+#pragma unroll
+  for (int ii = 0; ii < MBW; ++ii)
+#pragma unroll
+    for (int jn = 0; jn < NBW; ++jn) {
+      acc[ii][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ii], bh[jn], acc[ii][jn], 0, 0, 0);
+      acc[ii][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ii], bl[jn], acc[ii][jn], 0, 0, 0);
+      acc[ii][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ii], bh[jn], acc[ii][jn], 0, 0, 0);
+    }
+}
+
+template <int MBW, int NBW>
+__global__ __launch_bounds__(256, NBW == 2 ? 2 : 1) void dtg_gemm_bf2_kernel(GemmParams P) {
+  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
+  constexpr int RS = NBT * 64 + BF2_RPAD;          // floats per LDS row of B
+  constexpr int A_ST = MT * 2 * 64 * 4;            // floats per A stage (hi, lo)
+  constexpr int B_ST = 8 * RS;                     // floats per B stage
+  constexpr int ST = A_ST + B_ST;
+  constexpr int NA = MT * 2 * 64 / 256;            // uint4 of A per thread and chunk
+  constexpr int NBQ = 8 * NBT * 16 / 256;          // float4 of B per thread and chunk
+  extern __shared__ float lds[];
+  const int64_t nwg = gridDim.x;
+  const int64_t L = (int64_t)(blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+  if (L >= P.nitems) return;
+  const int mt = (int)(L % P.mtiles);
+  int64_t rest = L / P.mtiles;
+  const int nt = (int)(rest % P.ntiles);
+  rest /= P.ntiles;
+  const int k = (int)(rest % P.q);
+  const int s = (int)(rest / P.q);
+  // chunk ranges of the splits start and end on even chunks (stacked rows
+  // are padded to 16, so every component has an even number of chunks)
+  const int c0 = 2 * (int)((int64_t)P.kst[k] * s / P.S);
+  const int c1 = 2 * (int)((int64_t)P.kst[k] * (s + 1) / P.S);
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1, h = lane >> 5, ln = lane & 31;
+  const uint4* Ag = (const uint4*)P.apack4 + P.a4off[k] + (int64_t)mt * MT * 128;
+  const float* Bg = P.B + P.brow[k] * P.ldb + (int64_t)nt * NBT * 64;
+
+  v4u ra0[NA], ra1[NA];
+  v4f rb0[NBQ], rb1[NBQ];
+  // global loads of chunk c (clamped to the last chunk, so the tail repeats
+  // a load instead of branching) into a register set, and the set's store
+  // into an LDS buffer
+#define TV_BF2_GLOAD(c, RA, RB)                                                  \
+  {                                                                             \
+    const int cc = min((c), c1 - 1);                                            \
+    const v4u* ac = (const v4u*)(Ag + (int64_t)cc * P.nbtp * 128);              \
+    _Pragma("unroll") for (int j = 0; j < NA; ++j) RA[j] = ac[j * 256 + tid];   \
+    const float* bc = Bg + (int64_t)cc * 8 * P.ldb;                             \
+    _Pragma("unroll") for (int j = 0; j < NBQ; ++j) {                           \
+      const int u = j * 256 + tid, r = u / (NBT * 16), q = u % (NBT * 16);      \
+      RB[j] = *(const v4f*)(bc + r * P.ldb + q * 4);                            \
+    }                                                                           \
+  }
+#define TV_BF2_LSTORE(buf, RA, RB)                                               \
+  {                                                                             \
+    float* As = lds + (buf) * ST;                                               \
+    float* Bs = As + A_ST;                                                      \
+    _Pragma("unroll") for (int j = 0; j < NA; ++j)                              \
+      *(v4u*)(As + (j * 256 + tid) * 4) = RA[j];                                \
+    _Pragma("unroll") for (int j = 0; j < NBQ; ++j) {                           \
+      const int u = j * 256 + tid, r = u / (NBT * 16), q = u % (NBT * 16);      \
+      *(v4f*)(Bs + r * RS + q * 4) = RB[j];                                     \
+    }                                                                           \
+  }
+
+  v16f acc[MBW][NBW];
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int jn = 0; jn < NBW; ++jn) acc[i][jn] = v16f{0.f};
+
+  // register set (c - c0) % 2 carries chunk c from global memory to LDS
+  if (c0 < c1) {
+    TV_BF2_GLOAD(c0, ra0, rb0);
+    TV_BF2_GLOAD(c0 + 1, ra1, rb1);
+    TV_BF2_LSTORE(0, ra0, rb0);
+  }
+  __syncthreads();
+  for (int c = c0; c < c1; c += 2) {
+    // even step: chunk c in LDS buffer 0, chunk c + 1 in set 1
+    TV_BF2_GLOAD(c + 2, ra0, rb0);
+    bf2_compute<MBW, NBW>(lds, 0, lane, wm, wn, acc);
+    TV_BF2_LSTORE(1, ra1, rb1);
+    __syncthreads();
+    // odd step: chunk c + 1 in LDS buffer 1, chunk c + 2 in set 0
+    TV_BF2_GLOAD(c + 3, ra1, rb1);
+    bf2_compute<MBW, NBW>(lds, 1, lane, wm, wn, acc);
+    TV_BF2_LSTORE(0, ra0, rb0);
+    __syncthreads();
+  }
+#undef TV_BF2_GLOAD
+#undef TV_BF2_LSTORE
+
+  float2* out = P.out + (int64_t)s * P.out_stride + (int64_t)k * P.nv;
+#pragma unroll
+  for (int jn = 0; jn < NBW; ++jn) {
+    const int64_t n = ((int64_t)nt * NBT + wn * NBW + jn) * 32 + ln;
+    if (n >= P.ncols) continue;
+    float2* col = out + (int64_t)P.n1 * (P.col0 + n);
+#pragma unroll
+    for (int ii = 0; ii < MBW; ++ii) {
+      const int blk = mt * MT + wm * MBW + ii;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int i1 = blk * 16 + 4 * g + 2 * h;
+        const v16f& d = acc[ii][jn];
+        if (i1 + 1 < P.n1) {
+          if (P.vec4) {
+            *(v4f*)(col + i1) = v4f{d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]};
+          } else {
+            col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
+            col[i1 + 1] = make_float2(d[4 * g + 2], d[4 * g + 3]);
+          }
+        } else if (i1 < P.n1) {
+          col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
+        }
+      }
+    }
+  }
+}
+
 // ---- adjoint as a GEMM over voxel columns ---------------------------------
 // Algorithm 2's inner products with the sum over the columns (i2, i3) taken
 // first: Z_k = Y^k_(1) B_k^* (n1 x stacked rows, contraction over the slab's
@@ -758,6 +934,17 @@ gemm_fn gemm_pick_bf(int mbw, int nbw) {
   return nullptr;
 }
 
+gemm_fn gemm_pick_bf2(int mbw, int nbw) {
+  if (mbw == 4 && nbw == 4) return dtg_gemm_bf2_kernel<4, 4>;
+  if (mbw == 4 && nbw == 2) return dtg_gemm_bf2_kernel<4, 2>;
+  if (mbw == 2 && nbw == 4) return dtg_gemm_bf2_kernel<2, 4>;
+  if (mbw == 2 && nbw == 2) return dtg_gemm_bf2_kernel<2, 2>;
+  return nullptr;
+}
+size_t bf2_lds(int mbw, int nbw) {
+  return sizeof(float) * 2 * ((size_t)2 * mbw * 2 * 64 * 4 + 8 * ((size_t)2 * nbw * 64 + BF2_RPAD));
+}
+
 gemm_fn gemm_pick(int mbw, int nbw) {
   if (mbw == 4 && nbw == 2) return dtg_gemm_kernel<4, 2>;
   if (mbw == 4 && nbw == 4) return dtg_gemm_kernel<4, 4>;
@@ -963,12 +1150,16 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
     G.kst[k] = (int)(p->dtg_rpad[k] / DTG_KC);
   }
   const int MT = dtg_mt(p);
-  const bool bf = p->precision == TV_PREC_BF16X3;
-  const int mbw = MT / 2, nbw = (bf && p->dtg_nbw == 1) ? 2 : p->dtg_nbw;
-  const int cps = (bf && p->dtg_nbw == 1) ? 1 : 2;
-  gemm_fn fn = bf ? gemm_pick_bf(mbw, p->dtg_nbw) : gemm_pick(mbw, nbw);
+  const bool bf16 = p->precision == TV_PREC_BF16X3;
+  // BF16X3 plans: gemm_nbw 2 and 4 split the FP32 slab in the GEMM; 1 takes
+  // the slab split into hi/lo by the decompression
+  const bool bf = bf16 && p->dtg_nbw == 1;
+  const int mbw = MT / 2, nbw = bf ? 2 : p->dtg_nbw;
+  const int cps = bf ? 1 : 2;
+  gemm_fn fn = bf ? gemm_pick_bf(mbw, p->dtg_nbw)
+                  : (bf16 ? gemm_pick_bf2(mbw, nbw) : gemm_pick(mbw, nbw));
   if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no GEMM instance for this tile");
-  if (bf) {
+  if (bf16) {
     G.apack4 = (const float*)p->d_abf;
     for (int k = 0; k < g.q; ++k) G.a4off[k] = p->dtg_abfoff[k];
   }
@@ -980,14 +1171,15 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
   G.nv = (int64_t)g.n1 * g.n2 * g.n3;
   G.n1 = g.n1;
   G.vec4 = (g.n1 % 2 == 0) && ((uintptr_t)out % 16 == 0);
-  const size_t lds = bf ? 2 * sizeof(uint4) * (size_t)(cps * 2 * mbw * 128 + cps * 2 * nbw * 128)
-                       : dtg_gemm_lds(mbw, nbw);
+  const size_t lds = bf     ? 2 * sizeof(uint4) * (size_t)(cps * 2 * mbw * 128 + cps * 2 * nbw * 128)
+                     : bf16 ? bf2_lds(mbw, nbw)
+                            : dtg_gemm_lds(mbw, nbw);
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
   const int t3w = dtg_t3w(p);
   D.t3w = t3w;
-  D.layout = p->precision == TV_PREC_BF16X3 ? 2 : 0;
+  D.layout = bf ? 2 : 0;
   const size_t hl = sizeof(float2) * (size_t)p->max_r[0] * t3w * p->max_r[1];
   decomp_fn dfn = decomp_pick(p->max_r[1]);
   e = hipFuncSetAttribute((const void*)dfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
