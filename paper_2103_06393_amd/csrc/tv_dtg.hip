@@ -901,7 +901,230 @@ __global__ __launch_bounds__(256) void dtg_colgemm_reduce_kernel(ColReduceParams
   if (threadIdx.x == 0) P.x[j] = make_float2((float)red[0][0], (float)red[1][0]);
 }
 
+// BF16X3 plans: the packed y as hi/lo bf16 in the A-operand order of
+// v_mfma_f32_32x32x16_bf16, 8-column chunks (k = 2 (column) + Re/Im):
+// uint4 index ((c * nbtp + blk) * 2 + hl) * 64 + lane per component, lane
+// 32 h + m%32 holding columns 8c + 4h .. 8c + 4h + 3 of row m, the real
+// embedding as in dtg_ypack_kernel.
+__global__ void dtg_ypack_bf_kernel(YPackParams P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nchk = P.ngrp / 2;                 // 8-column chunks
+  const int64_t total = (int64_t)P.q * nchk * P.nbtp * 64;
+  if (idx >= total) return;
+  const int lane = (int)(idx & 63);
+  int64_t rest = idx >> 6;
+  const int blk = (int)(rest % P.nbtp);
+  rest /= P.nbtp;
+  const int64_t c = rest % nchk;
+  const int k = (int)(rest / nchk);
+  const int mrow = 32 * blk + (lane & 31), i1 = mrow >> 1, sr = mrow & 1, h = lane >> 5;
+  uint32_t hw[4], lw[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t n = 8 * c + 4 * h + j;
+    float v0 = 0.f, v1 = 0.f;                      // k = 2j (Re part), 2j + 1 (Im part)
+    if (n < P.ncols && i1 < P.n1) {
+      const float2 y = P.y[(int64_t)k * P.nv + (P.col0 + n) * P.n1 + i1];
+      v0 = sr == 0 ? y.x : y.y;
+      v1 = sr == 0 ? y.y : -y.x;
+    }
+    hw[j] = bf2_pack(v0, v1);
+    const float h0 = __builtin_bit_cast(float, hw[j] << 16);
+    const float h1 = __builtin_bit_cast(float, hw[j] & 0xFFFF0000u);
+    lw[j] = bf2_pack(v0 - h0, v1 - h1);
+  }
+  uint4* dst = (uint4*)(P.yp + (int64_t)k * P.ystride) + ((c * P.nbtp + blk) * 2) * 64 + lane;
+  dst[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+  dst[64] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+}
+
+// The adjoint's column GEMM for BF16X3 plans: A = the packed y (hi/lo), B =
+// the unscaled FP32 slab split into hi/lo while the operands are built; one
+// LDS stage is one 8-column chunk, staged through two register sets as in
+// dtg_gemm_bf2_kernel.  A B row of a stage (8 Re then 8 Im values of one
+// stacked row) sits in LDS at a stride of 20 floats, free of bank conflicts
+// for the 16-byte operand reads.
+constexpr int CBF_RS = 20;
+
+template <int MBW, int NBW>
+__device__ __forceinline__ void colbf2_compute(const float* lds, int buf, int lane, int wm, int wn,
+                                               v16f (&acc)[MBW][NBW]) {
+  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
+  constexpr int A_ST = MT * 2 * 64 * 4;
+  constexpr int ST = A_ST + NBT * 32 * CBF_RS;
+  const int h = lane >> 5, ln = lane & 31;
+  const float* As = lds + buf * ST;
+  const float* Bs = As + A_ST;
+  v8bf ah[MBW], al[MBW], bh[NBW], bl[NBW];
+#pragma unroll
+  for (int ii = 0; ii < MBW; ++ii) {
+    const int b = wm * MBW + ii;
+    ah[ii] = as_v8bf(*(const uint4*)(As + ((b * 2) * 64 + lane) * 4));
+    al[ii] = as_v8bf(*(const uint4*)(As + ((b * 2 + 1) * 64 + lane) * 4));
+  }
+#pragma unroll
+  for (int jn = 0; jn < NBW; ++jn) {
+    const float* bp = Bs + ((wn * NBW + jn) * 32 + ln) * CBF_RS + 4 * h;
+    const v4f re = *(const v4f*)bp, im = *(const v4f*)(bp + 8);
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hw[j] = bf2_pack(re[j], im[j]);
+      const float hre = __builtin_bit_cast(float, hw[j] << 16);
+      const float him = __builtin_bit_cast(float, hw[j] & 0xFFFF0000u);
+      lw[j] = bf2_pack(re[j] - hre, im[j] - him);
+    }
+    bh[jn] = as_v8bf(make_uint4(hw[0], hw[1], hw[2], hw[3]));
+    bl[jn] = as_v8bf(make_uint4(lw[0], lw[1], lw[2], lw[3]));
+  }
+#pragma unroll
+  for (int ii = 0; ii < MBW; ++ii)
+#pragma unroll
+    for (int jn = 0; jn < NBW; ++jn) {
+      acc[ii][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ii], bh[jn], acc[ii][jn], 0, 0, 0);
+      acc[ii][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ii], bl[jn], acc[ii][jn], 0, 0, 0);
+      acc[ii][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ii], bh[jn], acc[ii][jn], 0, 0, 0);
+    }
+}
+
+template <int MBW, int NBW>
+__global__ __launch_bounds__(256, NBW == 2 ? 2 : 1) void dtg_colgemm_bf2_kernel(ColGemmParams P) {
+  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
+  constexpr int A_ST = MT * 2 * 64 * 4;
+  constexpr int ST = A_ST + NBT * 32 * CBF_RS;
+  constexpr int NA = MT * 2 * 64 / 256;            // uint4 of A per thread and chunk
+  constexpr int NBQ = NBT * 32 * 4 / 256;          // float4 of B per thread and chunk
+  extern __shared__ float lds[];
+  const int64_t nwg = gridDim.x;
+  const int64_t L = (int64_t)(blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+  if (L >= P.nitems) return;
+  const int ntot = P.ntb[P.q];
+  int mt, ntg;
+  int64_t rest;
+  if (P.order == 0) {
+    mt = (int)(L % P.mtiles);
+    rest = L / P.mtiles;
+    ntg = (int)(rest % ntot);
+    rest /= ntot;
+  } else {
+    ntg = (int)(L % ntot);
+    rest = L / ntot;
+    mt = (int)(rest % P.mtiles);
+    rest /= P.mtiles;
+  }
+  const int s = (int)rest;
+  int k = 0;
+  while (ntg >= P.ntb[k + 1]) ++k;
+  const int nt = ntg - P.ntb[k];
+  // 16-column stages split as in the FP32 kernel, two chunks each
+  const int nst = (int)((P.ncols + DTG_KC - 1) / DTG_KC);
+  const int c0 = 2 * (int)((int64_t)nst * s / P.S), c1 = 2 * (int)((int64_t)nst * (s + 1) / P.S);
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const v4u* Ag = (const v4u*)((const uint4*)(P.ypack + (int64_t)k * P.ystride) +
+                               (int64_t)mt * MT * 128);
+  const float* Bg = P.B + P.brow[k] * P.ldb;
+  const int64_t rk = P.rk[k];
+
+  v4u ra0[NA], ra1[NA];
+  v4f rb0[NBQ], rb1[NBQ];
+  // thread u of a chunk's B: stacked row R = u / 4, q = u % 4: Re (q < 2) or
+  // Im of columns 8c + 4 (q & 1) .. + 3
+#define TV_CBF_GLOAD(c, RA, RB)                                                  \
+  {                                                                             \
+    const int cc = min((c), c1 - 1);                                            \
+    const v4u* ac = Ag + (int64_t)cc * P.nbtp * 128;                            \
+    _Pragma("unroll") for (int j = 0; j < NA; ++j) RA[j] = ac[j * 256 + tid];   \
+    _Pragma("unroll") for (int j = 0; j < NBQ; ++j) {                           \
+      const int u = j * 256 + tid, q = u & 3;                                   \
+      const int64_t R = (int64_t)nt * (NBT * 32) + (u >> 2);                    \
+      const int64_t n = (int64_t)cc * 8 + (q & 1) * 4;                          \
+      v4f v = v4f{0.f, 0.f, 0.f, 0.f};                                          \
+      if (R < rk) {                                                             \
+        const float* src = Bg + R * P.ldb + (n >> 5) * 64 + (q >> 1) * 32 + (n & 31); \
+        if (n + 4 <= P.ncols) {                                                 \
+          v = *(const v4f*)src;                                                 \
+        } else {                                                                \
+          _Pragma("unroll") for (int e = 0; e < 4; ++e)                          \
+            if (n + e < P.ncols) v[e] = src[e];                                 \
+        }                                                                       \
+      }                                                                         \
+      RB[j] = v;                                                                \
+    }                                                                           \
+  }
+#define TV_CBF_LSTORE(buf, RA, RB)                                               \
+  {                                                                             \
+    float* As = lds + (buf) * ST;                                               \
+    float* Bs = As + A_ST;                                                      \
+    _Pragma("unroll") for (int j = 0; j < NA; ++j)                              \
+      *(v4u*)(As + (j * 256 + tid) * 4) = RA[j];                                \
+    _Pragma("unroll") for (int j = 0; j < NBQ; ++j) {                           \
+      const int u = j * 256 + tid, q = u & 3;                                   \
+      *(v4f*)(Bs + (u >> 2) * CBF_RS + (q >> 1) * 8 + (q & 1) * 4) = RB[j];     \
+    }                                                                           \
+  }
+
+  v16f acc[MBW][NBW];
+#pragma unroll
+  for (int i = 0; i < MBW; ++i)
+#pragma unroll
+    for (int jn = 0; jn < NBW; ++jn) acc[i][jn] = v16f{0.f};
+
+  if (c0 < c1) {
+    TV_CBF_GLOAD(c0, ra0, rb0);
+    TV_CBF_GLOAD(c0 + 1, ra1, rb1);
+    TV_CBF_LSTORE(0, ra0, rb0);
+  }
+  __syncthreads();
+  for (int c = c0; c < c1; c += 2) {
+    TV_CBF_GLOAD(c + 2, ra0, rb0);
+    colbf2_compute<MBW, NBW>(lds, 0, lane, wm, wn, acc);
+    TV_CBF_LSTORE(1, ra1, rb1);
+    __syncthreads();
+    TV_CBF_GLOAD(c + 3, ra1, rb1);
+    colbf2_compute<MBW, NBW>(lds, 1, lane, wm, wn, acc);
+    TV_CBF_LSTORE(0, ra0, rb0);
+    __syncthreads();
+  }
+#undef TV_CBF_GLOAD
+#undef TV_CBF_LSTORE
+
+  float2* zs = P.z + (int64_t)s * P.zsplit;
+#pragma unroll
+  for (int jn = 0; jn < NBW; ++jn) {
+    const int64_t R = ((int64_t)nt * NBT + wn * NBW + jn) * 32 + (lane & 31);
+    if (R >= rk) continue;
+    float2* col = zs + (P.brow[k] + R) * P.n1;
+#pragma unroll
+    for (int i = 0; i < MBW; ++i) {
+      const int blk = mt * MT + wm * MBW + i;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int i1 = blk * 16 + 4 * g + 2 * (lane >> 5);
+        const v16f& d = acc[i][jn];
+        if (i1 + 1 < P.n1 && P.vec4) {
+          *(v4f*)(col + i1) = v4f{d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]};
+        } else {
+          if (i1 < P.n1) col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
+          if (i1 + 1 < P.n1) col[i1 + 1] = make_float2(d[4 * g + 2], d[4 * g + 3]);
+        }
+      }
+    }
+  }
+}
+
 typedef void (*colgemm_fn)(ColGemmParams);
+colgemm_fn colgemm_pick_bf2(int mbw, int nbw) {
+  if (mbw == 4 && nbw == 2) return dtg_colgemm_bf2_kernel<4, 2>;
+  if (mbw == 4 && nbw == 4) return dtg_colgemm_bf2_kernel<4, 4>;
+  if (mbw == 2 && nbw == 2) return dtg_colgemm_bf2_kernel<2, 2>;
+  if (mbw == 2 && nbw == 4) return dtg_colgemm_bf2_kernel<2, 4>;
+  return nullptr;
+}
+size_t colgemm_bf2_lds(int mbw, int nbw) {
+  return 2 * sizeof(float) * (size_t)(2 * mbw * 2 * 64 * 4 + 2 * nbw * 32 * CBF_RS);
+}
 colgemm_fn colgemm_pick(int mbw, int nbw) {
   if (mbw == 4 && nbw == 2) return dtg_colgemm_kernel<4, 2>;
   if (mbw == 4 && nbw == 4) return dtg_colgemm_kernel<4, 4>;
@@ -1240,7 +1463,8 @@ static tv_status launch_dtg_colgemm_adjoint(const tv_plan_s* p, const float2* y,
   const int S = dtg_colgemm_splits(p, s3);
   const int MT = dtg_mt(p);
   const int mbw = MT / 2, nbw = p->dtg_nbw_a;
-  colgemm_fn fn = colgemm_pick(mbw, nbw);
+  const bool bf16 = p->precision == TV_PREC_BF16X3;
+  colgemm_fn fn = bf16 ? colgemm_pick_bf2(mbw, nbw) : colgemm_pick(mbw, nbw);
   if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no adjoint GEMM instance for this tile");
 
   DecompParams D;
@@ -1300,7 +1524,7 @@ static tv_status launch_dtg_colgemm_adjoint(const tv_plan_s* p, const float2* y,
   C.n1 = g.n1;
   C.vec4 = (g.n1 % 2 == 0) && ((uintptr_t)z % 16 == 0);
   C.nitems = (int64_t)C.mtiles * C.ntb[g.q] * S;
-  const size_t lds = colgemm_lds(mbw, nbw);
+  const size_t lds = bf16 ? colgemm_bf2_lds(mbw, nbw) : colgemm_lds(mbw, nbw);
   e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
 
@@ -1318,8 +1542,9 @@ static tv_status launch_dtg_colgemm_adjoint(const tv_plan_s* p, const float2* y,
     Y.col0 = (int64_t)g.n2 * i30;
     Y.ncols = ncols;
     Y.ngrp = (ncols + DTG_KC - 1) / DTG_KC * DTG_KC / 4;
-    const int64_t yth = (int64_t)g.q * Y.ngrp * Y.nbtp * 64;
-    hipLaunchKernelGGL(dtg_ypack_kernel, dim3((unsigned)((yth + 255) / 256)), dim3(256), 0, st, Y);
+    const int64_t yth = (int64_t)g.q * (bf16 ? Y.ngrp / 2 : Y.ngrp) * Y.nbtp * 64;
+    hipLaunchKernelGGL(bf16 ? dtg_ypack_bf_kernel : dtg_ypack_kernel,
+                       dim3((unsigned)((yth + 255) / 256)), dim3(256), 0, st, Y);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "adjoint operand packing launch");
     C.ncols = ncols;

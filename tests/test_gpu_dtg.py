@@ -146,6 +146,37 @@ def test_dtg_bf16x3_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab
         print(f"bf16x3 dtg {dims}: rel err {e:.2e}")
 
 
+@pytest.mark.parametrize("dims,q,m,rmax,seed,slab,nbw,splits,order", [
+    ((20, 13, 7), 2, 5, 5, 41, 0, 2, 1, 0),     # ragged 8-column chunk, n1 = 20
+    ((64, 32, 24), 3, 9, 12, 42, 5, 4, 3, 1),   # five slabs, 3 splits
+    ((130, 24, 10), 1, 7, 32, 43, 0, 4, 5, 0),  # n1 > 128, ranks to 32
+    ((33, 9, 7), 2, 4, 7, 44, 0, 2, 2, 1),      # odd n1
+    ((17, 9, 5), 12, 1, 4, 45, 2, 4, 64, 0),    # q = 12, splits past the stages
+])
+def test_dtg_bf16x3_column_adjoint_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw,
+                                                  splits, order):
+    """BF16X3 plans: y packed as bf16 hi/lo, the FP32 slab split into hi/lo
+    in the column GEMM (hi hi + hi lo + lo hi, FP32 accumulation); within
+    1e-4 of the moduli of the terms, two calls on one workspace."""
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    S = random_struct(dims, q, m, rmax, seed)
+    P = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
+                                precision=lib.TV_PREC_BF16X3)
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=splits, slab_i3=slab, gemm_nbw=nbw,
+                          gemm_order=order)
+    P._ws.clear()
+    assert P.info.kernel[1] == 2
+    rng = np.random.default_rng(seed)
+    for rep in range(2):
+        y = rng.standard_normal(S.q * S.nv) + 1j * rng.standard_normal(S.q * S.nv)
+        gx = P.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
+        e = assert_close(gx, om.alg2(S, y)[:, 0], 1e-4, terms=adj_terms(S, y),
+                         what=f"BF16X3 column adjoint, call {rep}")
+        print(f"bf16x3 column adjoint {dims}: rel err {e:.2e}")
+
+
 def test_dtg_adjoint_poisoned_workspace_and_multi_rhs(gpu_lib):
     import torch
     from paper_2103_06393_amd import lib
