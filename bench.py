@@ -102,6 +102,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def time_products(plan, x, y, K, warmup):
+    """Warm-up, then K steps of one Z x and one Z^* y on the current stream,
+    bracketed by HIP events; returns (fwd_ms, adj_ms, total_ms, wall_s, xo)."""
+    import torch
+    from paper_2103_06393_amd import lib
+    yo = torch.empty(plan.rows, dtype=torch.complex64, device="cuda")
+    xo = torch.empty(plan.m, dtype=torch.complex64, device="cuda")
+    wsf, wsa = plan.workspace(0, 1), plan.workspace(1, 1)
+    st = torch.cuda.current_stream()
+    sp = st.cuda_stream
+    h = plan.handle
+
+    def fwd():
+        lib.tv_matvec(h, x.data_ptr(), plan.m, 1, yo.data_ptr(), plan.rows,
+                      wsf.data_ptr(), wsf.numel(), sp)
+
+    def adj():
+        lib.tv_rmatvec(h, y.data_ptr(), plan.rows, 1, xo.data_ptr(), plan.m,
+                       wsa.data_ptr(), wsa.numel(), sp)
+
+    for _ in range(warmup):
+        fwd()
+        adj()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    start.record(st)
+    for i in range(K):
+        ev[i][0].record(st)
+        fwd()
+        ev[i][1].record(st)
+        adj()
+        ev[i][2].record(st)
+    end.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    return fwd_ms, adj_ms, start.elapsed_time(end), wall, xo
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -178,6 +222,8 @@ def main(argv=None):
                     help="only run a plain device copy of this many bytes --steps "
                          "times (calibration of the HBM traffic counters)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-bf16x3", action="store_true",
+                    help="skip the BF16 hi/lo split measurement after the FP32 one")
     ap.add_argument("--tune-cache", default=os.path.join(
         os.environ.get("TMPDIR", "/tmp"), "tuckvsie_tune.json"),
         help="autotuner cache (JSON); a cached entry skips the timing runs")
@@ -232,44 +278,8 @@ def main(argv=None):
     y_np = wl.y()[:, 0]
     x = torch.from_numpy(x_np.astype(np.complex64)).cuda()
     y = torch.from_numpy(y_np.astype(np.complex64)).cuda()
-    yo = torch.empty(plan.rows, dtype=torch.complex64, device="cuda")
-    xo = torch.empty(plan.m, dtype=torch.complex64, device="cuda")
-    wsf, wsa = plan.workspace(0, 1), plan.workspace(1, 1)
-    st = torch.cuda.current_stream()
-    sp = st.cuda_stream
-    h = plan.handle
-
-    def fwd():
-        lib.tv_matvec(h, x.data_ptr(), plan.m, 1, yo.data_ptr(), plan.rows,
-                      wsf.data_ptr(), wsf.numel(), sp)
-
-    def adj():
-        lib.tv_rmatvec(h, y.data_ptr(), plan.rows, 1, xo.data_ptr(), plan.m,
-                       wsa.data_ptr(), wsa.numel(), sp)
-
-    for _ in range(args.warmup):
-        fwd()
-        adj()
-    torch.cuda.synchronize()
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    start.record(st)
-    for i in range(K):
-        ev[i][0].record(st)
-        fwd()
-        ev[i][1].record(st)
-        adj()
-        ev[i][2].record(st)
-    end.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    total_ms = start.elapsed_time(end)
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
-    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    fwd_ms, adj_ms, total_ms, wall, xo = time_products(plan, x, y, K, args.warmup)
     ms_step = total_ms / K
     value = 2.0 * K / (total_ms / 1e3)
     tf_f = info.flops_matvec / (fwd_ms * 1e-3) / 1e12
@@ -331,7 +341,41 @@ def main(argv=None):
         out["rel_err_adj"] = float(np.linalg.norm(xa - x_ref) / np.linalg.norm(x_ref))
         log(f"[bench] oracle {cb['value']:.4f} matvecs/s on {cb['cores']} threads; "
             f"rel err fwd {out['rel_err_fwd']:.2e} adj {out['rel_err_adj']:.2e}")
-    plan.close()
+    if prec == lib.TV_PREC_FP32 and not args.no_bf16x3:
+        # the BF16 hi/lo split form on the same factors and inputs, its
+        # speedup over FP32 and its error on the same sampled columns
+        fac = plan.export_factors()
+        plan.close()
+        torch.cuda.empty_cache()
+        bplan = TuckerPlan.from_factors(wl.grid.dims, wl.q, wl.m, *fac, lib.TV_PREC_BF16X3)
+        del fac
+        if not args.no_autotune:
+            bplan.autotune(2, args.tune_cache)
+        bi = bplan.info
+        bf_f, bf_a, bf_total, _, bxo = time_products(bplan, x, y, K, args.warmup)
+        bb = {"value": 2.0 * K / (bf_total / 1e3), "ms_per_step": bf_total / K,
+              "fwd_ms": bf_f, "adj_ms": bf_a,
+              "speedup_vs_fp32": ms_step / (bf_total / K),
+              "tflops_fwd": bi.flops_matvec / (bf_f * 1e-3) / 1e12,
+              "tflops_adj": bi.flops_rmatvec / (bf_a * 1e-3) / 1e12,
+              "peak_three_products": PEAK_BF16_MFMA / 3.0,
+              "launch": {"tile_t2": list(bi.tile_t2), "tile_t3": list(bi.tile_t3),
+                         "splits": list(bi.splits)}}
+        bb["frac"] = max(bb["tflops_fwd"] if bf_f > bf_a else bb["tflops_adj"], 0.0) / (
+            PEAK_BF16_MFMA / 3.0)
+        if not args.no_cpu:
+            ys = bplan.matvec(torch.from_numpy(xs.astype(np.complex64)).cuda()).cpu().numpy()
+            bb["rel_err_fwd"] = float(np.linalg.norm(ys - y_ref) / np.linalg.norm(y_ref))
+            bb["rel_err_adj"] = float(np.linalg.norm(bxo.cpu().numpy()[cols] - x_ref) /
+                                      np.linalg.norm(x_ref))
+        log(f"[bench] bf16x3: fwd {bf_f:.4f} ms, adj {bf_a:.4f} ms, "
+            f"{bb['speedup_vs_fp32']:.2f}x the FP32 step"
+            + (f", rel err fwd {bb['rel_err_fwd']:.2e} adj {bb['rel_err_adj']:.2e}"
+               if "rel_err_fwd" in bb else ""))
+        out["bf16x3"] = bb
+        bplan.close()
+    else:
+        plan.close()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -190,9 +190,9 @@ tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
  *     of i3 (0: all), modes 3 and 2 of every tensor are decompressed into
  *     the stacked operand B_k = [x_1 M_1; ...] (unscaled for the adjoint) in
  *     the workspace, then the forward runs Y^k_(1) = A_k B_k as one MFMA
- *     GEMM per component (gemm_nbw = 2 or 4 column blocks per wave; for
- *     BF16X3 plans also 1: two blocks per wave with 8 k-steps per LDS stage
- *     and two workgroups per CU; splits k-step splits); the adjoint takes
+ *     GEMM per component (gemm_nbw = 2 or 4 column blocks per wave; splits
+ *     k-step splits; BF16X3 plans split the FP32 slab into bf16 hi/lo
+ *     inside the GEMM); the adjoint takes
  *     Algorithm 2's sum over voxel columns first: Z_k = Y^k_(1) B_k^* as one
  *     GEMM per slab over the slab's columns (gemm_nbw 2 or 4 blocks of 32
  *     stacked rows per wave, splits 1..64 column splits, gemm_order 0:

@@ -126,9 +126,8 @@ static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
       p->use_dtg[1] = true;
       return TV_OK;
     }
-    const bool nbw_ok = c.gemm_nbw == 2 || c.gemm_nbw == 4 ||
-                        (c.gemm_nbw == 1 && p->precision == TV_PREC_BF16X3);
-    if (!nbw_ok) return set_error(TV_ERR_INVALID_ARG, "gemm_nbw");
+    if (c.gemm_nbw != 2 && c.gemm_nbw != 4)
+      return set_error(TV_ERR_INVALID_ARG, "the GEMM takes gemm_nbw 2 or 4");
     if (c.splits < 1 || c.splits > 64) return set_error(TV_ERR_INVALID_ARG, "GEMM splits");
     p->dtg_nbw = c.gemm_nbw;
     p->dtg_split = c.splits;
@@ -238,7 +237,6 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
     if (dtg_supported(p)) {
       for (int slab = g.n3; slab >= 1; slab = (slab + 1) / 2) {
         std::vector<int> nbws = o == 1 ? std::vector<int>{2} : std::vector<int>{2, 4};
-        if (o == 0 && p->precision == TV_PREC_BF16X3) nbws.push_back(1);
         for (int nbw : nbws) {
           tv_launch_config c{};
           c.path = 1;

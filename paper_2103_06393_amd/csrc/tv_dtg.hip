@@ -51,19 +51,8 @@ struct DecompParams {
   int64_t m;
   int n2, n3, i30, s3, nsub;
   int t3w;           // i3 values per decompression workgroup
-  int layout;        // 0: FP32 planar, 2: BF16 hi/lo operand order (BF16X3 forward)
   int64_t nitems;
 };
-
-// BF16X3 layout of B: stacked rows in chunks of 8, per (chunk, 32-column
-// block) the hi then the lo halves as 64 lanes x 8 bf16, lane 32 h + n%32
-// holding rows 8c + 4h + 0..3 as (Re, Im) pairs: the B operand of
-// v_mfma_f32_32x32x16_bf16 for eight k-steps.  Index of the 32-bit (Re, Im)
-// word of row R, column n, hi half (the lo half is 256 words further).
-__host__ __device__ inline int64_t bf_b_index(int64_t R, int64_t n, int64_t nbl) {
-  const int rl = (int)(R & 7);
-  return (((R >> 3) * nbl + (n >> 5)) * 2) * 256 + (32 * (rl >> 2) + (n & 31)) * 4 + (rl & 3);
-}
 
 __host__ __device__ inline uint32_t bf16_rne(float x) {
   uint32_t u;
@@ -120,7 +109,6 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
   __syncthreads();
   const int64_t row0 = P.brow[k] + P.drow[kt];
   float* Bk = P.B + row0 * P.ldb;
-  const int64_t nbl = P.ldb / 64;
   for (int i2 = threadIdx.x; i2 < P.n2; i2 += 256) {
     float2 u[R2MAX];
     const float2* u2 = P.u2t + t.u2_off + (int64_t)i2 * r2;
@@ -140,17 +128,9 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
           }
         }
         const int64_t n = i2 + (int64_t)P.n2 * (i3a + i3l - P.i30);
-        if (P.layout == 2) {
-          const uint32_t hr = bf16_rne(sr), hi_ = bf16_rne(si);
-          const uint32_t lr = bf16_rne(sr - bf16_float(hr)), li = bf16_rne(si - bf16_float(hi_));
-          uint32_t* dst = (uint32_t*)P.B + bf_b_index(row0 + a, n, nbl);
-          dst[0] = hr | (hi_ << 16);
-          dst[256] = lr | (li << 16);
-        } else {
-          float* dst = row + (n >> 5) * 64 + (n & 31);
-          dst[0] = sr;
-          dst[32] = si;
-        }
+        float* dst = row + (n >> 5) * 64 + (n & 31);
+        dst[0] = sr;
+        dst[32] = si;
       }
     }
   }
@@ -311,157 +291,6 @@ __global__ __launch_bounds__(256) void dtg_gemm_kernel(GemmParams P) {
   }
 }
 
-// zero rows [from_k, to_k) of the BF16 layout (both halves, every column)
-__global__ void dtg_zero_rows_bf_kernel(ZeroParams Z) {
-  const int64_t nbl = Z.ldb / 64;
-  for (int k = 0; k < Z.q; ++k) {
-    const int64_t n = (Z.to[k] - Z.from[k]) * nbl * 32;
-    uint32_t* B = (uint32_t*)Z.B;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t R = Z.from[k] + i / (nbl * 32), c = i % (nbl * 32);
-      const int64_t w = bf_b_index(R, c, nbl);
-      B[w] = 0u;
-      B[w + 256] = 0u;
-    }
-  }
-}
-
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-__device__ __forceinline__ v8bf as_v8bf(uint4 v) { return __builtin_bit_cast(v8bf, v); }
-
-// The stacked mode-1 GEMM with BF16 hi/lo operands: per 16 k-steps (two
-// chunks of 8), Y += Ah Bh + Ah Bl + Al Bh on v_mfma_f32_32x32x16_bf16 (the
-// lo x lo term is dropped), FP32 accumulation.  Tiles, waves, XCD grouping
-// and epilogue as dtg_gemm_kernel; A (abf) per component as
-// ((chunk * nbtp + blk) * 2 + hl) * 64 + lane uint4, lane l holding
-// A_emb[32 blk + l%32][(8 chunk + 4 (l/32) + e/2, e%2)], e < 8.
-template <int MBW, int NBW, int CPS>
-__global__ __launch_bounds__(256, CPS == 1 ? 2 : 1) void dtg_gemm_bf_kernel(GemmParams P) {
-  // CPS chunks of 8 k-steps per LDS stage; with one chunk per stage two
-  // workgroups share a CU, which hides the loads behind the other's MFMAs
-  constexpr int MT = 2 * MBW, NBT = 2 * NBW;
-  constexpr int A_ST = CPS * MT * 128;      // uint4 per A stage
-  constexpr int B_ST = CPS * NBT * 128;     // uint4 per B stage
-  extern __shared__ uint4 ldsq[];
-  const int64_t nwg = gridDim.x;
-  const int64_t L = (int64_t)(blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
-  if (L >= P.nitems) return;
-  const int mt = (int)(L % P.mtiles);
-  int64_t rest = L / P.mtiles;
-  const int nt = (int)(rest % P.ntiles);
-  rest /= P.ntiles;
-  const int k = (int)(rest % P.q);
-  const int s = (int)(rest / P.q);
-  const int nst = P.kst[k] * (2 / CPS);
-  const int st0 = (int)((int64_t)nst * s / P.S), st1 = (int)((int64_t)nst * (s + 1) / P.S);
-
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const uint4* Ag = (const uint4*)P.apack4 + P.a4off[k];
-  const int64_t nbl = P.ldb / 64;
-  const uint4* Bg = (const uint4*)P.B + (P.brow[k] >> 3) * nbl * 128;
-
-  constexpr int NA = CPS * MT / 2, NB = CPS * NBT / 2;   // uint4 loads per thread
-  uint4 ra[NA], rb[NB];
-  auto gload = [&](int st) {
-#pragma unroll
-    for (int c = 0; c < NA; ++c) {
-      const int u = c * 256 + tid;
-      const int ch = u / (MT * 128), rem = u % (MT * 128);
-      ra[c] = Ag[(((int64_t)st * CPS + ch) * P.nbtp + mt * MT + rem / 128) * 128 + rem % 128];
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const int u = c * 256 + tid;
-      const int ch = u / (NBT * 128), rem = u % (NBT * 128);
-      rb[c] = Bg[(((int64_t)st * CPS + ch) * nbl + (int64_t)nt * NBT + rem / 128) * 128 +
-                 rem % 128];
-    }
-  };
-  auto lstore = [&](int buf) {
-    uint4* As = ldsq + buf * (A_ST + B_ST);
-    uint4* Bs = As + A_ST;
-#pragma unroll
-    for (int c = 0; c < NA; ++c) As[c * 256 + tid] = ra[c];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) Bs[c * 256 + tid] = rb[c];
-  };
-
-  v16f acc[MBW][NBW];
-#pragma unroll
-  for (int i = 0; i < MBW; ++i)
-#pragma unroll
-    for (int jn = 0; jn < NBW; ++jn) acc[i][jn] = v16f{0.f};
-
-  if (st0 < st1) {
-    gload(st0);
-    lstore(0);
-  }
-  __syncthreads();
-  for (int st = st0; st < st1; ++st) {
-    const int buf = (st - st0) & 1;
-    if (st + 1 < st1) gload(st + 1);
-    const uint4* As = ldsq + buf * (A_ST + B_ST);
-    const uint4* Bs = As + A_ST;
-#pragma unroll
-    for (int ch = 0; ch < CPS; ++ch) {
-      v8bf ah[MBW], al[MBW], bh[NBW], bl[NBW];
-#pragma unroll
-      for (int i = 0; i < MBW; ++i) {
-        const int b = ch * MT + wm * MBW + i;
-        ah[i] = as_v8bf(As[(b * 2) * 64 + lane]);
-        al[i] = as_v8bf(As[(b * 2 + 1) * 64 + lane]);
-      }
-#pragma unroll
-      for (int jn = 0; jn < NBW; ++jn) {
-        const int b = ch * NBT + wn * NBW + jn;
-        bh[jn] = as_v8bf(Bs[(b * 2) * 64 + lane]);
-        bl[jn] = as_v8bf(Bs[(b * 2 + 1) * 64 + lane]);
-      }
-#pragma unroll
-      for (int i = 0; i < MBW; ++i)
-#pragma unroll
-        for (int jn = 0; jn < NBW; ++jn) {
-          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[jn], acc[i][jn], 0, 0, 0);
-          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[jn], acc[i][jn], 0, 0, 0);
-          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[jn], acc[i][jn], 0, 0, 0);
-        }
-    }
-    if (st + 1 < st1) lstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  float2* out = P.out + (int64_t)s * P.out_stride + (int64_t)k * P.nv;
-#pragma unroll
-  for (int jn = 0; jn < NBW; ++jn) {
-    const int64_t n = ((int64_t)nt * NBT + wn * NBW + jn) * 32 + (lane & 31);
-    if (n >= P.ncols) continue;
-    float2* col = out + (int64_t)P.n1 * (P.col0 + n);
-#pragma unroll
-    for (int i = 0; i < MBW; ++i) {
-      const int blk = mt * MT + wm * MBW + i;
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int i1 = blk * 16 + 4 * g + 2 * (lane >> 5);
-        const v16f& d = acc[i][jn];
-        if (i1 + 1 < P.n1) {
-          if (P.vec4) {
-            *(v4f*)(col + i1) = v4f{d[4 * g], d[4 * g + 1], d[4 * g + 2], d[4 * g + 3]};
-          } else {
-            col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
-            col[i1 + 1] = make_float2(d[4 * g + 2], d[4 * g + 3]);
-          }
-        } else if (i1 < P.n1) {
-          col[i1] = make_float2(d[4 * g], d[4 * g + 1]);
-        }
-      }
-    }
-  }
-}
-
-typedef void (*gemm_fn)(GemmParams);
-
 // ---- BF16X3 GEMM on the FP32 stacked operand ------------------------------
 // The forward GEMM of BF16X3 plans: A_k hi/lo from the plan (8-k-step chunks
 // in the A-operand order of v_mfma_f32_32x32x16_bf16), B_k FP32 as the
@@ -474,7 +303,9 @@ typedef void (*gemm_fn)(GemmParams);
 // one barrier per chunk.  B rows are padded by 8 floats in LDS so that the
 // operand reads of the two half-waves (rows 4 apart) fall on disjoint banks.
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v8bf as_v8bf(uint4 v) { return __builtin_bit_cast(v8bf, v); }
 constexpr int BF2_RPAD = 8;        // floats of padding per B row in LDS
 
 __device__ __forceinline__ uint32_t bf2_pack(float a, float b) {
@@ -1144,18 +975,7 @@ decomp_fn decomp_pick(int r2max) {
   return dtg_decomp_kernel<64>;
 }
 
-// BF16X3 GEMM instances: nbw 2 and 4 with two chunks per stage (one
-// workgroup per CU), nbw 1 stands for 2 column blocks per wave with one chunk
-// per stage (two workgroups per CU)
-gemm_fn gemm_pick_bf(int mbw, int nbw) {
-  if (mbw == 4 && nbw == 1) return dtg_gemm_bf_kernel<4, 2, 1>;
-  if (mbw == 4 && nbw == 2) return dtg_gemm_bf_kernel<4, 2, 2>;
-  if (mbw == 4 && nbw == 4) return dtg_gemm_bf_kernel<4, 4, 2>;
-  if (mbw == 2 && nbw == 1) return dtg_gemm_bf_kernel<2, 2, 1>;
-  if (mbw == 2 && nbw == 2) return dtg_gemm_bf_kernel<2, 2, 2>;
-  if (mbw == 2 && nbw == 4) return dtg_gemm_bf_kernel<2, 4, 2>;
-  return nullptr;
-}
+typedef void (*gemm_fn)(GemmParams);
 
 gemm_fn gemm_pick_bf2(int mbw, int nbw) {
   if (mbw == 4 && nbw == 4) return dtg_gemm_bf2_kernel<4, 4>;
@@ -1290,8 +1110,7 @@ static int dtg_t3w(const tv_plan_s* p) {
 
 int64_t dtg_launch_tiles(const tv_plan_s* p, int s3, int nbw) {
   const int64_t cols = (int64_t)p->grid.n2 * std::min(s3, p->grid.n3);
-  const int w = nbw == 1 ? 2 : nbw;  // BF16X3's one-chunk stages keep 2 blocks per wave
-  return (int64_t)p->grid.q * (p->dtg_nbtp / dtg_mt(p)) * ((cols + 64 * w - 1) / (64 * w));
+  return (int64_t)p->grid.q * (p->dtg_nbtp / dtg_mt(p)) * ((cols + 64 * nbw - 1) / (64 * nbw));
 }
 
 int64_t dtg_colgemm_tiles(const tv_plan_s* p, int nbw) {
@@ -1374,13 +1193,8 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
   }
   const int MT = dtg_mt(p);
   const bool bf16 = p->precision == TV_PREC_BF16X3;
-  // BF16X3 plans: gemm_nbw 2 and 4 split the FP32 slab in the GEMM; 1 takes
-  // the slab split into hi/lo by the decompression
-  const bool bf = bf16 && p->dtg_nbw == 1;
-  const int mbw = MT / 2, nbw = bf ? 2 : p->dtg_nbw;
-  const int cps = bf ? 1 : 2;
-  gemm_fn fn = bf ? gemm_pick_bf(mbw, p->dtg_nbw)
-                  : (bf16 ? gemm_pick_bf2(mbw, nbw) : gemm_pick(mbw, nbw));
+  const int mbw = MT / 2, nbw = p->dtg_nbw;
+  gemm_fn fn = bf16 ? gemm_pick_bf2(mbw, nbw) : gemm_pick(mbw, nbw);
   if (!fn) return set_error(TV_ERR_NOT_SUPPORTED, "no GEMM instance for this tile");
   if (bf16) {
     G.apack4 = (const float*)p->d_abf;
@@ -1394,15 +1208,12 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
   G.nv = (int64_t)g.n1 * g.n2 * g.n3;
   G.n1 = g.n1;
   G.vec4 = (g.n1 % 2 == 0) && ((uintptr_t)out % 16 == 0);
-  const size_t lds = bf     ? 2 * sizeof(uint4) * (size_t)(cps * 2 * mbw * 128 + cps * 2 * nbw * 128)
-                     : bf16 ? bf2_lds(mbw, nbw)
-                            : dtg_gemm_lds(mbw, nbw);
+  const size_t lds = bf16 ? bf2_lds(mbw, nbw) : dtg_gemm_lds(mbw, nbw);
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
   const int t3w = dtg_t3w(p);
   D.t3w = t3w;
-  D.layout = bf ? 2 : 0;
   const size_t hl = sizeof(float2) * (size_t)p->max_r[0] * t3w * p->max_r[1];
   decomp_fn dfn = decomp_pick(p->max_r[1]);
   e = hipFuncSetAttribute((const void*)dfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
@@ -1418,10 +1229,7 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
     Z.from[k] = D.brow[k] + p->sum_r1_k[k];
     Z.to[k] = D.brow[k] + p->dtg_rpad[k];
   }
-  if (bf)
-    hipLaunchKernelGGL(dtg_zero_rows_bf_kernel, dim3(64), dim3(256), 0, st, Z);
-  else
-    hipLaunchKernelGGL(dtg_zero_rows_kernel, dim3(64), dim3(256), 0, st, Z);
+  hipLaunchKernelGGL(dtg_zero_rows_kernel, dim3(64), dim3(256), 0, st, Z);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "padding rows");
   for (int i30 = 0; i30 < g.n3; i30 += s3) {
@@ -1486,7 +1294,6 @@ static tv_status launch_dtg_colgemm_adjoint(const tv_plan_s* p, const float2* y,
   D.n3 = g.n3;
   const int t3w = dtg_t3w(p);
   D.t3w = t3w;
-  D.layout = 0;
   const size_t hl = sizeof(float2) * (size_t)p->max_r[0] * t3w * p->max_r[1];
   decomp_fn dfn = decomp_pick(p->max_r[1]);
   hipError_t e = hipFuncSetAttribute((const void*)dfn,

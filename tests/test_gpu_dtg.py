@@ -120,14 +120,14 @@ def test_dtg_workspace_poisoned_and_multi_rhs(gpu_lib):
     ((96, 40, 33), 3, 6, 20, 23, 16, 4, 1),
     ((130, 24, 10), 1, 7, 32, 24, 0, 2, 2),
     ((17, 9, 5), 12, 1, 4, 25, 2, 2, 1),
-    ((64, 32, 24), 3, 9, 12, 26, 5, 1, 1),    # one chunk per stage, 2 workgroups per CU
-    ((160, 20, 9), 2, 5, 10, 27, 0, 1, 2),
+    ((64, 32, 24), 3, 9, 12, 26, 5, 2, 1),    # 2 workgroups per CU
+    ((160, 20, 9), 2, 5, 10, 27, 0, 2, 2),
 ])
 def test_dtg_bf16x3_forward_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, nbw, splits):
     """BF16X3 plans: the stacked GEMM on v_mfma_f32_32x32x16_bf16 with hi/lo
-    operands (hi hi + hi lo + lo hi, FP32 accumulation), B written as bf16
-    hi/lo by the decompression; every entry within 1e-4 of the moduli of its
-    terms (each product carries a relative error of about 2^-17)."""
+    operands (hi hi + hi lo + lo hi, FP32 accumulation), the FP32 slab split
+    into bf16 hi/lo inside the GEMM; every entry within 1e-4 of the moduli of
+    its terms (each product carries a relative error of about 2^-17)."""
     import torch
     from paper_2103_06393_amd import lib
     from paper_2103_06393_amd.ops import TuckerPlan
@@ -216,6 +216,8 @@ def test_dtg_refused_configurations(gpu_lib):
         lib.tv_plan_configure(P.handle, 1, path=1, splits=65, gemm_nbw=4, gemm_order=1)
     with pytest.raises(lib.TuckVsieError):
         lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=3)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=1)
     assert P.info.kernel[0] != 2 and P.info.kernel[1] != 2   # refusals left no trace
 
 
