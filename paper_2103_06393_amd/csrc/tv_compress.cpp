@@ -30,6 +30,13 @@ tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const
                       double2* G, hipStream_t st);
 tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, double* W,
                               double2* U, double* tr, double2* ws, hipStream_t st);
+tv_status launch_jacobi_batch(const JacobiGroup* groups, int ng, hipStream_t st);
+tv_status launch_subspace_prep(const double2* S, int nmat, int n, int64_t sS, double* tr,
+                               double2* ws, hipStream_t st);
+tv_status launch_subspace_finish(int nmat, int n, const double2* ws, const double2* V,
+                                 double2* U, hipStream_t st);
+double2* subspace_T(double2* ws, int nmat, int n);
+double2* subspace_V(double2* ws, int nmat, int n);
 tv_status finalize_plan(tv_plan_s* p);
 tv_status validate_ranks_and_offsets(tv_plan_s* p);
 
@@ -206,33 +213,53 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   std::vector<std::vector<double>> W(3), TR(3);
   std::vector<std::vector<double2>> V(3);
   int L[3];
+  // the three modes' eigenproblems: subspace preparation for the long modes,
+  // then one Jacobi launch over every mode's matrices (n x n directly for
+  // modes <= 64, the 64 x 64 Rayleigh-Ritz matrices otherwise), the long
+  // modes' vectors, and one readback
+  double2* dV[3];
+  double* dW[3];
+  double* dTr[3] = {nullptr, nullptr, nullptr};
+  double2* dWs[3] = {nullptr, nullptr, nullptr};
+  JacobiGroup groups[3];
   for (int d = 0; d < 3; ++d) {
     const int n = dims[d];
     L[d] = n <= 64 ? n : 64;
-    double2* dV;
-    double *dW, *dTr = nullptr;
-    if ((s = ds.alloc(&dV, (size_t)T * n * L[d])) != TV_OK) return s;
-    if ((s = ds.alloc(&dW, (size_t)T * L[d])) != TV_OK) return s;
+    if ((s = ds.alloc(&dV[d], (size_t)T * n * L[d])) != TV_OK) return s;
+    if ((s = ds.alloc(&dW[d], (size_t)T * L[d])) != TV_OK) return s;
     const double2* Sd = dS + (int64_t)d * T * mat;
     if (n <= 64) {
       // eigenvectors are written compactly, n x n per matrix
-      if ((s = launch_jacobi(Sd, T, n, mat, dW, n, dV, (int64_t)n * n, st)) != TV_OK) return s;
+      groups[d] = JacobiGroup{Sd, dW[d], dV[d], mat, n, (int64_t)n * n, n, T};
     } else {
-      double2* dWs;
-      if ((s = ds.alloc(&dTr, (size_t)T)) != TV_OK) return s;
-      if ((s = ds.alloc(&dWs, (size_t)T * (3 * (size_t)n * 64 + 64 * 64))) != TV_OK) return s;
-      if ((s = launch_subspace_eig(Sd, T, n, mat, dW, dV, dTr, dWs, st)) != TV_OK) return s;
+      if ((s = ds.alloc(&dTr[d], (size_t)T)) != TV_OK) return s;
+      if ((s = ds.alloc(&dWs[d], (size_t)T * (3 * (size_t)n * 64 + 64 * 64))) != TV_OK) return s;
+      if ((s = launch_subspace_prep(Sd, T, n, mat, dTr[d], dWs[d], st)) != TV_OK) return s;
+      groups[d] = JacobiGroup{subspace_T(dWs[d], T, n), dW[d], subspace_V(dWs[d], T, n),
+                              64 * 64, 64, 64 * 64, 64, T};
     }
-    W[d].resize((size_t)T * L[d]);
-    V[d].resize((size_t)T * n * L[d]);
-    hipError_t e = hipMemcpyAsync(W[d].data(), dW, W[d].size() * sizeof(double),
-                                  hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(V[d].data(), dV, V[d].size() * sizeof(double2), hipMemcpyDeviceToHost,
-                         st);
-    if (e == hipSuccess && dTr) {
-      TR[d].resize(T);
-      e = hipMemcpyAsync(TR[d].data(), dTr, T * sizeof(double), hipMemcpyDeviceToHost, st);
+  }
+  if ((s = launch_jacobi_batch(groups, 3, st)) != TV_OK) return s;
+  for (int d = 0; d < 3; ++d)
+    if (dims[d] > 64 &&
+        (s = launch_subspace_finish(T, dims[d], dWs[d], subspace_V(dWs[d], T, dims[d]), dV[d],
+                                    st)) != TV_OK)
+      return s;
+  {
+    hipError_t e = hipSuccess;
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+      const int n = dims[d];
+      W[d].resize((size_t)T * L[d]);
+      V[d].resize((size_t)T * n * L[d]);
+      e = hipMemcpyAsync(W[d].data(), dW[d], W[d].size() * sizeof(double),
+                         hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(V[d].data(), dV[d], V[d].size() * sizeof(double2),
+                           hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess && dTr[d]) {
+        TR[d].resize(T);
+        e = hipMemcpyAsync(TR[d].data(), dTr[d], T * sizeof(double), hipMemcpyDeviceToHost, st);
+      }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_error(e, "eigenpair readback");

@@ -9,6 +9,8 @@
 //   jacobi_kernel   cyclic parallel Jacobi eigensolver of one Hermitian
 //                   matrix (n <= 64) per workgroup, held in LDS
 //   proj1/2/3       the three n-mode products with U_d^* that form the core
+#include <algorithm>
+
 #include "tv_internal.h"
 
 namespace tv {
@@ -137,11 +139,22 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
 // diagonalise the real matrix [[A_ii, d], [d, A_jj]] (Golub and Van Loan's
 // symmetric 2x2 Schur step).  Output: eigenvalues W (unsorted) and
 // eigenvectors as the columns of V, both per matrix.
-__global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__ S, int n,
-                                                     int64_t stride, double* __restrict__ W,
-                                                     int64_t wstride, double2* __restrict__ Vout,
-                                                     int64_t vstride, int max_sweeps) {
+__global__ __launch_bounds__(256) void jacobi_kernel(JacobiBatch B) {
   extern __shared__ double2 jsm[];
+  // workgroup -> (group, matrix)
+  int64_t mat = blockIdx.x;
+  int gi = 0;
+  while (gi + 1 < B.ng && mat >= B.g[gi].nmat) {
+    mat -= B.g[gi].nmat;
+    ++gi;
+  }
+  const JacobiGroup& G = B.g[gi];
+  const int n = G.n;
+  const int64_t stride = G.stride, wstride = G.wstride, vstride = G.vstride;
+  const double2* __restrict__ S = G.S;
+  double* __restrict__ W = G.W;
+  double2* __restrict__ Vout = G.V;
+  const int max_sweeps = B.max_sweeps;
   const int np = n + (n & 1);
   double2* A = jsm;              // n x n, row-major
   double2* V = A + n * n;        // n x n
@@ -153,7 +166,6 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
   int* pj = pi + np / 2;
   double* red = reinterpret_cast<double*>(pj + np / 2 + 2);  // [2][256]
   const int tid = threadIdx.x;
-  const int64_t mat = blockIdx.x;
   const double2* Sm = S + mat * stride;
   for (int e = tid; e < n * n; e += 256) {
     A[e] = Sm[e];
@@ -179,7 +191,12 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
       }
       __syncthreads();
     }
-    const bool done = !(red[0] > 1e-30 * red[256]);
+    // rotations below 1e-15 of the matrix norm only churn rounding noise
+    // (Gram matrices of low multilinear rank have many near-zero diagonal
+    // entries, where a threshold relative to sqrt(a_ii a_jj) never settles);
+    // the sweeps end once every off-diagonal entry is below that
+    const double skip2 = 1e-30 * (red[0] + red[256]);
+    const bool done = !(red[0] > (double)n * n * skip2);
     __syncthreads();
     if (done) break;
     for (int round = 0; round < np - 1; ++round) {
@@ -202,7 +219,7 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const double2* __restrict__
           const double2 aij = A[i * n + j];
           const double dd = sqrt(aij.x * aij.x + aij.y * aij.y);
           const double aii = A[i * n + i].x, ajj = A[j * n + j].x;
-          if (dd > 1e-300 && dd > 1e-17 * sqrt(fabs(aii * ajj))) {
+          if (dd > 1e-300 && dd > 1e-17 * sqrt(fabs(aii * ajj)) && dd * dd > skip2) {
             cp = aij.x / dd;
             sp = aij.y / dd;
             const double tau = (ajj - aii) / (2.0 * dd);
@@ -365,20 +382,37 @@ tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int n
   return last("gram_kernel");
 }
 
-// S: nmat input matrices n x n at stride `stride`; W: n eigenvalues per
-// matrix at stride wstride; V: n x n eigenvectors per matrix at stride
-// vstride (both output strides must leave room for a whole matrix).
-tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
-                        int64_t wstride, double2* V, int64_t vstride, hipStream_t st) {
-  if (n < 1 || n > 64 || stride < (int64_t)n * n || vstride < (int64_t)n * n || wstride < n)
-    return set_error(TV_ERR_INVALID_ARG, "jacobi: matrix larger than 64 or strides too small");
-  const size_t lds = jacobi_lds_bytes(n);
+// Groups of Hermitian matrices (n <= 64 each) diagonalized in one launch,
+// one workgroup per matrix: S, nmat input matrices n x n at `stride`; W, n
+// eigenvalues per matrix at `wstride`; V, n x n eigenvectors per matrix at
+// `vstride` (both output strides leave room for a whole matrix).
+tv_status launch_jacobi_batch(const JacobiGroup* groups, int ng, hipStream_t st) {
+  if (ng < 1 || ng > 3) return set_error(TV_ERR_INVALID_ARG, "jacobi: 1 to 3 groups");
+  JacobiBatch B{};
+  B.ng = ng;
+  B.max_sweeps = 40;
+  size_t lds = 0;
+  int64_t blocks = 0;
+  for (int g = 0; g < ng; ++g) {
+    const JacobiGroup& G = groups[g];
+    if (G.n < 1 || G.n > 64 || G.stride < (int64_t)G.n * G.n || G.vstride < (int64_t)G.n * G.n ||
+        G.wstride < G.n || G.nmat < 1)
+      return set_error(TV_ERR_INVALID_ARG, "jacobi: matrix larger than 64 or strides too small");
+    B.g[g] = G;
+    lds = std::max(lds, jacobi_lds_bytes(G.n));
+    blocks += G.nmat;
+  }
   hipError_t e = hipFuncSetAttribute((const void*)jacobi_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(jacobi)");
-  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)nmat), dim3(256), lds, st, S, n, stride, W,
-                     wstride, V, vstride, 40);
+  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)blocks), dim3(256), lds, st, B);
   return last("jacobi_kernel");
+}
+
+tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
+                        int64_t wstride, double2* V, int64_t vstride, hipStream_t st) {
+  JacobiGroup G{S, W, V, stride, wstride, vstride, n, nmat};
+  return launch_jacobi_batch(&G, 1, st);
 }
 
 tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const double2* u1,
@@ -591,14 +625,19 @@ tv_status launch_zgemm(int trans, int M, int N, int K, const double2* A, int lda
 // Outputs: W[b*l + i] eigenvalues (unsorted), U[b*n*l] eigenvectors as the
 // columns of an n x l row-major matrix, tr[b] traces.  ws: 3 * nmat * n * l
 // + nmat * l * l complex.
-tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, double* W,
-                              double2* U, double* tr, double2* ws, hipStream_t st) {
+// Subspace iteration for the leading 64 eigenpairs of nmat Hermitian n x n
+// matrices (n > 64), in two parts around the Rayleigh-Ritz diagonalization
+// (so that the caller can batch it with other Jacobi problems): prep builds
+// Q = orth(S orth(S Omega)) and T = Q^* S Q (64 x 64) in ws and the traces;
+// finish forms U = Q V from T's eigenvectors V.  ws layout: Q, Z, V (n x 64
+// each per matrix), T (64 x 64 per matrix).
+tv_status launch_subspace_prep(const double2* S, int nmat, int n, int64_t sS, double* tr,
+                               double2* ws, hipStream_t st) {
   const int l = 64;
   const int64_t nl = (int64_t)n * l, ll = (int64_t)l * l;
   double2* Q = ws;
   double2* Z = Q + nmat * nl;
-  double2* V = Z + nmat * nl;
-  double2* T = V + nmat * nl;
+  double2* T = Z + 2 * nmat * nl;
   tv_status s;
   const int64_t tot = (int64_t)nmat * nl;
   hipLaunchKernelGGL(omega_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Q, n,
@@ -607,7 +646,7 @@ tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, dou
   hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((nmat + 255) / 256)), dim3(256), 0, st, S, n,
                      sS, nmat, tr);
   if ((s = last("trace_kernel")) != TV_OK) return s;
-  // Z = S Omega, Q = orth(Z); Z = S Q, Q = orth(Z)
+  // Z = S Omega, Q = orth(Z); Z = S Q, Q = orth(Z) (two swaps: Q ends in ws)
   for (int it = 0; it < 2; ++it) {
     if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
     hipLaunchKernelGGL(cgs2_kernel, dim3((unsigned)nmat), dim3(256), 0, st, Z, n, l, nl);
@@ -616,11 +655,31 @@ tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, dou
     Q = Z;
     Z = tmp;
   }
-  // Rayleigh-Ritz: T = Q^* (S Q), T = W diag(mu) W^*, U = Q W
+  // Rayleigh-Ritz matrix T = Q^* (S Q)
   if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
-  if ((s = launch_zgemm(1, l, l, n, Q, l, nl, Z, l, nl, T, l, ll, nmat, st)) != TV_OK) return s;
-  if ((s = launch_jacobi(T, nmat, l, ll, W, l, V, ll, st)) != TV_OK) return s;
-  return launch_zgemm(0, n, l, l, Q, l, nl, V, l, ll, U, l, nl, nmat, st);
+  (void)ll;
+  return launch_zgemm(1, l, l, n, Q, l, nl, Z, l, nl, T, l, (int64_t)l * l, nmat, st);
+}
+
+// the 64 x 64 Rayleigh-Ritz matrices of launch_subspace_prep's workspace
+double2* subspace_T(double2* ws, int nmat, int n) { return ws + (int64_t)3 * nmat * n * 64; }
+double2* subspace_V(double2* ws, int nmat, int n) { return ws + (int64_t)2 * nmat * n * 64; }
+
+tv_status launch_subspace_finish(int nmat, int n, const double2* ws, const double2* V,
+                                 double2* U, hipStream_t st) {
+  const int l = 64;
+  const int64_t nl = (int64_t)n * l, ll = (int64_t)l * l;
+  return launch_zgemm(0, n, l, l, ws, l, nl, V, l, ll, U, l, nl, nmat, st);
+}
+
+tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, double* W,
+                              double2* U, double* tr, double2* ws, hipStream_t st) {
+  tv_status s = launch_subspace_prep(S, nmat, n, sS, tr, ws, st);
+  if (s != TV_OK) return s;
+  double2* T = subspace_T(ws, nmat, n);
+  double2* V = subspace_V(ws, nmat, n);
+  if ((s = launch_jacobi(T, nmat, 64, 64 * 64, W, 64, V, 64 * 64, st)) != TV_OK) return s;
+  return launch_subspace_finish(nmat, n, ws, V, U, st);
 }
 
 }  // namespace tv

@@ -47,6 +47,19 @@ struct HostPack {
 // column-split tables hold up to this many splits per component
 constexpr int TV_SPLIT_MAX = 64;
 
+// one group of Hermitian matrices for the batched Jacobi eigensolver
+struct JacobiGroup {
+  const double2* S;   // nmat matrices n x n at `stride`
+  double* W;          // n eigenvalues per matrix at `wstride`
+  double2* V;         // n x n eigenvectors per matrix at `vstride`
+  int64_t stride, wstride, vstride;
+  int n, nmat;
+};
+struct JacobiBatch {
+  JacobiGroup g[3];
+  int ng, max_sweeps;
+};
+
 }  // namespace tv
 
 struct tv_plan_s {
