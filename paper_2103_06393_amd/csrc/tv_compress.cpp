@@ -31,8 +31,7 @@ tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const
 tv_status launch_subspace_eig(const double2* S, int nmat, int n, int64_t sS, double* W,
                               double2* U, double* tr, double2* ws, hipStream_t st);
 tv_status launch_jacobi_batch(const JacobiGroup* groups, int ng, hipStream_t st);
-tv_status launch_subspace_prep(const double2* S, int nmat, int n, int64_t sS, double* tr,
-                               double2* ws, hipStream_t st);
+tv_status launch_subspace_prep_batch(const SubspaceJob* jobs, int nj, int nmat, hipStream_t st);
 tv_status launch_subspace_finish(int nmat, int n, const double2* ws, const double2* V,
                                  double2* U, hipStream_t st);
 double2* subspace_T(double2* ws, int nmat, int n);
@@ -222,6 +221,8 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   double* dTr[3] = {nullptr, nullptr, nullptr};
   double2* dWs[3] = {nullptr, nullptr, nullptr};
   JacobiGroup groups[3];
+  SubspaceJob jobs[3];
+  int nj = 0;
   for (int d = 0; d < 3; ++d) {
     const int n = dims[d];
     L[d] = n <= 64 ? n : 64;
@@ -234,11 +235,12 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
     } else {
       if ((s = ds.alloc(&dTr[d], (size_t)T)) != TV_OK) return s;
       if ((s = ds.alloc(&dWs[d], (size_t)T * (3 * (size_t)n * 64 + 64 * 64))) != TV_OK) return s;
-      if ((s = launch_subspace_prep(Sd, T, n, mat, dTr[d], dWs[d], st)) != TV_OK) return s;
+      jobs[nj++] = SubspaceJob{Sd, mat, dTr[d], dWs[d], n};
       groups[d] = JacobiGroup{subspace_T(dWs[d], T, n), dW[d], subspace_V(dWs[d], T, n),
                               64 * 64, 64, 64 * 64, 64, T};
     }
   }
+  if (nj > 0 && (s = launch_subspace_prep_batch(jobs, nj, T, st)) != TV_OK) return s;
   if ((s = launch_jacobi_batch(groups, 3, st)) != TV_OK) return s;
   for (int d = 0; d < 3; ++d)
     if (dims[d] > 64 &&

@@ -512,17 +512,33 @@ __global__ __launch_bounds__(256) void zgemm_batched_kernel(
 // column, in place on Z (n x l, row-major).  A column whose norm falls below
 // 1e-13 of its norm before projection lies in the span of the previous
 // ones and is set to zero.  One workgroup per matrix.
-__global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int n, int l,
-                                                   int64_t stride) {
+template <bool INLDS>
+__global__ __launch_bounds__(256) void cgs2_kernel(Cgs2Batch B) {
+  // with INLDS the matrix is staged in LDS (rows padded by one value, so a
+  // thread per row reading along its row meets no bank conflict)
+  extern __shared__ double2 zs[];
   __shared__ double2 c[64];
   __shared__ double2 cpart[4][64];
   __shared__ double red[256];
-  double2* Zb = Z + blockIdx.x * stride;
+  int64_t mat = blockIdx.x;
+  int gi = 0;
+  while (gi + 1 < B.ng && mat >= B.g[gi].nmat) {
+    mat -= B.g[gi].nmat;
+    ++gi;
+  }
+  const int n = B.g[gi].n, l = B.l;
+  double2* Zg = B.g[gi].Z + mat * B.g[gi].stride;
+  const int ls = INLDS ? l + 1 : l;
+  double2* Zb = INLDS ? zs : Zg;
   const int tid = threadIdx.x;
+  if (INLDS) {
+    for (int e = tid; e < n * l; e += 256) zs[(e / l) * ls + e % l] = Zg[e];
+    __syncthreads();
+  }
   for (int j = 0; j < l; ++j) {
     double s = 0.0;
     for (int i = tid; i < n; i += 256) {
-      const double2 v = Zb[(int64_t)i * l + j];
+      const double2 v = Zb[(int64_t)i * ls + j];
       s += v.x * v.x + v.y * v.y;
     }
     red[tid] = s;
@@ -541,7 +557,7 @@ __global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int 
         double2 a = make_double2(0.0, 0.0);
         if (kk < j)
           for (int i = part; i < n; i += 4) {
-            const double2 q = Zb[(int64_t)i * l + kk], z = Zb[(int64_t)i * l + j];
+            const double2 q = Zb[(int64_t)i * ls + kk], z = Zb[(int64_t)i * ls + j];
             a.x += q.x * z.x + q.y * z.y;  // conj(q) z
             a.y += q.x * z.y - q.y * z.x;
           }
@@ -553,19 +569,19 @@ __global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int 
                               cpart[0][tid].y + cpart[1][tid].y + cpart[2][tid].y + cpart[3][tid].y);
       __syncthreads();
       for (int i = tid; i < n; i += 256) {
-        double2 z = Zb[(int64_t)i * l + j];
+        double2 z = Zb[(int64_t)i * ls + j];
         for (int k = 0; k < j; ++k) {
-          const double2 q = Zb[(int64_t)i * l + k], ck = c[k];
+          const double2 q = Zb[(int64_t)i * ls + k], ck = c[k];
           z.x -= q.x * ck.x - q.y * ck.y;
           z.y -= q.x * ck.y + q.y * ck.x;
         }
-        Zb[(int64_t)i * l + j] = z;
+        Zb[(int64_t)i * ls + j] = z;
       }
       __syncthreads();
     }
     s = 0.0;
     for (int i = tid; i < n; i += 256) {
-      const double2 v = Zb[(int64_t)i * l + j];
+      const double2 v = Zb[(int64_t)i * ls + j];
       s += v.x * v.x + v.y * v.y;
     }
     red[tid] = s;
@@ -578,11 +594,13 @@ __global__ __launch_bounds__(256) void cgs2_kernel(double2* __restrict__ Z, int 
     const double scale = (nrm > 1e-13 * nrm0 && nrm > 1e-300) ? 1.0 / nrm : 0.0;
     __syncthreads();
     for (int i = tid; i < n; i += 256) {
-      double2 v = Zb[(int64_t)i * l + j];
-      Zb[(int64_t)i * l + j] = make_double2(v.x * scale, v.y * scale);
+      double2 v = Zb[(int64_t)i * ls + j];
+      Zb[(int64_t)i * ls + j] = make_double2(v.x * scale, v.y * scale);
     }
     __syncthreads();
   }
+  if (INLDS)
+    for (int e = tid; e < n * l; e += 256) Zg[e] = zs[(e / l) * ls + e % l];
 }
 
 // Deterministic start block Omega (n x l, row-major, complex entries in
@@ -631,34 +649,83 @@ tv_status launch_zgemm(int trans, int M, int N, int K, const double2* A, int lda
 // Q = orth(S orth(S Omega)) and T = Q^* S Q (64 x 64) in ws and the traces;
 // finish forms U = Q V from T's eigenvectors V.  ws layout: Q, Z, V (n x 64
 // each per matrix), T (64 x 64 per matrix).
+// CGS2 over groups of n x l matrices (row-major), one workgroup per matrix;
+// staged in LDS when every matrix of the batch fits
+double2* subspace_T(double2* ws, int nmat, int n);
+double2* subspace_V(double2* ws, int nmat, int n);
+
+tv_status launch_cgs2(const Cgs2Group* groups, int ng, int l, hipStream_t st) {
+  Cgs2Batch B{};
+  B.ng = ng;
+  B.l = l;
+  int nmax = 0;
+  int64_t blocks = 0;
+  for (int g = 0; g < ng; ++g) {
+    B.g[g] = groups[g];
+    nmax = std::max(nmax, groups[g].n);
+    blocks += groups[g].nmat;
+  }
+  const size_t lds = (size_t)nmax * (l + 1) * sizeof(double2);
+  if (lds <= 128 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)cgs2_kernel<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(cgs2)");
+    hipLaunchKernelGGL(cgs2_kernel<true>, dim3((unsigned)blocks), dim3(256), lds, st, B);
+  } else {
+    hipLaunchKernelGGL(cgs2_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, B);
+  }
+  return last("cgs2_kernel");
+}
+
+tv_status launch_subspace_prep_batch(const SubspaceJob* jobs, int nj, int nmat, hipStream_t st) {
+  const int l = 64;
+  tv_status s;
+  double2 *Q[3], *Z[3];
+  for (int j = 0; j < nj; ++j) {
+    const int n = jobs[j].n;
+    const int64_t nl = (int64_t)n * l, tot = (int64_t)nmat * nl;
+    Q[j] = jobs[j].ws;
+    Z[j] = Q[j] + nmat * nl;
+    hipLaunchKernelGGL(omega_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Q[j],
+                       n, l, nl, nmat);
+    if ((s = last("omega_kernel")) != TV_OK) return s;
+    hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((nmat + 255) / 256)), dim3(256), 0, st,
+                       jobs[j].S, n, jobs[j].sS, nmat, jobs[j].tr);
+    if ((s = last("trace_kernel")) != TV_OK) return s;
+  }
+  // Z = S Omega, Q = orth(Z); Z = S Q, Q = orth(Z) (two swaps: Q ends in ws),
+  // the orthogonalizations of all jobs in one launch
+  for (int it = 0; it < 2; ++it) {
+    Cgs2Group cg[3];
+    for (int j = 0; j < nj; ++j) {
+      const int n = jobs[j].n;
+      const int64_t nl = (int64_t)n * l;
+      if ((s = launch_zgemm(0, n, l, n, jobs[j].S, n, jobs[j].sS, Q[j], l, nl, Z[j], l, nl, nmat,
+                            st)) != TV_OK)
+        return s;
+      cg[j] = Cgs2Group{Z[j], nl, n, nmat};
+    }
+    if ((s = launch_cgs2(cg, nj, l, st)) != TV_OK) return s;
+    for (int j = 0; j < nj; ++j) std::swap(Q[j], Z[j]);
+  }
+  // Rayleigh-Ritz matrices T = Q^* (S Q)
+  for (int j = 0; j < nj; ++j) {
+    const int n = jobs[j].n;
+    const int64_t nl = (int64_t)n * l;
+    if ((s = launch_zgemm(0, n, l, n, jobs[j].S, n, jobs[j].sS, Q[j], l, nl, Z[j], l, nl, nmat,
+                          st)) != TV_OK)
+      return s;
+    if ((s = launch_zgemm(1, l, l, n, Q[j], l, nl, Z[j], l, nl, subspace_T(jobs[j].ws, nmat, n), l,
+                          (int64_t)l * l, nmat, st)) != TV_OK)
+      return s;
+  }
+  return TV_OK;
+}
+
 tv_status launch_subspace_prep(const double2* S, int nmat, int n, int64_t sS, double* tr,
                                double2* ws, hipStream_t st) {
-  const int l = 64;
-  const int64_t nl = (int64_t)n * l, ll = (int64_t)l * l;
-  double2* Q = ws;
-  double2* Z = Q + nmat * nl;
-  double2* T = Z + 2 * nmat * nl;
-  tv_status s;
-  const int64_t tot = (int64_t)nmat * nl;
-  hipLaunchKernelGGL(omega_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Q, n,
-                     l, nl, nmat);
-  if ((s = last("omega_kernel")) != TV_OK) return s;
-  hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((nmat + 255) / 256)), dim3(256), 0, st, S, n,
-                     sS, nmat, tr);
-  if ((s = last("trace_kernel")) != TV_OK) return s;
-  // Z = S Omega, Q = orth(Z); Z = S Q, Q = orth(Z) (two swaps: Q ends in ws)
-  for (int it = 0; it < 2; ++it) {
-    if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
-    hipLaunchKernelGGL(cgs2_kernel, dim3((unsigned)nmat), dim3(256), 0, st, Z, n, l, nl);
-    if ((s = last("cgs2_kernel")) != TV_OK) return s;
-    double2* tmp = Q;
-    Q = Z;
-    Z = tmp;
-  }
-  // Rayleigh-Ritz matrix T = Q^* (S Q)
-  if ((s = launch_zgemm(0, n, l, n, S, n, sS, Q, l, nl, Z, l, nl, nmat, st)) != TV_OK) return s;
-  (void)ll;
-  return launch_zgemm(1, l, l, n, Q, l, nl, Z, l, nl, T, l, (int64_t)l * l, nmat, st);
+  SubspaceJob j{S, sS, tr, ws, n};
+  return launch_subspace_prep_batch(&j, 1, nmat, st);
 }
 
 // the 64 x 64 Rayleigh-Ritz matrices of launch_subspace_prep's workspace

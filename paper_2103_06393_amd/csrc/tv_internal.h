@@ -59,6 +59,25 @@ struct JacobiBatch {
   JacobiGroup g[3];
   int ng, max_sweeps;
 };
+// one group of n x l matrices for the batched CGS2 orthogonalization
+struct Cgs2Group {
+  double2* Z;
+  int64_t stride;
+  int n, nmat;
+};
+struct Cgs2Batch {
+  Cgs2Group g[3];
+  int ng, l;
+};
+// one mode's subspace iteration: nmat Gram matrices n x n at sS, traces,
+// workspace (Q, Z, V: n x 64 each per matrix, then T: 64 x 64 per matrix)
+struct SubspaceJob {
+  const double2* S;
+  int64_t sS;
+  double* tr;
+  double2* ws;
+  int n;
+};
 
 }  // namespace tv
 
