@@ -296,17 +296,25 @@ static tv_status pack_plan(tv_plan_s* p) {
     for (int k = 0; k < g.q; ++k)
       p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * nbt * 64;
     apack.assign((size_t)p->apack_koff[g.q], 0.f);
+    // row a of tensor t: voxel row i1 fills embedded rows 2 i1 (Re) and
+    // 2 i1 + 1 (Im) of both K slots (lanes < 32: Re part, >= 32: Im part);
+    // rows past n1 stay zero
     for (int64_t j = 0; j < g.m; ++j)
       for (int k = 0; k < g.q; ++k) {
         const int64_t t = k + (int64_t)g.q * j;
         const TensorMeta& M = meta[(size_t)k * g.m + j];
         for (int a = 0; a < M.r1; ++a) {
           float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * nbt) * 64];
-          for (int blk = 0; blk < nbt; ++blk)
-            for (int lane = 0; lane < 64; ++lane) {
-              const int mrow = 32 * blk + (lane & 31);
-              row[blk * 64 + lane] = (float)emb(t, mrow >> 1, mrow & 1, a, lane >> 5);
-            }
+          const double* u = &p->u1[2 * (p->u1_off[t] + (size_t)g.n1 * a)];
+          const int n1 = std::min(g.n1, nbt * 16);
+          for (int i1 = 0; i1 < n1; ++i1) {
+            const float ar = (float)u[2 * i1], ai = (float)u[2 * i1 + 1];
+            float* rb = row + ((2 * i1) >> 5) * 64 + ((2 * i1) & 31);
+            rb[0] = ar;        // (Re row, Re part)
+            rb[32] = -ai;      // (Re row, Im part)
+            rb[1] = ai;        // (Im row, Re part)
+            rb[33] = ar;       // (Im row, Im part)
+          }
         }
       }
   } else {

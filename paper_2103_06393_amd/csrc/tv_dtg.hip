@@ -1023,63 +1023,60 @@ tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta) {
   // stacked row of each tensor's first U1 column in A_k (the fused BF16X3
   // kernels pad tensors to 8-row chunks in their own packing; this one does not)
   std::vector<int32_t> drow((size_t)g.q * g.m);
-  std::vector<std::vector<int64_t>> owner(g.q);
   for (int k = 0; k < g.q; ++k) {
-    owner[k].assign(p->dtg_rpad[k], 0);
     int64_t r = 0;
     for (int64_t j = 0; j < g.m; ++j) {
-      const TensorMeta& M = meta[(size_t)k * g.m + j];
       drow[(size_t)k * g.m + j] = (int32_t)r;
-      for (int a = 0; a < M.r1; ++a) owner[k][r + a] = j;
-      r += M.r1;
+      r += meta[(size_t)k * g.m + j].r1;
     }
   }
-  // value of the real-embedded stacked U1 of component k at real row mrow
-  // and k-step (stacked row a, part pp), from the tensor owning a
-  auto emb = [&](const std::vector<int64_t>& own, int k, int64_t a, int mrow, int pp) -> double {
-    const int i1 = mrow >> 1, s = mrow & 1;
-    if (i1 >= g.n1 || a >= p->sum_r1_k[k]) return 0.0;
-    const int64_t j = own[a];
-    const int64_t t = k + (int64_t)g.q * j;
-    const int al = (int)(a - drow[(size_t)k * g.m + j]);
-    const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * al;
-    const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
-    return s == pp ? ar : (s == 0 ? -ai : ai);
+  // every stacked row a (column al of tensor j's U1) fills, for each voxel row
+  // i1, the real-embedded rows 2 i1 (Re) and 2 i1 + 1 (Im) of its two k-steps
+  // (a, Re part) and (a, Im part): A_emb = [[Ur, -Ui], [Ui, Ur]]; rows past n1
+  // stay zero
+  const int n1e = std::min(g.n1, nbtp * 16);
+  auto for_rows = [&](auto&& put) {
+    for (int64_t j = 0; j < g.m; ++j)
+      for (int k = 0; k < g.q; ++k) {
+        const int64_t t = k + (int64_t)g.q * j;
+        const int r1 = meta[(size_t)k * g.m + j].r1;
+        for (int al = 0; al < r1; ++al) {
+          const int64_t a = drow[(size_t)k * g.m + j] + al;
+          const double* u = &p->u1[2 * (p->u1_off[t] + (size_t)g.n1 * al)];
+          for (int i1 = 0; i1 < n1e; ++i1) {
+            const float ur = (float)u[2 * i1], ui = (float)u[2 * i1 + 1];
+            const int mrow = 2 * i1, blk = mrow >> 5, l = mrow & 31;
+            put(k, a, blk, l, 0, ur);        // (Re row, Re part)
+            put(k, a, blk, l, 1, -ui);       // (Re row, Im part)
+            put(k, a, blk, l + 1, 0, ui);    // (Im row, Re part)
+            put(k, a, blk, l + 1, 1, ur);    // (Im row, Im part)
+          }
+        }
+      }
   };
   if (p->precision == TV_PREC_BF16X3) {
-    // hi/lo bf16 in the A-operand order of v_mfma_f32_32x32x16_bf16
+    // hi/lo bf16 in the A-operand order of v_mfma_f32_32x32x16_bf16: chunk c
+    // = 8 stacked rows, lane 32 h + row%32 holds k-slots e = 0..7 of rows
+    // 8c + 4h + e/2, part e%2
     p->dtg_abfoff.assign(g.q + 1, 0);
     for (int k = 0; k < g.q; ++k)
       p->dtg_abfoff[k + 1] = p->dtg_abfoff[k] + p->dtg_rpad[k] / 8 * nbtp * 128;
     std::vector<uint4> abf((size_t)p->dtg_abfoff[g.q], make_uint4(0, 0, 0, 0));
-    for (int k = 0; k < g.q; ++k)
-      for (int64_t c = 0; c < p->dtg_rpad[k] / 8; ++c)
-        for (int blk = 0; blk < nbtp; ++blk)
-          for (int lane = 0; lane < 64; ++lane) {
-            uint32_t hi[8], lo[8];
-            for (int e = 0; e < 8; ++e) {
-              const int64_t a = 8 * c + 4 * (lane >> 5) + e / 2;
-              const float v = (float)emb(owner[k], k, a, 32 * blk + (lane & 31), e % 2);
-              hi[e] = bf16_rne(v);
-              lo[e] = bf16_rne(v - bf16_float(hi[e]));
-            }
-            uint4* dst = &abf[p->dtg_abfoff[k] + ((c * nbtp + blk) * 2) * 64 + lane];
-            dst[0] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16),
-                                hi[4] | (hi[5] << 16), hi[6] | (hi[7] << 16));
-            dst[64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
-                                 lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
-          }
+    uint16_t* h16 = reinterpret_cast<uint16_t*>(abf.data());
+    for_rows([&](int k, int64_t a, int blk, int l, int pp, float v) {
+      const int64_t c = a >> 3;
+      const int h = (int)((a >> 2) & 1), e = (int)(2 * (a & 3) + pp);
+      const int64_t q4 = p->dtg_abfoff[k] + ((c * nbtp + blk) * 2) * 64 + 32 * h + l;
+      const uint32_t hi = bf16_rne(v);
+      h16[q4 * 8 + e] = (uint16_t)hi;
+      h16[(q4 + 64) * 8 + e] = (uint16_t)bf16_rne(v - bf16_float(hi));
+    });
     p->hp.abf = std::move(abf);
   } else {
     std::vector<float> a4((size_t)p->dtg_a4off[g.q], 0.f);
-    for (int k = 0; k < g.q; ++k)
-      for (int64_t a = 0; a < p->sum_r1_k[k]; ++a) {
-        float* base = &a4[p->dtg_a4off[k] + (a / 4) * nbtp * 256 + a % 4];
-        for (int blk = 0; blk < nbtp; ++blk)
-          for (int lane = 0; lane < 64; ++lane)
-            base[((int64_t)blk * 64 + lane) * 4] =
-                (float)emb(owner[k], k, a, 32 * blk + (lane & 31), lane >> 5);
-      }
+    for_rows([&](int k, int64_t a, int blk, int l, int pp, float v) {
+      a4[p->dtg_a4off[k] + (a / 4) * nbtp * 256 + ((int64_t)blk * 64 + 32 * pp + l) * 4 + a % 4] = v;
+    });
     p->hp.a4 = std::move(a4);
   }
   int64_t rp = 0;
