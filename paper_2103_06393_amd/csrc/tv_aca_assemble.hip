@@ -482,9 +482,17 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   };
 
   HostFactors F;
-  tv_plan U = nullptr;  // the compressed U of the steps so far (bound to uarena)
+  // the compressed U of the steps so far: a growable plan in uarena
+  tv_plan U = nullptr;
+  {
+    int rmax[3];
+    rank_bounds(g, rank_cap, rmax);
+    tv_grid gk = g;
+    gk.m = K;
+    if ((s = grow_plan_create(gk, rmax, precision, uarena, Z.uarena, st, &U)) != TV_OK) return s;
+  }
   auto fail = [&](tv_status r) {
-    if (U) tv_plan_destroy(U);
+    tv_plan_destroy(U);
     return r;
   };
   int64_t i = 0;
@@ -549,24 +557,17 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
       if (e != hipSuccess) return fail(hip_error(e, "cross term readback"));
       s_next += cross;
     }
-    // U = [U HOSVD(x)] and V = [V y] (y is already in place)
+    // U = [U HOSVD(x)] and V = [V y] (y is already in place); the products
+    // above have been waited for (the cross-term readback), so U's arrays
+    // may grow in place
+    const size_t o0 = F.cores.size(), o1 = F.u1.size(), o2 = F.u2.size(), o3 = F.u3.size(),
+                 orank = F.ranks.size();
     if ((s = compress_column(g, d_x, htol, rank_min, rank_cap, precision, F, cws, Z.comp,
                              stream)) != TV_OK)
       return fail(s);
-    tv_grid gk = g;
-    gk.m = k + 1;
-    tv_plan U2 = nullptr;
-    if ((s = plan_from_factors_ex(&gk, F.ranks.data(), F.cores.data(), F.u1.data(),
-                                  F.u2.data(), F.u3.data(), precision, false, &U2)) != TV_OK)
+    if ((s = grow_plan_append(U, &F.ranks[orank], &F.cores[o0], &F.u1[o1], &F.u2[o2], &F.u3[o3],
+                              st)) != TV_OK)
       return fail(s);
-    // the previous U is no longer read: its arena region takes the new one
-    if (U) tv_plan_destroy(U);
-    U = nullptr;
-    if ((s = tv_plan_bind_arena(U2, uarena, Z.uarena, stream)) != TV_OK) {
-      tv_plan_destroy(U2);
-      return fail(s);
-    }
-    U = U2;
     if (pivots) {
       pivots[2 * k] = i;
       pivots[2 * k + 1] = j;
@@ -589,7 +590,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     // the first row was zero: no term; report an empty approximation
     *rc_out = 0;
     *converged_out = 1;
-    return set_error(TV_ERR_NUMERIC, "the first pivot row of Z is zero");
+    return fail(set_error(TV_ERR_NUMERIC, "the first pivot row of Z is zero"));
   }
   e = hipMemcpy(v_out, d_V, sizeof(double2) * (size_t)m * rc, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(hip_error(e, "V readback"));
@@ -603,7 +604,6 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     if (s != TV_OK) return fail(s);
   }
   tv_plan_destroy(U);
-  U = nullptr;
   *u_out = Uout;
   *rc_out = rc;
   *converged_out = converged ? 1 : 0;

@@ -212,6 +212,77 @@ tv_status set_split(tv_plan_s* p, int op, int S) {
   return TV_OK;
 }
 
+// FP32 copies of one tensor's factors (ranks r, FP64 interleaved inputs):
+// the core as is, U1..U3 transposed to row-major (i, rank).
+static void pack_tensor_f32(const tv_grid& g, const int32_t* r, const double* core,
+                            const double* u1, const double* u2, const double* u3, float2* dc,
+                            float2* d1, float2* d2, float2* d3) {
+  const int64_t nc = (int64_t)r[0] * r[1] * r[2];
+  for (int64_t i = 0; i < nc; ++i) dc[i] = make_float2((float)core[2 * i], (float)core[2 * i + 1]);
+  auto transpose = [](int n, int rk, const double* u, float2* d) {
+    for (int a = 0; a < rk; ++a)
+      for (int i = 0; i < n; ++i) {
+        const size_t src = i + (size_t)n * a;
+        d[(size_t)i * rk + a] = make_float2((float)u[2 * src], (float)u[2 * src + 1]);
+      }
+  };
+  transpose(g.n1, r[0], u1, d1);
+  transpose(g.n2, r[1], u2, d2);
+  transpose(g.n3, r[2], u3, d3);
+}
+
+// Stacked U1 rows of one tensor in MFMA A-operand lane order, as the real
+// embedding A_emb[2 i1 + s][(a, p)] = Ar (s == p), -Ai (s = 0, p = 1),
+// Ai (s = 1, p = 0) of U1 (n1 x r1, FP64 interleaved, column-major).
+// FP32: r1 rows of nbt * 64 floats, rows[(a * nbt + blk) * 64 + lane] =
+//   A_emb[32 blk + lane % 32][(a, lane / 32)]; voxel row i1 fills embedded
+//   rows 2 i1 (Re) and 2 i1 + 1 (Im) of both K slots; rows past n1 are zero.
+static void pack_apack_f32(const tv_grid& g, int r1, const double* u1, int nbt, float* rows) {
+  std::fill(rows, rows + (size_t)r1 * nbt * 64, 0.f);
+  const int n1 = std::min(g.n1, nbt * 16);
+  for (int a = 0; a < r1; ++a) {
+    float* row = rows + (size_t)a * nbt * 64;
+    const double* u = u1 + 2 * (size_t)g.n1 * a;
+    for (int i1 = 0; i1 < n1; ++i1) {
+      const float ar = (float)u[2 * i1], ai = (float)u[2 * i1 + 1];
+      float* rb = row + ((2 * i1) >> 5) * 64 + ((2 * i1) & 31);
+      rb[0] = ar;    // (Re row, Re part)
+      rb[32] = -ai;  // (Re row, Im part)
+      rb[1] = ai;    // (Im row, Re part)
+      rb[33] = ar;   // (Im row, Im part)
+    }
+  }
+}
+
+// BF16X3: ceil(r1 / 8) chunks of nbt * 128 uint4,
+//   chunks[((c * nbt + blk) * 2 + hl) * 64 + lane] = 8 bf16 (hi or lo) for K
+//   slots 8 (lane / 32) + i, i < 8, slot k = (row 8 c + k / 2, part k % 2).
+static void pack_apack_bf(const tv_grid& g, int r1, const double* u1, int nbt, uint4* chunks) {
+  const int nch = (r1 + 7) / 8;
+  for (int c = 0; c < nch; ++c)
+    for (int blk = 0; blk < nbt; ++blk)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int mrow = 32 * blk + (lane & 31), i1 = mrow >> 1, srow = mrow & 1;
+        uint32_t hi[8], lo[8];
+        for (int i = 0; i < 8; ++i) {
+          const int kk = 8 * (lane >> 5) + i, a = 8 * c + kk / 2, pp = kk % 2;
+          double v = 0.0;
+          if (i1 < g.n1 && a < r1) {
+            const size_t src = i1 + (size_t)g.n1 * a;
+            const double ar = u1[2 * src], ai = u1[2 * src + 1];
+            v = srow == pp ? ar : (srow == 0 ? -ai : ai);
+          }
+          hi[i] = bf16_bits(v);
+          lo[i] = bf16_bits(v - bf16_value(hi[i]));
+        }
+        uint4* dst = &chunks[((size_t)(c * nbt + blk) * 2) * 64 + lane];
+        dst[0] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16), hi[4] | (hi[5] << 16),
+                            hi[6] | (hi[7] << 16));
+        dst[64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16), lo[4] | (lo[5] << 16),
+                             lo[6] | (lo[7] << 16));
+      }
+}
+
 // Pack the FP64 host factors into the device layouts of the kernels (host
 // side; the device copy is made by tv_plan_bind_arena).
 static tv_status pack_plan(tv_plan_s* p) {
@@ -249,102 +320,35 @@ static tv_status pack_plan(tv_plan_s* p) {
       chunks_k[k] += (M.r1 + 7) / 8;
     }
 
-  // FP32 copies; U2, U3 transposed to row-major (i, r)
   std::vector<float2> cores((size_t)p->g_off[K]);
-  for (size_t i = 0; i < cores.size(); ++i)
-    cores[i] = make_float2((float)p->cores[2 * i], (float)p->cores[2 * i + 1]);
   std::vector<float2> u1t((size_t)p->u1_off[K]), u2t((size_t)p->u2_off[K]),
       u3t((size_t)p->u3_off[K]);
-  for (int64_t t = 0; t < K; ++t) {
-    const int r1 = p->ranks[3 * t], r2 = p->ranks[3 * t + 1], r3 = p->ranks[3 * t + 2];
-    for (int a = 0; a < r1; ++a)
-      for (int i = 0; i < g.n1; ++i) {
-        const size_t src = p->u1_off[t] + i + (size_t)g.n1 * a;
-        u1t[p->u1_off[t] + (size_t)i * r1 + a] =
-            make_float2((float)p->u1[2 * src], (float)p->u1[2 * src + 1]);
-      }
-    for (int b = 0; b < r2; ++b)
-      for (int i = 0; i < g.n2; ++i) {
-        const size_t src = p->u2_off[t] + i + (size_t)g.n2 * b;
-        u2t[p->u2_off[t] + (size_t)i * r2 + b] =
-            make_float2((float)p->u2[2 * src], (float)p->u2[2 * src + 1]);
-      }
-    for (int c = 0; c < r3; ++c)
-      for (int i = 0; i < g.n3; ++i) {
-        const size_t src = p->u3_off[t] + i + (size_t)g.n3 * c;
-        u3t[p->u3_off[t] + (size_t)i * r3 + c] =
-            make_float2((float)p->u3[2 * src], (float)p->u3[2 * src + 1]);
-      }
-  }
+  for (int64_t t = 0; t < K; ++t)
+    pack_tensor_f32(g, &p->ranks[3 * t], &p->cores[2 * p->g_off[t]], &p->u1[2 * p->u1_off[t]],
+                    &p->u2[2 * p->u2_off[t]], &p->u3[2 * p->u3_off[t]], &cores[p->g_off[t]],
+                    &u1t[p->u1_off[t]], &u2t[p->u2_off[t]], &u3t[p->u3_off[t]]);
 
-  // stacked U1 per component in MFMA A-operand lane order, as the real
-  // embedding A_emb[2 i1 + s][(a, p)] = Ar (s == p), -Ai (s = 0, p = 1),
-  // Ai (s = 1, p = 0).
-  // FP32: apack[koff + (row*nbt + blk)*64 + lane] = A_emb[32 blk + lane%32][(row, lane/32)]
-  // BF16X3: apack_bf[koff + ((chunk*nbt + blk)*2 + hl)*64 + lane] = 8 bf16 (hi or lo)
-  //   for K slots 8 (lane/32) + i, i < 8, slot k = (row 8 chunk + k/2, part k%2)
-  auto emb = [&](int64_t t, int i1, int s, int a, int pp) -> double {
-    if (i1 >= g.n1 || a >= p->ranks[3 * t]) return 0.0;
-    const size_t src = p->u1_off[t] + i1 + (size_t)g.n1 * a;
-    const double ar = p->u1[2 * src], ai = p->u1[2 * src + 1];
-    return s == pp ? ar : (s == 0 ? -ai : ai);
-  };
   p->apack_koff.assign(g.q + 1, 0);
   std::vector<float> apack;
   std::vector<uint4> apack_bf;
-  if (!bf) {
-    for (int k = 0; k < g.q; ++k)
-      p->apack_koff[k + 1] = p->apack_koff[k] + p->sum_r1_k[k] * nbt * 64;
-    apack.assign((size_t)p->apack_koff[g.q], 0.f);
-    // row a of tensor t: voxel row i1 fills embedded rows 2 i1 (Re) and
-    // 2 i1 + 1 (Im) of both K slots (lanes < 32: Re part, >= 32: Im part);
-    // rows past n1 stay zero
-    for (int64_t j = 0; j < g.m; ++j)
-      for (int k = 0; k < g.q; ++k) {
-        const int64_t t = k + (int64_t)g.q * j;
-        const TensorMeta& M = meta[(size_t)k * g.m + j];
-        for (int a = 0; a < M.r1; ++a) {
-          float* row = &apack[p->apack_koff[k] + ((int64_t)(M.arow + a) * nbt) * 64];
-          const double* u = &p->u1[2 * (p->u1_off[t] + (size_t)g.n1 * a)];
-          const int n1 = std::min(g.n1, nbt * 16);
-          for (int i1 = 0; i1 < n1; ++i1) {
-            const float ar = (float)u[2 * i1], ai = (float)u[2 * i1 + 1];
-            float* rb = row + ((2 * i1) >> 5) * 64 + ((2 * i1) & 31);
-            rb[0] = ar;        // (Re row, Re part)
-            rb[32] = -ai;      // (Re row, Im part)
-            rb[1] = ai;        // (Im row, Re part)
-            rb[33] = ar;       // (Im row, Im part)
-          }
-        }
-      }
-  } else {
-    for (int k = 0; k < g.q; ++k)
-      p->apack_koff[k + 1] = p->apack_koff[k] + chunks_k[k] * nbt * 128;
-    apack_bf.assign((size_t)p->apack_koff[g.q], make_uint4(0, 0, 0, 0));
-    for (int64_t j = 0; j < g.m; ++j)
-      for (int k = 0; k < g.q; ++k) {
-        const int64_t t = k + (int64_t)g.q * j;
-        const TensorMeta& M = meta[(size_t)k * g.m + j];
-        for (int c = 0; c < (M.r1 + 7) / 8; ++c)
-          for (int blk = 0; blk < nbt; ++blk)
-            for (int lane = 0; lane < 64; ++lane) {
-              const int mrow = 32 * blk + (lane & 31);
-              uint32_t hi[8], lo[8];
-              for (int i = 0; i < 8; ++i) {
-                const int kk = 8 * (lane >> 5) + i;
-                const double v = emb(t, mrow >> 1, mrow & 1, 8 * c + kk / 2, kk % 2);
-                hi[i] = bf16_bits(v);
-                lo[i] = bf16_bits(v - bf16_value(hi[i]));
-              }
-              uint4* dst = &apack_bf[p->apack_koff[k] +
-                                     (((int64_t)(M.arow + c) * nbt + blk) * 2) * 64 + lane];
-              dst[0] = make_uint4(hi[0] | (hi[1] << 16), hi[2] | (hi[3] << 16),
-                                  hi[4] | (hi[5] << 16), hi[6] | (hi[7] << 16));
-              dst[64] = make_uint4(lo[0] | (lo[1] << 16), lo[2] | (lo[3] << 16),
-                                   lo[4] | (lo[5] << 16), lo[6] | (lo[7] << 16));
-            }
-      }
-  }
+  for (int k = 0; k < g.q; ++k)
+    p->apack_koff[k + 1] =
+        p->apack_koff[k] + (bf ? chunks_k[k] * nbt * 128 : p->sum_r1_k[k] * nbt * 64);
+  if (!bf)
+    apack.resize((size_t)p->apack_koff[g.q]);
+  else
+    apack_bf.resize((size_t)p->apack_koff[g.q]);
+  for (int64_t j = 0; j < g.m; ++j)
+    for (int k = 0; k < g.q; ++k) {
+      const int64_t t = k + (int64_t)g.q * j;
+      const TensorMeta& M = meta[(size_t)k * g.m + j];
+      const double* u1 = &p->u1[2 * p->u1_off[t]];
+      if (!bf)
+        pack_apack_f32(g, M.r1, u1, nbt, &apack[p->apack_koff[k] + (int64_t)M.arow * nbt * 64]);
+      else
+        pack_apack_bf(g, M.r1, u1, nbt,
+                      &apack_bf[p->apack_koff[k] + (int64_t)M.arow * nbt * 128]);
+    }
 
   // column splits: spread the work over enough workgroups to fill the chip
   const int64_t base_f = (int64_t)g.q * p->tiling.tiles, base_a = (int64_t)g.q * p->tiling_a.tiles;
@@ -493,32 +497,266 @@ tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const 
   return TV_OK;
 }
 
-size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision) {
-  // the packed U1 rows hold the larger row-block count of the default
-  // forward (8 blocks per wave) and adjoint (2) tilings
-  Tiling Tf, Ta;
-  if (make_tiling(g, 0, 8, &Tf) != TV_OK || make_tiling(g, 0, 2, &Ta) != TV_OK) return 0;
-  const int nbt = std::max(Tf.nbt, Ta.nbt);
+// Device layout of a plan holding up to g.m columns at ranks up to rmax, in
+// the order of arena_layout, every array at its capacity; with p and base
+// set, p's device pointers are carved from base.
+static size_t capacity_layout(const tv_grid& g, const int rmax[3], int nbt,
+                              tv_precision precision, tv_plan_s* p, char* base) {
   const size_t K = (size_t)g.q * g.m;
   const size_t r1 = rmax[0], r2 = rmax[1], r3 = rmax[2];
+  const bool bf = precision == TV_PREC_BF16X3;
   size_t off = 0;
-  auto carve = [&](size_t bytes) { off = ((off + 255) & ~(size_t)255) + bytes; };
-  carve(K * sizeof(TensorMeta));
-  carve(K * r1 * r2 * r3 * sizeof(float2));
-  carve(K * g.n1 * r1 * sizeof(float2));
-  carve(K * g.n2 * r2 * sizeof(float2));
-  carve(K * g.n3 * r3 * sizeof(float2));
-  if (precision == TV_PREC_BF16X3) {
-    carve(0);
-    carve(K * ((r1 + 7) / 8) * nbt * 128 * sizeof(uint4));
-  } else {
-    carve(K * r1 * nbt * 64 * sizeof(float));
-    carve(0);
-  }
-  carve((size_t)(g.q + 1) * sizeof(int64_t));
-  carve((size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
-  carve((size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
+  auto carve = [&](auto** ptr, size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    typedef typename std::remove_reference<decltype(**ptr)>::type T;
+    if (p && base) *ptr = bytes ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+  };
+  tv_plan_s dummy;
+  tv_plan_s* d = p ? p : &dummy;
+  carve(&d->d_meta, K * sizeof(TensorMeta));
+  carve(&d->d_cores, K * r1 * r2 * r3 * sizeof(float2));
+  carve(&d->d_u1t, K * g.n1 * r1 * sizeof(float2));
+  carve(&d->d_u2t, K * g.n2 * r2 * sizeof(float2));
+  carve(&d->d_u3t, K * g.n3 * r3 * sizeof(float2));
+  carve(&d->d_apack, bf ? 0 : K * r1 * nbt * 64 * sizeof(float));
+  carve(&d->d_apack_bf, bf ? K * ((r1 + 7) / 8) * nbt * 128 * sizeof(uint4) : 0);
+  carve(&d->d_apack_koff, (size_t)(g.q + 1) * sizeof(int64_t));
+  carve(&d->d_split_f, (size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
+  carve(&d->d_split_a, (size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
   return (off + 255) & ~(size_t)255;
+}
+
+static int pack_nbt(const tv_grid& g, int nbcap_a) {
+  // the packed U1 rows hold the larger row-block count of the forward (8
+  // blocks per wave) and adjoint tilings
+  Tiling Tf, Ta;
+  if (make_tiling(g, 0, 8, &Tf) != TV_OK || make_tiling(g, 0, nbcap_a, &Ta) != TV_OK) return 0;
+  return std::max(Tf.nbt, Ta.nbt);
+}
+
+size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision) {
+  const int nbt = pack_nbt(g, 2);
+  return nbt ? capacity_layout(g, rmax, nbt, precision, nullptr, nullptr) : 0;
+}
+
+tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision precision,
+                           void* arena, size_t bytes, hipStream_t st, tv_plan* out) {
+  *out = nullptr;
+  tv_status s = validate_grid(&g);
+  if (s != TV_OK) return s;
+  if (precision != TV_PREC_FP32 && precision != TV_PREC_BF16X3)
+    return set_error(TV_ERR_INVALID_ARG, "unknown precision");
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  for (int d = 0; d < 3; ++d)
+    if (rmax[d] < 1 || rmax[d] > std::min(dims[d], TV_MAX_RANK))
+      return set_error(TV_ERR_RANK, "growable plan: rank cap outside [1, min(n, TV_MAX_RANK)]");
+  if (!arena || (uintptr_t)arena % 256)
+    return set_error(TV_ERR_INVALID_ARG, "arena must be non-NULL and 256-byte aligned");
+  tv_plan_s* p = new (std::nothrow) tv_plan_s;
+  if (!p) return set_error(TV_ERR_OOM, "host allocation");
+  p->grid = g;
+  p->grid.m = 0;
+  p->precision = precision;
+  p->with_dtg = false;
+  p->grow_mcap = g.m;
+  for (int d = 0; d < 3; ++d) p->grow_rcap[d] = rmax[d];
+  if ((s = make_tiling(g, 0, nb_cap(p, 0), &p->tiling)) != TV_OK ||
+      (s = make_tiling(g, 0, nb_cap(p, 1), &p->tiling_a)) != TV_OK) {
+    delete p;
+    return s;
+  }
+  const int nbt = std::max(p->tiling.nbt, p->tiling_a.nbt);
+  p->nbt_pack = nbt;
+  const size_t need = capacity_layout(g, rmax, nbt, precision, nullptr, nullptr);
+  if (bytes < need) {
+    delete p;
+    char buf[128];
+    snprintf(buf, sizeof buf, "growable plan arena of %zu bytes needed, %zu given", need, bytes);
+    return set_error(TV_ERR_WORKSPACE, buf);
+  }
+  capacity_layout(g, rmax, nbt, precision, p, (char*)arena);
+  const bool bf = precision == TV_PREC_BF16X3;
+  const int64_t cap_k = bf ? g.m * (int64_t)((rmax[0] + 7) / 8) * nbt * 128
+                           : g.m * (int64_t)rmax[0] * nbt * 64;
+  p->apack_koff.resize(g.q + 1);
+  for (int k = 0; k <= g.q; ++k) p->apack_koff[k] = k * cap_k;
+  p->sum_r1_k.assign(g.q, 0);
+  p->grow_chunks_k.assign(g.q, 0);
+  p->g_off.assign(1, 0);
+  p->u1_off.assign(1, 0);
+  p->u2_off.assign(1, 0);
+  p->u3_off.assign(1, 0);
+  hipError_t e = hipMemcpyAsync(p->d_apack_koff, p->apack_koff.data(),
+                                p->apack_koff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_error(e, "growable plan set-up");
+  }
+  p->finalized = true;
+  p->bound = true;
+  *out = p;
+  return TV_OK;
+}
+
+tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
+                           const double* u1, const double* u2, const double* u3,
+                           hipStream_t st) {
+  if (!p || !p->grow_mcap) return set_error(TV_ERR_INVALID_ARG, "not a growable plan");
+  tv_grid& g = p->grid;
+  const int64_t j = g.m;
+  if (j >= p->grow_mcap) return set_error(TV_ERR_SHAPE, "growable plan is full");
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  for (int k = 0; k < g.q; ++k)
+    for (int d = 0; d < 3; ++d)
+      if (ranks[3 * k + d] < 1 || ranks[3 * k + d] > p->grow_rcap[d] ||
+          ranks[3 * k + d] > dims[d])
+        return set_error(TV_ERR_RANK, "growable plan: rank above the plan's cap");
+  const bool bf = p->precision == TV_PREC_BF16X3;
+  const int nbt = p->nbt_pack;
+  const int64_t t0 = (int64_t)g.q * j;
+  // new tensors' offsets, ranks and running maxima
+  int max_r[3] = {p->max_r[0], p->max_r[1], p->max_r[2]};
+  int max_r12 = p->max_r12;
+  int64_t max_core = p->max_core;
+  for (int k = 0; k < g.q; ++k) {
+    const int32_t* r = &ranks[3 * k];
+    for (int d = 0; d < 3; ++d) max_r[d] = std::max(max_r[d], (int)r[d]);
+    max_r12 = std::max(max_r12, (int)(r[0] * r[1]));
+    max_core = std::max(max_core, (int64_t)r[0] * r[1] * r[2]);
+  }
+  {
+    // the fused kernels' LDS tile at the new maxima
+    tv_plan_s probe;
+    for (int d = 0; d < 3; ++d) probe.max_r[d] = max_r[d];
+    probe.max_r12 = max_r12;
+    probe.max_core = max_core;
+    if (fused_lds_bytes(&probe, p->tiling, false) > 160 * 1024 ||
+        fused_lds_bytes(&probe, p->tiling_a, true) > 160 * 1024)
+      return set_error(TV_ERR_NOT_SUPPORTED, "ranks too large for the LDS tile");
+  }
+  HostPack& H = p->grow_stage;
+  int64_t nc = 0, n1 = 0, n2 = 0, n3 = 0;
+  for (int k = 0; k < g.q; ++k) {
+    const int32_t* r = &ranks[3 * k];
+    nc += (int64_t)r[0] * r[1] * r[2];
+    n1 += (int64_t)g.n1 * r[0];
+    n2 += (int64_t)g.n2 * r[1];
+    n3 += (int64_t)g.n3 * r[2];
+  }
+  if (!all_finite(cores, 2 * nc) || !all_finite(u1, 2 * n1) || !all_finite(u2, 2 * n2) ||
+      !all_finite(u3, 2 * n3))
+    return set_error(TV_ERR_NUMERIC, "non-finite factor values");
+  H.cores.resize(nc);
+  H.u1t.resize(n1);
+  H.u2t.resize(n2);
+  H.u3t.resize(n3);
+  int64_t oc = 0, o1 = 0, o2 = 0, o3 = 0, arows = 0;
+  for (int k = 0; k < g.q; ++k) {
+    const int32_t* r = &ranks[3 * k];
+    pack_tensor_f32(g, r, cores + 2 * oc, u1 + 2 * o1, u2 + 2 * o2, u3 + 2 * o3, &H.cores[oc],
+                    &H.u1t[o1], &H.u2t[o2], &H.u3t[o3]);
+    oc += (int64_t)r[0] * r[1] * r[2];
+    o1 += (int64_t)g.n1 * r[0];
+    o2 += (int64_t)g.n2 * r[1];
+    o3 += (int64_t)g.n3 * r[2];
+    arows += bf ? (r[0] + 7) / 8 : r[0];
+  }
+  // stacked U1 rows of the new tensors, component by component
+  if (!bf)
+    H.apack.resize((size_t)arows * nbt * 64);
+  else
+    H.apack_bf.resize((size_t)arows * nbt * 128);
+  std::vector<int64_t> arow_new(g.q);
+  o1 = 0;
+  arows = 0;
+  for (int k = 0; k < g.q; ++k) {
+    const int r1 = ranks[3 * k];
+    arow_new[k] = bf ? p->grow_chunks_k[k] : p->sum_r1_k[k];
+    if (!bf)
+      pack_apack_f32(g, r1, u1 + 2 * o1, nbt, &H.apack[(size_t)arows * nbt * 64]);
+    else
+      pack_apack_bf(g, r1, u1 + 2 * o1, nbt, &H.apack_bf[(size_t)arows * nbt * 128]);
+    o1 += (int64_t)g.n1 * r1;
+    arows += bf ? (r1 + 7) / 8 : r1;
+  }
+  // commit the host state
+  for (int k = 0; k < g.q; ++k) {
+    const int32_t* r = &ranks[3 * k];
+    p->ranks.insert(p->ranks.end(), r, r + 3);
+    const int64_t t = t0 + k;
+    p->g_off.push_back(p->g_off[t] + (int64_t)r[0] * r[1] * r[2]);
+    p->u1_off.push_back(p->u1_off[t] + (int64_t)g.n1 * r[0]);
+    p->u2_off.push_back(p->u2_off[t] + (int64_t)g.n2 * r[1]);
+    p->u3_off.push_back(p->u3_off[t] + (int64_t)g.n3 * r[2]);
+    p->sum_r1_k[k] += r[0];
+    p->grow_chunks_k[k] += (r[0] + 7) / 8;
+    p->sum_r1 += r[0];
+  }
+  for (int d = 0; d < 3; ++d) p->max_r[d] = max_r[d];
+  p->max_r12 = max_r12;
+  p->max_core = max_core;
+  g.m = j + 1;
+  const int64_t K = (int64_t)g.q * g.m;
+  // metadata, component-major [k][j]
+  H.meta.resize(K);
+  {
+    std::vector<int64_t> row(g.q, 0);
+    for (int64_t jj = 0; jj < g.m; ++jj)
+      for (int k = 0; k < g.q; ++k) {
+        const int64_t t = k + (int64_t)g.q * jj;
+        TensorMeta& M = H.meta[(size_t)k * g.m + jj];
+        M.r1 = p->ranks[3 * t];
+        M.r2 = p->ranks[3 * t + 1];
+        M.r3 = p->ranks[3 * t + 2];
+        M.arow = (int32_t)row[k];
+        M.g_off = p->g_off[t];
+        M.u2_off = p->u2_off[t];
+        M.u3_off = p->u3_off[t];
+        M.u1_off = p->u1_off[t];
+        row[k] += bf ? (M.r1 + 7) / 8 : M.r1;
+      }
+  }
+  // column splits as pack_plan sets them
+  const int64_t base_f = (int64_t)g.q * p->tiling.tiles, base_a = (int64_t)g.q * p->tiling_a.tiles;
+  const int sf = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + base_f - 1) / base_f));
+  const int sa = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + base_a - 1) / base_a));
+  p->split_f = (int)std::max<int64_t>(1, std::min<int64_t>(sf, g.m));
+  p->split_a = (int)std::max<int64_t>(1, std::min<int64_t>(sa, g.m));
+  {
+    std::vector<int32_t> a = make_split(p, p->split_f), b = make_split(p, p->split_a);
+    p->grow_split.assign(a.begin(), a.end());
+    p->grow_split.insert(p->grow_split.end(), b.begin(), b.end());
+  }
+  // uploads, then wait so that the staging may be reused
+  hipError_t e = hipSuccess;
+  auto put = [&](void* d, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(d, src, n, hipMemcpyHostToDevice, st);
+  };
+  put(p->d_meta, H.meta.data(), H.meta.size() * sizeof(TensorMeta));
+  put(p->d_cores + p->g_off[t0], H.cores.data(), H.cores.size() * sizeof(float2));
+  put(p->d_u1t + p->u1_off[t0], H.u1t.data(), H.u1t.size() * sizeof(float2));
+  put(p->d_u2t + p->u2_off[t0], H.u2t.data(), H.u2t.size() * sizeof(float2));
+  put(p->d_u3t + p->u3_off[t0], H.u3t.data(), H.u3t.size() * sizeof(float2));
+  arows = 0;
+  for (int k = 0; k < g.q; ++k) {
+    const int r1 = ranks[3 * k];
+    const int64_t nr = bf ? (r1 + 7) / 8 : r1;
+    if (!bf)
+      put(p->d_apack + p->apack_koff[k] + arow_new[k] * nbt * 64, &H.apack[arows * nbt * 64],
+          (size_t)nr * nbt * 64 * sizeof(float));
+    else
+      put(p->d_apack_bf + p->apack_koff[k] + arow_new[k] * nbt * 128,
+          &H.apack_bf[arows * nbt * 128], (size_t)nr * nbt * 128 * sizeof(uint4));
+    arows += nr;
+  }
+  const size_t nsf = (size_t)g.q * (p->split_f + 1);
+  put(p->d_split_f, p->grow_split.data(), nsf * sizeof(int32_t));
+  put(p->d_split_a, p->grow_split.data() + nsf,
+      (size_t)g.q * (p->split_a + 1) * sizeof(int32_t));
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? TV_OK : hip_error(e, "growable plan upload");
 }
 
 }  // namespace tv

@@ -21,7 +21,8 @@
 
 namespace tv {
 tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
-                      hipStream_t st);
+                      double2* P, hipStream_t st);
+size_t gram_partial_count(int ntens, int nmax);
 tv_status launch_jacobi(const double2* S, int nmat, int n, int64_t stride, double* W,
                         int64_t wstride, double2* V, int64_t vstride, hipStream_t st);
 tv_status launch_proj(const double2* A, int ntens, int n1, int n2, int n3, const double2* u1,
@@ -57,7 +58,7 @@ struct DevScratch {
 };
 
 // Upper bound of the scratch of one append call of T tensors: Gram
-// matrices, eigenpairs (and the subspace solver's work arrays for modes
+// matrices (and their partial tiles when the columns are split), eigenpairs (and the subspace solver's work arrays for modes
 // longer than 64), factors at the largest rank a mode can keep, and the
 // partial projections and cores of the core computation.
 size_t compress_scratch_bytes(const tv_plan_s* p, int T) {
@@ -76,6 +77,7 @@ size_t compress_scratch_bytes(const tv_plan_s* p, int T) {
   int64_t* zi;
   int* zk;
   ds.alloc(&z2, (size_t)3 * T * nmax * nmax);
+  ds.alloc(&z2, gram_partial_count(T, nmax));
   for (int d = 0; d < 3; ++d) {
     const int n = dims[d], L = n <= 64 ? n : 64;
     ds.alloc(&z2, (size_t)T * n * L);
@@ -207,8 +209,10 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   //    64 pairs by subspace iteration otherwise
   const int64_t mat = (int64_t)nmax * nmax;
   double2* dS;
+  double2* dP;  // partial Gram tiles of calls with few tensors
   if ((s = ds.alloc(&dS, (size_t)3 * T * mat)) != TV_OK) return s;
-  if ((s = launch_gram(A, T, g.n1, g.n2, g.n3, nmax, dS, st)) != TV_OK) return s;
+  if ((s = ds.alloc(&dP, gram_partial_count(T, nmax))) != TV_OK) return s;
+  if ((s = launch_gram(A, T, g.n1, g.n2, g.n3, nmax, dS, dP, st)) != TV_OK) return s;
   std::vector<std::vector<double>> W(3), TR(3);
   std::vector<std::vector<double2>> V(3);
   int L[3];

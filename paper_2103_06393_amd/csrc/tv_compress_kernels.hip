@@ -40,36 +40,54 @@ __device__ __forceinline__ int64_t unfold_index(int d, int64_t i, int64_t o, int
   return o + (int64_t)n1 * n2 * i;
 }
 
+// Tile pair index -> (ti, tj) with ti <= tj over `tiles` row tiles.
+__device__ __forceinline__ void gram_pair(int pr, int tiles, int& ti, int& tj) {
+  ti = 0;
+  while (pr >= tiles - ti) {
+    pr -= tiles - ti;
+    ++ti;
+  }
+  tj = ti + pr;
+}
+
 // S_d = A_(d) A_(d)^*, one 64 x 64 tile (ti <= tj: S is Hermitian, the tile
 // below the diagonal is written as the conjugate transpose) of one (tensor,
 // mode) per workgroup.  The unfolding streams through LDS 16 columns at a
 // time, the next 16 loaded into registers during the current ones' products.
-// grid.x = tensors * 3 * tiles (tiles + 1) / 2 with tiles = ceil(nmax / 64).
+// With nsplit > 1 the unfolding's columns are cut into nsplit ranges (a
+// multiple of 16 each) and every workgroup writes the whole 64 x 64 partial
+// tile of its range to P, [split][tensor][mode][pair] tiles row-major;
+// gram_reduce_kernel sums them.  grid.x = nsplit * tensors * 3 * tiles
+// (tiles + 1) / 2 with tiles = ceil(nmax / 64).
 __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A, int ntens,
-                                                   int n1, int n2, int n3, int nmax,
-                                                   double2* __restrict__ S) {
+                                                   int n1, int n2, int n3, int nmax, int nsplit,
+                                                   double2* __restrict__ S,
+                                                   double2* __restrict__ P) {
   constexpr int OC = 16;
   __shared__ double2 Xr[64][OC + 1];
   __shared__ double2 Xc[64][OC + 1];
   const int tiles = (nmax + 63) / 64;
   const int pairs = tiles * (tiles + 1) / 2;
   int64_t b = blockIdx.x;
-  int pr = (int)(b % pairs);
+  const int sp = (int)(b % nsplit);
+  b /= nsplit;
+  const int pr = (int)(b % pairs);
+  const int64_t tile_id = b;  // (tensor, mode, pair)
   b /= pairs;
   const int d = (int)(b % 3);
   const int t = (int)(b / 3);
   if (t >= ntens) return;
-  int ti = 0;
-  while (pr >= tiles - ti) {  // pair index -> (ti, tj), ti <= tj
-    pr -= tiles - ti;
-    ++ti;
-  }
-  const int tj = ti + pr;
+  int ti, tj;
+  gram_pair(pr, tiles, ti, tj);
   const int dims[3] = {n1, n2, n3};
   const int n = dims[d];
   if (tj * 64 >= n) return;
   const int64_t nv = (int64_t)n1 * n2 * n3;
-  const int64_t no = nv / n;
+  const int64_t no_all = nv / n;
+  const int64_t chunk = ((no_all + nsplit - 1) / nsplit + OC - 1) / OC * OC;
+  const int64_t obase = (int64_t)sp * chunk;
+  // this workgroup's columns [obase, obase + no) of the unfolding
+  const int64_t no = std::max<int64_t>(0, std::min(no_all, obase + chunk) - obase);
   const double2* At = A + (int64_t)t * nv;
   const int tid = threadIdx.x;
   const int r0 = 4 * (tid / 16), c0 = 4 * (tid % 16);
@@ -96,8 +114,10 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
       coords(tid + 256 * q, i, oc);
       const int64_t o = o0 + oc;
       const int ir = ti * 64 + i, ic = tj * 64 + i;
-      pr_r[q] = (ir < n && o < no) ? At[unfold_index(d, ir, o, n1, n2)] : make_double2(0, 0);
-      pr_c[q] = (ic < n && o < no) ? At[unfold_index(d, ic, o, n1, n2)] : make_double2(0, 0);
+      pr_r[q] = (ir < n && o < no) ? At[unfold_index(d, ir, obase + o, n1, n2)]
+                                   : make_double2(0, 0);
+      pr_c[q] = (ic < n && o < no) ? At[unfold_index(d, ic, obase + o, n1, n2)]
+                                   : make_double2(0, 0);
     }
   };
   gload(0);
@@ -120,6 +140,12 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
     }
     __syncthreads();
   }
+  if (nsplit > 1) {
+    double2* Pt = P + ((int64_t)sp * ntens * 3 * pairs + tile_id) * 4096;
+    for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) Pt[(r0 + u) * 64 + c0 + v] = acc[u][v];
+    return;
+  }
   double2* St = S + ((int64_t)d * ntens + t) * nmax * nmax;
   for (int u = 0; u < 4; ++u)
     for (int v = 0; v < 4; ++v) {
@@ -129,6 +155,39 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
         if (ti != tj) St[(int64_t)j * n + i] = make_double2(acc[u][v].x, -acc[u][v].y);
       }
     }
+}
+
+// Sum of the nsplit partial tiles of gram_kernel, in split order, into S.
+// One thread per tile element; grid.x = tensors * 3 * pairs * 16.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double2* __restrict__ P,
+                                                          int ntens, int n1, int n2, int n3,
+                                                          int nmax, int nsplit,
+                                                          double2* __restrict__ S) {
+  const int tiles = (nmax + 63) / 64;
+  const int pairs = tiles * (tiles + 1) / 2;
+  const int64_t tile_id = blockIdx.x / 16;
+  const int e = (int)(blockIdx.x % 16) * 256 + threadIdx.x;
+  const int pr = (int)(tile_id % pairs);
+  const int d = (int)((tile_id / pairs) % 3);
+  const int t = (int)(tile_id / pairs / 3);
+  if (t >= ntens) return;
+  int ti, tj;
+  gram_pair(pr, tiles, ti, tj);
+  const int dims[3] = {n1, n2, n3};
+  const int n = dims[d];
+  const int i = ti * 64 + e / 64, j = tj * 64 + e % 64;
+  if (tj * 64 >= n || i >= n || j >= n) return;
+  const int64_t per_split = (int64_t)ntens * 3 * pairs * 4096;
+  const double2* Pe = P + tile_id * 4096 + e;
+  double2 s = make_double2(0.0, 0.0);
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double2 v = Pe[sp * per_split];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  double2* St = S + ((int64_t)d * ntens + t) * nmax * nmax;
+  St[(int64_t)i * n + j] = s;
+  if (ti != tj) St[(int64_t)j * n + i] = make_double2(s.x, -s.y);
 }
 
 // Cyclic Jacobi for a Hermitian n x n matrix (n <= 64) in LDS.  Rounds use
@@ -373,13 +432,34 @@ static tv_status last(const char* what) {
   return e == hipSuccess ? TV_OK : hip_error(e, what);
 }
 
-tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
-                      hipStream_t st) {
+// Column ranges of the Gram products: calls with few tensors (a handful of
+// workgroups) cut the unfolding's columns so that about 1024 workgroups run.
+int gram_splits(int ntens, int nmax) {
   const int tiles = (nmax + 63) / 64;
-  const int64_t blocks = (int64_t)ntens * 3 * (tiles * (tiles + 1) / 2);
-  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, ntens, n1, n2,
-                     n3, nmax, S);
-  return last("gram_kernel");
+  const int64_t base = (int64_t)ntens * 3 * (tiles * (tiles + 1) / 2);
+  if (base >= 512) return 1;
+  return (int)std::min<int64_t>(64, (1024 + base - 1) / base);
+}
+
+size_t gram_partial_count(int ntens, int nmax) {
+  const int s = gram_splits(ntens, nmax);
+  const int tiles = (nmax + 63) / 64;
+  return s > 1 ? (size_t)s * ntens * 3 * (tiles * (tiles + 1) / 2) * 4096 : 0;
+}
+
+tv_status launch_gram(const double2* A, int ntens, int n1, int n2, int n3, int nmax, double2* S,
+                      double2* P, hipStream_t st) {
+  const int tiles = (nmax + 63) / 64;
+  const int64_t base = (int64_t)ntens * 3 * (tiles * (tiles + 1) / 2);
+  const int ns = gram_splits(ntens, nmax);
+  if (ns > 1 && !P) return set_error(TV_ERR_INVALID_ARG, "gram: partial buffer missing");
+  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)(base * ns)), dim3(256), 0, st, A, ntens, n1,
+                     n2, n3, nmax, ns, S, P);
+  tv_status s = last("gram_kernel");
+  if (s != TV_OK || ns == 1) return s;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)(base * 16)), dim3(256), 0, st, P, ntens,
+                     n1, n2, n3, nmax, ns, S);
+  return last("gram_reduce_kernel");
 }
 
 // Groups of Hermitian matrices (n <= 64 each) diagonalized in one launch,

@@ -143,6 +143,13 @@ struct tv_plan_s {
   int max_r12 = 0;       // largest r1 r2
   int64_t max_core = 0;  // largest r1 r2 r3
   int64_t sum_r1 = 0;
+  // growable plans (grow_plan_create): column capacity, rank caps, BF16X3
+  // chunks per component and the host staging of one append
+  int64_t grow_mcap = 0;
+  int grow_rcap[3] = {0, 0, 0};
+  std::vector<int64_t> grow_chunks_k;
+  tv::HostPack grow_stage;
+  std::vector<int32_t> grow_split;
 };
 
 namespace tv {
@@ -185,13 +192,25 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
                              hipStream_t st);
 tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,
                              hipStream_t st);
-// plan creation without the decompress-then-GEMM operands (plans rebuilt
-// inside Algorithm 3), and an upper bound of the device arena of a plan of
-// grid g whose ranks are at most rmax (that packing)
+// plan creation without the decompress-then-GEMM operands, and an upper
+// bound of the device arena of a plan of grid g whose ranks are at most rmax
+// (that packing; also the arena of a growable plan of g.m columns)
 tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const double* cores,
                                const double* u1, const double* u2, const double* u3,
                                tv_precision precision, bool with_dtg, tv_plan* out);
 size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision);
+// Growable plan (Algorithm 3's U, which gains one column per step): created
+// empty with its device arrays at fixed offsets of `arena`, each sized for
+// g.m columns at ranks up to rmax; every append converts and uploads only
+// the new column's factors (ranks [q][3], factors of its q tensors in tensor
+// order, FP64 interleaved, laid out as tv_plan_from_factors takes them) and
+// rewrites the small metadata and split tables, then waits for the copies.
+// The plan keeps no FP64 factors (no export).
+tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision precision,
+                           void* arena, size_t bytes, hipStream_t st, tv_plan* out);
+tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
+                           const double* u1, const double* u2, const double* u3,
+                           hipStream_t st);
 // compression scratch of one append call of T tensors (tv_compress.cpp)
 size_t compress_scratch_bytes(const tv_plan_s* p, int T);
 // the autotuners' JSON cache: key -> list of integers (tv_autotune.cpp)
