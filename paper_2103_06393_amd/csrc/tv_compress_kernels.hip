@@ -192,13 +192,23 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double2* __restr
 
 // Cyclic Jacobi for a Hermitian n x n matrix (n <= 64) in LDS.  Rounds use
 // the round-robin pairing, so the n/2 rotations of a round touch disjoint
-// rows/columns and are applied together: first A <- A J, V <- V J on
-// columns, then A <- J^* A on rows.  For a pair (i, j) with A_ij = d e^{i phi}
-// the rotation is J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] where (c, s)
-// diagonalise the real matrix [[A_ii, d], [d, A_jj]] (Golub and Van Loan's
-// symmetric 2x2 Schur step).  Output: eigenvalues W (unsorted) and
-// eigenvectors as the columns of V, both per matrix.
-__global__ __launch_bounds__(256) void jacobi_kernel(JacobiBatch B) {
+// rows/columns and are applied together as A <- J^* A J, V <- V J, where J
+// is block diagonal over the round's pairs.  Entry (a, b) of A J depends only
+// on row a and the pair holding column b, and J^* then mixes only the two
+// rows of a pair, so each 2 x 2 block (row pair p, column pair q) of the new
+// A is J_p^* A_pq J_q: one pass over the blocks per round.  For a pair (i, j)
+// with A_ij = d e^{i phi} the rotation is J = [[c, s], [-s e^{-i phi},
+// c e^{-i phi}]] where (c, s) diagonalise the real matrix [[A_ii, d],
+// [d, A_jj]] (Golub and Van Loan's symmetric 2x2 Schur step).  Output:
+// eigenvalues W (unsorted) and eigenvectors as the columns of V, per matrix.
+constexpr int JT = 1024;  // threads of the Jacobi workgroup
+
+__device__ __forceinline__ double2 jrot(double a, double2 x, double2 m, double2 y) {
+  // a x + m y (a real, m complex)
+  return make_double2(a * x.x + m.x * y.x - m.y * y.y, a * x.y + m.x * y.y + m.y * y.x);
+}
+
+__global__ __launch_bounds__(JT) void jacobi_kernel(JacobiBatch B) {
   extern __shared__ double2 jsm[];
   // workgroup -> (group, matrix)
   int64_t mat = blockIdx.x;
@@ -215,47 +225,51 @@ __global__ __launch_bounds__(256) void jacobi_kernel(JacobiBatch B) {
   double2* __restrict__ Vout = G.V;
   const int max_sweeps = B.max_sweeps;
   const int np = n + (n & 1);
+  const int half = np / 2;
   double2* A = jsm;              // n x n, row-major
   double2* V = A + n * n;        // n x n
-  double* rc = reinterpret_cast<double*>(V + n * n);  // [np/2] c
-  double* rs = rc + np / 2;                           // s
-  double* rpr = rs + np / 2;                          // cos phi
-  double* rpi = rpr + np / 2;                         // sin phi
-  int* pi = reinterpret_cast<int*>(rpi + np / 2);
-  int* pj = pi + np / 2;
-  double* red = reinterpret_cast<double*>(pj + np / 2 + 2);  // [2][256]
-  const int tid = threadIdx.x;
+  double* rc = reinterpret_cast<double*>(V + n * n);  // [half] c
+  double* rs = rc + 32;                               // s
+  double* rpr = rs + 32;                              // cos phi
+  double* rpi = rpr + 32;                             // sin phi
+  int* pi = reinterpret_cast<int*>(rpi + 32);
+  int* pj = pi + 32;
+  double* red = reinterpret_cast<double*>(pj + 32);  // [2][JT / 64]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double2* Sm = S + mat * stride;
-  for (int e = tid; e < n * n; e += 256) {
+  for (int e = tid; e < n * n; e += JT) {
     A[e] = Sm[e];
     V[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  const int half = np / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = tid; e < n * n; e += 256) {
+    for (int e = tid; e < n * n; e += JT) {
       const double2 v = A[e];
       const double a2 = v.x * v.x + v.y * v.y;
       if (e / n == e % n) dia += a2;
       else off += a2;
     }
-    red[tid] = off;
-    red[256 + tid] = dia;
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_down(off, o);
+      dia += __shfl_down(dia, o);
+    }
+    if (lane == 0) {
+      red[wv] = off;
+      red[JT / 64 + wv] = dia;
+    }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) {
-        red[tid] += red[tid + s];
-        red[256 + tid] += red[256 + tid + s];
-      }
-      __syncthreads();
+    double offs = 0.0, dias = 0.0;
+    for (int w = 0; w < JT / 64; ++w) {
+      offs += red[w];
+      dias += red[JT / 64 + w];
     }
     // rotations below 1e-15 of the matrix norm only churn rounding noise
     // (Gram matrices of low multilinear rank have many near-zero diagonal
     // entries, where a threshold relative to sqrt(a_ii a_jj) never settles);
     // the sweeps end once every off-diagonal entry is below that
-    const double skip2 = 1e-30 * (red[0] + red[256]);
-    const bool done = !(red[0] > (double)n * n * skip2);
+    const double skip2 = 1e-30 * (offs + dias);
+    const bool done = !(offs > (double)n * n * skip2);
     __syncthreads();
     if (done) break;
     for (int round = 0; round < np - 1; ++round) {
@@ -295,54 +309,54 @@ __global__ __launch_bounds__(256) void jacobi_kernel(JacobiBatch B) {
         pj[tid] = j < n ? j : -1;
       }
       __syncthreads();
-      // columns: A <- A J and V <- V J
-      for (int e = tid; e < half * n; e += 256) {
-        const int p = e / n, r = e % n;
-        const int i = pi[p], j = pj[p];
-        if (j < 0) continue;
-        const double c = rc[p], s = rs[p];
-        // -s e^{-i phi} and c e^{-i phi}
-        const double2 m1 = make_double2(-s * rpr[p], s * rpi[p]);
-        const double2 m2 = make_double2(c * rpr[p], -c * rpi[p]);
-        double2 x = A[r * n + i], y = A[r * n + j];
-        A[r * n + i] = make_double2(c * x.x + m1.x * y.x - m1.y * y.y,
-                                    c * x.y + m1.x * y.y + m1.y * y.x);
-        A[r * n + j] = make_double2(s * x.x + m2.x * y.x - m2.y * y.y,
-                                    s * x.y + m2.x * y.y + m2.y * y.x);
-        x = V[r * n + i];
-        y = V[r * n + j];
-        V[r * n + i] = make_double2(c * x.x + m1.x * y.x - m1.y * y.y,
-                                    c * x.y + m1.x * y.y + m1.y * y.x);
-        V[r * n + j] = make_double2(s * x.x + m2.x * y.x - m2.y * y.y,
-                                    s * x.y + m2.x * y.y + m2.y * y.x);
+      // 2 x 2 blocks: A_pq <- J_p^* A_pq J_q; a pair with no partner (odd n)
+      // holds one index and no rotation
+      for (int e = tid; e < half * half; e += JT) {
+        const int p = e / half, q = e % half;
+        const int ip = pi[p], jp = pj[p], iq = pi[q], jq = pj[q];
+        const double cq = rc[q], sq = rs[q], cpq = rpr[q], spq = rpi[q];
+        // columns: (x, y) -> (c x - s e^{-i phi} y, s x + c e^{-i phi} y)
+        const double2 m1 = make_double2(-sq * cpq, sq * spq);
+        const double2 m2 = make_double2(cq * cpq, -cq * spq);
+        const double2 z = make_double2(0.0, 0.0);
+        double2 x0 = A[ip * n + iq], y0 = jq >= 0 ? A[ip * n + jq] : z;
+        double2 x1 = jp >= 0 ? A[jp * n + iq] : z;
+        double2 y1 = (jp >= 0 && jq >= 0) ? A[jp * n + jq] : z;
+        const double2 X0 = jrot(cq, x0, m1, y0), Y0 = jrot(sq, x0, m2, y0);
+        const double2 X1 = jrot(cq, x1, m1, y1), Y1 = jrot(sq, x1, m2, y1);
+        // rows: (x, y) -> (c x - s e^{i phi} y, s x + c e^{i phi} y)
+        const double cpp = rc[p], spp = rs[p], cpr = rpr[p], cpi = rpi[p];
+        const double2 n1 = make_double2(-spp * cpr, -spp * cpi);
+        const double2 n2 = make_double2(cpp * cpr, cpp * cpi);
+        A[ip * n + iq] = jrot(cpp, X0, n1, X1);
+        if (jq >= 0) A[ip * n + jq] = jrot(cpp, Y0, n1, Y1);
+        if (jp >= 0) {
+          A[jp * n + iq] = jrot(spp, X0, n2, X1);
+          if (jq >= 0) A[jp * n + jq] = jrot(spp, Y0, n2, Y1);
+        }
       }
-      __syncthreads();
-      // rows: A <- J^* A, J^* = [[c, -s e^{i phi}], [s, c e^{i phi}]]
-      for (int e = tid; e < half * n; e += 256) {
-        const int p = e / n, r = e % n;
-        const int i = pi[p], j = pj[p];
+      // V <- V J
+      for (int e = tid; e < half * n; e += JT) {
+        const int q = e / n, r = e % n;
+        const int i = pi[q], j = pj[q];
         if (j < 0) continue;
-        const double c = rc[p], s = rs[p];
-        const double2 m1 = make_double2(-s * rpr[p], -s * rpi[p]);
-        const double2 m2 = make_double2(c * rpr[p], c * rpi[p]);
-        const double2 x = A[i * n + r], y = A[j * n + r];
-        A[i * n + r] = make_double2(c * x.x + m1.x * y.x - m1.y * y.y,
-                                    c * x.y + m1.x * y.y + m1.y * y.x);
-        A[j * n + r] = make_double2(s * x.x + m2.x * y.x - m2.y * y.y,
-                                    s * x.y + m2.x * y.y + m2.y * y.x);
+        const double c = rc[q], s = rs[q];
+        const double2 m1 = make_double2(-s * rpr[q], s * rpi[q]);
+        const double2 m2 = make_double2(c * rpr[q], -c * rpi[q]);
+        const double2 x = V[r * n + i], y = V[r * n + j];
+        V[r * n + i] = jrot(c, x, m1, y);
+        V[r * n + j] = jrot(s, x, m2, y);
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < n; i += 256) W[mat * wstride + i] = A[i * n + i].x;
+  for (int i = tid; i < n; i += JT) W[mat * wstride + i] = A[i * n + i].x;
   double2* Vm = Vout + mat * vstride;
-  for (int e = tid; e < n * n; e += 256) Vm[e] = V[e];
+  for (int e = tid; e < n * n; e += JT) Vm[e] = V[e];
 }
 
 size_t jacobi_lds_bytes(int n) {
-  const int np = n + (n & 1);
-  return 16 * (size_t)2 * n * n + 8 * (size_t)4 * (np / 2) + 4 * (size_t)(np + 2) +
-         8 * 512 + 16;
+  return 16 * (size_t)2 * n * n + 8 * 4 * 32 + 4 * 2 * 32 + 8 * 2 * (JT / 64);
 }
 
 // T1[t][a][o] = sum_i1 conj(U1[i1, a]) A[i1 + n1 o]; workgroup = 32 values of
@@ -485,7 +499,7 @@ tv_status launch_jacobi_batch(const JacobiGroup* groups, int ng, hipStream_t st)
   hipError_t e = hipFuncSetAttribute((const void*)jacobi_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute(jacobi)");
-  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)blocks), dim3(256), lds, st, B);
+  hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)blocks), dim3(JT), lds, st, B);
   return last("jacobi_kernel");
 }
 
@@ -599,7 +613,7 @@ __global__ __launch_bounds__(256) void cgs2_kernel(Cgs2Batch B) {
   extern __shared__ double2 zs[];
   __shared__ double2 c[64];
   __shared__ double2 cpart[4][64];
-  __shared__ double red[256];
+  __shared__ double red[2][4];
   int64_t mat = blockIdx.x;
   int gi = 0;
   while (gi + 1 < B.ng && mat >= B.g[gi].nmat) {
@@ -610,25 +624,33 @@ __global__ __launch_bounds__(256) void cgs2_kernel(Cgs2Batch B) {
   double2* Zg = B.g[gi].Z + mat * B.g[gi].stride;
   const int ls = INLDS ? l + 1 : l;
   double2* Zb = INLDS ? zs : Zg;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (INLDS) {
     for (int e = tid; e < n * l; e += 256) zs[(e / l) * ls + e % l] = Zg[e];
     __syncthreads();
   }
+  // workgroup sum of one value per thread (every thread calls it); the two
+  // slots alternate, so one barrier per sum suffices
+  int slot = 0;
+  auto block_sum = [&](double v) -> double {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[slot][wv] = v;
+    __syncthreads();
+    const double s = (red[slot][0] + red[slot][1]) + (red[slot][2] + red[slot][3]);
+    slot ^= 1;
+    return s;
+  };
+  // Each thread owns rows i = tid, tid + 256, ... of the column being
+  // orthogonalized: it updates, measures and scales only those, so the
+  // barriers order just the cross-row reads (the projections' dot products).
   for (int j = 0; j < l; ++j) {
     double s = 0.0;
     for (int i = tid; i < n; i += 256) {
       const double2 v = Zb[(int64_t)i * ls + j];
       s += v.x * v.x + v.y * v.y;
     }
-    red[tid] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double nrm0 = sqrt(red[0]);
-    __syncthreads();
+    const double nrm0 = sqrt(block_sum(s));
+    s = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       // c[k] = sum_i conj(Q[i,k]) z[i] for k < j: thread (part, kk) sums the
       // rows i = part mod 4, then the four parts are added in order
@@ -656,31 +678,21 @@ __global__ __launch_bounds__(256) void cgs2_kernel(Cgs2Batch B) {
           z.y -= q.x * ck.y + q.y * ck.x;
         }
         Zb[(int64_t)i * ls + j] = z;
+        if (pass == 1) s += z.x * z.x + z.y * z.y;
       }
-      __syncthreads();
+      if (pass == 0) __syncthreads();
     }
-    s = 0.0;
+    const double nrm = sqrt(block_sum(s));
+    const double scale = (nrm > 1e-13 * nrm0 && nrm > 1e-300) ? 1.0 / nrm : 0.0;
     for (int i = tid; i < n; i += 256) {
       const double2 v = Zb[(int64_t)i * ls + j];
-      s += v.x * v.x + v.y * v.y;
-    }
-    red[tid] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double nrm = sqrt(red[0]);
-    const double scale = (nrm > 1e-13 * nrm0 && nrm > 1e-300) ? 1.0 / nrm : 0.0;
-    __syncthreads();
-    for (int i = tid; i < n; i += 256) {
-      double2 v = Zb[(int64_t)i * ls + j];
       Zb[(int64_t)i * ls + j] = make_double2(v.x * scale, v.y * scale);
     }
-    __syncthreads();
   }
-  if (INLDS)
+  if (INLDS) {
+    __syncthreads();
     for (int e = tid; e < n * l; e += 256) Zg[e] = zs[(e / l) * ls + e % l];
+  }
 }
 
 // Deterministic start block Omega (n x l, row-major, complex entries in
