@@ -42,16 +42,16 @@ MEASURED_TRAFFIC = {
         "launch": {"kernel": 1},
     },
     ("c5", "fp32", "adjoint"): {
-        "bytes": 143918913172,
+        "bytes": 122285289237,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "9049465408b4a2b7e9fb9b75addaea219f3d5346e76b6936ecc4460ad5428e1b",
+        "sha256": "52924da87ba613c11cc11b0963271ad35e20849fd76aeaa33e6e9805d9fb4b58",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 16},
     },
     ("c5", "fp32", "forward"): {
-        "bytes": 58639544760,
+        "bytes": 58642937237,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "9049465408b4a2b7e9fb9b75addaea219f3d5346e76b6936ecc4460ad5428e1b",
+        "sha256": "52924da87ba613c11cc11b0963271ad35e20849fd76aeaa33e6e9805d9fb4b58",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 1},
     },

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "tv_internal.h"
@@ -302,9 +303,7 @@ AcaSizes aca_sizes(const tv_grid& g, int K, double htol, int rank_min, int rank_
   B.alloc(&d1, (size_t)6 * m);
   B.alloc(&d1, 1024);
   B.alloc(&i1, 1024);
-  B.alloc(&d1, 4);
-  B.alloc(&i1, 2);
-  B.alloc(&i1, 1);
+  B.alloc(&d1, 8);
   B.alloc(&z2, m);
   B.alloc(&z2, (size_t)m * K);
   B.alloc(&z2, K);
@@ -346,13 +345,13 @@ struct HostFactors {
 // to the host copies.
 tv_status compress_column(const tv_grid& grid, const double2* d_x, double tol, int rank_min,
                           int rank_cap, tv_precision prec, HostFactors& F, void* cws,
-                          size_t cws_bytes, void* stream) {
+                          size_t cws_bytes, void* stream, const HostStage& stage) {
   tv_grid g1 = grid;
   g1.m = 1;
   tv_plan cp = nullptr;
   tv_status s = tv_compress_begin(&g1, tol, rank_min, rank_cap, prec, &cp);
   if (s != TV_OK) return s;
-  s = tv_compress_append(cp, d_x, 1, cws, cws_bytes, stream);
+  s = compress_append_staged(cp, d_x, 1, cws, cws_bytes, (hipStream_t)stream, stage);
   std::vector<int32_t> rk((size_t)3 * grid.q);
   if (s == TV_OK) s = tv_plan_export_factors(cp, rk.data(), nullptr, nullptr, nullptr, nullptr);
   if (s == TV_OK) {
@@ -376,6 +375,42 @@ tv_status compress_column(const tv_grid& grid, const double2* d_x, double tol, i
 }
 
 }  // namespace
+}  // namespace tv
+
+namespace tv {
+
+struct CopySegs {
+  CopySeg s[kMaxCopySegs];
+};
+
+// blockIdx.y = segment; the workgroups of x stride over its 4-byte words
+__global__ __launch_bounds__(256) void segment_copy_kernel(CopySegs S, const uint32_t* src) {
+  const CopySeg g = S.s[blockIdx.y];
+  uint32_t* dst = reinterpret_cast<uint32_t*>(g.dst);
+  const uint32_t* from = src + g.src_off / 4;
+  const int64_t n = g.bytes / 4;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    dst[e] = from[e];
+}
+
+tv_status launch_segment_copy(const CopySeg* segs, int nseg, const void* src, hipStream_t st) {
+  if (nseg < 1) return TV_OK;
+  if (nseg > kMaxCopySegs) return set_error(TV_ERR_INVALID_ARG, "segment copy: too many segments");
+  CopySegs S{};
+  int64_t most = 0;
+  for (int i = 0; i < nseg; ++i) {
+    if (((uintptr_t)segs[i].dst | (uint64_t)segs[i].src_off | (uint64_t)segs[i].bytes) % 4)
+      return set_error(TV_ERR_INVALID_ARG, "segment copy: ranges must be 4-byte aligned");
+    S.s[i] = segs[i];
+    most = std::max(most, segs[i].bytes / 4);
+  }
+  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (most + 255) / 256));
+  hipLaunchKernelGGL(segment_copy_kernel, dim3(bx, (unsigned)nseg), dim3(256), 0, st, S,
+                     (const uint32_t*)src);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TV_OK : hip_error(e, "segment_copy_kernel");
+}
+
 }  // namespace tv
 
 using namespace tv;
@@ -446,17 +481,68 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   double2 *d_r, *d_V, *d_t, *d_b, *d_x;
   float2 *d_w32, *d_x32, *d_u32, *d_a32;
   if ((s = B.alloc(&d_src, src.size())) != TV_OK || (s = B.alloc(&d_bv, 1024)) != TV_OK ||
-      (s = B.alloc(&d_bi, 1024)) != TV_OK || (s = B.alloc(&d_scal, 4)) != TV_OK ||
-      (s = B.alloc(&d_iscal, 2)) != TV_OK || (s = B.alloc(&d_row, 1)) != TV_OK ||
+      (s = B.alloc(&d_bi, 1024)) != TV_OK || (s = B.alloc(&d_scal, 8)) != TV_OK ||
       (s = B.alloc(&d_r, m)) != TV_OK || (s = B.alloc(&d_V, (size_t)m * K)) != TV_OK ||
       (s = B.alloc(&d_t, K)) != TV_OK || (s = B.alloc(&d_b, K)) != TV_OK ||
       (s = B.alloc(&d_x, rows)) != TV_OK ||
       (s = B.alloc(&d_w32, K)) != TV_OK || (s = B.alloc(&d_x32, rows)) != TV_OK ||
       (s = B.alloc(&d_u32, rows)) != TV_OK || (s = B.alloc(&d_a32, K)) != TV_OK)
     return s;
+  // pinned host staging of the loop's transfers: the scalars below, one
+  // column's compression and U's growth (without it, host vectors serve)
+  struct Pinned {
+    char* p = nullptr;
+    hipStream_t st = nullptr;
+    ~Pinned() {
+      if (!p) return;
+      (void)hipStreamSynchronize(st);  // no copy may still read or write it
+      (void)hipHostFree(p);
+    }
+  } pin;
+  pin.st = st;
+  HostStage cstage, gstage;
+  double hs_vec[5];
+  double* hs = hs_vec;
+  {
+    tv_grid g1 = g;
+    g1.m = 1;
+    tv_plan cp = nullptr;
+    size_t cbytes = 0, gbytes = 0;
+    if (tv_compress_begin(&g1, htol, rank_min, rank_cap, precision, &cp) == TV_OK) {
+      cbytes = compress_stage_bytes(cp, g.q);
+      tv_plan_destroy(cp);
+    }
+    int rmax[3];
+    rank_bounds(g, rank_cap, rmax);
+    tv_grid gk = g;
+    gk.m = K;
+    gbytes = (grow_stage_bytes(gk, rmax, precision) + 255) & ~(size_t)255;
+    if (cbytes && gbytes &&
+        hipHostMalloc((void**)&pin.p, 256 + gbytes + cbytes, hipHostMallocDefault) == hipSuccess) {
+      hs = reinterpret_cast<double*>(pin.p);
+      gstage = HostStage{pin.p + 256, gbytes};
+      cstage = HostStage{pin.p + 256 + gbytes, cbytes};
+    } else {
+      pin.p = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  // scalar results in one small region read back with one copy: [0] argmax
+  // value, [1], [2] sums of squares, [3] cross term, [4] argmax index (int64),
+  // which is also the next pivot row that rows_kernel reads
+  d_iscal = reinterpret_cast<int64_t*>(d_scal + 4);
+  d_row = d_iscal;
+  const int64_t row0 = 0;
   hipError_t e =
       hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_row, &row0, sizeof(int64_t), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_error(e, "source upload");
+  auto readback = [&](int count, const char* what) -> tv_status {
+    hipError_t he = hipMemcpyAsync(hs, d_scal, count * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    return he == hipSuccess ? TV_OK : hip_error(he, what);
+  };
 
   // scalar results back to the host: (value, index) of an argmax, or a sum
   auto argmax = [&](const double2* x, int64_t n, int64_t skip, unsigned nb, double* v,
@@ -465,20 +551,17 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     hipLaunchKernelGGL(amax2_kernel, dim3(1), dim3(kT), 0, st, d_bv, d_bi, (int)nb, d_scal,
                        d_iscal);
     tv_status r = last("argmax kernels");
+    if (r == TV_OK) r = readback(5, "argmax readback");
     if (r != TV_OK) return r;
-    hipError_t he = hipMemcpyAsync(v, d_scal, sizeof(double), hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipMemcpyAsync(i, d_iscal, sizeof(int64_t), hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    return he == hipSuccess ? TV_OK : hip_error(he, "argmax readback");
+    *v = hs[0];
+    std::memcpy(i, &hs[4], sizeof(int64_t));
+    return TV_OK;
   };
-  auto sumsq = [&](const double2* x, int64_t n, unsigned nb, double* out) -> tv_status {
+  // sum of squares of x into d_scal[slot] (read back by the caller)
+  auto sumsq = [&](const double2* x, int64_t n, unsigned nb, int slot) -> tv_status {
     hipLaunchKernelGGL(sumsq1_kernel, dim3(nb), dim3(kT), 0, st, x, n, d_bv);
-    hipLaunchKernelGGL(sumsq2_kernel, dim3(1), dim3(kT), 0, st, d_bv, (int)nb, d_scal + 1);
-    tv_status r = last("norm kernels");
-    if (r != TV_OK) return r;
-    hipError_t he = hipMemcpyAsync(out, d_scal + 1, sizeof(double), hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    return he == hipSuccess ? TV_OK : hip_error(he, "norm readback");
+    hipLaunchKernelGGL(sumsq2_kernel, dim3(1), dim3(kT), 0, st, d_bv, (int)nb, d_scal + slot);
+    return last("norm kernels");
   };
 
   HostFactors F;
@@ -490,6 +573,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     tv_grid gk = g;
     gk.m = K;
     if ((s = grow_plan_create(gk, rmax, precision, uarena, Z.uarena, st, &U)) != TV_OK) return s;
+    grow_plan_set_stage(U, gstage);
   }
   auto fail = [&](tv_status r) {
     tv_plan_destroy(U);
@@ -500,9 +584,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
   int rc = 0;
   bool converged = false;
   for (int k = 0; k < K; ++k) {
-    // r = Z_{i:} - (U V^*)_{i:}
-    e = hipMemcpyAsync(d_row, &i, sizeof(int64_t), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return fail(hip_error(e, "row index upload"));
+    // r = Z_{i:} - (U V^*)_{i:} (row i is in d_row already)
     if ((s = launch_dipole_rows(g.n1, g.n2, g.n3, h, k0, basis, m, d_src, 1, d_row, d_r, st)) !=
         TV_OK)
       return fail(s);
@@ -539,9 +621,10 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
       if ((s = last("sub_kernel")) != TV_OK) return fail(s);
     }
     // s_{k+1} = s_k + (|x||y|)^2 + 2 Re sum conj(V^* y) (U^* x)
-    double nx2 = 0.0, ny2 = 0.0;
-    if ((s = sumsq(d_x, rows, nb_rows, &nx2)) != TV_OK || (s = sumsq(y, m, nb_m, &ny2)) != TV_OK)
+    if ((s = sumsq(d_x, rows, nb_rows, 1)) != TV_OK || (s = sumsq(y, m, nb_m, 2)) != TV_OK ||
+        (s = readback(3, "norm readback")) != TV_OK)
       return fail(s);
+    const double nx2 = hs[1], ny2 = hs[2];
     double s_next = ssum + nx2 * ny2;
     if (k > 0) {
       hipLaunchKernelGGL(to_c64_kernel, dim3(blocks(rows)), dim3(kT), 0, st, d_x, d_x32, rows);
@@ -549,13 +632,10 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
       if ((s = tv_rmatvec(U, d_x32, rows, 1, d_a32, k, pws, Z.prod, stream)) != TV_OK)
         return fail(s);
       hipLaunchKernelGGL(vhy_kernel, dim3((unsigned)k), dim3(kT), 0, st, d_V, m, y, m, d_b);
-      hipLaunchKernelGGL(cross_kernel, dim3(1), dim3(kT), 0, st, d_b, d_a32, k, d_scal + 2);
-      if ((s = last("cross_kernel")) != TV_OK) return fail(s);
-      double cross = 0.0;
-      e = hipMemcpyAsync(&cross, d_scal + 2, sizeof(double), hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return fail(hip_error(e, "cross term readback"));
-      s_next += cross;
+      hipLaunchKernelGGL(cross_kernel, dim3(1), dim3(kT), 0, st, d_b, d_a32, k, d_scal + 3);
+      if ((s = last("cross_kernel")) != TV_OK || (s = readback(4, "cross term readback")) != TV_OK)
+        return fail(s);
+      s_next += hs[3];
     }
     // U = [U HOSVD(x)] and V = [V y] (y is already in place); the products
     // above have been waited for (the cross-term readback), so U's arrays
@@ -563,7 +643,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     const size_t o0 = F.cores.size(), o1 = F.u1.size(), o2 = F.u2.size(), o3 = F.u3.size(),
                  orank = F.ranks.size();
     if ((s = compress_column(g, d_x, htol, rank_min, rank_cap, precision, F, cws, Z.comp,
-                             stream)) != TV_OK)
+                             stream, cstage)) != TV_OK)
       return fail(s);
     if ((s = grow_plan_append(U, &F.ranks[orank], &F.cores[o0], &F.u1[o1], &F.u2[o2], &F.u3[o3],
                               st)) != TV_OK)

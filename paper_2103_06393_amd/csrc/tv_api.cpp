@@ -497,6 +497,19 @@ tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const 
   return TV_OK;
 }
 
+// Staging of one growable-plan append: the metadata of every tensor and one
+// column's q tensors of every other array, each piece 16-byte aligned.
+static size_t stage_size(const tv_grid& g, const int rmax[3], int nbt, tv_precision precision) {
+  const size_t K = (size_t)g.q * g.m;
+  const size_t r1 = rmax[0], r2 = rmax[1], r3 = rmax[2];
+  const bool bf = precision == TV_PREC_BF16X3;
+  return K * sizeof(TensorMeta) +
+         (size_t)g.q * (r1 * r2 * r3 + g.n1 * r1 + g.n2 * r2 + g.n3 * r3) * sizeof(float2) +
+         (bf ? (size_t)g.q * ((r1 + 7) / 8) * nbt * 128 * sizeof(uint4)
+             : (size_t)g.q * r1 * nbt * 64 * sizeof(float)) +
+         (size_t)2 * g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t) + (size_t)(g.q + 8) * 16;
+}
+
 // Device layout of a plan holding up to g.m columns at ranks up to rmax, in
 // the order of arena_layout, every array at its capacity; with p and base
 // set, p's device pointers are carved from base.
@@ -524,7 +537,15 @@ static size_t capacity_layout(const tv_grid& g, const int rmax[3], int nbt,
   carve(&d->d_apack_koff, (size_t)(g.q + 1) * sizeof(int64_t));
   carve(&d->d_split_f, (size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
   carve(&d->d_split_a, (size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
+  const size_t stage = stage_size(g, rmax, nbt, precision);
+  carve(&d->d_stage, stage);
+  if (p && base) p->stage_bytes = stage;
   return (off + 255) & ~(size_t)255;
+}
+
+void grow_plan_set_stage(tv_plan p, const HostStage& stage) {
+  p->grow_pinned = stage.ptr;
+  p->grow_pinned_bytes = stage.bytes;
 }
 
 static int pack_nbt(const tv_grid& g, int nbcap_a) {
@@ -533,6 +554,11 @@ static int pack_nbt(const tv_grid& g, int nbcap_a) {
   Tiling Tf, Ta;
   if (make_tiling(g, 0, 8, &Tf) != TV_OK || make_tiling(g, 0, nbcap_a, &Ta) != TV_OK) return 0;
   return std::max(Tf.nbt, Ta.nbt);
+}
+
+size_t grow_stage_bytes(const tv_grid& g, const int rmax[3], tv_precision precision) {
+  const int nbt = pack_nbt(g, 2);
+  return nbt ? stage_size(g, rmax, nbt, precision) : 0;
 }
 
 size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision) {
@@ -553,6 +579,8 @@ tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision pre
       return set_error(TV_ERR_RANK, "growable plan: rank cap outside [1, min(n, TV_MAX_RANK)]");
   if (!arena || (uintptr_t)arena % 256)
     return set_error(TV_ERR_INVALID_ARG, "arena must be non-NULL and 256-byte aligned");
+  if (g.q + 7 > kMaxCopySegs)
+    return set_error(TV_ERR_NOT_SUPPORTED, "growable plan: too many components");
   tv_plan_s* p = new (std::nothrow) tv_plan_s;
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = g;
@@ -729,33 +757,52 @@ tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
     p->grow_split.assign(a.begin(), a.end());
     p->grow_split.insert(p->grow_split.end(), b.begin(), b.end());
   }
-  // uploads, then wait so that the staging may be reused
-  hipError_t e = hipSuccess;
-  auto put = [&](void* d, const void* src, size_t n) {
-    if (e == hipSuccess && n) e = hipMemcpyAsync(d, src, n, hipMemcpyHostToDevice, st);
+  // the pieces go up in one copy to the arena's staging region and one
+  // kernel scatters them; then wait, so that the host buffer may be reused
+  CopySeg segs[kMaxCopySegs];
+  int nseg = 0;
+  size_t off = 0;
+  const bool pinned = p->grow_pinned && p->grow_pinned_bytes >= p->stage_bytes;
+  if (!pinned && p->grow_buf.size() < p->stage_bytes) p->grow_buf.resize(p->stage_bytes);
+  char* const hbuf = pinned ? p->grow_pinned : p->grow_buf.data();
+  bool overflow = false;
+  auto add = [&](void* dst, const void* src, size_t n) {
+    if (!n) return;
+    off = (off + 15) & ~(size_t)15;
+    if (nseg == kMaxCopySegs || off + n > p->stage_bytes) {
+      overflow = true;
+      return;
+    }
+    std::memcpy(hbuf + off, src, n);
+    segs[nseg++] = CopySeg{dst, (int64_t)off, (int64_t)n};
+    off += n;
   };
-  put(p->d_meta, H.meta.data(), H.meta.size() * sizeof(TensorMeta));
-  put(p->d_cores + p->g_off[t0], H.cores.data(), H.cores.size() * sizeof(float2));
-  put(p->d_u1t + p->u1_off[t0], H.u1t.data(), H.u1t.size() * sizeof(float2));
-  put(p->d_u2t + p->u2_off[t0], H.u2t.data(), H.u2t.size() * sizeof(float2));
-  put(p->d_u3t + p->u3_off[t0], H.u3t.data(), H.u3t.size() * sizeof(float2));
+  add(p->d_meta, H.meta.data(), H.meta.size() * sizeof(TensorMeta));
+  add(p->d_cores + p->g_off[t0], H.cores.data(), H.cores.size() * sizeof(float2));
+  add(p->d_u1t + p->u1_off[t0], H.u1t.data(), H.u1t.size() * sizeof(float2));
+  add(p->d_u2t + p->u2_off[t0], H.u2t.data(), H.u2t.size() * sizeof(float2));
+  add(p->d_u3t + p->u3_off[t0], H.u3t.data(), H.u3t.size() * sizeof(float2));
   arows = 0;
   for (int k = 0; k < g.q; ++k) {
     const int r1 = ranks[3 * k];
     const int64_t nr = bf ? (r1 + 7) / 8 : r1;
     if (!bf)
-      put(p->d_apack + p->apack_koff[k] + arow_new[k] * nbt * 64, &H.apack[arows * nbt * 64],
+      add(p->d_apack + p->apack_koff[k] + arow_new[k] * nbt * 64, &H.apack[arows * nbt * 64],
           (size_t)nr * nbt * 64 * sizeof(float));
     else
-      put(p->d_apack_bf + p->apack_koff[k] + arow_new[k] * nbt * 128,
+      add(p->d_apack_bf + p->apack_koff[k] + arow_new[k] * nbt * 128,
           &H.apack_bf[arows * nbt * 128], (size_t)nr * nbt * 128 * sizeof(uint4));
     arows += nr;
   }
   const size_t nsf = (size_t)g.q * (p->split_f + 1);
-  put(p->d_split_f, p->grow_split.data(), nsf * sizeof(int32_t));
-  put(p->d_split_a, p->grow_split.data() + nsf,
-      (size_t)g.q * (p->split_a + 1) * sizeof(int32_t));
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  add(p->d_split_f, p->grow_split.data(), nsf * sizeof(int32_t));
+  add(p->d_split_a, p->grow_split.data() + nsf, (size_t)g.q * (p->split_a + 1) * sizeof(int32_t));
+  if (overflow) return set_error(TV_ERR_WORKSPACE, "growable plan staging overflow");
+  hipError_t e = hipMemcpyAsync(p->d_stage, hbuf, off, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_error(e, "growable plan upload");
+  tv_status cs = launch_segment_copy(segs, nseg, p->d_stage, st);
+  if (cs != TV_OK) return cs;
+  e = hipStreamSynchronize(st);
   return e == hipSuccess ? TV_OK : hip_error(e, "growable plan upload");
 }
 

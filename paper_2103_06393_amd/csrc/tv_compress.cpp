@@ -58,9 +58,11 @@ struct DevScratch {
 };
 
 // Upper bound of the scratch of one append call of T tensors: Gram
-// matrices (and their partial tiles when the columns are split), eigenpairs (and the subspace solver's work arrays for modes
-// longer than 64), factors at the largest rank a mode can keep, and the
-// partial projections and cores of the core computation.
+// matrices (and their partial tiles when the columns are split), eigenpairs
+// (and the subspace solver's work arrays for modes longer than 64), factors
+// at the largest rank a mode can keep, and the partial projections and cores
+// of the core computation.  The call carves some of these as one region (one
+// copy each way), which never needs more than the separately aligned pieces.
 size_t compress_scratch_bytes(const tv_plan_s* p, int T) {
   const tv_grid& g = p->grid;
   const int dims[3] = {g.n1, g.n2, g.n3};
@@ -176,6 +178,33 @@ tv_status tv_compress_workspace_bytes(tv_plan p, int64_t ncols, size_t* bytes) {
 tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* ws,
                              size_t ws_bytes, void* stream) {
   clear_error();
+  return compress_append_staged(p, cols, ncols, ws, ws_bytes, (hipStream_t)stream, HostStage{});
+}
+
+}  // extern "C"
+
+namespace tv {
+
+size_t compress_stage_bytes(const tv_plan_s* p, int T) {
+  const tv_grid& g = p->grid;
+  const int dims[3] = {g.n1, g.n2, g.n3};
+  size_t n2 = 0;  // double2 units: eigenpair readback, factor upload, cores
+  int rmax[3];
+  for (int d = 0; d < 3; ++d) {
+    const int n = dims[d], L = n <= 64 ? n : 64;
+    n2 += (size_t)T * n * L + ((size_t)T * L + 1) / 2 + (n > 64 ? ((size_t)T + 1) / 2 : 0);
+    int r = std::min(n, std::min(64, TV_MAX_RANK));
+    if (p->rank_cap > 0) r = std::min(r, (int)p->rank_cap);
+    rmax[d] = std::max(r, 1);
+    n2 += (size_t)T * n * rmax[d];
+  }
+  n2 += (4 * (size_t)T + 1) / 2 + (3 * (size_t)T + 3) / 4;
+  n2 += (size_t)T * rmax[0] * rmax[1] * rmax[2];
+  return n2 * sizeof(double2) + 3 * 256;
+}
+
+tv_status compress_append_staged(tv_plan p, const void* cols, int64_t ncols, void* ws,
+                                 size_t ws_bytes, hipStream_t st, const HostStage& stage) {
   if (!p) return set_error(TV_ERR_INVALID_ARG, "plan is NULL");
   if (p->finalized) return set_error(TV_ERR_INVALID_ARG, "plan is already finalized");
   if (ncols < 0 || p->appended + ncols > p->grid.m)
@@ -189,8 +218,21 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   const int nmax = std::max(g.n1, std::max(g.n2, g.n3));
   const int64_t nv = (int64_t)g.n1 * g.n2 * g.n3;
   const int T = (int)(ncols * g.q);
-  hipStream_t st = (hipStream_t)stream;
   const double2* A = (const double2*)cols;
+  // host side of the transfers: the caller's (pinned) staging when it covers
+  // this call, else host vectors; carved in call order
+  const bool staged = stage.ptr && stage.bytes >= compress_stage_bytes(p, T);
+  size_t stage_off = 0;
+  std::vector<double2> hv[3];
+  auto host_buf = [&](int slot, size_t n) -> double2* {
+    if (!staged) {
+      hv[slot].resize(n);
+      return hv[slot].data();
+    }
+    double2* q = reinterpret_cast<double2*>(stage.ptr + stage_off);
+    stage_off = (stage_off + n * sizeof(double2) + 255) & ~(size_t)255;
+    return q;
+  };
   const size_t need = compress_scratch_bytes(p, T);
   if (!ws || ws_bytes < need) {
     char buf[128];
@@ -213,13 +255,26 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   if ((s = ds.alloc(&dS, (size_t)3 * T * mat)) != TV_OK) return s;
   if ((s = ds.alloc(&dP, gram_partial_count(T, nmax))) != TV_OK) return s;
   if ((s = launch_gram(A, T, g.n1, g.n2, g.n3, nmax, dS, dP, st)) != TV_OK) return s;
-  std::vector<std::vector<double>> W(3), TR(3);
-  std::vector<std::vector<double2>> V(3);
   int L[3];
   // the three modes' eigenproblems: subspace preparation for the long modes,
   // then one Jacobi launch over every mode's matrices (n x n directly for
   // modes <= 64, the 64 x 64 Rayleigh-Ritz matrices otherwise), the long
-  // modes' vectors, and one readback
+  // modes' vectors, and one readback: the eigenvectors, eigenvalues and the
+  // long modes' Gram traces of all modes sit in one region (double2 units)
+  size_t rb_off[3][3];
+  size_t rb_n = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int n = dims[d];
+    L[d] = n <= 64 ? n : 64;
+    rb_off[d][0] = rb_n;
+    rb_n += (size_t)T * n * L[d];
+    rb_off[d][1] = rb_n;
+    rb_n += ((size_t)T * L[d] + 1) / 2;
+    rb_off[d][2] = rb_n;
+    rb_n += n > 64 ? ((size_t)T + 1) / 2 : 0;
+  }
+  double2* dRB;
+  if ((s = ds.alloc(&dRB, rb_n)) != TV_OK) return s;
   double2* dV[3];
   double* dW[3];
   double* dTr[3] = {nullptr, nullptr, nullptr};
@@ -229,15 +284,14 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   int nj = 0;
   for (int d = 0; d < 3; ++d) {
     const int n = dims[d];
-    L[d] = n <= 64 ? n : 64;
-    if ((s = ds.alloc(&dV[d], (size_t)T * n * L[d])) != TV_OK) return s;
-    if ((s = ds.alloc(&dW[d], (size_t)T * L[d])) != TV_OK) return s;
+    dV[d] = dRB + rb_off[d][0];
+    dW[d] = reinterpret_cast<double*>(dRB + rb_off[d][1]);
     const double2* Sd = dS + (int64_t)d * T * mat;
     if (n <= 64) {
       // eigenvectors are written compactly, n x n per matrix
       groups[d] = JacobiGroup{Sd, dW[d], dV[d], mat, n, (int64_t)n * n, n, T};
     } else {
-      if ((s = ds.alloc(&dTr[d], (size_t)T)) != TV_OK) return s;
+      dTr[d] = reinterpret_cast<double*>(dRB + rb_off[d][2]);
       if ((s = ds.alloc(&dWs[d], (size_t)T * (3 * (size_t)n * 64 + 64 * 64))) != TV_OK) return s;
       jobs[nj++] = SubspaceJob{Sd, mat, dTr[d], dWs[d], n};
       groups[d] = JacobiGroup{subspace_T(dWs[d], T, n), dW[d], subspace_V(dWs[d], T, n),
@@ -251,26 +305,20 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
         (s = launch_subspace_finish(T, dims[d], dWs[d], subspace_V(dWs[d], T, dims[d]), dV[d],
                                     st)) != TV_OK)
       return s;
+  const double2* RB = host_buf(0, rb_n);
   {
-    hipError_t e = hipSuccess;
-    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
-      const int n = dims[d];
-      W[d].resize((size_t)T * L[d]);
-      V[d].resize((size_t)T * n * L[d]);
-      e = hipMemcpyAsync(W[d].data(), dW[d], W[d].size() * sizeof(double),
-                         hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(V[d].data(), dV[d], V[d].size() * sizeof(double2),
-                           hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess && dTr[d]) {
-        TR[d].resize(T);
-        e = hipMemcpyAsync(TR[d].data(), dTr[d], T * sizeof(double), hipMemcpyDeviceToHost, st);
-      }
-    }
+    hipError_t e = hipMemcpyAsync((void*)RB, dRB, rb_n * sizeof(double2), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_error(e, "eigenpair readback");
   }
-  hipError_t e;
+  const double2* V[3];
+  const double* W[3];
+  const double* TR[3];
+  for (int d = 0; d < 3; ++d) {
+    V[d] = RB + rb_off[d][0];
+    W[d] = reinterpret_cast<const double*>(RB + rb_off[d][1]);
+    TR[d] = reinterpret_cast<const double*>(RB + rb_off[d][2]);
+  }
 
   // 2. ranks and factors on the host
   std::vector<int> rk((size_t)3 * T);
@@ -281,7 +329,7 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   for (int t = 0; t < T; ++t) {
     for (int d = 0; d < 3; ++d) {
       const int n = dims[d], Ld = L[d];
-      const double* w = &W[d][(size_t)t * Ld];
+      const double* w = W[d] + (size_t)t * Ld;
       std::vector<int> idx(Ld);
       std::iota(idx.begin(), idx.end(), 0);
       std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
@@ -297,7 +345,7 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
       rk[3 * t + d] = r;
       reld[3 * t + d] = rt;
       offs[(size_t)d * T + t] = tot[d];
-      const double2* Vm = &V[d][(size_t)t * n * Ld];  // row-major n x Ld
+      const double2* Vm = V[d] + (size_t)t * n * Ld;  // row-major n x Ld
       for (int a = 0; a < r; ++a)
         for (int i = 0; i < n; ++i) U[d].push_back(Vm[(size_t)i * Ld + idx[a]]);
       tot[d] += (int64_t)n * r;
@@ -311,32 +359,32 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
     r2max = std::max(r2max, rk[3 * t + 1]);
   }
 
-  // 3. core = A x1 U1^* x2 U2^* x3 U3^* on the device
-  double2 *dU1, *dU2, *dU3, *dT1, *dT2, *dG;
-  int64_t* dOffs;
-  int* dRk;
-  if ((s = ds.alloc(&dU1, U[0].size())) != TV_OK || (s = ds.alloc(&dU2, U[1].size())) != TV_OK ||
-      (s = ds.alloc(&dU3, U[2].size())) != TV_OK ||
+  // 3. core = A x1 U1^* x2 U2^* x3 U3^* on the device; the factors, offsets
+  //    and ranks go up in one copy (one region, double2 units)
+  const size_t up_off[5] = {0, U[0].size(), U[0].size() + U[1].size(),
+                            U[0].size() + U[1].size() + U[2].size(),
+                            U[0].size() + U[1].size() + U[2].size() + (offs.size() + 1) / 2};
+  const size_t up_n = up_off[4] + (rk.size() + 3) / 4;
+  double2 *dUp, *dT1, *dT2, *dG;
+  if ((s = ds.alloc(&dUp, up_n)) != TV_OK ||
       (s = ds.alloc(&dT1, (size_t)T * r1max * g.n2 * g.n3)) != TV_OK ||
       (s = ds.alloc(&dT2, (size_t)T * r1max * r2max * g.n3)) != TV_OK ||
-      (s = ds.alloc(&dG, (size_t)tot[3])) != TV_OK || (s = ds.alloc(&dOffs, offs.size())) != TV_OK ||
-      (s = ds.alloc(&dRk, rk.size())) != TV_OK)
+      (s = ds.alloc(&dG, (size_t)tot[3])) != TV_OK)
     return s;
-  e = hipMemcpyAsync(dU1, U[0].data(), U[0].size() * sizeof(double2), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dU2, U[1].data(), U[1].size() * sizeof(double2), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dU3, U[2].data(), U[2].size() * sizeof(double2), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dOffs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(dRk, rk.data(), rk.size() * sizeof(int), hipMemcpyHostToDevice, st);
+  double2* up = host_buf(1, up_n);
+  for (int d = 0; d < 3; ++d) std::copy(U[d].begin(), U[d].end(), up + up_off[d]);
+  std::memcpy(up + up_off[3], offs.data(), offs.size() * sizeof(int64_t));
+  std::memcpy(up + up_off[4], rk.data(), rk.size() * sizeof(int));
+  double2 *dU1 = dUp + up_off[0], *dU2 = dUp + up_off[1], *dU3 = dUp + up_off[2];
+  int64_t* dOffs = reinterpret_cast<int64_t*>(dUp + up_off[3]);
+  int* dRk = reinterpret_cast<int*>(dUp + up_off[4]);
+  hipError_t e = hipMemcpyAsync(dUp, up, up_n * sizeof(double2), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_error(e, "factor upload");
   if ((s = launch_proj(A, T, g.n1, g.n2, g.n3, dU1, dU2, dU3, dOffs, dRk, r1max, r2max, dT1, dT2,
                        dG, st)) != TV_OK)
     return s;
-  std::vector<double2> G((size_t)tot[3]);
-  e = hipMemcpyAsync(G.data(), dG, G.size() * sizeof(double2), hipMemcpyDeviceToHost, st);
+  double2* G = host_buf(2, (size_t)tot[3]);
+  e = hipMemcpyAsync(G, dG, (size_t)tot[3] * sizeof(double2), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_error(e, "core readback");
 
@@ -350,7 +398,7 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
       dst.resize(o + 2 * n);
       std::memcpy(&dst[o], src, n * sizeof(double2));
     };
-    put(p->cores, G.data(), G.size());
+    put(p->cores, G, (size_t)tot[3]);
     put(p->u1, U[0].data(), U[0].size());
     put(p->u2, U[1].data(), U[1].size());
     put(p->u3, U[2].data(), U[2].size());
@@ -367,6 +415,10 @@ tv_status tv_compress_append(tv_plan p, const void* cols, int64_t ncols, void* w
   p->grid = full;
   return s;
 }
+
+}  // namespace tv
+
+extern "C" {
 
 tv_status tv_plan_finalize(tv_plan p, void* stream) {
   clear_error();

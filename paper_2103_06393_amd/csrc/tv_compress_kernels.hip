@@ -50,10 +50,19 @@ __device__ __forceinline__ void gram_pair(int pr, int tiles, int& ti, int& tj) {
   tj = ti + pr;
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 // S_d = A_(d) A_(d)^*, one 64 x 64 tile (ti <= tj: S is Hermitian, the tile
 // below the diagonal is written as the conjugate transpose) of one (tensor,
 // mode) per workgroup.  The unfolding streams through LDS 16 columns at a
 // time, the next 16 loaded into registers during the current ones' products.
+// The products run on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], and accumulator r of lane l is
+// D[l / 16 + 4 r][l % 16]): wave w owns the 32 x 32 sub-tile at rows
+// 32 (w / 2), columns 32 (w % 2), as 2 x 2 blocks of 16 x 16, each with a
+// real and an imaginary accumulator; per 4 columns of the unfolding,
+// Re += Xr_re Xc_re^T + Xr_im Xc_im^T and Im += Xr_im Xc_re^T - Xr_re Xc_im^T
+// (S = Xr Xc^*).
 // With nsplit > 1 the unfolding's columns are cut into nsplit ranges (a
 // multiple of 16 each) and every workgroup writes the whole 64 x 64 partial
 // tile of its range to P, [split][tensor][mode][pair] tiles row-major;
@@ -89,11 +98,13 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
   // this workgroup's columns [obase, obase + no) of the unfolding
   const int64_t no = std::max<int64_t>(0, std::min(no_all, obase + chunk) - obase);
   const double2* At = A + (int64_t)t * nv;
-  const int tid = threadIdx.x;
-  const int r0 = 4 * (tid / 16), c0 = 4 * (tid % 16);
-  double2 acc[4][4];
-  for (int u = 0; u < 4; ++u)
-    for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  const int tid = threadIdx.x, lane = tid & 63, wr = (tid >> 6) >> 1, wc = (tid >> 6) & 1;
+  v4d re[2][2], im[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      re[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
+      im[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
   // element e of a stage: (row i, column oc), coalesced along the unfolding's
   // contiguous index
   auto coords = [&](int e, int& i, int& oc) {
@@ -131,30 +142,44 @@ __global__ __launch_bounds__(256) void gram_kernel(const double2* __restrict__ A
     }
     __syncthreads();
     if (o0 + OC < no) gload(o0 + OC);
-    for (int oc = 0; oc < OC; ++oc) {
-      double2 a[4], c[4];
-      for (int u = 0; u < 4; ++u) a[u] = Xr[r0 + u][oc];
-      for (int v = 0; v < 4; ++v) c[v] = Xc[c0 + v][oc];
-      for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) acc[u][v] = zfma_conj_b(a[u], c[v], acc[u][v]);
+#pragma unroll
+    for (int ks = 0; ks < OC; ks += 4) {
+      const int kk = ks + (lane >> 4), rr = lane & 15;
+      double2 a[2], c[2];
+      for (int u = 0; u < 2; ++u) a[u] = Xr[32 * wr + 16 * u + rr][kk];
+      for (int v = 0; v < 2; ++v) c[v] = Xc[32 * wc + 16 * v + rr][kk];
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, c[v].x, re[u][v], 0, 0, 0);
+          re[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, c[v].y, re[u][v], 0, 0, 0);
+          im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, c[v].x, im[u][v], 0, 0, 0);
+          im[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].x, c[v].y, im[u][v], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
+  // accumulator r of block (u, v): tile element (32 wr + 16 u + lane / 16 + 4 r,
+  // 32 wc + 16 v + lane % 16)
   if (nsplit > 1) {
     double2* Pt = P + ((int64_t)sp * ntens * 3 * pairs + tile_id) * 4096;
-    for (int u = 0; u < 4; ++u)
-      for (int v = 0; v < 4; ++v) Pt[(r0 + u) * 64 + c0 + v] = acc[u][v];
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v)
+        for (int r = 0; r < 4; ++r)
+          Pt[(32 * wr + 16 * u + (lane >> 4) + 4 * r) * 64 + 32 * wc + 16 * v + (lane & 15)] =
+              make_double2(re[u][v][r], im[u][v][r]);
     return;
   }
   double2* St = S + ((int64_t)d * ntens + t) * nmax * nmax;
-  for (int u = 0; u < 4; ++u)
-    for (int v = 0; v < 4; ++v) {
-      const int i = ti * 64 + r0 + u, j = tj * 64 + c0 + v;
-      if (i < n && j < n) {
-        St[(int64_t)i * n + j] = acc[u][v];
-        if (ti != tj) St[(int64_t)j * n + i] = make_double2(acc[u][v].x, -acc[u][v].y);
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v)
+      for (int r = 0; r < 4; ++r) {
+        const int i = ti * 64 + 32 * wr + 16 * u + (lane >> 4) + 4 * r;
+        const int j = tj * 64 + 32 * wc + 16 * v + (lane & 15);
+        if (i < n && j < n) {
+          St[(int64_t)i * n + j] = make_double2(re[u][v][r], im[u][v][r]);
+          if (ti != tj) St[(int64_t)j * n + i] = make_double2(re[u][v][r], -im[u][v][r]);
+        }
       }
-    }
 }
 
 // Sum of the nsplit partial tiles of gram_kernel, in split order, into S.

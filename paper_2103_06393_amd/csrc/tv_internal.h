@@ -44,6 +44,12 @@ struct HostPack {
   std::vector<int32_t> drow;
 };
 
+// caller-provided host staging (pinned memory makes copies asynchronous)
+struct HostStage {
+  char* ptr = nullptr;
+  size_t bytes = 0;
+};
+
 // column-split tables hold up to this many splits per component
 constexpr int TV_SPLIT_MAX = 64;
 
@@ -150,6 +156,11 @@ struct tv_plan_s {
   std::vector<int64_t> grow_chunks_k;
   tv::HostPack grow_stage;
   std::vector<int32_t> grow_split;
+  std::vector<char> grow_buf;  // the pieces of one append, packed for one copy
+  char* grow_pinned = nullptr; // or the caller's staging, when handed over
+  size_t grow_pinned_bytes = 0;
+  char* d_stage = nullptr;     // their device staging region in the arena
+  size_t stage_bytes = 0;
 };
 
 namespace tv {
@@ -208,11 +219,30 @@ size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precis
 // The plan keeps no FP64 factors (no export).
 tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision precision,
                            void* arena, size_t bytes, hipStream_t st, tv_plan* out);
+// host staging an append of a growable plan of g.m columns at ranks up to
+// rmax packs its pieces into (grow_plan_set_stage hands one over; without one
+// the plan uses a host vector)
+size_t grow_stage_bytes(const tv_grid& g, const int rmax[3], tv_precision precision);
+void grow_plan_set_stage(tv_plan p, const HostStage& stage);
 tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
                            const double* u1, const double* u2, const double* u3,
                            hipStream_t st);
+// Copy of up to kMaxCopySegs byte ranges of one device staging buffer to
+// their destinations (4-byte aligned, sizes multiples of 4), one launch.
+struct CopySeg {
+  void* dst;
+  int64_t src_off, bytes;
+};
+constexpr int kMaxCopySegs = 24;
+tv_status launch_segment_copy(const CopySeg* segs, int nseg, const void* src, hipStream_t st);
 // compression scratch of one append call of T tensors (tv_compress.cpp)
 size_t compress_scratch_bytes(const tv_plan_s* p, int T);
+// Host staging of one append call's transfers (eigenpair readback, factor
+// upload, core readback): with `bytes` >= compress_stage_bytes the call uses
+// it instead of host vectors (pinned memory makes the copies asynchronous).
+size_t compress_stage_bytes(const tv_plan_s* p, int T);
+tv_status compress_append_staged(tv_plan p, const void* cols, int64_t ncols, void* ws,
+                                 size_t ws_bytes, hipStream_t st, const HostStage& stage);
 // the autotuners' JSON cache: key -> list of integers (tv_autotune.cpp)
 std::map<std::string, std::vector<int>> read_tune_cache(const char* path);
 void write_tune_cache(const char* path, const std::map<std::string, std::vector<int>>& m);
