@@ -599,11 +599,11 @@ PAPER_TABLE8_S = {("aca5", "pwc"): 206, ("aca5", "pwl"): 598, ("aca2", "pwc"): 1
 
 def bench_assemble(args):
     """Algorithm 3 (Tucker-based ACA assembly, Sec. III.C) on the body-coil
-    stand-in: r_c steps (the paper's ACA rank), tolerance 1e-3, HOSVD 3e-3.
-    The stand-in coupling matrix decays more slowly than the paper's, so the
-    loop runs its r_c steps without meeting the stopping test; the time is
-    that of r_c steps, each with a row and a column of Z, two products with
-    the compressed U, the HOSVD of the new column and the plan rebuild."""
+    stand-in: at most r_c steps (the paper's ACA rank), tolerance 1e-3,
+    HOSVD 3e-3; the time is that of the steps run (the loop stops at the
+    norm test or after r_c steps), each with a row and a column of Z, two
+    products with the compressed U, the HOSVD of the new column and U's
+    growth by that column."""
     import numpy as np
     import torch
     import workloads
