@@ -253,13 +253,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(JacobiBatch B) {
   const int half = np / 2;
   double2* A = jsm;              // n x n, row-major
   double2* V = A + n * n;        // n x n
-  double* rc = reinterpret_cast<double*>(V + n * n);  // [half] c
-  double* rs = rc + 32;                               // s
-  double* rpr = rs + 32;                              // cos phi
-  double* rpi = rpr + 32;                             // sin phi
-  int* pi = reinterpret_cast<int*>(rpi + 32);
-  int* pj = pi + 32;
-  double* red = reinterpret_cast<double*>(pj + 32);  // [2][JT / 64]
+  double2* prm = V + n * n;      // per pair: (c, s), (cos phi, sin phi)
+  int2* pij = reinterpret_cast<int2*>(prm + 64);     // per pair: (i, j or -1)
+  double* red = reinterpret_cast<double*>(pij + 32);  // [2][JT / 64]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double2* Sm = S + mat * stride;
   for (int e = tid; e < n * n; e += JT) {
@@ -315,31 +311,33 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(JacobiBatch B) {
         double c = 1.0, s = 0.0, cp = 1.0, sp = 0.0;
         if (j < n) {
           const double2 aij = A[i * n + j];
-          const double dd = sqrt(aij.x * aij.x + aij.y * aij.y);
+          const double d2 = aij.x * aij.x + aij.y * aij.y;
           const double aii = A[i * n + i].x, ajj = A[j * n + j].x;
-          if (dd > 1e-300 && dd > 1e-17 * sqrt(fabs(aii * ajj)) && dd * dd > skip2) {
-            cp = aij.x / dd;
-            sp = aij.y / dd;
-            const double tau = (ajj - aii) / (2.0 * dd);
+          const double dd = sqrt(d2);
+          if (dd > 1e-300 && d2 > 1e-34 * fabs(aii * ajj) && d2 > skip2) {
+            const double inv = 1.0 / dd;
+            cp = aij.x * inv;
+            sp = aij.y * inv;
+            const double tau = (ajj - aii) * (0.5 * inv);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
             s = tt * c;
           }
         }
-        rc[tid] = c;
-        rs[tid] = s;
-        rpr[tid] = cp;
-        rpi[tid] = sp;
-        pi[tid] = i;
-        pj[tid] = j < n ? j : -1;
+        prm[2 * tid] = make_double2(c, s);
+        prm[2 * tid + 1] = make_double2(cp, sp);
+        pij[tid] = make_int2(i, j < n ? j : -1);
       }
       __syncthreads();
       // 2 x 2 blocks: A_pq <- J_p^* A_pq J_q; a pair with no partner (odd n)
       // holds one index and no rotation
       for (int e = tid; e < half * half; e += JT) {
         const int p = e / half, q = e % half;
-        const int ip = pi[p], jp = pj[p], iq = pi[q], jq = pj[q];
-        const double cq = rc[q], sq = rs[q], cpq = rpr[q], spq = rpi[q];
+        const int2 Pp = pij[p], Pq = pij[q];
+        const int ip = Pp.x, jp = Pp.y, iq = Pq.x, jq = Pq.y;
+        const double2 csq = prm[2 * q], eq = prm[2 * q + 1];
+        const double2 csp = prm[2 * p], ep = prm[2 * p + 1];
+        const double cq = csq.x, sq = csq.y, cpq = eq.x, spq = eq.y;
         // columns: (x, y) -> (c x - s e^{-i phi} y, s x + c e^{-i phi} y)
         const double2 m1 = make_double2(-sq * cpq, sq * spq);
         const double2 m2 = make_double2(cq * cpq, -cq * spq);
@@ -350,7 +348,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(JacobiBatch B) {
         const double2 X0 = jrot(cq, x0, m1, y0), Y0 = jrot(sq, x0, m2, y0);
         const double2 X1 = jrot(cq, x1, m1, y1), Y1 = jrot(sq, x1, m2, y1);
         // rows: (x, y) -> (c x - s e^{i phi} y, s x + c e^{i phi} y)
-        const double cpp = rc[p], spp = rs[p], cpr = rpr[p], cpi = rpi[p];
+        const double cpp = csp.x, spp = csp.y, cpr = ep.x, cpi = ep.y;
         const double2 n1 = make_double2(-spp * cpr, -spp * cpi);
         const double2 n2 = make_double2(cpp * cpr, cpp * cpi);
         A[ip * n + iq] = jrot(cpp, X0, n1, X1);
@@ -363,14 +361,14 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(JacobiBatch B) {
       // V <- V J
       for (int e = tid; e < half * n; e += JT) {
         const int q = e / n, r = e % n;
-        const int i = pi[q], j = pj[q];
-        if (j < 0) continue;
-        const double c = rc[q], s = rs[q];
-        const double2 m1 = make_double2(-s * rpr[q], s * rpi[q]);
-        const double2 m2 = make_double2(c * rpr[q], -c * rpi[q]);
-        const double2 x = V[r * n + i], y = V[r * n + j];
-        V[r * n + i] = jrot(c, x, m1, y);
-        V[r * n + j] = jrot(s, x, m2, y);
+        const int2 Pq = pij[q];
+        if (Pq.y < 0) continue;
+        const double2 cs = prm[2 * q], ph = prm[2 * q + 1];
+        const double2 m1 = make_double2(-cs.y * ph.x, cs.y * ph.y);
+        const double2 m2 = make_double2(cs.x * ph.x, -cs.x * ph.y);
+        const double2 x = V[r * n + Pq.x], y = V[r * n + Pq.y];
+        V[r * n + Pq.x] = jrot(cs.x, x, m1, y);
+        V[r * n + Pq.y] = jrot(cs.y, x, m2, y);
       }
       __syncthreads();
     }
@@ -381,7 +379,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(JacobiBatch B) {
 }
 
 size_t jacobi_lds_bytes(int n) {
-  return 16 * (size_t)2 * n * n + 8 * 4 * 32 + 4 * 2 * 32 + 8 * 2 * (JT / 64);
+  return 16 * (size_t)2 * n * n + 16 * 64 + 8 * 32 + 8 * 2 * (JT / 64);
 }
 
 // T1[t][a][o] = sum_i1 conj(U1[i1, a]) A[i1 + n1 o]; workgroup = 32 values of
