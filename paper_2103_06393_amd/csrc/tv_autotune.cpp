@@ -26,7 +26,7 @@ static std::string plan_key(const tv_plan_s* p, int op) {
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "k7|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k8|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -249,10 +249,12 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
           apply_config(p, o, keep);
           if (need > ((size_t)16 << 30)) continue;
           if (o == 1) {
-            // the column GEMM: both tiles and workgroup orders, column
-            // splits from the fewest giving 1024 workgroups to the fewest
-            // giving 4096 (as launched: at least the accumulation-chain
-            // minimum; the partials of Z within 4 GiB where that allows)
+            // the column GEMM: both tiles and workgroup orders, every
+            // distinct column split count (as launched: at least the
+            // accumulation-chain minimum) up to the fewest giving 4096
+            // workgroups (small grids can win with fewer workgroups than
+            // CUs: shorter partial sums), the partials of Z within 4 GiB
+            // where that allows
             const int nslabs = (g.n3 + slab - 1) / slab;
             for (int cnbw : {2, 4}) {
               const int64_t tiles = dtg_colgemm_tiles(p, cnbw);
@@ -267,11 +269,9 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
                 if (!sps.empty() && (double)nslabs * eff * p->dtg_rows * g.n1 * 8 >
                                         4.0 * (1u << 30))
                   break;
-                if (tiles * eff >= 1024 || sp == 64) {
-                  sps.push_back(sp);
-                  last = eff;
-                  if (tiles * eff >= 4096 || sp == 64) break;
-                }
+                sps.push_back(sp);
+                last = eff;
+                if (tiles * eff >= 4096) break;
               }
               if (sps.empty()) sps.push_back(1);
               for (int sp : sps)
