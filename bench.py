@@ -42,16 +42,16 @@ MEASURED_TRAFFIC = {
         "launch": {"kernel": 1},
     },
     ("c5", "fp32", "adjoint"): {
-        "bytes": 122285289237,
+        "bytes": 143799022464,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "52924da87ba613c11cc11b0963271ad35e20849fd76aeaa33e6e9805d9fb4b58",
+        "sha256": "03fea6289d7ec4553b89d69a76c506d3a1e8097e1c07c8daa6daac26fcd1c8c6",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 16},
     },
     ("c5", "fp32", "forward"): {
-        "bytes": 58642937237,
+        "bytes": 58489812714,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "52924da87ba613c11cc11b0963271ad35e20849fd76aeaa33e6e9805d9fb4b58",
+        "sha256": "03fea6289d7ec4553b89d69a76c506d3a1e8097e1c07c8daa6daac26fcd1c8c6",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 1},
     },

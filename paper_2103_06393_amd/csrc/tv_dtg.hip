@@ -34,6 +34,7 @@ namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
 constexpr int DTG_KC = 16;     // k-steps per LDS stage
 constexpr int DTG_MAXQ = 12;
@@ -109,6 +110,48 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
   __syncthreads();
   const int64_t row0 = P.brow[k] + P.drow[kt];
   float* Bk = P.B + row0 * P.ldb;
+  // B is written once and read back by the GEMM after this kernel, and is far
+  // larger than L2 and the MALL: non-temporal stores.  With n2 even (and U2
+  // rows that fit the registers twice) each thread takes two adjacent i2,
+  // whose entries are adjacent in both the Re and the Im 32-runs (n even),
+  // and stores each pair as one 8-byte store; the threads' second index then
+  // strides over i3.
+  if (R2MAX <= 32 && (P.n2 & 1) == 0) {
+    const int np2 = P.n2 >> 1;
+    const int li3 = max(1, 256 / np2);
+    for (int e = threadIdx.x; e < np2 * li3; e += 256) {
+      const int i2 = 2 * (e % np2), i3s = e / np2;
+      float2 u0[R2MAX], u1[R2MAX];
+      const float2* u2 = P.u2t + t.u2_off + (int64_t)i2 * r2;
+#pragma unroll
+      for (int b = 0; b < R2MAX; ++b) {
+        u0[b] = b < r2 ? u2[b] : make_float2(0.f, 0.f);
+        u1[b] = b < r2 ? u2[r2 + b] : make_float2(0.f, 0.f);
+      }
+      for (int a = 0; a < r1; ++a) {
+        float* row = Bk + (int64_t)a * P.ldb;
+        for (int i3l = i3s; i3l < cnt; i3l += li3) {
+          const float2* hv = h3 + (a * T3 + i3l) * r2;
+          float sr0 = 0.f, si0 = 0.f, sr1 = 0.f, si1 = 0.f;
+#pragma unroll
+          for (int b = 0; b < R2MAX; ++b) {
+            if (b < r2) {
+              const float2 h = hv[b];
+              sr0 = fmaf(h.x, u0[b].x, fmaf(-h.y, u0[b].y, sr0));
+              si0 = fmaf(h.x, u0[b].y, fmaf(h.y, u0[b].x, si0));
+              sr1 = fmaf(h.x, u1[b].x, fmaf(-h.y, u1[b].y, sr1));
+              si1 = fmaf(h.x, u1[b].y, fmaf(h.y, u1[b].x, si1));
+            }
+          }
+          const int64_t n = i2 + (int64_t)P.n2 * (i3a + i3l - P.i30);
+          float* dst = row + (n >> 5) * 64 + (n & 31);
+          __builtin_nontemporal_store(v2f{sr0, sr1}, reinterpret_cast<v2f*>(dst));
+          __builtin_nontemporal_store(v2f{si0, si1}, reinterpret_cast<v2f*>(dst + 32));
+        }
+      }
+    }
+    return;
+  }
   for (int i2 = threadIdx.x; i2 < P.n2; i2 += 256) {
     float2 u[R2MAX];
     const float2* u2 = P.u2t + t.u2_off + (int64_t)i2 * r2;
@@ -129,8 +172,8 @@ __global__ __launch_bounds__(256) void dtg_decomp_kernel(DecompParams P) {
         }
         const int64_t n = i2 + (int64_t)P.n2 * (i3a + i3l - P.i30);
         float* dst = row + (n >> 5) * 64 + (n & 31);
-        dst[0] = sr;
-        dst[32] = si;
+        __builtin_nontemporal_store(sr, dst);
+        __builtin_nontemporal_store(si, dst + 32);
       }
     }
   }
