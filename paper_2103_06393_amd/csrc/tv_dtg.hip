@@ -277,31 +277,52 @@ __global__ __launch_bounds__(256) void dtg_gemm_kernel(GemmParams P) {
     lstore(0);
   }
   __syncthreads();
+  // Per stage: the LDS operands of k-step q + 1 are read while the MFMAs of
+  // q run, and the next stage's operands (loaded from global memory at the
+  // top) are stored to the other buffer three quarters of the way through,
+  // so that only the barrier separates two stages' MFMAs.  The last stage
+  // reloads and stores its own operands (in bounds, never read), which keeps
+  // the body free of branches.
   for (int st = st0; st < st1; ++st) {
     const int buf = (st - st0) & 1;
-    if (st + 1 < st1) gload(st + 1);
+    gload(st + 1 < st1 ? st + 1 : st);
+    // keep the global loads at the top of the stage (the scheduler would
+    // otherwise sink them next to their LDS stores)
+    __builtin_amdgcn_sched_barrier(0);
     const float* As = lds + buf * (A_ST + B_ST);
     const float* Bs = As + A_ST;
+    v4f a[2][MBW];
+    float b[2][NBW];
 #pragma unroll
-    for (int kg = 0; kg < 4; ++kg) {
-      v4f a[MBW];
+    for (int i = 0; i < MBW; ++i) a[0][i] = *(const v4f*)(As + ((wm * MBW + i) * 64 + lane) * 4);
 #pragma unroll
-      for (int i = 0; i < MBW; ++i)
-        a[i] = *(const v4f*)(As + ((kg * MT + wm * MBW + i) * 64 + lane) * 4);
+    for (int jn = 0; jn < NBW; ++jn) b[0][jn] = Bs[(wn * NBW + jn) * 64 + lane];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        float b[NBW];
+    for (int q = 0; q < 16; ++q) {
+      const int kg = q >> 2, kk = q & 3, cur = q & 1;
+      if (q + 1 < 16) {
+        const int kg1 = (q + 1) >> 2;
+        if (((q + 1) & 3) == 0) {
+#pragma unroll
+          for (int i = 0; i < MBW; ++i)
+            a[(kg1 & 1)][i] = *(const v4f*)(As + ((kg1 * MT + wm * MBW + i) * 64 + lane) * 4);
+        }
 #pragma unroll
         for (int jn = 0; jn < NBW; ++jn)
-          b[jn] = Bs[((kg * 4 + kk) * NBT + wn * NBW + jn) * 64 + lane];
+          b[cur ^ 1][jn] = Bs[((q + 1) * NBT + wn * NBW + jn) * 64 + lane];
+      }
 #pragma unroll
-        for (int i = 0; i < MBW; ++i)
+      for (int i = 0; i < MBW; ++i)
 #pragma unroll
-          for (int jn = 0; jn < NBW; ++jn)
-            acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[jn], acc[i][jn], 0, 0, 0);
+        for (int jn = 0; jn < NBW; ++jn)
+          acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kg & 1][i][kk], b[cur][jn],
+                                                            acc[i][jn], 0, 0, 0);
+      if (q == 11) {
+        __builtin_amdgcn_sched_barrier(0);
+        lstore(buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-    if (st + 1 < st1) lstore(buf ^ 1);
     __syncthreads();
   }
 
@@ -675,29 +696,46 @@ __global__ __launch_bounds__(256) void dtg_colgemm_kernel(ColGemmParams P) {
     lstore(0);
   }
   __syncthreads();
+  // as in dtg_gemm_kernel: the next k-step group's operands are read while
+  // the current group's MFMAs run, the next stage is stored three quarters
+  // of the way through, and the last stage reloads its own (in bounds)
   for (int st = st0; st < st1; ++st) {
     const int buf = (st - st0) & 1;
-    if (st + 1 < st1) gload(st + 1);
+    gload(st + 1 < st1 ? st + 1 : st);
+    __builtin_amdgcn_sched_barrier(0);
     const float* As = lds + buf * (A_ST + B_ST);
     const float* Bs = As + A_ST;
+    v4f a[2][MBW], b[2][NBW];
+#pragma unroll
+    for (int i = 0; i < MBW; ++i) a[0][i] = *(const v4f*)(As + ((wm * MBW + i) * 64 + lane) * 4);
+#pragma unroll
+    for (int jn = 0; jn < NBW; ++jn)
+      b[0][jn] = *(const v4f*)(Bs + ((wn * NBW + jn) * 64 + lane) * 4);
 #pragma unroll
     for (int kg = 0; kg < 4; ++kg) {
-      v4f a[MBW], b[NBW];
+      const int cur = kg & 1;
+      if (kg + 1 < 4) {
 #pragma unroll
-      for (int i = 0; i < MBW; ++i)
-        a[i] = *(const v4f*)(As + ((kg * MT + wm * MBW + i) * 64 + lane) * 4);
+        for (int i = 0; i < MBW; ++i)
+          a[cur ^ 1][i] = *(const v4f*)(As + (((kg + 1) * MT + wm * MBW + i) * 64 + lane) * 4);
 #pragma unroll
-      for (int jn = 0; jn < NBW; ++jn)
-        b[jn] = *(const v4f*)(Bs + kg * KGS + ((wn * NBW + jn) * 64 + lane) * 4);
+        for (int jn = 0; jn < NBW; ++jn)
+          b[cur ^ 1][jn] = *(const v4f*)(Bs + (kg + 1) * KGS + ((wn * NBW + jn) * 64 + lane) * 4);
+      }
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
         for (int i = 0; i < MBW; ++i)
 #pragma unroll
           for (int jn = 0; jn < NBW; ++jn)
-            acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[jn][kk], acc[i][jn], 0, 0, 0);
+            acc[i][jn] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[cur][i][kk], b[cur][jn][kk],
+                                                              acc[i][jn], 0, 0, 0);
+      if (kg == 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        lstore(buf ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
-    if (st + 1 < st1) lstore(buf ^ 1);
     __syncthreads();
   }
 
