@@ -270,8 +270,10 @@ tv_status tv_dipole_columns(int32_t n1, int32_t n2, int32_t n3, double h,
  * tv_compress_append compresses the next ncols columns, given as device
  * complex128 in the layout written by tv_dipole_columns, with the caller's
  * device workspace ws (256-byte aligned, at least
- * tv_compress_workspace_bytes(plan, ncols) bytes: Gram matrices,
- * eigenpairs, factors and partial projections of the call; TV_ERR_WORKSPACE
+ * tv_compress_workspace_bytes(plan, ncols) bytes: Gram matrices (and, for
+ * calls of few tensors, whose Gram products are split over the unfoldings'
+ * columns, their partial tiles), eigenpairs, factors and partial
+ * projections of the call; TV_ERR_WORKSPACE
  * before any device work if short); work happens on `stream`, and the call
  * synchronises it before returning.  The factors are kept on the host.
  * tv_plan_finalize packs the plan for the products once all m columns are
