@@ -42,16 +42,16 @@ MEASURED_TRAFFIC = {
         "launch": {"kernel": 1},
     },
     ("c5", "fp32", "adjoint"): {
-        "bytes": 143799022464,
+        "bytes": 122870307829,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "03fea6289d7ec4553b89d69a76c506d3a1e8097e1c07c8daa6daac26fcd1c8c6",
+        "sha256": "abfedadd49b011cd5d9d1478415d905379459d761f5b3389cb91551f88c0b65e",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 16},
     },
     ("c5", "fp32", "forward"): {
-        "bytes": 58489812714,
+        "bytes": 58491124352,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "03fea6289d7ec4553b89d69a76c506d3a1e8097e1c07c8daa6daac26fcd1c8c6",
+        "sha256": "abfedadd49b011cd5d9d1478415d905379459d761f5b3389cb91551f88c0b65e",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 1},
     },
