@@ -199,6 +199,10 @@ tv_status tv_rmatvec(tv_plan plan, const void* y, int64_t ldy, int32_t nrhs,
  *     workgroups sharing B rows adjacent, 1: sharing y columns adjacent),
  *     one FP32 partial per slab and split, then x'_j = sum conj(U1_j) Z_k
  *     with the partials summed in FP64 (Algorithms 1 and 2, Sec. III.B).
+ *     row_cap on path 1: 0 (the plan's GEMM tile along the voxel rows) or
+ *     8 (BF16X3 plans whose 2 n1 real rows pack into 16 blocks of 32, with
+ *     gemm_nbw 2: one workgroup over all voxel rows, 8 row blocks per wave,
+ *     so the slab is read once per column tile).
  * TV_ERR_INVALID_ARG / TV_ERR_NOT_SUPPORTED for a configuration the plan
  * cannot run; the previous configuration is then kept.  Afterwards
  * tv_workspace_bytes reflects the configuration. */

@@ -26,7 +26,7 @@ static std::string plan_key(const tv_plan_s* p, int op) {
     h *= 1099511628211ull;
   }
   char buf[256];
-  snprintf(buf, sizeof buf, "k8|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
+  snprintf(buf, sizeof buf, "k9|%s|%dx%dx%d|q%d|m%lld|p%d|r%016llx|op%d", arch.c_str(), p->grid.n1,
            p->grid.n2, p->grid.n3, p->grid.q, (long long)p->grid.m, (int)p->precision,
            (unsigned long long)h, op);
   for (char* c = buf; *c; ++c)
@@ -112,6 +112,14 @@ static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
     if (!dtg_supported(p)) return set_error(TV_ERR_NOT_SUPPORTED, "plan has no GEMM operand");
     if (c.slab_i3 < 0) return set_error(TV_ERR_INVALID_ARG, "slab_i3 must be >= 0");
     const int slab = c.slab_i3 ? std::min(c.slab_i3, p->grid.n3) : p->grid.n3;
+    // row_cap: 0 (the default tile) or 8 row blocks per wave, a workgroup over
+    // all 512 voxel rows (BF16X3 plans with 2 n1 = 512, gemm_nbw 2)
+    if (c.row_cap != 0 && c.row_cap != 8)
+      return set_error(TV_ERR_INVALID_ARG, "the GEMM takes row_cap 0 or 8");
+    if (c.row_cap == 8 && (p->precision != TV_PREC_BF16X3 || c.gemm_nbw != 2 ||
+                           p->dtg_nbtp != 16))
+      return set_error(TV_ERR_NOT_SUPPORTED,
+                       "row_cap 8 needs a BF16X3 plan with 2 n1 = 512 and gemm_nbw 2");
     if (op == 1) {
       if (c.gemm_nbw != 2 && c.gemm_nbw != 4)
         return set_error(TV_ERR_INVALID_ARG, "the adjoint GEMM takes gemm_nbw 2 or 4");
@@ -123,6 +131,7 @@ static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
       p->dtg_nbw_a = c.gemm_nbw;
       p->dtg_s3_a = slab;
       p->dtg_order_a = c.gemm_order;
+      p->dtg_mbw[1] = c.row_cap;
       p->use_dtg[1] = true;
       return TV_OK;
     }
@@ -132,6 +141,7 @@ static tv_status apply_config(tv_plan_s* p, int op, const tv_launch_config& c) {
     p->dtg_nbw = c.gemm_nbw;
     p->dtg_split = c.splits;
     p->dtg_s3 = slab;
+    p->dtg_mbw[0] = c.row_cap;
     p->use_dtg[0] = true;
     return TV_OK;
   }
@@ -166,6 +176,7 @@ static tv_launch_config current_config(const tv_plan_s* p, int op) {
     c.slab_i3 = op == 0 ? p->dtg_s3 : p->dtg_s3_a;
     c.gemm_nbw = op == 0 ? p->dtg_nbw : p->dtg_nbw_a;
     c.gemm_order = op == 0 ? 0 : p->dtg_order_a;
+    c.row_cap = p->dtg_mbw[op];
     return c;
   }
   c.tile_t2 = op == 0 ? p->tiling.t2 : p->tiling_a.t2;
@@ -199,6 +210,7 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
   auto cache = read_tune_cache(cache_path);
   const tv_grid& g = p->grid;
   const int64_t rows = (int64_t)g.q * g.n1 * g.n2 * g.n3;
+  const bool bf = p->precision == TV_PREC_BF16X3;
   bool dirty = false;
   for (int o = 0; o < 2; ++o) {
     if (op != 2 && op != o) continue;
@@ -274,14 +286,18 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
                 if (tiles * eff >= 4096) break;
               }
               if (sps.empty()) sps.push_back(1);
+              const bool full_m = bf && cnbw == 2 && p->dtg_nbtp == 16;
               for (int sp : sps)
-                for (int order : {0, 1}) {
-                  tv_launch_config cc = c;
-                  cc.gemm_nbw = cnbw;
-                  cc.splits = sp;
-                  cc.gemm_order = order;
-                  cands.push_back(cc);
-                }
+                for (int order : {0, 1})
+                  for (int rc : {0, 8}) {
+                    if (rc == 8 && !full_m) continue;
+                    tv_launch_config cc = c;
+                    cc.gemm_nbw = cnbw;
+                    cc.splits = sp;
+                    cc.gemm_order = order;
+                    cc.row_cap = rc;
+                    cands.push_back(cc);
+                  }
             }
             continue;
           }
@@ -290,7 +306,13 @@ extern "C" tv_status tv_autotune(tv_plan p, int32_t op, const char* cache_path, 
             if (sp > 1 && tiles * (sp / 2) >= 1024) break;
             if (sp > 1 && (double)sp * rows * 8 > 2e9) break;
             c.splits = sp;
+            c.row_cap = 0;
             cands.push_back(c);
+            if (bf && nbw == 2 && p->dtg_nbtp == 16) {
+              c.row_cap = 8;
+              cands.push_back(c);
+              c.row_cap = 0;
+            }
           }
         }
         if (slab <= 8 || (int64_t)g.n2 * slab < 4096) break;

@@ -421,7 +421,7 @@ __device__ __forceinline__ void bf2_compute(const float* lds, int buf, int lane,
 }
 
 template <int MBW, int NBW>
-__global__ __launch_bounds__(256, NBW == 2 ? 2 : 1) void dtg_gemm_bf2_kernel(GemmParams P) {
+__global__ __launch_bounds__(256, (NBW == 2 && MBW < 8) ? 2 : 1) void dtg_gemm_bf2_kernel(GemmParams P) {
   constexpr int MT = 2 * MBW, NBT = 2 * NBW;
   constexpr int RS = NBT * 64 + BF2_RPAD;          // floats per LDS row of B
   constexpr int A_ST = MT * 2 * 64 * 4;            // floats per A stage (hi, lo)
@@ -900,7 +900,7 @@ __device__ __forceinline__ void colbf2_compute(const float* lds, int buf, int la
 }
 
 template <int MBW, int NBW>
-__global__ __launch_bounds__(256, NBW == 2 ? 2 : 1) void dtg_colgemm_bf2_kernel(ColGemmParams P) {
+__global__ __launch_bounds__(256, (NBW == 2 && MBW < 8) ? 2 : 1) void dtg_colgemm_bf2_kernel(ColGemmParams P) {
   constexpr int MT = 2 * MBW, NBT = 2 * NBW;
   constexpr int A_ST = MT * 2 * 64 * 4;
   constexpr int ST = A_ST + NBT * 32 * CBF_RS;
@@ -1029,6 +1029,7 @@ __global__ __launch_bounds__(256, NBW == 2 ? 2 : 1) void dtg_colgemm_bf2_kernel(
 typedef void (*colgemm_fn)(ColGemmParams);
 colgemm_fn colgemm_pick_bf2(int mbw, int nbw) {
   if (mbw == 4 && nbw == 2) return dtg_colgemm_bf2_kernel<4, 2>;
+  if (mbw == 8 && nbw == 2) return dtg_colgemm_bf2_kernel<8, 2>;
   if (mbw == 4 && nbw == 4) return dtg_colgemm_bf2_kernel<4, 4>;
   if (mbw == 2 && nbw == 2) return dtg_colgemm_bf2_kernel<2, 2>;
   if (mbw == 2 && nbw == 4) return dtg_colgemm_bf2_kernel<2, 4>;
@@ -1060,6 +1061,7 @@ typedef void (*gemm_fn)(GemmParams);
 
 gemm_fn gemm_pick_bf2(int mbw, int nbw) {
   if (mbw == 4 && nbw == 4) return dtg_gemm_bf2_kernel<4, 4>;
+  if (mbw == 8 && nbw == 2) return dtg_gemm_bf2_kernel<8, 2>;
   if (mbw == 4 && nbw == 2) return dtg_gemm_bf2_kernel<4, 2>;
   if (mbw == 2 && nbw == 4) return dtg_gemm_bf2_kernel<2, 4>;
   if (mbw == 2 && nbw == 2) return dtg_gemm_bf2_kernel<2, 2>;
@@ -1083,6 +1085,14 @@ gemm_fn gemm_pick(int mbw, int nbw) {
 
 // row blocks per workgroup tile of the GEMM for a plan (8 for n1 > 64, else 4)
 int dtg_mt(const tv_plan_s* p) { return p->nbt_pack > 4 ? 8 : 4; }
+
+// 32-row blocks of a GEMM workgroup tile along the voxel rows for op 0 / 1:
+// the plan's default, or all 16 blocks of 2 n1 = 512 rows when the launch
+// configuration asks for 8 blocks per wave (BF16X3 plans; the packed rows
+// come in tiles of 16 blocks when dtg_nbtp is a multiple of 16)
+int dtg_mt_op(const tv_plan_s* p, int op) {
+  return p->dtg_mbw[op] == 8 ? 16 : dtg_mt(p);
+}
 
 size_t dtg_gemm_lds(int mbw, int nbw) {
   return 2 * sizeof(float) * (size_t)(4 * 2 * mbw * 64 * 4 + DTG_KC * 2 * nbw * 64);
@@ -1269,7 +1279,7 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
     G.brow[k] = D.brow[k];
     G.kst[k] = (int)(p->dtg_rpad[k] / DTG_KC);
   }
-  const int MT = dtg_mt(p);
+  const int MT = dtg_mt_op(p, 0);
   const bool bf16 = p->precision == TV_PREC_BF16X3;
   const int mbw = MT / 2, nbw = p->dtg_nbw;
   gemm_fn fn = bf16 ? gemm_pick_bf2(mbw, nbw) : gemm_pick(mbw, nbw);
@@ -1347,7 +1357,7 @@ static tv_status launch_dtg_colgemm_adjoint(const tv_plan_s* p, const float2* y,
   float* yp = (float*)((char*)ws + bbytes);
   float2* z = (float2*)((char*)yp + (size_t)g.q * ystride * sizeof(float));
   const int S = dtg_colgemm_splits(p, s3);
-  const int MT = dtg_mt(p);
+  const int MT = dtg_mt_op(p, 1);
   const int mbw = MT / 2, nbw = p->dtg_nbw_a;
   const bool bf16 = p->precision == TV_PREC_BF16X3;
   colgemm_fn fn = bf16 ? colgemm_pick_bf2(mbw, nbw) : colgemm_pick(mbw, nbw);

@@ -144,6 +144,7 @@ struct tv_plan_s {
   int dtg_nbw_a = 4;               // 32-row blocks per wave along N of that GEMM
   int dtg_nbw = 2;                 // 32-column blocks per wave of the GEMM tile
   int dtg_split = 1;               // k-step splits of the GEMM
+  int dtg_mbw[2] = {0, 0};         // GEMM 32-row blocks per wave (0: default; 8: BF16X3 full-M tile)
   int max_r[3] = {0, 0, 0};
   int nbt_pack = 0;      // 32-row blocks per stacked A row in the packed layout
   int max_r12 = 0;       // largest r1 r2

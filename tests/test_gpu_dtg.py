@@ -177,6 +177,40 @@ def test_dtg_bf16x3_column_adjoint_matches_oracle(gpu_lib, dims, q, m, rmax, see
         print(f"bf16x3 column adjoint {dims}: rel err {e:.2e}")
 
 
+@pytest.mark.parametrize("dims,q,m,rmax,seed,slab,splits", [
+    ((256, 16, 9), 3, 4, 10, 51, 3, 1),     # 2 n1 = 512: one workgroup over all rows
+    ((256, 20, 11), 2, 6, 14, 52, 0, 2),    # ragged columns, 2 splits
+    ((250, 12, 7), 1, 5, 9, 53, 0, 1),      # n1 = 250: the last 6 rows are padding
+])
+def test_dtg_bf16x3_full_row_tile_matches_oracle(gpu_lib, dims, q, m, rmax, seed, slab, splits):
+    """BF16X3 plans with 2 n1 = 512 (the packed rows come in 16 blocks of
+    32): the GEMMs' workgroup tile over all voxel rows (row_cap 8, 8 blocks
+    per wave, one workgroup per CU, accumulators in AGPRs), forward and
+    column adjoint, within 1e-4 of the moduli of the terms, two calls each."""
+    import torch
+    from paper_2103_06393_amd import lib
+    from paper_2103_06393_amd.ops import TuckerPlan
+    S = random_struct(dims, q, m, rmax, seed)
+    P = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
+                                precision=lib.TV_PREC_BF16X3)
+    lib.tv_plan_configure(P.handle, 0, path=1, splits=splits, slab_i3=slab, gemm_nbw=2,
+                          row_cap=8)
+    lib.tv_plan_configure(P.handle, 1, path=1, splits=splits, slab_i3=slab, gemm_nbw=2,
+                          gemm_order=seed % 2, row_cap=8)
+    P._ws.clear()
+    assert P.info.kernel[0] == 2 and P.info.kernel[1] == 2
+    rng = np.random.default_rng(seed)
+    for rep in range(2):
+        x = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+        got = P.matvec(torch.from_numpy(x.astype(np.complex64)).cuda()).cpu().numpy()
+        assert_close(got, om.alg1(S, x)[:, 0], 1e-4, terms=fwd_terms(S, x),
+                     what=f"BF16X3 full-row tile Z x, call {rep}")
+        y = rng.standard_normal(S.q * S.nv) + 1j * rng.standard_normal(S.q * S.nv)
+        gx = P.rmatvec(torch.from_numpy(y.astype(np.complex64)).cuda()).cpu().numpy()
+        assert_close(gx, om.alg2(S, y)[:, 0], 1e-4, terms=adj_terms(S, y),
+                     what=f"BF16X3 full-row tile Z^* y, call {rep}")
+
+
 def test_dtg_adjoint_poisoned_workspace_and_multi_rhs(gpu_lib):
     import torch
     from paper_2103_06393_amd import lib
@@ -218,7 +252,21 @@ def test_dtg_refused_configurations(gpu_lib):
         lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=3)
     with pytest.raises(lib.TuckVsieError):
         lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=1)
+    # the full-row tile: BF16X3 plans with 2 n1 = 512 and gemm_nbw 2 only
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 0, path=1, splits=1, gemm_nbw=2, row_cap=8)
+    with pytest.raises(lib.TuckVsieError):
+        lib.tv_plan_configure(P.handle, 1, path=1, splits=1, gemm_nbw=2, row_cap=4)
     assert P.info.kernel[0] != 2 and P.info.kernel[1] != 2   # refusals left no trace
+    B = TuckerPlan.from_factors(S.dims, S.q, S.m, *struct_to_abi(S),
+                                precision=lib.TV_PREC_BF16X3)
+    with pytest.raises(lib.TuckVsieError):                   # 2 n1 = 40, not 512
+        lib.tv_plan_configure(B.handle, 0, path=1, splits=1, gemm_nbw=2, row_cap=8)
+    W = TuckerPlan.from_factors((256, 8, 5), 1, 2, *struct_to_abi(random_struct((256, 8, 5), 1, 2,
+                                                                                4, 2)),
+                                precision=lib.TV_PREC_BF16X3)
+    with pytest.raises(lib.TuckVsieError):                   # full-row tile needs gemm_nbw 2
+        lib.tv_plan_configure(W.handle, 1, path=1, splits=1, gemm_nbw=4, row_cap=8)
 
 
 def test_dtg_several_slabs_in_a_graph(gpu_lib):
