@@ -444,16 +444,6 @@ const char* tv_last_error(void) { return g_last_error.c_str(); }
 tv_status tv_plan_from_factors(const tv_grid* grid, const int32_t* ranks, const double* cores,
                                const double* u1, const double* u2, const double* u3,
                                tv_precision precision, tv_plan* out) {
-  return plan_from_factors_ex(grid, ranks, cores, u1, u2, u3, precision, true, out);
-}
-
-}  // extern "C"
-
-namespace tv {
-
-tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const double* cores,
-                               const double* u1, const double* u2, const double* u3,
-                               tv_precision precision, bool with_dtg, tv_plan* out) {
   clear_error();
   if (!out) return set_error(TV_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -467,7 +457,7 @@ tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const 
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
   p->grid = *grid;
   p->precision = precision;
-  p->with_dtg = with_dtg;
+  p->with_dtg = true;
   p->appended = grid->m;
   const int64_t K = (int64_t)grid->q * grid->m;
   p->ranks.assign(ranks, ranks + 3 * K);
@@ -496,6 +486,10 @@ tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const 
   *out = p;
   return TV_OK;
 }
+
+}  // extern "C"
+
+namespace tv {
 
 // Staging of one growable-plan append: the metadata of every tensor and one
 // column's q tensors of every other array, each piece 16-byte aligned.

@@ -204,12 +204,9 @@ tv_status launch_dtg_forward(const tv_plan_s* p, const float2* x, float2* y, voi
                              hipStream_t st);
 tv_status launch_dtg_adjoint(const tv_plan_s* p, const float2* y, float2* x, void* ws,
                              hipStream_t st);
-// plan creation without the decompress-then-GEMM operands, and an upper
-// bound of the device arena of a plan of grid g whose ranks are at most rmax
-// (that packing; also the arena of a growable plan of g.m columns)
-tv_status plan_from_factors_ex(const tv_grid* grid, const int32_t* ranks, const double* cores,
-                               const double* u1, const double* u2, const double* u3,
-                               tv_precision precision, bool with_dtg, tv_plan* out);
+// an upper bound of the device arena of a plan of grid g whose ranks are at
+// most rmax, without the decompress-then-GEMM operands (the arena of a
+// growable plan of g.m columns)
 size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision);
 // Growable plan (Algorithm 3's U, which gains one column per step): created
 // empty with its device arrays at fixed offsets of `arena`, each sized for
