@@ -42,16 +42,16 @@ MEASURED_TRAFFIC = {
         "launch": {"kernel": 1},
     },
     ("c5", "fp32", "adjoint"): {
-        "bytes": 122870307829,
+        "bytes": 144831707146,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "abfedadd49b011cd5d9d1478415d905379459d761f5b3389cb91551f88c0b65e",
+        "sha256": "ff210939ce74c66dc3bfbac714fe9776d2c22c710a66bca479c86712c9b7e010",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 16},
     },
     ("c5", "fp32", "forward"): {
-        "bytes": 58491124352,
+        "bytes": 58489939018,
         "source": "paper_2103_06393_amd/csrc/tv_dtg.hip",
-        "sha256": "abfedadd49b011cd5d9d1478415d905379459d761f5b3389cb91551f88c0b65e",
+        "sha256": "ff210939ce74c66dc3bfbac714fe9776d2c22c710a66bca479c86712c9b7e010",
         "profile": "profiles/dtg_c5_fp32_pmc.md",
         "launch": {"kernel": 2, "tile_t2": 128, "tile_t3": 4, "splits": 1},
     },
