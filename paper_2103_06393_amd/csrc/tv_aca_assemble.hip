@@ -276,6 +276,8 @@ struct Buffers {
 };
 
 // Largest rank per mode a new column of U may keep (the HOSVD's clamps).
+constexpr size_t kGrowAdjBudget = (size_t)8 << 30;
+
 void rank_bounds(const tv_grid& g, int rank_cap, int rmax[3]) {
   const int dims[3] = {g.n1, g.n2, g.n3};
   for (int d = 0; d < 3; ++d) {
@@ -331,6 +333,9 @@ AcaSizes aca_sizes(const tv_grid& g, int K, double htol, int rank_min, int rank_
   Tiling Ta;
   make_tiling(g, 0, 2, &Ta);
   z.prod = std::max((size_t)8 * 8 * rows, (size_t)8 * g.q * Ta.tiles * K);
+  // U's adjoint runs as the column GEMM once U has a few columns, in at most
+  // kGrowAdjBudget bytes (the fused kernels again past that)
+  z.prod = std::max(z.prod, std::min(grow_adjoint_ws_bytes(gk, rmax), kGrowAdjBudget));
   z.total = z.fixed + z.comp + z.uarena + z.prod + 4 * 256;
   return z;
 }
@@ -573,7 +578,7 @@ extern "C" tv_status tv_aca_assemble(const tv_grid* grid, double h, double k0, i
     tv_grid gk = g;
     gk.m = K;
     if ((s = grow_plan_create(gk, rmax, precision, uarena, Z.uarena, st, &U)) != TV_OK) return s;
-    grow_plan_set_stage(U, gstage);
+    grow_plan_set_stage(U, gstage, Z.prod);
   }
   auto fail = [&](tv_status r) {
     tv_plan_destroy(U);

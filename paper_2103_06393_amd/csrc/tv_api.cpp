@@ -501,7 +501,8 @@ static size_t stage_size(const tv_grid& g, const int rmax[3], int nbt, tv_precis
          (size_t)g.q * (r1 * r2 * r3 + g.n1 * r1 + g.n2 * r2 + g.n3 * r3) * sizeof(float2) +
          (bf ? (size_t)g.q * ((r1 + 7) / 8) * nbt * 128 * sizeof(uint4)
              : (size_t)g.q * r1 * nbt * 64 * sizeof(float)) +
-         (size_t)2 * g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t) + (size_t)(g.q + 8) * 16;
+         (size_t)2 * g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t) + K * sizeof(int32_t) +
+         (size_t)(g.q + 9) * 16;
 }
 
 // Device layout of a plan holding up to g.m columns at ranks up to rmax, in
@@ -531,15 +532,17 @@ static size_t capacity_layout(const tv_grid& g, const int rmax[3], int nbt,
   carve(&d->d_apack_koff, (size_t)(g.q + 1) * sizeof(int64_t));
   carve(&d->d_split_f, (size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
   carve(&d->d_split_a, (size_t)g.q * (TV_SPLIT_MAX + 1) * sizeof(int32_t));
+  carve(&d->d_drow, K * sizeof(int32_t));
   const size_t stage = stage_size(g, rmax, nbt, precision);
   carve(&d->d_stage, stage);
   if (p && base) p->stage_bytes = stage;
   return (off + 255) & ~(size_t)255;
 }
 
-void grow_plan_set_stage(tv_plan p, const HostStage& stage) {
+void grow_plan_set_stage(tv_plan p, const HostStage& stage, size_t adj_ws_bytes) {
   p->grow_pinned = stage.ptr;
   p->grow_pinned_bytes = stage.bytes;
+  p->grow_adj_ws = adj_ws_bytes;
 }
 
 static int pack_nbt(const tv_grid& g, int nbcap_a) {
@@ -553,6 +556,41 @@ static int pack_nbt(const tv_grid& g, int nbcap_a) {
 size_t grow_stage_bytes(const tv_grid& g, const int rmax[3], tv_precision precision) {
   const int nbt = pack_nbt(g, 2);
   return nbt ? stage_size(g, rmax, nbt, precision) : 0;
+}
+
+// Growable plans run their adjoint as the column GEMM of tv_dtg.hip (its
+// operands are the plan's U1 rows, cores, U2 and U3 and the caller's y, so
+// only the stacked row layout follows the appends): set-up for the plan's
+// geometry, then the padded rows per component after each append. Rows of
+// A_k are padded to the GEMM's k-step of 16, as dtg_pack pads them.
+constexpr int kDtgRowPad = 16;
+static void dtg_grow_setup(tv_plan_s* p) {
+  if (p->grid.q > DTG_MAXQ_HOST) return;
+  const int MT = dtg_mt(p);
+  p->dtg_nbtp = (p->nbt_pack + MT - 1) / MT * MT;
+  p->dtg_rpad.assign(p->grid.q, 0);
+  p->dtg_rows = 0;
+  p->dtg_packed = true;
+}
+
+static void dtg_grow_rows(tv_plan_s* p) {
+  if (!p->dtg_packed) return;
+  p->dtg_rows = 0;
+  for (int k = 0; k < p->grid.q; ++k) {
+    p->dtg_rpad[k] = (p->sum_r1_k[k] + kDtgRowPad - 1) / kDtgRowPad * kDtgRowPad;
+    p->dtg_rows += p->dtg_rpad[k];
+  }
+}
+
+size_t grow_adjoint_ws_bytes(const tv_grid& g, const int rmax[3]) {
+  const int nbt = pack_nbt(g, 2);
+  if (!nbt || g.q > DTG_MAXQ_HOST) return 0;
+  tv_plan_s t;
+  t.grid = g;
+  t.nbt_pack = nbt;
+  dtg_grow_setup(&t);
+  t.dtg_rows = (int64_t)g.q * (((int64_t)g.m * rmax[0] + kDtgRowPad - 1) / kDtgRowPad * kDtgRowPad);
+  return dtg_workspace_bytes(&t, 1);
 }
 
 size_t plan_arena_bound(const tv_grid& g, const int rmax[3], tv_precision precision) {
@@ -573,7 +611,7 @@ tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision pre
       return set_error(TV_ERR_RANK, "growable plan: rank cap outside [1, min(n, TV_MAX_RANK)]");
   if (!arena || (uintptr_t)arena % 256)
     return set_error(TV_ERR_INVALID_ARG, "arena must be non-NULL and 256-byte aligned");
-  if (g.q + 7 > kMaxCopySegs)
+  if (g.q + 8 > kMaxCopySegs)
     return set_error(TV_ERR_NOT_SUPPORTED, "growable plan: too many components");
   tv_plan_s* p = new (std::nothrow) tv_plan_s;
   if (!p) return set_error(TV_ERR_OOM, "host allocation");
@@ -609,6 +647,7 @@ tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision pre
   p->u1_off.assign(1, 0);
   p->u2_off.assign(1, 0);
   p->u3_off.assign(1, 0);
+  dtg_grow_setup(p);
   hipError_t e = hipMemcpyAsync(p->d_apack_koff, p->apack_koff.data(),
                                 p->apack_koff.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -740,6 +779,20 @@ tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
         row[k] += bf ? (M.r1 + 7) / 8 : M.r1;
       }
   }
+  // stacked row of each tensor's first U1 column in A_k, [k][j] (the column
+  // GEMM's layout: no padding between tensors), and the adjoint's path
+  H.drow.resize(K);
+  {
+    std::vector<int64_t> row(g.q, 0);
+    for (int64_t jj = 0; jj < g.m; ++jj)
+      for (int k = 0; k < g.q; ++k) {
+        H.drow[(size_t)k * g.m + jj] = (int32_t)row[k];
+        row[k] += p->ranks[3 * (k + (int64_t)g.q * jj)];
+      }
+  }
+  dtg_grow_rows(p);
+  p->use_dtg[1] = p->dtg_packed && g.m >= kGrowColGemmMin &&
+                  dtg_workspace_bytes(p, 1) <= p->grow_adj_ws;
   // column splits as pack_plan sets them
   const int64_t base_f = (int64_t)g.q * p->tiling.tiles, base_a = (int64_t)g.q * p->tiling_a.tiles;
   const int sf = (int)std::min<int64_t>(8, std::max<int64_t>(1, (1024 + base_f - 1) / base_f));
@@ -772,6 +825,7 @@ tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
     off += n;
   };
   add(p->d_meta, H.meta.data(), H.meta.size() * sizeof(TensorMeta));
+  add(p->d_drow, H.drow.data(), H.drow.size() * sizeof(int32_t));
   add(p->d_cores + p->g_off[t0], H.cores.data(), H.cores.size() * sizeof(float2));
   add(p->d_u1t + p->u1_off[t0], H.u1t.data(), H.u1t.size() * sizeof(float2));
   add(p->d_u2t + p->u2_off[t0], H.u2t.data(), H.u2t.size() * sizeof(float2));

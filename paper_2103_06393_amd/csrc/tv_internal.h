@@ -162,6 +162,7 @@ struct tv_plan_s {
   size_t grow_pinned_bytes = 0;
   char* d_stage = nullptr;     // their device staging region in the arena
   size_t stage_bytes = 0;
+  size_t grow_adj_ws = 0;      // adjoint workspace the caller provides
 };
 
 namespace tv {
@@ -196,6 +197,10 @@ tv_status set_split(tv_plan_s* p, int op, int S);
 // decompress-then-GEMM forward (tv_dtg.hip)
 tv_status dtg_pack(tv_plan_s* p, const std::vector<TensorMeta>& meta);
 bool dtg_supported(const tv_plan_s* p);
+// 32-row blocks of one decompress-then-GEMM workgroup tile (tv_dtg.hip), and
+// the most components that path takes (DTG_MAXQ there)
+int dtg_mt(const tv_plan_s* p);
+constexpr int DTG_MAXQ_HOST = 12;
 size_t dtg_workspace_bytes(const tv_plan_s* p, int op);
 int64_t dtg_launch_tiles(const tv_plan_s* p, int s3, int nbw);  // workgroups of one GEMM launch
 int64_t dtg_colgemm_tiles(const tv_plan_s* p, int nbw);  // adjoint column GEMM tiles per split
@@ -221,7 +226,13 @@ tv_status grow_plan_create(const tv_grid& g, const int rmax[3], tv_precision pre
 // rmax packs its pieces into (grow_plan_set_stage hands one over; without one
 // the plan uses a host vector)
 size_t grow_stage_bytes(const tv_grid& g, const int rmax[3], tv_precision precision);
-void grow_plan_set_stage(tv_plan p, const HostStage& stage);
+// workspace of a growable plan's column-GEMM adjoint at its capacity; the
+// plan takes that path from kGrowColGemmMin columns on while its workspace at
+// the current ranks fits what grow_plan_set_stage was told the caller holds,
+// the fused kernels otherwise
+constexpr int kGrowColGemmMin = 8;
+size_t grow_adjoint_ws_bytes(const tv_grid& g, const int rmax[3]);
+void grow_plan_set_stage(tv_plan p, const HostStage& stage, size_t adj_ws_bytes);
 tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
                            const double* u1, const double* u2, const double* u3,
                            hipStream_t st);
