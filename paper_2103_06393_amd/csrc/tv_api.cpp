@@ -793,13 +793,15 @@ tv_status grow_plan_append(tv_plan p, const int32_t* ranks, const double* cores,
   dtg_grow_rows(p);
   if (p->dtg_packed) {
     // column splits of the adjoint's column GEMM: U holds a few stacked rows
-    // per component, so split the voxel columns until about 1024 workgroups
-    // share the work (each split at least 4 k-steps), fewer where the
-    // workspace would not hold their partials
+    // per component, so split the voxel columns towards 1024 workgroups (each
+    // split at least 4 k-steps), at most 16 ways (the reduction, one
+    // workgroup per column of U, reads every split's partials: at 64 splits
+    // it took longer than the GEMM), fewer where the workspace would not hold
+    // their partials
     const int64_t tiles = std::max<int64_t>(1, dtg_colgemm_tiles(p, p->dtg_nbw_a));
     const int64_t nst = ((int64_t)g.n2 * g.n3 + kDtgRowPad - 1) / kDtgRowPad;
     int S = (int)std::max<int64_t>(
-        1, std::min<int64_t>({(1024 + tiles - 1) / tiles, 64, nst / 4}));
+        1, std::min<int64_t>({(1024 + tiles - 1) / tiles, 16, nst / 4}));
     p->dtg_split_a = S;
     while (S > 1 && dtg_workspace_bytes(p, 1) > p->grow_adj_ws) p->dtg_split_a = S /= 2;
   }
