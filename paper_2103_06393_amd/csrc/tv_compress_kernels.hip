@@ -680,7 +680,10 @@ __global__ __launch_bounds__(256) void cgs2_kernel(Cgs2Batch B) {
       {
         const int kk = tid & 63, part = tid >> 6;
         double2 a = make_double2(0.0, 0.0);
+        // unrolled so that the loads of several rows are in flight at once
+        // (the sums keep their order)
         if (kk < j)
+#pragma unroll 8
           for (int i = part; i < n; i += 4) {
             const double2 q = Zb[(int64_t)i * ls + kk], z = Zb[(int64_t)i * ls + j];
             a.x += q.x * z.x + q.y * z.y;  // conj(q) z
@@ -695,6 +698,7 @@ __global__ __launch_bounds__(256) void cgs2_kernel(Cgs2Batch B) {
       __syncthreads();
       for (int i = tid; i < n; i += 256) {
         double2 z = Zb[(int64_t)i * ls + j];
+#pragma unroll 8
         for (int k = 0; k < j; ++k) {
           const double2 q = Zb[(int64_t)i * ls + k], ck = c[k];
           z.x -= q.x * ck.x - q.y * ck.y;
