@@ -408,7 +408,7 @@ tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h,
  * decompression, U V_j^* from the fused forward and U^* x from the
  * decompress-then-GEMM adjoint once U has 8 columns (the fused adjoint
  * before, or when that path's workspace at the current ranks would pass
- * 8 GiB), in the given precision.
+ * 16 GiB), in the given precision.
  * The loop stops when |x||y| <= tol sqrt(s) (s the running estimate of
  * ||U V^*||_F^2, with the cross term 2 Re sum conj(V^* y) (U^* x)), when a
  * residual row is exactly zero, or after max_terms steps.
@@ -426,7 +426,7 @@ tv_status tv_dipole_rows(int32_t n1, int32_t n2, int32_t n3, double h,
  * rank_min, rank_cap, precision) bytes: the row, column and V buffers, one
  * column's compression scratch, U's device arena at max_terms columns of the
  * largest ranks the HOSVD clamps allow (rank_cap bounds it) and the products'
- * workspace (the adjoint's slab of U at those ranks, at most 8 GiB);
+ * workspace (the adjoint's slab of U at those ranks, at most 16 GiB);
  * TV_ERR_WORKSPACE before any device work if short.
  * TV_ERR_NUMERIC if the first pivot row of Z is zero.
  * ---------------------------------------------------------------------- */

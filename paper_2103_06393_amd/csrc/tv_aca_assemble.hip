@@ -276,7 +276,7 @@ struct Buffers {
 };
 
 // Largest rank per mode a new column of U may keep (the HOSVD's clamps).
-constexpr size_t kGrowAdjBudget = (size_t)8 << 30;
+constexpr size_t kGrowAdjBudget = (size_t)16 << 30;
 
 void rank_bounds(const tv_grid& g, int rank_cap, int rmax[3]) {
   const int dims[3] = {g.n1, g.n2, g.n3};
